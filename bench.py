@@ -1,0 +1,192 @@
+"""Throughput of the MI355X immersed-boundary DNS time step.
+
+One step = the whole hot path (RHS + AB2 predictor, outflow, immersed-boundary
+forcing of the grid points and the flag, FFT/tridiagonal pressure projection,
+CFL time step, flag sub-steps) over the paper-like workload: 12L x 6L x 6L on
+768 x 384 x 384 cells (113M), Re 1000, passive grid of square bars
+(M = 0.5L, d = 0.1L, about 3.0e5 solid points) and a 96 x 96 flag 6M
+downstream, dt from CFL 0.5, plain FP64.  Inputs are seeded and synthetic
+(uniform inflow plus Gaussian noise of amplitude 0.05) and resident in HBM
+before the timed region.
+
+Prints one JSON line.  --gpus above 1 is rejected: this build runs on one GPU.
+"""
+from __future__ import annotations
+
+import argparse
+import json
+import math
+import os
+import sys
+import time
+
+import numpy as np
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+METRIC = ("Mcell-steps/s and HBM GB/s: plain FP64 vs FP32-mixed / batched, fixed accuracy")
+HBM_PEAK_GBS = 8000.0
+
+# Algorithmic HBM bytes per cell of each FP64 kernel (compulsory reads + writes;
+# half-spectrum complex arrays hold (ny/2+1)/ny of a complex per cell).
+def kernel_bytes_per_cell(ny: int) -> dict:
+    half = 16.0 * (ny // 2 + 1) / ny          # bytes of half spectrum per cell
+    return {
+        "predict": 7 * 8 + 6 * 8,            # u v w p H(3) in; H(3) u~(3) out
+        "div_ffty": 3 * 8 + half,             # u~(3) in; spectrum out
+        "fftz_fwd": 2 * half,
+        "tri_x": 2 * half,
+        "fftz_inv": 2 * half,
+        "iffty": half + 8,                    # spectrum in; phi out
+        "project": 5 * 8 + 4 * 8,             # u~(3) phi p in; u v w p out
+    }
+
+
+def make_workload(name: str):
+    import synth
+    if name in ("grid_flag_768x384x384_re1000", "default"):
+        return synth.grid_flag_768_re1000()
+    if name == "flag_64x32x32_re200":
+        return synth.flag_64_re200()
+    raise SystemExit(f"unknown workload {name}")
+
+
+def cpu_baseline(w, budget_s: float = 20.0) -> dict:
+    """Time the oracle (as it stands) on a bounded sample of the workload.
+
+    Sample: the workload's mesh spacing, Re, CFL rule, bars and seeded noise on
+    a 128 x 96 x 96 sub-box (2L x 1.5L x 1.5L), stepped for about
+    budget_s/2; plus the oracle's flag update (the workload's full flag at the
+    workload's dt) timed on its own.  Scaled to one full step:
+    t = cells / (sub-box cell rate) + t_flag.
+    """
+    import synth
+    from oracle.flag import FlagModel
+    from oracle.solver import Solver
+    import dataclasses
+    sub = dataclasses.replace(w, nx=128, ny=96, nz=96, lx=128 * w.h, ly=96 * w.h,
+                              lz=96 * w.h, flag=None)
+    noise = synth.ic_noise(sub)
+    bars = synth.bar_points(sub) if sub.grid is not None else None
+    S = Solver(sub, noise, bars, None)
+    S.step(1)   # warm-up
+    t0 = time.perf_counter()
+    n = 0
+    while time.perf_counter() - t0 < budget_s / 2 or n < 1:
+        S.step(1)
+        n += 1
+    t_cells = (time.perf_counter() - t0) / n
+    rate = sub.cells / t_cells                     # cell-steps per second
+    t_flag = 0.0
+    if w.flag is not None:
+        f = w.flag
+        X0 = synth.flag_reference(w)
+        F = FlagModel(X0, f.length, f.mass_ratio, f.bending, f.stretch, f.le_bc)
+        X = X0.reshape(-1, 3).copy()
+        V = np.zeros_like(X)
+        dt = w.cfl * w.h / 1.5 if w.dt <= 0 else w.dt   # representative CFL step
+        t1 = time.perf_counter()
+        m = 0
+        while time.perf_counter() - t1 < budget_s / 2 or m < 1:
+            X, V, _ = F.advance(X, V, np.zeros_like(X), dt)
+            m += 1
+        t_flag = (time.perf_counter() - t1) / m
+    t_step = w.cells / rate + t_flag
+    # numpy's element-wise kernels and pocketfft run on one thread
+    return {"value": w.cells / t_step / 1e6, "unit": "Mcell-steps/s", "cores": 1,
+            "kind": "oracle",
+            "sample": (f"numpy FP64 oracle: {n} steps of a 128x96x96 sub-box at the workload's "
+                       f"h, Re, CFL and bars ({t_cells:.2f} s/step, "
+                       f"{rate / 1e6:.3f} Mcell-steps/s) plus {0 if w.flag is None else m} "
+                       f"flag updates of the full flag ({t_flag:.2f} s each), scaled to "
+                       f"{w.cells} cells")}
+
+
+def main():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=30)
+    ap.add_argument("--warmup", type=int, default=5)
+    ap.add_argument("--workload", default="grid_flag_768x384x384_re1000")
+    ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--cpu-budget", type=float, default=20.0)
+    args = ap.parse_args()
+    if args.gpus != 1:
+        print(json.dumps({"error": "this build runs on one GPU; --gpus must be 1"}))
+        sys.exit(2)
+
+    import torch
+    import synth
+    import paper_2103_08246_amd as ib
+
+    w = make_workload(args.workload)
+    print(f"# workload {w.name}: {w.nx}x{w.ny}x{w.nz} = {w.cells} cells", file=sys.stderr, flush=True)
+    noise = synth.ic_noise(w)
+    bars = synth.bar_points(w) if w.grid is not None else None
+    X0 = synth.flag_reference(w) if w.flag is not None else None
+    run = ib.create(ib.domain_from(w), noise, points=bars,
+                    flag=ib.flag_from(w.flag) if w.flag is not None else None, flag_X0=X0)
+    del noise
+    print(f"# set up; {len(bars[1]) if bars else 0} solid points", file=sys.stderr, flush=True)
+    run.step(args.warmup)
+    ib.sync(run.ctx)
+    print("# warm-up done", file=sys.stderr, flush=True)
+
+    stream = torch.cuda.current_stream()
+    ib.enable_timing(run.ctx, True)
+    ev0 = torch.cuda.Event(enable_timing=True)
+    ev1 = torch.cuda.Event(enable_timing=True)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    ev0.record(stream)
+    run.step(args.steps)
+    ev1.record(stream)
+    ib.sync(run.ctx)
+    torch.cuda.synchronize()
+    wall = time.perf_counter() - t0
+    gpu_ms = ev0.elapsed_time(ev1)
+    ib.enable_timing(run.ctx, False)
+    times = ib.kernel_times(run.ctx)
+    sc = ib.get_scalars(run.ctx)
+    ms_per_step = wall * 1e3 / args.steps
+    value = w.cells * args.steps / wall / 1e6
+
+    # roofline of the dominant fluid kernel
+    bpc = kernel_bytes_per_cell(w.ny)
+    dom = max((k for k in times if k in bpc), key=lambda k: times[k][0])
+    avg_ms = times[dom][0] / times[dom][1]
+    achieved = bpc[dom] * w.cells / (avg_ms * 1e-3) / 1e9
+    traffic = None
+    tf = os.path.join(ROOT, "profiles", f"traffic_{dom}.json")
+    if os.path.exists(tf):
+        traffic = json.load(open(tf)).get("hbm_bytes_per_launch")
+    roofline = {"bound": "hbm", "kernel": dom, "achieved": round(achieved, 1),
+                "peak": HBM_PEAK_GBS, "unit": "GB/s", "frac": round(achieved / HBM_PEAK_GBS, 4),
+                "traffic": traffic,
+                "algorithmic_bytes_per_launch": int(bpc[dom] * w.cells),
+                "avg_launch_ms": round(avg_ms, 4)}
+    breakdown = {k: round(v[0] / max(v[1], 1), 4) for k, v in sorted(times.items(),
+                 key=lambda kv: -kv[1][0])}
+    step_bytes = sum(bpc.values()) * w.cells
+    out = {"metric": METRIC, "value": round(value, 1), "unit": "Mcell-steps/s", "n_gpus": 1,
+           "steps": args.steps, "warmup": args.warmup, "ms_per_step": round(ms_per_step, 4),
+           "higher_is_better": True, "scaling": "weak", "vs_baseline": None, "dtype": "f64",
+           "data": "synthetic",
+           "config": {"workload": w.name, "cells": w.cells, "grid": [w.nx, w.ny, w.nz],
+                      "re": w.re, "cfl": w.cfl, "solid_points": 0 if bars is None else len(bars[1]),
+                      "flag_nodes": 0 if w.flag is None else w.flag.ns ** 2,
+                      "precision": "fp64", "flag_substeps": sc["nsub"], "dt": sc["dt"]},
+           "roofline": roofline,
+           "step_hbm_gbs": round(step_bytes / (ms_per_step * 1e-3) / 1e9, 1),
+           "gpu_event_ms_per_step": round(gpu_ms / args.steps, 4),
+           "kernel_avg_ms": breakdown}
+    run.close()
+    if not args.no_cpu_baseline:
+        print("# timing the CPU oracle sample", file=sys.stderr, flush=True)
+        out["cpu_baseline"] = cpu_baseline(w, args.cpu_budget)
+    print(json.dumps(out), flush=True)
+
+
+if __name__ == "__main__":
+    main()

@@ -1,0 +1,201 @@
+/*
+ * ibdns.h -- C ABI of the MI355X immersed-boundary DNS time step.
+ *
+ * One call of ibdns_step advances, on one GPU, the fractional-step scheme of
+ * Olivieri, Viola, Mazzino & Rosti, "Direct numerical simulation of flapping
+ * flags in grid-induced turbulence" (arXiv 2103.08246), Sec. II:
+ *   - incompressible Navier-Stokes, Eqs. (2)-(3), on a staggered Cartesian mesh
+ *     with second-order centred differences (Sec. II.B);
+ *   - uniform inflow (U,0,0) at x = 0, convective outflow at x = Lx, periodic
+ *     in y and z (Sec. II.A);
+ *   - direct-forcing immersed boundaries for static solid points (the passive
+ *     grid, Sec. II.A) and for the moving flag (Sec. II.B);
+ *   - pressure-Poisson projection (FFT in y and z, tridiagonal solve in x);
+ *   - the flag's spring-network / bending update (Sec. II.B, last paragraphs).
+ *
+ * Conventions
+ *   Cells i = 0..nx-1, j = 0..ny-1, k = 0..nz-1 of size h = lx/nx = ly/ny = lz/nz.
+ *   Host field arrays are x fastest:  a[i + NX * (j + ny * k)]  with
+ *     u: NX = nx+1 (x faces, i = 0 inlet, i = nx outlet) at (i h, (j+1/2) h, (k+1/2) h)
+ *     v: NX = nx at ((i+1/2) h, j h, (k+1/2) h);  w: NX = nx at ((i+1/2) h, (j+1/2) h, k h)
+ *     p: NX = nx at cell centres.
+ *   Flag arrays are ns*ns*3 doubles, index (a + ns*b)*3 + c, a streamwise from the
+ *   leading edge, b spanwise, c the Cartesian component.
+ *   All device arrays live inside one caller-owned workspace; all host arrays
+ *   passed in or out are caller-owned and only read/written during the call.
+ *
+ * Errors
+ *   Every entry point returns an int status (IBDNS_OK = 0 or a negative code);
+ *   nothing throws across the ABI.  EUNSTABLE is sticky: it is raised on the
+ *   device (non-finite velocity, CFL number above 1, or an immersed point whose
+ *   support leaves the evolved x range) and reported by the next call that
+ *   synchronises (ibdns_get_fields, ibdns_get_flag, ibdns_sync).
+ *   Calls on one context must not overlap; use one context per host thread.
+ */
+#ifndef IBDNS_H
+#define IBDNS_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef struct ibdns_ctx ibdns_ctx; /* opaque, library-owned host object */
+
+enum {
+  IBDNS_OK = 0,
+  IBDNS_EINVAL = -1,    /* bad argument or unsupported size                */
+  IBDNS_ENOMEM = -2,    /* workspace too small                             */
+  IBDNS_EHIP = -3,      /* a HIP runtime call failed                       */
+  IBDNS_EUNSTABLE = -4, /* device status: non-finite / CFL > 1 / point left range */
+  IBDNS_ESTATE = -5     /* call out of order (e.g. step before init)       */
+};
+
+enum { IBDNS_FP64 = 0, IBDNS_MIXED = 1 };
+enum { IBDNS_LE_HINGED = 0, IBDNS_LE_CLAMPED = 1 };
+
+/* Test hook: v and w use zero-gradient ghosts at both x ends instead of the
+ * zero-inflow ghost and the convective outflow (keeps x-invariant flows such
+ * as a y-z Taylor-Green vortex x-invariant). */
+enum { IBDNS_TEST_VW_NEUMANN_X = 1u << 0 };
+
+/* Domain and physics (Sec. II.A: box lx*ly*lz, Re = U L / nu with L = 1). */
+typedef struct {
+  int32_t nx, ny, nz;  /* cells; ny and nz must be 2^a 3^b (a >= 1), nx >= 8    */
+  double lx, ly, lz;   /* box; h = lx/nx must equal ly/ny and lz/nz              */
+  double re;           /* nu = 1 / re                                            */
+  double u_in;         /* inflow speed U                                         */
+  double dt;           /* > 0: fixed time step; <= 0: from the CFL number         */
+  double cfl;          /* CFL number used when dt <= 0                           */
+  double noise_amp;    /* amplitude A of the initial-condition noise             */
+  int32_t precision;   /* IBDNS_FP64 (only FP64 is implemented)                  */
+  uint32_t flags;      /* IBDNS_TEST_* bits, 0 in production                      */
+} ibdns_domain;
+
+/* Flag (Sec. II.A: square of side L, mass ratio rho, bending coefficient beta,
+ * hinged at its leading edge; Sec. II.B: spring network, essentially
+ * inextensible). */
+typedef struct {
+  int32_t ns;          /* nodes per side, 3 <= ns <= 128                         */
+  double length;       /* L                                                      */
+  double mass_ratio;   /* rho: mass per unit area                                */
+  double bending;      /* beta                                                   */
+  double stretch;      /* in-plane spring stiffness per unit width (large)       */
+  int32_t le_bc;       /* IBDNS_LE_HINGED or IBDNS_LE_CLAMPED                    */
+} ibdns_flag;
+
+/* Bytes of device workspace needed for a domain with up to n_points static
+ * solid points and a flag of flag_ns nodes per side (0: no flag).
+ * Returns EINVAL for an unsupported domain. */
+int ibdns_workspace_size(const ibdns_domain* d, int64_t n_points, int32_t flag_ns,
+                         size_t* bytes);
+
+/* Create a context over the caller's device workspace (dev_ws, ws_bytes; at
+ * least ibdns_workspace_size bytes, 256-byte aligned) on the caller's HIP
+ * stream (hipStream_t passed as void*; NULL = default stream) of the current
+ * device, and set the initial condition (reading of the paper's uniform
+ * stream start): u = U + A zu on every u face but the inlet, v = A zv,
+ * w = A zw, p = 0, made divergence free by one projection; dt_0 from the CFL
+ * number unless fixed.  zu (nz*ny*(nx+1)), zv, zw (nz*ny*nx) are host arrays
+ * of standard-normal noise in the field layouts above, or NULL for no noise.
+ * The context keeps pointers into dev_ws only; the caller keeps dev_ws alive
+ * until ibdns_destroy.  On error *out is NULL. */
+int ibdns_init_domain(const ibdns_domain* d, const double* zu, const double* zv,
+                      const double* zw, void* dev_ws, size_t ws_bytes, void* hip_stream,
+                      ibdns_ctx** out);
+
+/* Immersed bodies (Sec. II.B direct forcing).  n_points static solid points
+ * with positions X (host, n_points*3, point-major) and volumes dV (host,
+ * n_points), forced to zero velocity (the passive grid).  flag (may be NULL)
+ * with its reference lattice X0 (host, ns*ns*3, layout above); its nodes are
+ * forced to the flag velocity.  Every point's 3x3x3 delta support must stay
+ * on evolved velocity nodes in x (else EINVAL).  May be called once, before
+ * the first ibdns_step. */
+int ibdns_set_geometry(ibdns_ctx* ctx, int64_t n_points, const double* X, const double* dV,
+                       const ibdns_flag* flag, const double* flag_X0);
+
+/* Advance n_steps time steps, asynchronously on the context's stream. */
+int ibdns_step(ibdns_ctx* ctx, int32_t n_steps);
+
+/* Wait for the stream and report the sticky device status. */
+int ibdns_sync(ibdns_ctx* ctx);
+
+/* Copy the current state to host arrays (any may be NULL): u, v, w, p in the
+ * layouts above, the time t and the step count.  Synchronises. */
+int ibdns_get_fields(ibdns_ctx* ctx, double* u, double* v, double* w, double* p, double* t,
+                     int64_t* step);
+
+/* Copy the flag's node positions X, velocities V and the hydrodynamic force
+ * density F applied to the fluid at each node in the last step (host arrays of
+ * ns*ns*3, any may be NULL).  Synchronises.  EINVAL if there is no flag. */
+int ibdns_get_flag(ibdns_ctx* ctx, double* X, double* V, double* F);
+
+/* Release the context (not the workspace). */
+int ibdns_destroy(ibdns_ctx* ctx);
+
+const char* ibdns_strerror(int status);
+
+/* ------------------------------------------------------------------------
+ * Diagnostic entry points (tests and profiling).
+ * ---------------------------------------------------------------------- */
+
+/* Stages of one step, in order. */
+enum {
+  IBDNS_STAGE_PREDICT = 0, /* S1-S3: RHS, AB2 predictor, convective outflow */
+  IBDNS_STAGE_FLUX = 1,    /* S4: outflow flux correction                  */
+  IBDNS_STAGE_IBM = 2,     /* S5: interpolation, forcing, spreading        */
+  IBDNS_STAGE_PROJECT = 3, /* S6-S8: divergence, Poisson, projection       */
+  IBDNS_STAGE_FLAG = 4,    /* S10: flag sub-steps                           */
+  IBDNS_STAGE_ADVANCE = 5, /* S9 + S11: next dt, time, history             */
+  IBDNS_NUM_STAGES = 6
+};
+
+/* Run one stage of the current step on the stream. */
+int ibdns_run_stage(ibdns_ctx* ctx, int32_t stage);
+
+/* Arrays reachable by ibdns_get_array / ibdns_set_array (host layouts as for
+ * ibdns_get_fields; provisional velocities and H histories use the u, v, w
+ * layouts; PHI the p layout; point arrays are n_points*3). */
+enum {
+  IBDNS_ARR_U = 0, IBDNS_ARR_V, IBDNS_ARR_W, IBDNS_ARR_P,
+  IBDNS_ARR_UT, IBDNS_ARR_VT, IBDNS_ARR_WT,
+  IBDNS_ARR_HU, IBDNS_ARR_HV, IBDNS_ARR_HW,
+  IBDNS_ARR_PHI,
+  IBDNS_ARR_POINT_F,      /* force density of the static points, last step */
+  IBDNS_ARR_V_GHOST,      /* v outlet ghost plane, ny*nz (x index nx)      */
+  IBDNS_ARR_W_GHOST,
+  IBDNS_NUM_ARRAYS
+};
+
+/* Synchronous copies between a device array and a host array. */
+int ibdns_get_array(ibdns_ctx* ctx, int32_t which, double* host);
+int ibdns_set_array(ibdns_ctx* ctx, int32_t which, const double* host);
+
+/* Scalars of the step: [dt, dt_prev, t, max cell speed of the last CFL pass,
+ * outflow correction of the last step, flag sub-steps of the last step]. */
+int ibdns_get_scalars(ibdns_ctx* ctx, double* out6);
+
+/* Overwrite dt and dt_prev (tests: reproduce an oracle state). first_step
+ * non-zero makes the next predictor an Euler step (H^{n-1} := H^n). */
+int ibdns_set_time(ibdns_ctx* ctx, double dt, double dt_prev, int32_t first_step);
+
+/* Index maps of the immersed points: centre node (i, j, k) of the 3x3x3
+ * support of every point (static points first, then flag nodes a-fastest) for
+ * velocity component comp (0 u, 1 v, 2 w), computed on the device from the
+ * current positions as floor((X - o_comp)/h + 1/2).  out: n_total*3 int32. */
+int ibdns_get_maps(ibdns_ctx* ctx, int32_t comp, int32_t* out);
+
+/* Per-kernel timing with HIP events recorded on the context's stream.
+ * enable != 0 starts accumulating; ibdns_kernel_times fills up to n entries
+ * of names/total milliseconds/launch counts (sync first) and returns the
+ * number of timed kernels. */
+int ibdns_enable_timing(ibdns_ctx* ctx, int32_t enable);
+int ibdns_kernel_times(ibdns_ctx* ctx, int32_t n, const char** names, double* total_ms,
+                       int64_t* launches);
+
+#ifdef __cplusplus
+}
+#endif
+#endif /* IBDNS_H */

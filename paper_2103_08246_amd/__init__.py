@@ -1,0 +1,287 @@
+"""Python binding of the MI355X immersed-boundary DNS library (libibdns.so).
+
+Argument marshalling only: every stage of the time step runs in the HIP
+kernels behind the C ABI declared in include/ibdns.h.  PyTorch provides the
+device workspace and the stream.  Importing this package fails loudly if the
+compiled library is missing; there is no CPU fallback.
+"""
+from __future__ import annotations
+
+import ctypes
+import os
+from dataclasses import dataclass
+
+import numpy as np
+
+HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(HERE, "libibdns.so")
+
+OK, EINVAL, ENOMEM, EHIP, EUNSTABLE, ESTATE = 0, -1, -2, -3, -4, -5
+FP64, MIXED = 0, 1
+LE_HINGED, LE_CLAMPED = 0, 1
+TEST_VW_NEUMANN_X = 1
+STAGE_PREDICT, STAGE_FLUX, STAGE_IBM, STAGE_PROJECT, STAGE_FLAG, STAGE_ADVANCE = range(6)
+(ARR_U, ARR_V, ARR_W, ARR_P, ARR_UT, ARR_VT, ARR_WT, ARR_HU, ARR_HV, ARR_HW, ARR_PHI,
+ ARR_POINT_F, ARR_V_GHOST, ARR_W_GHOST) = range(14)
+
+EXPORTED = ("ibdns_workspace_size", "ibdns_init_domain", "ibdns_set_geometry", "ibdns_step",
+            "ibdns_sync", "ibdns_get_fields", "ibdns_get_flag", "ibdns_destroy",
+            "ibdns_strerror", "ibdns_run_stage", "ibdns_get_array", "ibdns_set_array",
+            "ibdns_get_scalars", "ibdns_set_time", "ibdns_get_maps", "ibdns_enable_timing",
+            "ibdns_kernel_times")
+
+
+class Domain(ctypes.Structure):
+    _fields_ = [("nx", ctypes.c_int32), ("ny", ctypes.c_int32), ("nz", ctypes.c_int32),
+                ("lx", ctypes.c_double), ("ly", ctypes.c_double), ("lz", ctypes.c_double),
+                ("re", ctypes.c_double), ("u_in", ctypes.c_double), ("dt", ctypes.c_double),
+                ("cfl", ctypes.c_double), ("noise_amp", ctypes.c_double),
+                ("precision", ctypes.c_int32), ("flags", ctypes.c_uint32)]
+
+
+class FlagParams(ctypes.Structure):
+    _fields_ = [("ns", ctypes.c_int32), ("length", ctypes.c_double),
+                ("mass_ratio", ctypes.c_double), ("bending", ctypes.c_double),
+                ("stretch", ctypes.c_double), ("le_bc", ctypes.c_int32)]
+
+
+class IbdnsError(RuntimeError):
+    def __init__(self, code, what):
+        self.code = code
+        super().__init__(f"{what}: {strerror(code)} ({code})")
+
+
+def _load():
+    # torch ships its own HIP runtime (soname libamdhip64.so.7); importing it
+    # first makes this library bind to that same runtime, so that device
+    # pointers from torch allocations are valid here.
+    try:
+        import torch  # noqa: F401
+    except ImportError:
+        pass
+    if not os.path.exists(LIB_PATH):
+        raise ImportError(f"{LIB_PATH} is not built; run paper_2103_08246_amd/build.py "
+                          "(hipcc --offload-arch=gfx950). There is no CPU fallback.")
+    lib = ctypes.CDLL(LIB_PATH)
+    P = ctypes.c_void_p
+    D = ctypes.POINTER(ctypes.c_double)
+    lib.ibdns_workspace_size.argtypes = [ctypes.POINTER(Domain), ctypes.c_int64, ctypes.c_int32,
+                                         ctypes.POINTER(ctypes.c_size_t)]
+    lib.ibdns_init_domain.argtypes = [ctypes.POINTER(Domain), D, D, D, P, ctypes.c_size_t, P,
+                                      ctypes.POINTER(P)]
+    lib.ibdns_set_geometry.argtypes = [P, ctypes.c_int64, D, D, ctypes.POINTER(FlagParams), D]
+    lib.ibdns_step.argtypes = [P, ctypes.c_int32]
+    lib.ibdns_sync.argtypes = [P]
+    lib.ibdns_get_fields.argtypes = [P, D, D, D, D, D, ctypes.POINTER(ctypes.c_int64)]
+    lib.ibdns_get_flag.argtypes = [P, D, D, D]
+    lib.ibdns_destroy.argtypes = [P]
+    lib.ibdns_strerror.argtypes = [ctypes.c_int]
+    lib.ibdns_strerror.restype = ctypes.c_char_p
+    lib.ibdns_run_stage.argtypes = [P, ctypes.c_int32]
+    lib.ibdns_get_array.argtypes = [P, ctypes.c_int32, D]
+    lib.ibdns_set_array.argtypes = [P, ctypes.c_int32, D]
+    lib.ibdns_get_scalars.argtypes = [P, D]
+    lib.ibdns_set_time.argtypes = [P, ctypes.c_double, ctypes.c_double, ctypes.c_int32]
+    lib.ibdns_get_maps.argtypes = [P, ctypes.c_int32, ctypes.POINTER(ctypes.c_int32)]
+    lib.ibdns_enable_timing.argtypes = [P, ctypes.c_int32]
+    lib.ibdns_kernel_times.argtypes = [P, ctypes.c_int32, ctypes.POINTER(ctypes.c_char_p), D,
+                                       ctypes.POINTER(ctypes.c_int64)]
+    return lib
+
+
+_lib = _load()
+
+
+def lib():
+    return _lib
+
+
+def strerror(code: int) -> str:
+    return _lib.ibdns_strerror(code).decode()
+
+
+def _check(code, what):
+    if code != OK:
+        raise IbdnsError(code, what)
+    return code
+
+
+def _dptr(a):
+    if a is None:
+        return None
+    assert a.dtype == np.float64 and a.flags.c_contiguous
+    return a.ctypes.data_as(ctypes.POINTER(ctypes.c_double))
+
+
+def make_domain(nx, ny, nz, lx, ly, lz, re, u_in=1.0, dt=0.0, cfl=0.5, noise_amp=0.0,
+                precision=FP64, flags=0) -> Domain:
+    return Domain(nx, ny, nz, lx, ly, lz, re, u_in, dt, cfl, noise_amp, precision, flags)
+
+
+def workspace_size(dom: Domain, n_points: int = 0, flag_ns: int = 0) -> int:
+    out = ctypes.c_size_t(0)
+    _check(_lib.ibdns_workspace_size(ctypes.byref(dom), n_points, flag_ns, ctypes.byref(out)),
+           "workspace_size")
+    return out.value
+
+
+def init_domain(dom: Domain, noise, ws_ptr: int, ws_bytes: int, stream_ptr: int):
+    """noise: (zu, zv, zw) float64 arrays or None.  Returns the context handle."""
+    ctx = ctypes.c_void_p()
+    zu = zv = zw = None
+    if noise is not None:
+        zu, zv, zw = (np.ascontiguousarray(z, dtype=np.float64) for z in noise)
+    _check(_lib.ibdns_init_domain(ctypes.byref(dom), _dptr(zu), _dptr(zv), _dptr(zw),
+                                  ctypes.c_void_p(ws_ptr), ws_bytes, ctypes.c_void_p(stream_ptr),
+                                  ctypes.byref(ctx)), "init_domain")
+    return ctx
+
+
+def set_geometry(ctx, points=None, flag: FlagParams | None = None, flag_X0=None):
+    n = 0
+    X = dV = None
+    if points is not None:
+        X = np.ascontiguousarray(points[0], dtype=np.float64).reshape(-1)
+        dV = np.ascontiguousarray(points[1], dtype=np.float64).reshape(-1)
+        n = dV.size
+    X0 = None if flag_X0 is None else np.ascontiguousarray(flag_X0, dtype=np.float64).reshape(-1)
+    _check(_lib.ibdns_set_geometry(ctx, n, _dptr(X), _dptr(dV),
+                                   ctypes.byref(flag) if flag is not None else None, _dptr(X0)),
+           "set_geometry")
+
+
+def step(ctx, n: int = 1):
+    _check(_lib.ibdns_step(ctx, n), "step")
+
+
+def sync(ctx):
+    return _check(_lib.ibdns_sync(ctx), "sync")
+
+
+def run_stage(ctx, stage: int):
+    _check(_lib.ibdns_run_stage(ctx, stage), "run_stage")
+
+
+def destroy(ctx):
+    _check(_lib.ibdns_destroy(ctx), "destroy")
+
+
+def get_fields(ctx, nx, ny, nz, check=True):
+    u = np.empty((nz, ny, nx + 1))
+    v = np.empty((nz, ny, nx))
+    w = np.empty((nz, ny, nx))
+    p = np.empty((nz, ny, nx))
+    t = ctypes.c_double()
+    s = ctypes.c_int64()
+    code = _lib.ibdns_get_fields(ctx, _dptr(u), _dptr(v), _dptr(w), _dptr(p), ctypes.byref(t),
+                                 ctypes.byref(s))
+    if check:
+        _check(code, "get_fields")
+    return u, v, w, p, t.value, s.value
+
+
+def get_flag(ctx, ns, check=True):
+    X = np.empty((ns, ns, 3))
+    V = np.empty((ns, ns, 3))
+    F = np.empty((ns, ns, 3))
+    code = _lib.ibdns_get_flag(ctx, _dptr(X), _dptr(V), _dptr(F))
+    if check:
+        _check(code, "get_flag")
+    return X, V, F
+
+
+def get_array(ctx, which, shape):
+    a = np.empty(shape)
+    _check(_lib.ibdns_get_array(ctx, which, _dptr(a)), "get_array")
+    return a
+
+
+def set_array(ctx, which, arr):
+    a = np.ascontiguousarray(arr, dtype=np.float64)
+    _check(_lib.ibdns_set_array(ctx, which, _dptr(a)), "set_array")
+
+
+def get_scalars(ctx, check=True):
+    out = np.empty(6)
+    code = _lib.ibdns_get_scalars(ctx, _dptr(out))
+    if check:
+        _check(code, "get_scalars")
+    return dict(dt=out[0], dt_prev=out[1], t=out[2], speed=out[3], corr=out[4], nsub=int(out[5]))
+
+
+def set_time(ctx, dt, dt_prev, first_step):
+    _check(_lib.ibdns_set_time(ctx, dt, dt_prev, 1 if first_step else 0), "set_time")
+
+
+def get_maps(ctx, comp, n_total):
+    out = np.empty((n_total, 3), dtype=np.int32)
+    _check(_lib.ibdns_get_maps(ctx, comp, out.ctypes.data_as(ctypes.POINTER(ctypes.c_int32))),
+           "get_maps")
+    return out
+
+
+def enable_timing(ctx, on=True):
+    _check(_lib.ibdns_enable_timing(ctx, 1 if on else 0), "enable_timing")
+
+
+def kernel_times(ctx, nmax=64):
+    names = (ctypes.c_char_p * nmax)()
+    ms = np.zeros(nmax)
+    cnt = np.zeros(nmax, dtype=np.int64)
+    m = _lib.ibdns_kernel_times(ctx, nmax, names, _dptr(ms),
+                                cnt.ctypes.data_as(ctypes.POINTER(ctypes.c_int64)))
+    if m < 0:
+        raise IbdnsError(m, "kernel_times")
+    return {names[q].decode(): (ms[q], int(cnt[q])) for q in range(min(m, nmax))}
+
+
+@dataclass
+class Run:
+    """A context plus the torch tensor that owns its workspace."""
+    ctx: object
+    ws: object
+    nx: int
+    ny: int
+    nz: int
+    ns: int = 0
+
+    def step(self, n=1):
+        step(self.ctx, n)
+
+    def fields(self, check=True):
+        return get_fields(self.ctx, self.nx, self.ny, self.nz, check)
+
+    def flag(self, check=True):
+        return get_flag(self.ctx, self.ns, check)
+
+    def close(self):
+        if self.ctx is not None:
+            destroy(self.ctx)
+            self.ctx = None
+
+
+def create(dom: Domain, noise=None, points=None, flag: FlagParams | None = None, flag_X0=None,
+           device="cuda:0", stream=None) -> Run:
+    """Allocate the workspace with torch on ``device`` and build a context."""
+    import torch
+    n_points = 0 if points is None else int(np.asarray(points[1]).size)
+    ns = 0 if flag is None else flag.ns
+    nbytes = workspace_size(dom, n_points, ns)
+    ws = torch.empty(nbytes, dtype=torch.uint8, device=device)
+    st = stream if stream is not None else torch.cuda.current_stream(device)
+    ctx = init_domain(dom, noise, ws.data_ptr(), nbytes, st.cuda_stream)
+    run = Run(ctx, ws, dom.nx, dom.ny, dom.nz, ns)
+    if points is not None or flag is not None:
+        set_geometry(ctx, points, flag, flag_X0)
+    return run
+
+
+def domain_from(w, precision=FP64, flags=0) -> Domain:
+    """Domain struct from any object with nx, ny, nz, lx, ly, lz, re, u_in, dt, cfl, noise_amp."""
+    return make_domain(w.nx, w.ny, w.nz, w.lx, w.ly, w.lz, w.re, w.u_in, w.dt, w.cfl,
+                       w.noise_amp, precision, flags)
+
+
+def flag_from(f) -> FlagParams:
+    """FlagParams from any object with ns, length, mass_ratio, bending, stretch, le_bc."""
+    return FlagParams(f.ns, f.length, f.mass_ratio, f.bending, f.stretch, f.le_bc)

@@ -1,0 +1,792 @@
+// Host side of the C ABI (include/ibdns.h): validation, workspace carving,
+// initial condition, immersed-body set-up and the launch sequence of a step.
+// Every stage of the step runs in the HIP kernels of this directory; the host
+// only prepares static tables (twiddles, eigenvalue shifts, the static
+// points' spreading map, flag masses and the structural sub-step bound).
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <cmath>
+#include <cstring>
+#include <string>
+#include <utility>
+#include <vector>
+
+#include "../../include/ibdns.h"
+#include "ibdns_internal.h"
+
+using namespace ibdns;
+
+namespace {
+
+constexpr size_t ALIGN = 256;
+size_t up(size_t x) { return (x + ALIGN - 1) / ALIGN * ALIGN; }
+
+struct Timed {
+  const char* name;
+  hipEvent_t a, b;
+};
+
+bool is_2a3b(int n) {
+  if (n < 2) return false;
+  while (n % 2 == 0) n /= 2;
+  while (n % 3 == 0) n /= 3;
+  return n == 1;
+}
+
+}  // namespace
+
+struct ibdns_ctx {
+  ibdns_domain dom;
+  Dims d;
+  Fields f;
+  Scalars* s = nullptr;
+  hipStream_t st = nullptr;
+  char* ws = nullptr;
+  size_t ws_bytes = 0;
+  size_t used = 0;
+  double2* tw_y = nullptr;
+  double2* tw_z = nullptr;
+  double* lam_y = nullptr;
+  double* lam_z = nullptr;
+  int nparts = 0;
+  // static points
+  int64_t nbars = 0;
+  PointSet bars{};
+  SpreadCSR csr[3]{};
+  // flag
+  bool has_flag = false;
+  FlagDev fl{};
+  PointSet flagpts{};
+  int ntx = 0, nty = 0, ntz = 0;
+  int* bbox = nullptr;
+  bool geometry_set = false;
+  bool stepped = false;
+  // timing
+  bool timing = false;
+  std::vector<Timed> recs;
+  std::vector<std::pair<std::string, std::pair<double, long long>>> totals;
+
+  template <class T>
+  T* carve(size_t count) {
+    size_t bytes = up(count * sizeof(T));
+    if (used + bytes > ws_bytes) return nullptr;
+    T* p = reinterpret_cast<T*>(ws + used);
+    used += bytes;
+    return p;
+  }
+};
+
+namespace {
+
+// Bytes of the fluid part of the workspace.
+size_t fluid_bytes(const ibdns_domain& dm) {
+  const long long P = ((dm.nx + 1 + 15) / 16) * 16;
+  const long long FS = P * dm.ny * dm.nz;
+  const long long MY = dm.ny / 2 + 1;
+  const long long nparts = ((long long)dm.ny * dm.nz + 255) / 256;
+  size_t b = up(sizeof(Scalars));
+  b += 11 * up(FS * sizeof(double));
+  b += up((size_t)dm.nx * MY * dm.nz * sizeof(double2));
+  b += up(2 * nparts * sizeof(double));
+  b += up(dm.ny * sizeof(double2)) + up(dm.nz * sizeof(double2));
+  b += up(MY * sizeof(double)) + up(dm.nz * sizeof(double));
+  return b;
+}
+
+size_t points_bytes(int64_t n) {
+  if (n <= 0) return 0;
+  size_t b = 0;
+  b += up(3 * n * sizeof(double));        // X
+  b += up(n * sizeof(double));            // dV
+  b += up(3 * n * sizeof(double));        // F
+  b += up(3 * n * sizeof(double));        // amount
+  b += up(9 * n * sizeof(int));           // centre
+  b += up(27 * n * sizeof(double));       // wts
+  for (int c = 0; c < 3; ++c) {
+    b += up(27 * n * sizeof(int));        // row_node
+    b += up((27 * n + 1) * sizeof(int));  // row_ptr
+    b += up(27 * n * sizeof(int));        // entries
+  }
+  return b;
+}
+
+size_t flag_bytes(int ns) {
+  if (ns <= 0) return 0;
+  const size_t n = (size_t)ns * ns;
+  size_t b = 0;
+  b += 5 * up(3 * n * sizeof(double));  // X, V, Fh, X0, f
+  b += 2 * up(n * sizeof(double));      // mass, dV
+  b += up(3 * n * sizeof(double));      // amount
+  b += up(9 * n * sizeof(int));         // centre
+  b += up(27 * n * sizeof(double));     // wts
+  b += up(18 * sizeof(int));            // bbox
+  return b;
+}
+
+int validate(const ibdns_domain* d) {
+  if (!d) return IBDNS_EINVAL;
+  if (d->nx < 8 || d->ny < 2 || d->nz < 2) return IBDNS_EINVAL;
+  if (!is_2a3b(d->ny) || !is_2a3b(d->nz)) return IBDNS_EINVAL;
+  if (!fft_size_supported(d->ny) || !fft_size_supported(d->nz)) return IBDNS_EINVAL;
+  if (!tri_size_supported(d->nx)) return IBDNS_EINVAL;
+  if (!(d->lx > 0 && d->ly > 0 && d->lz > 0 && d->re > 0)) return IBDNS_EINVAL;
+  const double h = d->lx / d->nx;
+  if (std::fabs(d->ly / d->ny - h) > 1e-12 * h || std::fabs(d->lz / d->nz - h) > 1e-12 * h)
+    return IBDNS_EINVAL;
+  if (d->dt <= 0 && !(d->cfl > 0 && d->cfl < 1)) return IBDNS_EINVAL;
+  if (d->precision != IBDNS_FP64) return IBDNS_EINVAL;
+  if ((long long)(((d->nx + 1 + 15) / 16) * 16) * d->ny * d->nz >= (1LL << 31)) return IBDNS_EINVAL;
+  return IBDNS_OK;
+}
+
+#define HIPCHK(x)                        \
+  do {                                   \
+    if ((x) != hipSuccess) return IBDNS_EHIP; \
+  } while (0)
+
+void rec_begin(ibdns_ctx* c, const char* name, hipEvent_t* a) {
+  (void)name;
+  if (!c->timing) return;
+  hipEventCreate(a);
+  hipEventRecord(*a, c->st);
+}
+void rec_end(ibdns_ctx* c, const char* name, hipEvent_t a) {
+  if (!c->timing) return;
+  hipEvent_t b;
+  hipEventCreate(&b);
+  hipEventRecord(b, c->st);
+  c->recs.push_back({name, a, b});
+}
+
+#define TIMED(ctx, name, call)       \
+  do {                               \
+    hipEvent_t ev_a_ = nullptr;      \
+    rec_begin(ctx, name, &ev_a_);    \
+    call;                            \
+    rec_end(ctx, name, ev_a_);       \
+  } while (0)
+
+void stage_predict(ibdns_ctx* c) {
+  TIMED(c, "predict", launch_predict(c->d, c->f, c->s, c->st));
+  TIMED(c, "outlet", launch_outlet(c->d, c->f, c->s, c->nparts, 1, c->st));
+}
+void stage_flux(ibdns_ctx* c) { TIMED(c, "flux_apply", launch_flux_apply(c->d, c->f, c->s, c->nparts, c->st)); }
+
+void stage_ibm(ibdns_ctx* c) {
+  if (c->has_flag) TIMED(c, "flag_stencil", launch_point_stencil(c->d, c->flagpts, c->s, c->st));
+  if (c->nbars) TIMED(c, "bars_interp", launch_point_interp(c->d, c->f, c->bars, c->s, c->st));
+  if (c->has_flag) TIMED(c, "flag_interp", launch_point_interp(c->d, c->f, c->flagpts, c->s, c->st));
+  if (c->nbars) TIMED(c, "bars_spread", launch_spread_csr(c->d, c->f, c->bars, c->csr, c->st));
+  if (c->has_flag) {
+    TIMED(c, "flag_bbox", launch_point_bbox(c->flagpts, c->bbox, c->st));
+    TIMED(c, "flag_spread",
+          launch_spread_tiles(c->d, c->f, c->flagpts, c->bbox, c->ntx, c->nty, c->ntz, c->s, c->st));
+  }
+}
+
+void stage_project(ibdns_ctx* c, int mode) {
+  TIMED(c, "div_ffty", launch_div_ffty(c->d, c->f, c->s, c->tw_y, c->st));
+  TIMED(c, "fftz_fwd", launch_fftz(c->d, c->f, c->tw_z, -1, c->st));
+  TIMED(c, "tri_x", launch_tri(c->d, c->f, c->lam_y, c->lam_z, c->st));
+  TIMED(c, "fftz_inv", launch_fftz(c->d, c->f, c->tw_z, 1, c->st));
+  TIMED(c, "iffty", launch_iffty(c->d, c->f, c->tw_y, c->st));
+  TIMED(c, "project", launch_project(c->d, c->f, c->s, mode, c->st));
+}
+
+void stage_flag(ibdns_ctx* c) {
+  if (c->has_flag) TIMED(c, "flag_step", launch_flag_step(c->fl, c->s, c->st));
+}
+void stage_advance(ibdns_ctx* c) { TIMED(c, "advance", launch_advance(c->s, c->d.h, c->st)); }
+
+int check_launch() { return hipGetLastError() == hipSuccess ? IBDNS_OK : IBDNS_EHIP; }
+
+int read_status(ibdns_ctx* c) {
+  if (hipStreamSynchronize(c->st) != hipSuccess) return IBDNS_EHIP;
+  Scalars hs;
+  if (hipMemcpy(&hs, c->s, sizeof(Scalars), hipMemcpyDeviceToHost) != hipSuccess) return IBDNS_EHIP;
+  return hs.status ? IBDNS_EUNSTABLE : IBDNS_OK;
+}
+
+// Host array dimensions of a field id: x extent (nx+1 or nx) and device pointer.
+double* field_ptr(ibdns_ctx* c, int which, int* nxh) {
+  const int nx = c->d.nx;
+  switch (which) {
+    case IBDNS_ARR_U: *nxh = nx + 1; return c->f.u;
+    case IBDNS_ARR_V: *nxh = nx; return c->f.v;
+    case IBDNS_ARR_W: *nxh = nx; return c->f.w;
+    case IBDNS_ARR_P: *nxh = nx; return c->f.p;
+    case IBDNS_ARR_UT: *nxh = nx + 1; return c->f.ut;
+    case IBDNS_ARR_VT: *nxh = nx; return c->f.vt;
+    case IBDNS_ARR_WT: *nxh = nx; return c->f.wt;
+    case IBDNS_ARR_HU: *nxh = nx + 1; return c->f.hu;
+    case IBDNS_ARR_HV: *nxh = nx; return c->f.hv;
+    case IBDNS_ARR_HW: *nxh = nx; return c->f.hw;
+    case IBDNS_ARR_PHI: *nxh = nx; return c->f.phi;
+    default: return nullptr;
+  }
+}
+
+int copy_field(ibdns_ctx* c, double* dev, int nxh, double* host, bool to_host) {
+  const size_t w = (size_t)nxh * sizeof(double);
+  const size_t sp = (size_t)c->d.P * sizeof(double);
+  const size_t rows = (size_t)c->d.ny * c->d.nz;
+  hipError_t e = to_host ? hipMemcpy2D(host, w, dev, sp, w, rows, hipMemcpyDeviceToHost)
+                         : hipMemcpy2D(dev, sp, host, w, w, rows, hipMemcpyHostToDevice);
+  return e == hipSuccess ? IBDNS_OK : IBDNS_EHIP;
+}
+
+double roma_host(double r) {
+  const double a = std::fabs(r);
+  if (a <= 0.5) return (1.0 + std::sqrt(1.0 - 3.0 * a * a)) / 3.0;
+  if (a <= 1.5) {
+    const double b = 1.0 - a;
+    return (5.0 - 3.0 * a - std::sqrt(std::fmax(1.0 - 3.0 * b * b, 0.0))) / 6.0;
+  }
+  return 0.0;
+}
+
+}  // namespace
+
+extern "C" {
+
+const char* ibdns_strerror(int status) {
+  switch (status) {
+    case IBDNS_OK: return "ok";
+    case IBDNS_EINVAL: return "invalid argument or unsupported size";
+    case IBDNS_ENOMEM: return "workspace too small";
+    case IBDNS_EHIP: return "HIP runtime error";
+    case IBDNS_EUNSTABLE: return "unstable: non-finite velocity, CFL > 1 or immersed point out of range";
+    case IBDNS_ESTATE: return "call out of order";
+    default: return "unknown status";
+  }
+}
+
+int ibdns_workspace_size(const ibdns_domain* d, int64_t n_points, int32_t flag_ns, size_t* bytes) {
+  int v = validate(d);
+  if (v) return v;
+  if (!bytes || n_points < 0 || flag_ns < 0) return IBDNS_EINVAL;
+  *bytes = fluid_bytes(*d) + points_bytes(n_points) + flag_bytes(flag_ns) + ALIGN;
+  return IBDNS_OK;
+}
+
+int ibdns_init_domain(const ibdns_domain* dm, const double* zu, const double* zv, const double* zw,
+                      void* dev_ws, size_t ws_bytes, void* hip_stream, ibdns_ctx** out) {
+  if (!out) return IBDNS_EINVAL;
+  *out = nullptr;
+  int v = validate(dm);
+  if (v) return v;
+  if (!dev_ws || (reinterpret_cast<uintptr_t>(dev_ws) % ALIGN) != 0) return IBDNS_EINVAL;
+  if (ws_bytes < fluid_bytes(*dm)) return IBDNS_ENOMEM;
+  ibdns_ctx* c = new ibdns_ctx();
+  c->dom = *dm;
+  c->st = reinterpret_cast<hipStream_t>(hip_stream);
+  c->ws = reinterpret_cast<char*>(dev_ws);
+  c->ws_bytes = ws_bytes;
+  Dims& d = c->d;
+  d.nx = dm->nx;
+  d.ny = dm->ny;
+  d.nz = dm->nz;
+  d.P = ((dm->nx + 1 + 15) / 16) * 16;
+  d.MY = dm->ny / 2 + 1;
+  d.PS = (long long)d.P * d.ny;
+  d.FS = d.PS * d.nz;
+  d.h = dm->lx / dm->nx;
+  d.inv_h = 1.0 / d.h;
+  d.nu = 1.0 / dm->re;
+  d.u_in = dm->u_in;
+  d.flags = dm->flags;
+  c->nparts = outlet_blocks(d);
+
+  c->s = c->carve<Scalars>(1);
+  double** fl[11] = {&c->f.u, &c->f.v, &c->f.w, &c->f.p, &c->f.hu, &c->f.hv, &c->f.hw,
+                     &c->f.ut, &c->f.vt, &c->f.wt, &c->f.phi};
+  for (auto p : fl) *p = c->carve<double>(d.FS);
+  c->f.spec = c->carve<double2>((size_t)d.nx * d.MY * d.nz);
+  c->f.partial = c->carve<double>(2 * (size_t)c->nparts);
+  c->tw_y = c->carve<double2>(d.ny);
+  c->tw_z = c->carve<double2>(d.nz);
+  c->lam_y = c->carve<double>(d.MY);
+  c->lam_z = c->carve<double>(d.nz);
+  if (!c->lam_z) {
+    delete c;
+    return IBDNS_ENOMEM;
+  }
+  // zero the fluid part (padding included)
+  if (hipMemsetAsync(c->ws, 0, c->used, c->st) != hipSuccess) {
+    delete c;
+    return IBDNS_EHIP;
+  }
+  // twiddles exp(-2 pi i m / N) and eigenvalue shifts -(4/h^2) sin^2(pi m / N)
+  auto twiddles = [](int n) {
+    std::vector<double2> t(n);
+    for (int m = 0; m < n; ++m) {
+      const double a = 2.0 * M_PI * (double)m / (double)n;
+      t[m] = make_double2(std::cos(a), -std::sin(a));
+    }
+    return t;
+  };
+  auto shifts = [&](int n, int count) {
+    std::vector<double> s(count);
+    for (int m = 0; m < count; ++m) {
+      const double sn = std::sin(M_PI * (double)m / (double)n);
+      s[m] = -(4.0 / (d.h * d.h)) * (sn * sn);
+    }
+    return s;
+  };
+  std::vector<double2> ty = twiddles(d.ny), tz = twiddles(d.nz);
+  std::vector<double> ly = shifts(d.ny, d.MY), lz = shifts(d.nz, d.nz);
+  bool ok = hipMemcpyAsync(c->tw_y, ty.data(), ty.size() * sizeof(double2), hipMemcpyHostToDevice, c->st) == hipSuccess &&
+            hipMemcpyAsync(c->tw_z, tz.data(), tz.size() * sizeof(double2), hipMemcpyHostToDevice, c->st) == hipSuccess &&
+            hipMemcpyAsync(c->lam_y, ly.data(), ly.size() * sizeof(double), hipMemcpyHostToDevice, c->st) == hipSuccess &&
+            hipMemcpyAsync(c->lam_z, lz.data(), lz.size() * sizeof(double), hipMemcpyHostToDevice, c->st) == hipSuccess;
+  // initial condition (host), uploaded plane by plane
+  Scalars hs{};
+  hs.dt = 1.0;
+  hs.dt_prev = 1.0;
+  hs.dt_fixed = dm->dt > 0 ? dm->dt : 0.0;
+  hs.cfl = dm->cfl;
+  hs.first = 1;
+  ok = ok && hipMemcpyAsync(c->s, &hs, sizeof(Scalars), hipMemcpyHostToDevice, c->st) == hipSuccess;
+  ok = ok && hipStreamSynchronize(c->st) == hipSuccess;
+  if (ok) {
+    const int nx = d.nx;
+    const double A = dm->noise_amp;
+    const bool noise = zu && zv && zw && A != 0.0;
+    const size_t plane = (size_t)d.ny;
+    std::vector<double> hu((size_t)d.P * plane), hv((size_t)d.P * plane), hw((size_t)d.P * plane);
+    for (int k = 0; k < d.nz && ok; ++k) {
+      for (int j = 0; j < d.ny; ++j) {
+        double* ur = &hu[(size_t)j * d.P];
+        double* vr = &hv[(size_t)j * d.P];
+        double* wr = &hw[(size_t)j * d.P];
+        const size_t ru = ((size_t)k * d.ny + j) * (nx + 1);
+        const size_t rc = ((size_t)k * d.ny + j) * nx;
+        ur[0] = dm->u_in;
+        for (int i = 1; i <= nx; ++i) ur[i] = noise ? dm->u_in + A * zu[ru + i] : dm->u_in;
+        for (int i = 0; i < nx; ++i) {
+          vr[i] = noise ? A * zv[rc + i] : 0.0;
+          wr[i] = noise ? A * zw[rc + i] : 0.0;
+        }
+        vr[nx] = vr[nx - 1];
+        wr[nx] = wr[nx - 1];
+      }
+      const size_t off = (size_t)k * d.PS;
+      ok = hipMemcpy(c->f.u + off, hu.data(), hu.size() * sizeof(double), hipMemcpyHostToDevice) == hipSuccess &&
+           hipMemcpy(c->f.v + off, hv.data(), hv.size() * sizeof(double), hipMemcpyHostToDevice) == hipSuccess &&
+           hipMemcpy(c->f.w + off, hw.data(), hw.size() * sizeof(double), hipMemcpyHostToDevice) == hipSuccess;
+    }
+  }
+  if (!ok) {
+    delete c;
+    return IBDNS_EHIP;
+  }
+  // initial projection with dt = 1, pressure untouched, then dt_0
+  const size_t fbytes = (size_t)d.FS * sizeof(double);
+  ok = hipMemcpyAsync(c->f.ut, c->f.u, fbytes, hipMemcpyDeviceToDevice, c->st) == hipSuccess &&
+       hipMemcpyAsync(c->f.vt, c->f.v, fbytes, hipMemcpyDeviceToDevice, c->st) == hipSuccess &&
+       hipMemcpyAsync(c->f.wt, c->f.w, fbytes, hipMemcpyDeviceToDevice, c->st) == hipSuccess;
+  if (!ok) {
+    delete c;
+    return IBDNS_EHIP;
+  }
+  launch_outlet(d, c->f, c->s, c->nparts, 0, c->st);
+  launch_flux_apply(d, c->f, c->s, c->nparts, c->st);
+  stage_project(c, 1);
+  launch_set_dt0(c->s, d.h, c->st);
+  if (check_launch() != IBDNS_OK || hipStreamSynchronize(c->st) != hipSuccess) {
+    delete c;
+    return IBDNS_EHIP;
+  }
+  *out = c;
+  return IBDNS_OK;
+}
+
+int ibdns_set_geometry(ibdns_ctx* c, int64_t n_points, const double* X, const double* dV,
+                       const ibdns_flag* flag, const double* flag_X0) {
+  if (!c) return IBDNS_EINVAL;
+  if (c->geometry_set || c->stepped) return IBDNS_ESTATE;
+  if (n_points < 0 || (n_points > 0 && (!X || !dV))) return IBDNS_EINVAL;
+  if (27 * n_points >= (1LL << 31)) return IBDNS_EINVAL;
+  const Dims& d = c->d;
+  const double h = d.h;
+  const int nx = d.nx;
+  // ---- static points: stencil centres on the host for the transposed map ----
+  if (n_points > 0) {
+    const int64_t n = n_points;
+    std::vector<std::vector<std::pair<int, int>>> pairs(3);
+    for (int comp = 0; comp < 3; ++comp) {
+      auto& pr = pairs[comp];
+      pr.reserve(27 * n);
+      for (int64_t q = 0; q < n; ++q) {
+        int cen[3];
+        for (int dir = 0; dir < 3; ++dir) {
+          const double o = comp == dir ? 0.0 : 0.5 * h;
+          const double t = (X[3 * q + dir] - o) / h;
+          cen[dir] = (int)std::floor(t + 0.5);
+        }
+        const int lo = comp == 0 ? 1 : 0;
+        if (cen[0] - 1 < lo || cen[0] + 1 > nx - 1) return IBDNS_EINVAL;
+        for (int tap = 0; tap < 27; ++tap) {
+          const int dk = tap / 9, dj = (tap / 3) % 3, di = tap % 3;
+          const int ii = cen[0] + di - 1;
+          int jj = (cen[1] + dj - 1) % d.ny;
+          if (jj < 0) jj += d.ny;
+          int kk = (cen[2] + dk - 1) % d.nz;
+          if (kk < 0) kk += d.nz;
+          pr.push_back({(int)fidx(d, ii, jj, kk), (int)(q * 27 + tap)});
+        }
+      }
+      std::stable_sort(pr.begin(), pr.end(),
+                       [](const std::pair<int, int>& a, const std::pair<int, int>& b) { return a.first < b.first; });
+    }
+    if (c->ws_bytes < c->used + points_bytes(n)) return IBDNS_ENOMEM;
+    PointSet& ps = c->bars;
+    ps.n = (int)n;
+    double* Xd = c->carve<double>(3 * n);
+    double* dVd = c->carve<double>(n);
+    ps.X = Xd;
+    ps.dV = dVd;
+    ps.Ud = nullptr;
+    ps.F = c->carve<double>(3 * n);
+    ps.amount = c->carve<double>(3 * n);
+    ps.centre = c->carve<int>(9 * n);
+    ps.wts = c->carve<double>(27 * n);
+    bool ok = hipMemcpy(Xd, X, 3 * n * sizeof(double), hipMemcpyHostToDevice) == hipSuccess &&
+              hipMemcpy(dVd, dV, n * sizeof(double), hipMemcpyHostToDevice) == hipSuccess &&
+              hipMemset(ps.F, 0, 3 * n * sizeof(double)) == hipSuccess;
+    for (int comp = 0; comp < 3 && ok; ++comp) {
+      auto& pr = pairs[comp];
+      std::vector<int> rows, ptr, ent;
+      rows.reserve(pr.size());
+      ptr.reserve(pr.size() + 1);
+      ent.reserve(pr.size());
+      for (size_t e = 0; e < pr.size(); ++e) {
+        if (e == 0 || pr[e].first != pr[e - 1].first) {
+          rows.push_back(pr[e].first);
+          ptr.push_back((int)e);
+        }
+        ent.push_back(pr[e].second);
+      }
+      ptr.push_back((int)pr.size());
+      int* rn = c->carve<int>(27 * n);
+      int* rp = c->carve<int>(27 * n + 1);
+      int* en = c->carve<int>(27 * n);
+      ok = hipMemcpy(rn, rows.data(), rows.size() * sizeof(int), hipMemcpyHostToDevice) == hipSuccess &&
+           hipMemcpy(rp, ptr.data(), ptr.size() * sizeof(int), hipMemcpyHostToDevice) == hipSuccess &&
+           hipMemcpy(en, ent.data(), ent.size() * sizeof(int), hipMemcpyHostToDevice) == hipSuccess;
+      c->csr[comp] = {(int)rows.size(), rn, rp, en};
+      std::vector<std::pair<int, int>>().swap(pr);
+    }
+    if (!ok) return IBDNS_EHIP;
+    c->nbars = n;
+    launch_point_stencil(d, ps, c->s, c->st);
+  }
+  // ---- flag ----
+  if (flag) {
+    const int ns = flag->ns;
+    if (ns < 3 || ns > 128 || !flag_X0) return IBDNS_EINVAL;
+    if (!(flag->length > 0 && flag->mass_ratio > 0 && flag->bending >= 0 && flag->stretch >= 0))
+      return IBDNS_EINVAL;
+    if (flag->bending == 0 && flag->stretch == 0) return IBDNS_EINVAL;
+    const double L = flag->length;
+    if (L > std::min(c->dom.ly, c->dom.lz) - 4 * h) return IBDNS_EINVAL;
+    const int n = ns * ns;
+    const double ds = L / (ns - 1);
+    // initial supports must stay on evolved nodes in x
+    for (int q = 0; q < n; ++q)
+      for (int comp = 0; comp < 3; ++comp) {
+        const double o = comp == 0 ? 0.0 : 0.5 * h;
+        const int cx = (int)std::floor((flag_X0[3 * q] - o) / h + 0.5);
+        const int lo = comp == 0 ? 1 : 0;
+        if (cx - 1 < lo || cx + 1 > nx - 1) return IBDNS_EINVAL;
+      }
+    if (c->ws_bytes < c->used + flag_bytes(ns)) return IBDNS_ENOMEM;
+    FlagDev& F = c->fl;
+    F.ns = ns;
+    F.ds = ds;
+    F.rho = flag->mass_ratio;
+    F.beta = flag->bending;
+    F.ks = flag->stretch;
+    F.clamped = flag->le_bc == IBDNS_LE_CLAMPED ? 1 : 0;
+    F.X = c->carve<double>(3 * n);
+    F.V = c->carve<double>(3 * n);
+    F.Fh = c->carve<double>(3 * n);
+    double* X0d = c->carve<double>(3 * n);
+    F.X0 = X0d;
+    F.f = c->carve<double>(3 * n);
+    double* massd = c->carve<double>(n);
+    double* dVd = c->carve<double>(n);
+    F.mass = massd;
+    F.dV = dVd;
+    PointSet& ps = c->flagpts;
+    ps.n = n;
+    ps.X = F.X;
+    ps.Ud = F.V;
+    ps.dV = dVd;
+    ps.F = F.Fh;
+    ps.amount = c->carve<double>(3 * n);
+    ps.centre = c->carve<int>(9 * n);
+    ps.wts = c->carve<double>(27 * n);
+    c->bbox = c->carve<int>(18);
+    F.bbox = c->bbox;
+    // masses and volumes: dA = ds^2 w_a w_b (trapezoid), m = rho dA, dV = dA h
+    std::vector<double> wgt(ns, 1.0);
+    wgt[0] = wgt[ns - 1] = 0.5;
+    std::vector<double> mass(n), vol(n);
+    for (int b = 0; b < ns; ++b)
+      for (int a = 0; a < ns; ++a) {
+        const double dA = (ds * ds) * (wgt[b] * wgt[a]);
+        mass[a + ns * b] = F.rho * dA;
+        vol[a + ns * b] = dA * h;
+      }
+    // structural sub-step bound: Gershgorin row sums of M^-1/2 (beta K + springs) M^-1/2
+    // K = sum_rows W_r D_r^T D_r over the bending rows; couplings within +-2 nodes
+    std::vector<double> Ksum((size_t)n * 25, 0.0);  // K per node and offset (da+2, db+2)
+    auto addrow = [&](const std::vector<std::pair<int, double>>& ent, double Wr) {
+      for (auto& e1 : ent)
+        for (auto& e2 : ent) {
+          const int a1 = e1.first % ns, b1 = e1.first / ns, a2 = e2.first % ns, b2 = e2.first / ns;
+          const int off = (a2 - a1 + 2) + 5 * (b2 - b1 + 2);
+          Ksum[(size_t)e1.first * 25 + off] += Wr * e1.second * e2.second;
+        }
+    };
+    const double inv2 = 1.0 / (ds * ds);
+    for (int b = 0; b < ns; ++b) {
+      for (int a = 1; a < ns - 1; ++a)
+        addrow({{a - 1 + ns * b, inv2}, {a + ns * b, -2 * inv2}, {a + 1 + ns * b, inv2}},
+               ds * ds * wgt[a] * wgt[b]);
+      if (F.clamped) addrow({{1 + ns * b, 2 * inv2}, {0 + ns * b, -2 * inv2}}, ds * ds * wgt[0] * wgt[b]);
+    }
+    for (int b = 1; b < ns - 1; ++b)
+      for (int a = 0; a < ns; ++a)
+        addrow({{a + ns * (b - 1), inv2}, {a + ns * b, -2 * inv2}, {a + ns * (b + 1), inv2}},
+               ds * ds * wgt[a] * wgt[b]);
+    for (int b = 0; b < ns - 1; ++b)
+      for (int a = 0; a < ns - 1; ++a)
+        addrow({{a + 1 + ns * (b + 1), inv2}, {a + 1 + ns * b, -inv2}, {a + ns * (b + 1), -inv2}, {a + ns * b, inv2}},
+               2.0 * ds * ds);
+    double om2 = 0.0;
+    for (int b = 0; b < ns; ++b)
+      for (int a = 1; a < ns; ++a) {
+        const int p = a + ns * b;
+        double r = 0.0;
+        for (int off = 0; off < 25; ++off) {
+          const double kv = Ksum[(size_t)p * 25 + off];
+          if (kv == 0.0) continue;
+          const int a2 = a + off % 5 - 2, b2 = b + off / 5 - 2;
+          const int q = a2 + ns * b2;
+          r += F.beta * std::fabs(kv) / std::sqrt(mass[p] * mass[q]);
+        }
+        const int nb[6][2] = {{1, 0}, {-1, 0}, {0, 1}, {0, -1}, {1, 1}, {-1, -1}};
+        for (auto& e : nb) {
+          const int a2 = a + e[0], b2 = b + e[1];
+          if (a2 < 0 || a2 >= ns || b2 < 0 || b2 >= ns) continue;
+          const int q = a2 + ns * b2;
+          r += F.ks * (1.0 / mass[p] + 1.0 / std::sqrt(mass[p] * mass[q]));
+        }
+        om2 = std::max(om2, r);
+      }
+    F.dts_max = 1.8 / std::sqrt(om2);
+    bool ok = hipMemcpy(F.X, flag_X0, 3 * n * sizeof(double), hipMemcpyHostToDevice) == hipSuccess &&
+              hipMemcpy(X0d, flag_X0, 3 * n * sizeof(double), hipMemcpyHostToDevice) == hipSuccess &&
+              hipMemset(F.V, 0, 3 * n * sizeof(double)) == hipSuccess &&
+              hipMemset(F.Fh, 0, 3 * n * sizeof(double)) == hipSuccess &&
+              hipMemcpy(massd, mass.data(), n * sizeof(double), hipMemcpyHostToDevice) == hipSuccess &&
+              hipMemcpy(dVd, vol.data(), n * sizeof(double), hipMemcpyHostToDevice) == hipSuccess;
+    if (!ok) return IBDNS_EHIP;
+    // tiles covering the flag's support: its extent never exceeds the diagonal sqrt(2) L
+    const int ext = (int)std::ceil(std::sqrt(2.0) * 1.01 * L / h) + 4;
+    c->ntx = c->nty = c->ntz = (ext + 7) / 8 + 1;
+    c->has_flag = true;
+  }
+  c->geometry_set = true;
+  if (check_launch() != IBDNS_OK || hipStreamSynchronize(c->st) != hipSuccess) return IBDNS_EHIP;
+  return IBDNS_OK;
+}
+
+int ibdns_step(ibdns_ctx* c, int32_t n_steps) {
+  if (!c || n_steps < 0) return IBDNS_EINVAL;
+  for (int n = 0; n < n_steps; ++n) {
+    stage_predict(c);
+    stage_flux(c);
+    stage_ibm(c);
+    stage_project(c, 0);
+    stage_flag(c);
+    stage_advance(c);
+  }
+  c->stepped = true;
+  return check_launch();
+}
+
+int ibdns_run_stage(ibdns_ctx* c, int32_t stage) {
+  if (!c) return IBDNS_EINVAL;
+  switch (stage) {
+    case IBDNS_STAGE_PREDICT: stage_predict(c); break;
+    case IBDNS_STAGE_FLUX: stage_flux(c); break;
+    case IBDNS_STAGE_IBM: stage_ibm(c); break;
+    case IBDNS_STAGE_PROJECT: stage_project(c, 0); break;
+    case IBDNS_STAGE_FLAG: stage_flag(c); break;
+    case IBDNS_STAGE_ADVANCE: stage_advance(c); break;
+    default: return IBDNS_EINVAL;
+  }
+  c->stepped = true;
+  return check_launch();
+}
+
+int ibdns_sync(ibdns_ctx* c) {
+  if (!c) return IBDNS_EINVAL;
+  return read_status(c);
+}
+
+int ibdns_get_fields(ibdns_ctx* c, double* u, double* v, double* w, double* p, double* t,
+                     int64_t* step) {
+  if (!c) return IBDNS_EINVAL;
+  if (hipStreamSynchronize(c->st) != hipSuccess) return IBDNS_EHIP;
+  const int nx = c->d.nx;
+  int r;
+  if (u && (r = copy_field(c, c->f.u, nx + 1, u, true))) return r;
+  if (v && (r = copy_field(c, c->f.v, nx, v, true))) return r;
+  if (w && (r = copy_field(c, c->f.w, nx, w, true))) return r;
+  if (p && (r = copy_field(c, c->f.p, nx, p, true))) return r;
+  Scalars hs;
+  if (hipMemcpy(&hs, c->s, sizeof(Scalars), hipMemcpyDeviceToHost) != hipSuccess) return IBDNS_EHIP;
+  if (t) *t = hs.t;
+  if (step) *step = hs.step;
+  return hs.status ? IBDNS_EUNSTABLE : IBDNS_OK;
+}
+
+int ibdns_get_flag(ibdns_ctx* c, double* X, double* V, double* F) {
+  if (!c) return IBDNS_EINVAL;
+  if (!c->has_flag) return IBDNS_EINVAL;
+  if (hipStreamSynchronize(c->st) != hipSuccess) return IBDNS_EHIP;
+  const size_t bytes = 3 * (size_t)c->fl.ns * c->fl.ns * sizeof(double);
+  if (X && hipMemcpy(X, c->fl.X, bytes, hipMemcpyDeviceToHost) != hipSuccess) return IBDNS_EHIP;
+  if (V && hipMemcpy(V, c->fl.V, bytes, hipMemcpyDeviceToHost) != hipSuccess) return IBDNS_EHIP;
+  if (F && hipMemcpy(F, c->fl.Fh, bytes, hipMemcpyDeviceToHost) != hipSuccess) return IBDNS_EHIP;
+  return read_status(c);
+}
+
+int ibdns_destroy(ibdns_ctx* c) {
+  if (!c) return IBDNS_EINVAL;
+  hipStreamSynchronize(c->st);
+  for (auto& r : c->recs) {
+    hipEventDestroy(r.a);
+    hipEventDestroy(r.b);
+  }
+  delete c;
+  return IBDNS_OK;
+}
+
+int ibdns_get_array(ibdns_ctx* c, int32_t which, double* host) {
+  if (!c || !host) return IBDNS_EINVAL;
+  if (hipStreamSynchronize(c->st) != hipSuccess) return IBDNS_EHIP;
+  int nxh = 0;
+  if (double* dev = field_ptr(c, which, &nxh)) return copy_field(c, dev, nxh, host, true);
+  if (which == IBDNS_ARR_POINT_F) {
+    if (!c->nbars) return IBDNS_EINVAL;
+    return hipMemcpy(host, c->bars.F, 3 * c->nbars * sizeof(double), hipMemcpyDeviceToHost) == hipSuccess
+               ? IBDNS_OK : IBDNS_EHIP;
+  }
+  if (which == IBDNS_ARR_V_GHOST || which == IBDNS_ARR_W_GHOST) {
+    double* dev = (which == IBDNS_ARR_V_GHOST ? c->f.v : c->f.w) + c->d.nx;
+    return hipMemcpy2D(host, sizeof(double), dev, (size_t)c->d.P * sizeof(double), sizeof(double),
+                       (size_t)c->d.ny * c->d.nz, hipMemcpyDeviceToHost) == hipSuccess ? IBDNS_OK : IBDNS_EHIP;
+  }
+  return IBDNS_EINVAL;
+}
+
+int ibdns_set_array(ibdns_ctx* c, int32_t which, const double* host) {
+  if (!c || !host) return IBDNS_EINVAL;
+  if (hipStreamSynchronize(c->st) != hipSuccess) return IBDNS_EHIP;
+  int nxh = 0;
+  if (double* dev = field_ptr(c, which, &nxh))
+    return copy_field(c, dev, nxh, const_cast<double*>(host), false);
+  if (which == IBDNS_ARR_V_GHOST || which == IBDNS_ARR_W_GHOST) {
+    double* dev = (which == IBDNS_ARR_V_GHOST ? c->f.v : c->f.w) + c->d.nx;
+    return hipMemcpy2D(dev, (size_t)c->d.P * sizeof(double), host, sizeof(double), sizeof(double),
+                       (size_t)c->d.ny * c->d.nz, hipMemcpyHostToDevice) == hipSuccess ? IBDNS_OK : IBDNS_EHIP;
+  }
+  return IBDNS_EINVAL;
+}
+
+int ibdns_get_scalars(ibdns_ctx* c, double* out6) {
+  if (!c || !out6) return IBDNS_EINVAL;
+  if (hipStreamSynchronize(c->st) != hipSuccess) return IBDNS_EHIP;
+  Scalars hs;
+  if (hipMemcpy(&hs, c->s, sizeof(Scalars), hipMemcpyDeviceToHost) != hipSuccess) return IBDNS_EHIP;
+  out6[0] = hs.dt;
+  out6[1] = hs.dt_prev;
+  out6[2] = hs.t;
+  out6[3] = hs.speed_last;
+  out6[4] = hs.corr;
+  out6[5] = hs.nsub;
+  return hs.status ? IBDNS_EUNSTABLE : IBDNS_OK;
+}
+
+int ibdns_set_time(ibdns_ctx* c, double dt, double dt_prev, int32_t first_step) {
+  if (!c || !(dt > 0) || !(dt_prev > 0)) return IBDNS_EINVAL;
+  if (hipStreamSynchronize(c->st) != hipSuccess) return IBDNS_EHIP;
+  Scalars hs;
+  if (hipMemcpy(&hs, c->s, sizeof(Scalars), hipMemcpyDeviceToHost) != hipSuccess) return IBDNS_EHIP;
+  hs.dt = dt;
+  hs.dt_prev = dt_prev;
+  hs.first = first_step ? 1 : 0;
+  return hipMemcpy(c->s, &hs, sizeof(Scalars), hipMemcpyHostToDevice) == hipSuccess ? IBDNS_OK : IBDNS_EHIP;
+}
+
+int ibdns_get_maps(ibdns_ctx* c, int32_t comp, int32_t* out) {
+  if (!c || !out || comp < 0 || comp > 2) return IBDNS_EINVAL;
+  if (c->has_flag) launch_point_stencil(c->d, c->flagpts, c->s, c->st);
+  if (hipStreamSynchronize(c->st) != hipSuccess) return IBDNS_EHIP;
+  size_t off = 0;
+  if (c->nbars) {
+    if (hipMemcpy(out, c->bars.centre + (size_t)comp * c->nbars * 3, 3 * c->nbars * sizeof(int),
+                  hipMemcpyDeviceToHost) != hipSuccess)
+      return IBDNS_EHIP;
+    off = 3 * c->nbars;
+  }
+  if (c->has_flag) {
+    const size_t n = (size_t)c->flagpts.n;
+    if (hipMemcpy(out + off, c->flagpts.centre + (size_t)comp * n * 3, 3 * n * sizeof(int),
+                  hipMemcpyDeviceToHost) != hipSuccess)
+      return IBDNS_EHIP;
+  }
+  return IBDNS_OK;
+}
+
+int ibdns_enable_timing(ibdns_ctx* c, int32_t enable) {
+  if (!c) return IBDNS_EINVAL;
+  c->timing = enable != 0;
+  return IBDNS_OK;
+}
+
+int ibdns_kernel_times(ibdns_ctx* c, int32_t n, const char** names, double* total_ms,
+                       int64_t* launches) {
+  if (!c) return IBDNS_EINVAL;
+  if (hipStreamSynchronize(c->st) != hipSuccess) return IBDNS_EHIP;
+  for (auto& r : c->recs) {
+    float ms = 0.0f;
+    hipEventElapsedTime(&ms, r.a, r.b);
+    hipEventDestroy(r.a);
+    hipEventDestroy(r.b);
+    bool found = false;
+    for (auto& t : c->totals)
+      if (t.first == r.name) {
+        t.second.first += ms;
+        t.second.second += 1;
+        found = true;
+      }
+    if (!found) c->totals.push_back({r.name, {(double)ms, 1}});
+  }
+  c->recs.clear();
+  const int m = (int)c->totals.size();
+  for (int q = 0; q < m && q < n; ++q) {
+    if (names) names[q] = c->totals[q].first.c_str();
+    if (total_ms) total_ms[q] = c->totals[q].second.first;
+    if (launches) launches[q] = c->totals[q].second.second;
+  }
+  return m;
+}
+
+}  // extern "C"

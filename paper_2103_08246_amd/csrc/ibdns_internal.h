@@ -1,0 +1,128 @@
+// Internal declarations shared by the HIP kernels and the host orchestration.
+//
+// Device layout (one run):
+//   field arrays u, v, w, p, H (3), provisional u~ (3), phi: doubles at
+//   a[i + P * (j + ny * k)], P = x pitch >= nx + 1 (a multiple of 16 doubles);
+//   u uses i = 0..nx (faces), v and w use i = 0..nx-1 plus the outlet ghost at
+//   i = nx, p and phi use i = 0..nx-1.
+//   spectrum: complex half spectrum of the Poisson right-hand side,
+//   s[i + nx * (m + MY * l)], MY = ny/2 + 1 (y wavenumber m, z wavenumber l or
+//   plane k between the two FFT passes), x fastest so that every x-line of a
+//   mode is contiguous.
+#pragma once
+
+#include <hip/hip_runtime.h>
+
+#include <cstdint>
+
+namespace ibdns {
+
+struct Dims {
+  int nx, ny, nz;
+  int P;             // x pitch of field arrays (doubles)
+  int MY;            // ny / 2 + 1
+  long long PS;      // plane stride P * ny
+  long long FS;      // field size P * ny * nz
+  double h, inv_h, nu, u_in;
+  uint32_t flags;    // IBDNS_TEST_* bits
+};
+
+__host__ __device__ inline long long fidx(const Dims& d, int i, int j, int k) {
+  return (long long)i + (long long)d.P * ((long long)j + (long long)d.ny * k);
+}
+
+// Device-resident scalars of the time step (one per run).
+struct Scalars {
+  double dt;          // dt_n
+  double dt_prev;     // dt_{n-1}
+  double t;           // time at the start of step n
+  double corr;        // outflow flux correction of the last step
+  double speed_last;  // max cell speed found by the last CFL pass
+  double dt_fixed;    // > 0: fixed step
+  double cfl;
+  double pad0;
+  unsigned long long speed_bits;  // running max of the cell speed (bits of a double >= 0)
+  long long step;
+  int first;          // 1: next predictor uses H^{n-1} := H^n
+  int status;         // sticky StatusBits
+  int nsub;           // flag sub-steps of the last step
+  int pad1;
+};
+
+enum StatusBits : int { ST_NONFINITE = 1, ST_CFL = 2, ST_RANGE = 4 };
+
+struct Fields {
+  double *u, *v, *w, *p;
+  double *hu, *hv, *hw;
+  double *ut, *vt, *wt;
+  double* phi;
+  double2* spec;
+  double* partial;    // per-block partial sums of the outflow pass (2 per block)
+};
+
+// Immersed points of one group (static solid points or flag nodes).
+struct PointSet {
+  int n;                   // number of points
+  const double* X;         // n*3 positions
+  const double* Ud;        // n*3 target velocities (nullptr: zero)
+  const double* dV;        // n volumes
+  double* F;               // n*3 force density (output)
+  double* amount;          // 3*n: dt F dV / h^3 per component
+  int* centre;             // 3*n*3: centre node per component
+  double* wts;             // 3*n*9: 1-D delta factors per component (x, y, z taps)
+};
+
+// Static point-to-grid transposed map for atomic-free spreading (per component).
+struct SpreadCSR {
+  int nrows;               // touched grid nodes
+  const int* row_node;     // field index of each touched node
+  const int* row_ptr;      // nrows+1
+  const int* entry;        // point * 27 + tap, increasing point within a row
+};
+
+struct FlagDev {
+  int ns;
+  double ds, rho, beta, ks, dts_max;
+  int clamped;
+  double* X;               // ns*ns*3
+  double* V;
+  double* Fh;              // ns*ns*3 hydrodynamic force density (from the IBM)
+  const double* X0;        // reference lattice (rest lengths, clamp tangent)
+  const double* mass;      // ns*ns
+  const double* dV;        // ns*ns IBM volumes
+  double* f;               // scratch force ns*ns*3
+  int* bbox;               // 6 ints: node-index box of the flag support (per component max)
+};
+
+// ---- launchers (one per kernel family) ----
+void launch_predict(const Dims& d, const Fields& f, const Scalars* s, hipStream_t st);
+void launch_outlet(const Dims& d, const Fields& f, const Scalars* s, int nblocks, int update,
+                   hipStream_t st);
+void launch_flux_apply(const Dims& d, const Fields& f, Scalars* s, int nblocks, hipStream_t st);
+int outlet_blocks(const Dims& d);
+
+void launch_point_stencil(const Dims& d, const PointSet& ps, Scalars* s, hipStream_t st);
+void launch_point_interp(const Dims& d, const Fields& f, const PointSet& ps, Scalars* s,
+                         hipStream_t st);
+void launch_spread_csr(const Dims& d, const Fields& f, const PointSet& ps,
+                       const SpreadCSR* csr3, hipStream_t st);
+void launch_point_bbox(const PointSet& ps, int* bbox, hipStream_t st);
+void launch_spread_tiles(const Dims& d, const Fields& f, const PointSet& ps, const int* bbox,
+                         int ntx, int nty, int ntz, Scalars* s, hipStream_t st);
+
+void launch_div_ffty(const Dims& d, const Fields& f, const Scalars* s, const double2* tw_y,
+                     hipStream_t st);
+void launch_fftz(const Dims& d, const Fields& f, const double2* tw_z, int sign, hipStream_t st);
+void launch_tri(const Dims& d, const Fields& f, const double* shift_y, const double* shift_z,
+                hipStream_t st);
+void launch_iffty(const Dims& d, const Fields& f, const double2* tw_y, hipStream_t st);
+void launch_project(const Dims& d, const Fields& f, Scalars* s, int mode, hipStream_t st);
+
+void launch_flag_step(const FlagDev& fl, Scalars* s, hipStream_t st);
+void launch_advance(Scalars* s, double h, hipStream_t st);
+void launch_set_dt0(Scalars* s, double h, hipStream_t st);
+
+bool fft_size_supported(int n);
+bool tri_size_supported(int nx);
+
+}  // namespace ibdns

@@ -1,0 +1,252 @@
+// Direct-forcing immersed boundary (paper Sec. II.B) with the 3-point
+// regularised delta of Roma, Peskin & Berger (1999):
+//   phi(r) = (1 + sqrt(1 - 3 r^2)) / 3                  |r| <= 1/2
+//   phi(r) = (5 - 3|r| - sqrt(1 - 3 (1 - |r|)^2)) / 6   1/2 <= |r| <= 3/2
+// Single pass on the provisional velocity: every point interpolates
+// U~ = sum u~ phi phi phi over its 3x3x3 support, the force density is
+// F = (U^d - U~) / dt, and every grid node gathers dt F dV / h^3 phi phi phi
+// from the points that cover it, in increasing point order (no atomics).
+#include "ibdns_internal.h"
+
+namespace ibdns {
+
+namespace {
+
+__device__ __forceinline__ double roma(double r) {
+  const double a = fabs(r);
+  if (a <= 0.5) return (1.0 + sqrt(1.0 - 3.0 * a * a)) / 3.0;
+  if (a <= 1.5) {
+    const double b = 1.0 - a;
+    return (5.0 - 3.0 * a - sqrt(fmax(1.0 - 3.0 * b * b, 0.0))) / 6.0;
+  }
+  return 0.0;
+}
+
+__device__ __forceinline__ int wrap(int a, int n) {
+  int r = a % n;
+  return r < 0 ? r + n : r;
+}
+
+// Staggered origin of component comp in direction dir, in units of h: the
+// component's own direction has offset 0, the two others 1/2.
+__device__ __forceinline__ double origin(int comp, int dir, double h) {
+  return comp == dir ? 0.0 : 0.5 * h;
+}
+
+// Centre node and 1-D delta factors of every point for every component.
+__global__ void k_point_stencil(Dims d, PointSet ps, Scalars* s) {
+  const int q = blockIdx.x * blockDim.x + threadIdx.x;
+  const int comp = blockIdx.y;
+  if (q >= ps.n) return;
+  int* cen = ps.centre + ((size_t)comp * ps.n + q) * 3;
+  double* wt = ps.wts + ((size_t)comp * ps.n + q) * 9;
+  for (int dir = 0; dir < 3; ++dir) {
+    const double t = (ps.X[3 * q + dir] - origin(comp, dir, d.h)) / d.h;
+    if (!(fabs(t) < 1.0e8)) {  // non-finite or absurd position: park the support off-grid
+      if (s) atomicOr(&s->status, (int)ST_NONFINITE);
+      for (int a = 0; a < 3; ++a) cen[a] = -(1 << 28);
+      for (int a = 0; a < 9; ++a) wt[a] = 0.0;
+      return;
+    }
+    const int n = (int)floor(t + 0.5);
+    cen[dir] = n;
+    for (int tap = 0; tap < 3; ++tap) wt[3 * dir + tap] = roma(t - (double)(n + tap - 1));
+  }
+}
+
+__device__ __forceinline__ double* comp_field(const Fields& f, int comp) {
+  return comp == 0 ? f.ut : (comp == 1 ? f.vt : f.wt);
+}
+
+// Interpolation and force density; also flags a support that leaves the
+// evolved x range (u faces 1..nx-1, v and w cells 0..nx-1).
+__global__ void k_point_interp(Dims d, Fields f, PointSet ps, Scalars* s) {
+  const int q = blockIdx.x * blockDim.x + threadIdx.x;
+  const int comp = blockIdx.y;
+  if (q >= ps.n) return;
+  const int* cen = ps.centre + ((size_t)comp * ps.n + q) * 3;
+  const double* wt = ps.wts + ((size_t)comp * ps.n + q) * 9;
+  const double* fld = comp_field(f, comp);
+  const int lo = comp == 0 ? 1 : 0;
+  if (cen[0] - 1 < lo || cen[0] + 1 > d.nx - 1) {
+    atomicOr(&s->status, (int)ST_RANGE);
+    ps.F[3 * q + comp] = 0.0;
+    ps.amount[(size_t)comp * ps.n + q] = 0.0;
+    return;
+  }
+  double U = 0.0;
+  for (int dk = 0; dk < 3; ++dk) {
+    const int kk = wrap(cen[2] + dk - 1, d.nz);
+    for (int dj = 0; dj < 3; ++dj) {
+      const int jj = wrap(cen[1] + dj - 1, d.ny);
+      for (int di = 0; di < 3; ++di) {
+        const int ii = cen[0] + di - 1;
+        U += fld[fidx(d, ii, jj, kk)] * (wt[di] * wt[3 + dj] * wt[6 + dk]);
+      }
+    }
+  }
+  const double dt = s->dt;
+  const double ud = ps.Ud ? ps.Ud[3 * q + comp] : 0.0;
+  const double F = (ud - U) / dt;
+  ps.F[3 * q + comp] = F;
+  const double h3 = d.h * d.h * d.h;
+  ps.amount[(size_t)comp * ps.n + q] = dt * F * ps.dV[q] / h3;
+}
+
+// Static points: one thread per touched grid node, gathering its CSR row.
+__global__ void k_spread_csr(Dims d, Fields f, PointSet ps, SpreadCSR csr, int comp) {
+  const int r = blockIdx.x * blockDim.x + threadIdx.x;
+  if (r >= csr.nrows) return;
+  const double* amt = ps.amount + (size_t)comp * ps.n;
+  const double* wts = ps.wts + (size_t)comp * ps.n * 9;
+  double acc = 0.0;
+  const int e0 = csr.row_ptr[r], e1 = csr.row_ptr[r + 1];
+  for (int e = e0; e < e1; ++e) {
+    const int code = csr.entry[e];
+    const int q = code / 27, tap = code % 27;
+    const int dk = tap / 9, dj = (tap / 3) % 3, di = tap % 3;
+    const double* wt = wts + (size_t)q * 9;
+    acc += amt[q] * (wt[di] * wt[3 + dj] * wt[6 + dk]);
+  }
+  double* fld = comp_field(f, comp);
+  fld[csr.row_node[r]] += acc;
+}
+
+// Bounding box (in unwrapped node indices) of the 3x3x3 supports of a point
+// set, per component: bbox[6*comp + 0..2] = min, [3..5] = max.
+__global__ void __launch_bounds__(256) k_point_bbox(PointSet ps, int* bbox) {
+  const int comp = blockIdx.x;
+  __shared__ int mn[3][256], mx[3][256];
+  int lo[3] = {1 << 30, 1 << 30, 1 << 30}, hi[3] = {-(1 << 30), -(1 << 30), -(1 << 30)};
+  for (int q = threadIdx.x; q < ps.n; q += 256) {
+    const int* cen = ps.centre + ((size_t)comp * ps.n + q) * 3;
+    for (int a = 0; a < 3; ++a) {
+      lo[a] = min(lo[a], cen[a] - 1);
+      hi[a] = max(hi[a], cen[a] + 1);
+    }
+  }
+  for (int a = 0; a < 3; ++a) {
+    mn[a][threadIdx.x] = lo[a];
+    mx[a][threadIdx.x] = hi[a];
+  }
+  __syncthreads();
+  for (int w = 128; w > 0; w >>= 1) {
+    if ((int)threadIdx.x < w)
+      for (int a = 0; a < 3; ++a) {
+        mn[a][threadIdx.x] = min(mn[a][threadIdx.x], mn[a][threadIdx.x + w]);
+        mx[a][threadIdx.x] = max(mx[a][threadIdx.x], mx[a][threadIdx.x + w]);
+      }
+    __syncthreads();
+  }
+  if (threadIdx.x == 0)
+    for (int a = 0; a < 3; ++a) {
+      bbox[6 * comp + a] = mn[a][0];
+      bbox[6 * comp + 3 + a] = mx[a][0];
+    }
+}
+
+constexpr int TS = 8;               // tile edge (nodes)
+constexpr int TN = TS * TS * TS;    // threads per tile
+
+// Moving points: one workgroup per 8x8x8 tile of nodes inside the bounding
+// box.  The points are scanned in chunks, those whose support meets the tile
+// are compacted (in increasing order) into LDS, and every thread gathers the
+// contributions to its node.
+__global__ void __launch_bounds__(TN) k_spread_tiles(Dims d, Fields f, PointSet ps, const int* bbox,
+                                                     int ntx, int nty, int ntz, int comp,
+                                                     Scalars* s) {
+  const int* bb = bbox + 6 * comp;
+  const int tx = blockIdx.x % ntx, ty = (blockIdx.x / ntx) % nty, tz = blockIdx.x / (ntx * nty);
+  const int x0 = bb[0] + tx * TS, y0 = bb[1] + ty * TS, z0 = bb[2] + tz * TS;
+  if (blockIdx.x == 0 && threadIdx.x == 0) {
+    // the launch must cover the whole box
+    if ((bb[3] - bb[0]) >= ntx * TS || (bb[4] - bb[1]) >= nty * TS || (bb[5] - bb[2]) >= ntz * TS)
+      atomicOr(&s->status, (int)ST_RANGE);
+  }
+  if (x0 > bb[3] || y0 > bb[4] || z0 > bb[5]) return;
+  const int lx = threadIdx.x % TS, ly = (threadIdx.x / TS) % TS, lz = threadIdx.x / (TS * TS);
+  const int ni = x0 + lx, nj = y0 + ly, nk = z0 + lz;  // unwrapped node of this thread
+
+  __shared__ int list[TN];
+  __shared__ int scan[TN];
+  const int* cenb = ps.centre + (size_t)comp * ps.n * 3;
+  const double* wts = ps.wts + (size_t)comp * ps.n * 9;
+  const double* amt = ps.amount + (size_t)comp * ps.n;
+  double acc = 0.0;
+  for (int base = 0; base < ps.n; base += TN) {
+    const int q = base + threadIdx.x;
+    int hit = 0;
+    if (q < ps.n) {
+      const int* c = cenb + (size_t)q * 3;
+      hit = (c[0] + 1 >= x0 && c[0] - 1 < x0 + TS && c[1] + 1 >= y0 && c[1] - 1 < y0 + TS &&
+             c[2] + 1 >= z0 && c[2] - 1 < z0 + TS) ? 1 : 0;
+    }
+    scan[threadIdx.x] = hit;
+    __syncthreads();
+    // inclusive scan (Hillis-Steele)
+    for (int off = 1; off < TN; off <<= 1) {
+      const int v = (int)threadIdx.x >= off ? scan[threadIdx.x - off] : 0;
+      __syncthreads();
+      scan[threadIdx.x] += v;
+      __syncthreads();
+    }
+    const int nhit = scan[TN - 1];
+    if (hit) list[scan[threadIdx.x] - 1] = q;
+    __syncthreads();
+    for (int e = 0; e < nhit; ++e) {
+      const int p = list[e];
+      const int* c = cenb + (size_t)p * 3;
+      const int di = ni - c[0] + 1, dj = nj - c[1] + 1, dk = nk - c[2] + 1;
+      if (di >= 0 && di < 3 && dj >= 0 && dj < 3 && dk >= 0 && dk < 3) {
+        const double* wt = wts + (size_t)p * 9;
+        acc += amt[p] * (wt[di] * wt[3 + dj] * wt[6 + dk]);
+      }
+    }
+    __syncthreads();
+  }
+  if (ni <= bb[3] && nj <= bb[4] && nk <= bb[5]) {
+    const int lo = comp == 0 ? 1 : 0;
+    if (ni >= lo && ni <= d.nx - 1) {
+      double* fld = comp_field(f, comp);
+      fld[fidx(d, ni, wrap(nj, d.ny), wrap(nk, d.nz))] += acc;
+    }
+  }
+}
+
+}  // namespace
+
+void launch_point_stencil(const Dims& d, const PointSet& ps, Scalars* s, hipStream_t st) {
+  if (ps.n == 0) return;
+  hipLaunchKernelGGL(k_point_stencil, dim3((ps.n + 255) / 256, 3), dim3(256), 0, st, d, ps, s);
+}
+
+void launch_point_interp(const Dims& d, const Fields& f, const PointSet& ps, Scalars* s,
+                         hipStream_t st) {
+  if (ps.n == 0) return;
+  hipLaunchKernelGGL(k_point_interp, dim3((ps.n + 255) / 256, 3), dim3(256), 0, st, d, f, ps, s);
+}
+
+void launch_spread_csr(const Dims& d, const Fields& f, const PointSet& ps, const SpreadCSR* csr3,
+                       hipStream_t st) {
+  if (ps.n == 0) return;
+  for (int c = 0; c < 3; ++c) {
+    if (csr3[c].nrows == 0) continue;
+    hipLaunchKernelGGL(k_spread_csr, dim3((csr3[c].nrows + 255) / 256), dim3(256), 0, st, d, f, ps,
+                       csr3[c], c);
+  }
+}
+
+void launch_point_bbox(const PointSet& ps, int* bbox, hipStream_t st) {
+  if (ps.n == 0) return;
+  hipLaunchKernelGGL(k_point_bbox, dim3(3), dim3(256), 0, st, ps, bbox);
+}
+
+void launch_spread_tiles(const Dims& d, const Fields& f, const PointSet& ps, const int* bbox,
+                         int ntx, int nty, int ntz, Scalars* s, hipStream_t st) {
+  if (ps.n == 0) return;
+  for (int c = 0; c < 3; ++c)
+    hipLaunchKernelGGL(k_spread_tiles, dim3(ntx * nty * ntz), dim3(TN), 0, st, d, f, ps, bbox, ntx,
+                       nty, ntz, c, s);
+}
+
+}  // namespace ibdns

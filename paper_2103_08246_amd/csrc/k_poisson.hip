@@ -1,0 +1,599 @@
+// Pressure-Poisson projection of the fractional step (paper Sec. II.B):
+//   r = D u~ / dt,  L phi = r,  u^{n+1} = u~ - dt G phi,  p^{n+1} = p^n + phi,
+// with L the 7-point Laplacian, periodic in y and z and Neumann in x.  The
+// solve diagonalises y and z with FFTs (AFiD's approach, cited in Sec. II.B)
+// and solves, for every transverse mode (m, l), the x-tridiagonal system
+//   phi_{i-1} + (-2 + h^2 (lam_y(m) + lam_z(l))) phi_i + phi_{i+1} = h^2 r_i
+// (Neumann rows with -1).  The (0,0) mode is singular: its first row becomes
+// phi_0 = 0 and its x-mean is removed afterwards.
+//
+// Kernels:
+//   k_div_ffty  divergence of u~ fused with the real-to-complex y FFT of r
+//               (two real x-columns packed into one complex line);
+//   k_fftz      complex z FFT in place on the half spectrum (both signs);
+//   k_tri       one wavefront per x-line: each lane eliminates a contiguous
+//               chunk down to its two end unknowns, the 128-row reduced system
+//               is solved by cyclic reduction in LDS, then back-substitution;
+//               the singular line is solved by a serial Thomas sweep;
+//   k_iffty     complex-to-real inverse y FFT to phi;
+//   k_project   projection, pressure update and the CFL maximum (max of the
+//               cell speed per block, one atomicMax per block).
+// FFTs: mixed-radix (8, 4, 2, 3) Stockham passes over lines held in LDS, one
+// register-staged butterfly set per thread and pass, twiddles from a table
+// exp(-2 pi i m / N) built on the host.
+#include "ibdns_internal.h"
+
+namespace ibdns {
+
+namespace {
+
+__device__ __forceinline__ double2 cmul(double2 a, double2 b) {
+  return make_double2(a.x * b.x - a.y * b.y, a.x * b.y + a.y * b.x);
+}
+__device__ __forceinline__ double2 cadd(double2 a, double2 b) { return make_double2(a.x + b.x, a.y + b.y); }
+__device__ __forceinline__ double2 csub(double2 a, double2 b) { return make_double2(a.x - b.x, a.y - b.y); }
+__device__ __forceinline__ double2 cscale(double2 a, double s) { return make_double2(a.x * s, a.y * s); }
+// (SIGN i) * a
+template <int SIGN>
+__device__ __forceinline__ double2 mul_si(double2 a) {
+  return SIGN > 0 ? make_double2(-a.y, a.x) : make_double2(a.y, -a.x);
+}
+
+// In-register DFT of size R with kernel exp(SIGN 2 pi i q t / R).
+template <int R, int SIGN>
+struct DFT;
+
+template <int SIGN>
+struct DFT<2, SIGN> {
+  static __device__ __forceinline__ void run(double2* v) {
+    const double2 a = v[0], b = v[1];
+    v[0] = cadd(a, b);
+    v[1] = csub(a, b);
+  }
+};
+
+template <int SIGN>
+struct DFT<3, SIGN> {
+  static __device__ __forceinline__ void run(double2* v) {
+    const double s = SIGN * 0.86602540378443864676;  // sin(2 pi / 3)
+    const double2 t = cadd(v[1], v[2]);
+    const double2 m = csub(v[0], cscale(t, 0.5));
+    const double2 dd = cscale(csub(v[1], v[2]), s);
+    const double2 id = mul_si<1>(dd);
+    v[0] = cadd(v[0], t);
+    v[1] = cadd(m, id);
+    v[2] = csub(m, id);
+  }
+};
+
+template <int SIGN>
+struct DFT<4, SIGN> {
+  static __device__ __forceinline__ void run(double2* v) {
+    const double2 t0 = cadd(v[0], v[2]), t1 = csub(v[0], v[2]);
+    const double2 t2 = cadd(v[1], v[3]), t3 = mul_si<SIGN>(csub(v[1], v[3]));
+    v[0] = cadd(t0, t2);
+    v[1] = cadd(t1, t3);
+    v[2] = csub(t0, t2);
+    v[3] = csub(t1, t3);
+  }
+};
+
+template <int SIGN>
+struct DFT<8, SIGN> {
+  static __device__ __forceinline__ void run(double2* v) {
+    double2 e[4] = {v[0], v[2], v[4], v[6]};
+    double2 o[4] = {v[1], v[3], v[5], v[7]};
+    DFT<4, SIGN>::run(e);
+    DFT<4, SIGN>::run(o);
+    const double r = 0.70710678118654752440;
+    const double2 o1 = cscale(cadd(o[1], mul_si<SIGN>(o[1])), r);
+    const double2 o2 = mul_si<SIGN>(o[2]);
+    const double2 o3 = cscale(csub(mul_si<SIGN>(o[3]), o[3]), r);
+    v[0] = cadd(e[0], o[0]);
+    v[4] = csub(e[0], o[0]);
+    v[1] = cadd(e[1], o1);
+    v[5] = csub(e[1], o1);
+    v[2] = cadd(e[2], o2);
+    v[6] = csub(e[2], o2);
+    v[3] = cadd(e[3], o3);
+    v[7] = csub(e[3], o3);
+  }
+};
+
+// One Stockham pass of radix R over NL lines of length N (line stride LS) in
+// LDS: butterfly i of a line reads x[i + q N/R], applies the twiddles
+// w^(q k), k = i mod P, and writes y[(i/P) P R + k + q P].  All inputs are
+// loaded before the barrier, so the pass runs in place.
+template <int N, int R, int P, int SIGN, int NL, int NT, int LS>
+__device__ __forceinline__ void stockham_pass(double2* buf, const double2* __restrict__ tw) {
+  constexpr int T = N / R;
+  constexpr int TOT = T * NL;
+  constexpr int NB = (TOT + NT - 1) / NT;
+  double2 v[NB][R];
+#pragma unroll
+  for (int b = 0; b < NB; ++b) {
+    const int g = threadIdx.x + b * NT;
+    if (g < TOT) {
+      const int line = g / T, i = g % T;
+      const double2* x = buf + line * LS;
+#pragma unroll
+      for (int q = 0; q < R; ++q) v[b][q] = x[i + q * T];
+    }
+  }
+  __syncthreads();
+#pragma unroll
+  for (int b = 0; b < NB; ++b) {
+    const int g = threadIdx.x + b * NT;
+    if (g < TOT) {
+      const int line = g / T, i = g % T;
+      const int k = i % P;
+      if constexpr (P > 1) {
+#pragma unroll
+        for (int q = 1; q < R; ++q) {
+          double2 w = tw[(q * k) * (N / (P * R))];
+          if (SIGN > 0) w.y = -w.y;
+          v[b][q] = cmul(v[b][q], w);
+        }
+      }
+      DFT<R, SIGN>::run(v[b]);
+      const int j = (i / P) * P * R + k;
+      double2* y = buf + line * LS;
+#pragma unroll
+      for (int q = 0; q < R; ++q) y[j + q * P] = v[b][q];
+    }
+  }
+  __syncthreads();
+}
+
+template <int N, int P, int SIGN, int NL, int NT, int LS>
+struct FFTPasses {
+  static __device__ __forceinline__ void run(double2* buf, const double2* __restrict__ tw) {
+    constexpr int REM = N / P;
+    if constexpr (REM > 1) {
+      constexpr int R = (REM % 8 == 0) ? 8 : (REM % 4 == 0) ? 4 : (REM % 2 == 0) ? 2 : 3;
+      static_assert(REM % R == 0, "FFT length must be 2^a 3^b");
+      stockham_pass<N, R, P, SIGN, NL, NT, LS>(buf, tw);
+      FFTPasses<N, P * R, SIGN, NL, NT, LS>::run(buf, tw);
+    }
+  }
+};
+
+constexpr int FT = 256;  // threads per FFT workgroup
+
+// r = D u~ / dt for a 16-column x tile of one z plane, then the y FFT of the
+// 16 real columns as 8 complex lines, unpacked into the half spectrum.
+template <int NY>
+__global__ void __launch_bounds__(FT) k_div_ffty(Dims d, Fields f, const Scalars* __restrict__ s,
+                                                 const double2* __restrict__ tw) {
+  constexpr int TXC = 16, NL = 8, LS = NY + 1, MY = NY / 2 + 1;
+  __shared__ double2 buf[NL * LS];
+  const int i0 = blockIdx.x * TXC;
+  const int k = blockIdx.y;
+  const int kp = (k + 1 == d.nz) ? 0 : k + 1;
+  const double dt = s->dt;
+  for (int e = threadIdx.x; e < TXC * NY; e += FT) {
+    const int ix = e % TXC, j = e / TXC;
+    const int i = i0 + ix;
+    double r = 0.0;
+    if (i < d.nx) {
+      const int jp = (j + 1 == NY) ? 0 : j + 1;
+      const long long c = fidx(d, i, j, k);
+      r = (((f.ut[c + 1] - f.ut[c]) + (f.vt[fidx(d, i, jp, k)] - f.vt[c])) +
+           (f.wt[fidx(d, i, j, kp)] - f.wt[c])) / d.h / dt;
+    }
+    double2* slot = &buf[(ix >> 1) * LS + j];
+    if (ix & 1)
+      slot->y = r;
+    else
+      slot->x = r;
+  }
+  __syncthreads();
+  FFTPasses<NY, 1, -1, NL, FT, LS>::run(buf, tw);
+  for (int e = threadIdx.x; e < TXC * MY; e += FT) {
+    const int ix = e % TXC, m = e / TXC;
+    const int i = i0 + ix;
+    const int L = ix >> 1;
+    const double2 A = buf[L * LS + m];
+    const double2 B = buf[L * LS + (m == 0 ? 0 : NY - m)];
+    double2 out;
+    if ((ix & 1) == 0)
+      out = make_double2(0.5 * (A.x + B.x), 0.5 * (A.y - B.y));   // (Z_m + conj Z_{N-m}) / 2
+    else
+      out = make_double2(0.5 * (A.y + B.y), -0.5 * (A.x - B.x));  // (Z_m - conj Z_{N-m}) / 2i
+    if (i < d.nx) f.spec[i + (long long)d.nx * (m + (long long)MY * k)] = out;
+  }
+}
+
+// Complex z FFT (sign SIGN) of an 8-column x tile of one y wavenumber m, in place.
+template <int NZ, int SIGN>
+__global__ void __launch_bounds__(FT) k_fftz(Dims d, Fields f, const double2* __restrict__ tw) {
+  constexpr int TXC = 8, NL = 8, LS = NZ + 1;
+  __shared__ double2 buf[NL * LS];
+  const int i0 = blockIdx.x * TXC;
+  const int m = blockIdx.y;
+  const long long lstride = (long long)d.nx * d.MY;
+  double2* base = f.spec + (long long)d.nx * m;
+  for (int e = threadIdx.x; e < TXC * NZ; e += FT) {
+    const int ix = e % TXC, k = e / TXC;
+    const int i = i0 + ix;
+    buf[ix * LS + k] = (i < d.nx) ? base[i + lstride * k] : make_double2(0.0, 0.0);
+  }
+  __syncthreads();
+  FFTPasses<NZ, 1, SIGN, NL, FT, LS>::run(buf, tw);
+  for (int e = threadIdx.x; e < TXC * NZ; e += FT) {
+    const int ix = e % TXC, k = e / TXC;
+    const int i = i0 + ix;
+    if (i < d.nx) base[i + lstride * k] = buf[ix * LS + k];
+  }
+}
+
+// Inverse y FFT of a 16-column tile of one z plane to phi (unnormalised; the
+// 1/(ny nz) factor is applied in k_tri).
+template <int NY>
+__global__ void __launch_bounds__(FT) k_iffty(Dims d, Fields f, const double2* __restrict__ tw) {
+  constexpr int TXC = 16, NL = 8, LS = NY + 1, MY = NY / 2 + 1;
+  __shared__ double2 buf[NL * LS];
+  const int i0 = blockIdx.x * TXC;
+  const int k = blockIdx.y;
+  for (int e = threadIdx.x; e < NL * MY; e += FT) {
+    const int L = e % NL, m = e / NL;
+    const int ie = i0 + 2 * L, io = ie + 1;
+    const long long off = (long long)d.nx * (m + (long long)MY * k);
+    double2 xe = ie < d.nx ? f.spec[ie + off] : make_double2(0.0, 0.0);
+    double2 xo = io < d.nx ? f.spec[io + off] : make_double2(0.0, 0.0);
+    if (m == 0 || 2 * m == NY) {  // real-signal spectrum: these bins are real
+      xe.y = 0.0;
+      xo.y = 0.0;
+    }
+    buf[L * LS + m] = make_double2(xe.x - xo.y, xe.y + xo.x);          // Xe + i Xo
+    if (m > 0 && 2 * m < NY)
+      buf[L * LS + NY - m] = make_double2(xe.x + xo.y, xo.x - xe.y);   // conj(Xe) + i conj(Xo)
+  }
+  __syncthreads();
+  FFTPasses<NY, 1, 1, NL, FT, LS>::run(buf, tw);
+  for (int e = threadIdx.x; e < TXC * NY; e += FT) {
+    const int ix = e % TXC, j = e / TXC;
+    const int i = i0 + ix;
+    if (i < d.nx) {
+      const double2 z = buf[(ix >> 1) * LS + j];
+      f.phi[fidx(d, i, j, k)] = (ix & 1) ? z.y : z.x;
+    }
+  }
+}
+
+// ---------------------------------------------------------------------------
+// x-tridiagonal solves, one wavefront per mode line.
+constexpr int TRI_WAVES = 4;
+
+__device__ __forceinline__ void tri_coef(int g, int nx, double shift, bool singular, double& a,
+                                         double& b, double& c) {
+  if (g >= nx) {  // padding rows: identity, decoupled
+    a = 0.0;
+    b = 1.0;
+    c = 0.0;
+    return;
+  }
+  a = (g == 0) ? 0.0 : 1.0;
+  c = (g >= nx - 1) ? 0.0 : 1.0;
+  b = (g == 0 || g == nx - 1) ? -1.0 + shift : -2.0 + shift;
+  if (singular && g == 0) {
+    b = 1.0;
+    c = 0.0;
+  }
+}
+
+template <int C>
+__global__ void __launch_bounds__(64 * TRI_WAVES) k_tri(Dims d, Fields f,
+                                                       const double* __restrict__ lam_y,
+                                                       const double* __restrict__ lam_z,
+                                                       double scale) {
+  constexpr int LSP = C + 1;     // LDS chunk stride (padding against bank conflicts)
+  constexpr int R = 128;         // reduced rows (2 per lane)
+  __shared__ double2 lb[TRI_WAVES][64 * LSP];
+  __shared__ double rA[TRI_WAVES][R], rB[TRI_WAVES][R], rC[TRI_WAVES][R];
+  __shared__ double2 rD[TRI_WAVES][R];
+  __shared__ double cps[64 * C];   // c' of the singular line (one per grid)
+  const int wv = threadIdx.x / 64, lane = threadIdx.x % 64;
+  const long long nlines = (long long)d.MY * d.nz;
+  const long long line = (long long)blockIdx.x * TRI_WAVES + wv;
+  const bool active = line < nlines;
+  const int m = active ? (int)(line % d.MY) : 0;
+  const int l = active ? (int)(line / d.MY) : 0;
+  const int nx = d.nx;
+  double2* g = f.spec + (active ? line : 0) * (long long)nx;
+  double2* L = lb[wv];
+
+  for (int t = 0; t < C; ++t) {
+    const int e = lane + 64 * t;
+    L[(e / C) * LSP + e % C] = (active && e < nx) ? cscale(g[e], scale) : make_double2(0.0, 0.0);
+  }
+  __syncthreads();
+  const double shift = active ? (d.h * d.h) * (lam_z[l] + lam_y[m]) : -1.0;
+  const bool singular = active && m == 0 && l == 0;
+  double2 x[C];
+
+  if (singular) {
+    // serial Thomas sweep of the singular line (row 0 replaced by phi_0 = 0),
+    // then removal of the x-mean; c' kept in LDS
+    if (lane == 0) {
+      double cp = 0.0;
+      double2 dp = make_double2(0.0, 0.0);
+      for (int e = 0; e < nx; ++e) {
+        double a, b, c;
+        tri_coef(e, nx, shift, true, a, b, c);
+        const double2 dd = (e == 0) ? make_double2(0.0, 0.0) : L[(e / C) * LSP + e % C];
+        const double den = b - a * cp;
+        cp = c / den;
+        dp = make_double2((dd.x - a * dp.x) / den, (dd.y - a * dp.y) / den);
+        cps[e] = cp;
+        L[(e / C) * LSP + e % C] = dp;
+      }
+      double2 xn = make_double2(0.0, 0.0);
+      for (int e = nx - 1; e >= 0; --e) {
+        const double2 dpe = L[(e / C) * LSP + e % C];
+        const double2 xe = (e == nx - 1) ? dpe : make_double2(dpe.x - cps[e] * xn.x, dpe.y - cps[e] * xn.y);
+        L[(e / C) * LSP + e % C] = xe;
+        xn = xe;
+      }
+      double2 sum = make_double2(0.0, 0.0);
+      for (int e = 0; e < nx; ++e) sum = cadd(sum, L[(e / C) * LSP + e % C]);
+      const double2 mean = make_double2(sum.x / nx, sum.y / nx);
+      for (int e = 0; e < nx; ++e) L[(e / C) * LSP + e % C] = csub(L[(e / C) * LSP + e % C], mean);
+    }
+    // same number of barriers as the cyclic reduction of the other waves
+    for (int st = 1; st < R; st <<= 1) {
+      __syncthreads();
+      __syncthreads();
+    }
+#pragma unroll
+    for (int t = 0; t < C; ++t) x[t] = L[lane * LSP + t];
+  } else {
+    const int s0 = lane * C;
+    double a[C], b[C], c[C];
+    double2 dd[C];
+#pragma unroll
+    for (int t = 0; t < C; ++t) {
+      tri_coef(s0 + t, nx, shift, false, a[t], b[t], c[t]);
+      dd[t] = L[lane * LSP + t];
+    }
+    double cp[C], be[C], ga[C];
+    double2 al[C];
+#pragma unroll
+    for (int t = 0; t < C; ++t) {
+      cp[t] = 0.0;
+      be[t] = 0.0;
+      ga[t] = 0.0;
+      al[t] = make_double2(0.0, 0.0);
+    }
+    // interior rows t = 1..C-2: x_t = al_t + be_t x_s + ga_t x_e
+#pragma unroll
+    for (int t = 1; t <= C - 2; ++t) {
+      const double den = (t == 1) ? b[1] : b[t] - a[t] * cp[t - 1];
+      const double inv = 1.0 / den;
+      cp[t] = c[t] * inv;
+      if (t == 1) {
+        al[t] = cscale(dd[1], inv);
+        be[t] = -a[1] * inv;
+        ga[t] = (t == C - 2 ? -c[t] : 0.0) * inv;
+      } else {
+        al[t] = cscale(csub(dd[t], cscale(al[t - 1], a[t])), inv);
+        be[t] = (-a[t] * be[t - 1]) * inv;
+        ga[t] = ((t == C - 2 ? -c[t] : 0.0) - a[t] * ga[t - 1]) * inv;
+      }
+    }
+#pragma unroll
+    for (int t = C - 3; t >= 1; --t) {
+      al[t] = csub(al[t], cscale(al[t + 1], cp[t]));
+      be[t] = be[t] - cp[t] * be[t + 1];
+      ga[t] = ga[t] - cp[t] * ga[t + 1];
+    }
+    double A0, B0, C0, A1, B1, C1;
+    double2 D0, D1;
+    if constexpr (C >= 3) {
+      A0 = a[0];
+      B0 = b[0] + c[0] * be[1];
+      C0 = c[0] * ga[1];
+      D0 = csub(dd[0], cscale(al[1], c[0]));
+      A1 = a[C - 1] * be[C - 2];
+      B1 = b[C - 1] + a[C - 1] * ga[C - 2];
+      C1 = c[C - 1];
+      D1 = csub(dd[C - 1], cscale(al[C - 2], a[C - 1]));
+    } else {
+      A0 = a[0]; B0 = b[0]; C0 = c[0]; D0 = dd[0];
+      A1 = a[1]; B1 = b[1]; C1 = c[1]; D1 = dd[1];
+    }
+    const int r0 = 2 * lane, r1 = 2 * lane + 1;
+    rA[wv][r0] = A0; rB[wv][r0] = B0; rC[wv][r0] = C0; rD[wv][r0] = D0;
+    rA[wv][r1] = A1; rB[wv][r1] = B1; rC[wv][r1] = C1; rD[wv][r1] = D1;
+    // cyclic reduction (PCR) of the reduced system
+    for (int st = 1; st < R; st <<= 1) {
+      __syncthreads();
+      double nA[2], nB[2], nC[2];
+      double2 nD[2];
+#pragma unroll
+      for (int q = 0; q < 2; ++q) {
+        const int r = 2 * lane + q;
+        const int rm = r - st, rp = r + st;
+        double Aq = 0.0, Cq = 0.0, Bq = rB[wv][r];
+        double2 Dq = rD[wv][r];
+        if (rm >= 0) {
+          const double k1 = rA[wv][r] / rB[wv][rm];
+          Aq = -rA[wv][rm] * k1;
+          Bq -= rC[wv][rm] * k1;
+          Dq = csub(Dq, cscale(rD[wv][rm], k1));
+        }
+        if (rp < R) {
+          const double k2 = rC[wv][r] / rB[wv][rp];
+          Cq = -rC[wv][rp] * k2;
+          Bq -= rA[wv][rp] * k2;
+          Dq = csub(Dq, cscale(rD[wv][rp], k2));
+        }
+        nA[q] = Aq; nB[q] = Bq; nC[q] = Cq; nD[q] = Dq;
+      }
+      __syncthreads();
+#pragma unroll
+      for (int q = 0; q < 2; ++q) {
+        const int r = 2 * lane + q;
+        rA[wv][r] = nA[q]; rB[wv][r] = nB[q]; rC[wv][r] = nC[q]; rD[wv][r] = nD[q];
+      }
+    }
+    const double2 xs = cscale(rD[wv][r0], 1.0 / rB[wv][r0]);
+    const double2 xe = cscale(rD[wv][r1], 1.0 / rB[wv][r1]);
+    x[0] = xs;
+    x[C - 1] = xe;
+#pragma unroll
+    for (int t = 1; t <= C - 2; ++t)
+      x[t] = make_double2(al[t].x + be[t] * xs.x + ga[t] * xe.x, al[t].y + be[t] * xs.y + ga[t] * xe.y);
+  }
+  __syncthreads();
+#pragma unroll
+  for (int t = 0; t < C; ++t) L[lane * LSP + t] = x[t];
+  __syncthreads();
+  for (int t = 0; t < C; ++t) {
+    const int e = lane + 64 * t;
+    if (active && e < nx) g[e] = L[(e / C) * LSP + e % C];
+  }
+}
+
+// ---------------------------------------------------------------------------
+constexpr int PBX = 64, PBY = 4;
+
+// Projection of one cell's faces, pressure update and the per-block maximum
+// of the cell speed |u_c| + |v_c| + |w_c| (face means of the projected field).
+// mode 1 (initial projection) leaves p unchanged.
+__global__ void __launch_bounds__(PBX* PBY) k_project(Dims d, Fields f, Scalars* s, int mode) {
+  const int i = blockIdx.x * PBX + threadIdx.x;
+  const int j = blockIdx.y * PBY + threadIdx.y;
+  const int k = blockIdx.z;
+  double speed = 0.0;
+  if (i < d.nx && j < d.ny) {
+    const int nx = d.nx;
+    const int jm = j == 0 ? d.ny - 1 : j - 1, jp = j == d.ny - 1 ? 0 : j + 1;
+    const int km = k == 0 ? d.nz - 1 : k - 1, kp = k == d.nz - 1 ? 0 : k + 1;
+    const double dt = s->dt, inv_h = d.inv_h;
+    const long long c = fidx(d, i, j, k);
+    const double ph = f.phi[c];
+    const double ui = (i >= 1) ? f.ut[c] - dt * (ph - f.phi[c - 1]) * inv_h : f.ut[c];
+    const double uip = (i + 1 <= nx - 1) ? f.ut[c + 1] - dt * (f.phi[c + 1] - ph) * inv_h : f.ut[c + 1];
+    const long long cjm = fidx(d, i, jm, k), cjp = fidx(d, i, jp, k);
+    const long long ckm = fidx(d, i, j, km), ckp = fidx(d, i, j, kp);
+    const double vj = f.vt[c] - dt * (ph - f.phi[cjm]) * inv_h;
+    const double vjp = f.vt[cjp] - dt * (f.phi[cjp] - ph) * inv_h;
+    const double wk = f.wt[c] - dt * (ph - f.phi[ckm]) * inv_h;
+    const double wkp = f.wt[ckp] - dt * (f.phi[ckp] - ph) * inv_h;
+    f.u[c] = ui;
+    f.v[c] = vj;
+    f.w[c] = wk;
+    if (i == nx - 1) {
+      f.u[c + 1] = uip;         // outlet face keeps u~
+      f.v[c + 1] = f.vt[c + 1];  // outlet ghosts keep their provisional values
+      f.w[c + 1] = f.wt[c + 1];
+    }
+    if (mode == 0) f.p[c] = f.p[c] + ph;
+    speed = fabs(0.5 * (ui + uip)) + fabs(0.5 * (vj + vjp)) + fabs(0.5 * (wk + wkp));
+    if (!(speed <= 1.7976931348623157e308)) {
+      atomicOr(&s->status, (int)ST_NONFINITE);
+      speed = 0.0;
+    }
+  }
+  // block maximum
+  for (int off = 32; off > 0; off >>= 1) speed = fmax(speed, __shfl_xor(speed, off, 64));
+  __shared__ double wmax[PBX * PBY / 64];
+  const int tid = threadIdx.y * PBX + threadIdx.x;
+  if ((tid & 63) == 0) wmax[tid >> 6] = speed;
+  __syncthreads();
+  if (tid == 0) {
+    double mx = wmax[0];
+    for (int q = 1; q < PBX * PBY / 64; ++q) mx = fmax(mx, wmax[q]);
+    atomicMax(&s->speed_bits, (unsigned long long)__double_as_longlong(mx));
+  }
+}
+
+}  // namespace
+
+bool fft_size_supported(int n) {
+  switch (n) {
+    case 16: case 24: case 32: case 48: case 64: case 96: case 128: case 192: case 256:
+    case 384: case 512: case 768:
+      return true;
+    default:
+      return false;
+  }
+}
+
+#define IBDNS_FFT_SWITCH(N, CALL) \
+  switch (N) {                     \
+    case 16: CALL(16); break;      \
+    case 24: CALL(24); break;      \
+    case 32: CALL(32); break;      \
+    case 48: CALL(48); break;      \
+    case 64: CALL(64); break;      \
+    case 96: CALL(96); break;      \
+    case 128: CALL(128); break;    \
+    case 192: CALL(192); break;    \
+    case 256: CALL(256); break;    \
+    case 384: CALL(384); break;    \
+    case 512: CALL(512); break;    \
+    case 768: CALL(768); break;    \
+    default: break;                \
+  }
+
+void launch_div_ffty(const Dims& d, const Fields& f, const Scalars* s, const double2* tw_y,
+                     hipStream_t st) {
+  dim3 grid((d.nx + 15) / 16, d.nz);
+#define CALL(NY) hipLaunchKernelGGL(k_div_ffty<NY>, grid, dim3(FT), 0, st, d, f, s, tw_y)
+  IBDNS_FFT_SWITCH(d.ny, CALL)
+#undef CALL
+}
+
+void launch_fftz(const Dims& d, const Fields& f, const double2* tw_z, int sign, hipStream_t st) {
+  dim3 grid((d.nx + 7) / 8, d.MY);
+  if (sign < 0) {
+#define CALL(NZ) hipLaunchKernelGGL((k_fftz<NZ, -1>), grid, dim3(FT), 0, st, d, f, tw_z)
+    IBDNS_FFT_SWITCH(d.nz, CALL)
+#undef CALL
+  } else {
+#define CALL(NZ) hipLaunchKernelGGL((k_fftz<NZ, 1>), grid, dim3(FT), 0, st, d, f, tw_z)
+    IBDNS_FFT_SWITCH(d.nz, CALL)
+#undef CALL
+  }
+}
+
+void launch_iffty(const Dims& d, const Fields& f, const double2* tw_y, hipStream_t st) {
+  dim3 grid((d.nx + 15) / 16, d.nz);
+#define CALL(NY) hipLaunchKernelGGL(k_iffty<NY>, grid, dim3(FT), 0, st, d, f, tw_y)
+  IBDNS_FFT_SWITCH(d.ny, CALL)
+#undef CALL
+}
+
+bool tri_size_supported(int nx) {
+  int C = (nx + 63) / 64;
+  if (C < 2) C = 2;
+  return nx >= 8 && (C == 2 || C == 3 || C == 4 || C == 5 || C == 6 || C == 8 || C == 12);
+}
+
+void launch_tri(const Dims& d, const Fields& f, const double* lam_y, const double* lam_z,
+                hipStream_t st) {
+  const long long nlines = (long long)d.MY * d.nz;
+  dim3 grid((unsigned)((nlines + TRI_WAVES - 1) / TRI_WAVES));
+  const double scale = (d.h * d.h) / ((double)d.ny * (double)d.nz);
+  int C = (d.nx + 63) / 64;
+  if (C < 2) C = 2;
+  switch (C) {
+    case 2: hipLaunchKernelGGL(k_tri<2>, grid, dim3(64 * TRI_WAVES), 0, st, d, f, lam_y, lam_z, scale); break;
+    case 3: hipLaunchKernelGGL(k_tri<3>, grid, dim3(64 * TRI_WAVES), 0, st, d, f, lam_y, lam_z, scale); break;
+    case 4: hipLaunchKernelGGL(k_tri<4>, grid, dim3(64 * TRI_WAVES), 0, st, d, f, lam_y, lam_z, scale); break;
+    case 5: hipLaunchKernelGGL(k_tri<5>, grid, dim3(64 * TRI_WAVES), 0, st, d, f, lam_y, lam_z, scale); break;
+    case 6: hipLaunchKernelGGL(k_tri<6>, grid, dim3(64 * TRI_WAVES), 0, st, d, f, lam_y, lam_z, scale); break;
+    case 8: hipLaunchKernelGGL(k_tri<8>, grid, dim3(64 * TRI_WAVES), 0, st, d, f, lam_y, lam_z, scale); break;
+    case 12: hipLaunchKernelGGL(k_tri<12>, grid, dim3(64 * TRI_WAVES), 0, st, d, f, lam_y, lam_z, scale); break;
+    default: break;
+  }
+}
+
+void launch_project(const Dims& d, const Fields& f, Scalars* s, int mode, hipStream_t st) {
+  dim3 grid((d.nx + PBX - 1) / PBX, (d.ny + PBY - 1) / PBY, d.nz);
+  hipLaunchKernelGGL(k_project, grid, dim3(PBX, PBY), 0, st, d, f, s, mode);
+}
+
+}  // namespace ibdns

@@ -1,0 +1,48 @@
+"""The C-ABI library loads and exports every entry point of include/ibdns.h;
+host-side argument validation (no GPU needed)."""
+import ctypes
+import os
+import re
+
+import pytest
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+
+
+def declared_symbols():
+    src = open(os.path.join(ROOT, "include", "ibdns.h")).read()
+    return sorted(set(re.findall(r"\b(ibdns_[a-z_]+)\s*\(", src)))
+
+
+def test_header_and_binding_agree():
+    import paper_2103_08246_amd as ib
+    assert sorted(ib.EXPORTED) == declared_symbols()
+
+
+def test_library_exports_every_declared_symbol():
+    lib = ctypes.CDLL(os.path.join(ROOT, "paper_2103_08246_amd", "libibdns.so"))
+    for name in declared_symbols():
+        assert hasattr(lib, name), name
+
+
+def test_workspace_size_validation():
+    import paper_2103_08246_amd as ib
+    good = ib.make_domain(64, 32, 32, 4.0, 2.0, 2.0, 200.0, dt=1e-3)
+    n = ib.workspace_size(good, 0, 16)
+    P = 80  # pitch of nx+1 = 65 rounded to 16
+    assert n > 11 * P * 32 * 32 * 8
+    bad = [ib.make_domain(64, 30, 32, 4.0, 1.875, 2.0, 200.0, dt=1e-3),   # 30 = 2*3*5
+           ib.make_domain(64, 32, 32, 4.0, 2.5, 2.0, 200.0, dt=1e-3),     # anisotropic h
+           ib.make_domain(4, 32, 32, 0.25, 2.0, 2.0, 200.0, dt=1e-3),     # nx too small
+           ib.make_domain(64, 32, 32, 4.0, 2.0, 2.0, 200.0, dt=0.0, cfl=1.5),
+           ib.make_domain(64, 32, 32, 4.0, 2.0, 2.0, 200.0, dt=1e-3, precision=ib.MIXED)]
+    for d in bad:
+        with pytest.raises(ib.IbdnsError) as e:
+            ib.workspace_size(d)
+        assert e.value.code == ib.EINVAL
+
+
+def test_strerror():
+    import paper_2103_08246_amd as ib
+    assert "workspace" in ib.strerror(ib.ENOMEM)
+    assert ib.strerror(ib.OK) == "ok"
