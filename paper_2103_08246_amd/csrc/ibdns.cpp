@@ -61,6 +61,7 @@ struct ibdns_ctx {
   int ntx = 0, nty = 0, ntz = 0;
   int* bbox = nullptr;
   bool geometry_set = false;
+  bool launch_failed = false;
   bool stepped = false;
   // timing
   bool timing = false;
@@ -89,6 +90,11 @@ size_t fluid_bytes(const ibdns_domain& dm) {
   b += 11 * up(FS * sizeof(double));
   b += up((size_t)dm.nx * MY * dm.nz * sizeof(double2));
   b += up(2 * nparts * sizeof(double));
+  Dims dd{};
+  dd.nx = dm.nx;
+  dd.ny = dm.ny;
+  dd.nz = dm.nz;
+  b += up(project_blocks(dd) * sizeof(double));
   b += up(dm.ny * sizeof(double2)) + up(dm.nz * sizeof(double2));
   b += up(MY * sizeof(double)) + up(dm.nz * sizeof(double));
   return b;
@@ -115,8 +121,11 @@ size_t flag_bytes(int ns) {
   if (ns <= 0) return 0;
   const size_t n = (size_t)ns * ns;
   size_t b = 0;
-  b += 5 * up(3 * n * sizeof(double));  // X, V, Fh, X0, f
+  b += 4 * up(3 * n * sizeof(double));  // X, V, Fh, X0
   b += 2 * up(n * sizeof(double));      // mass, dV
+  b += up(6 * n * sizeof(double));      // rest lengths
+  b += up(2 * (size_t)flag_bands(ns) * 4 * 3 * ns * sizeof(double));  // band-edge exchange
+  b += up(64 * sizeof(int));            // band counters
   b += up(3 * n * sizeof(double));      // amount
   b += up(9 * n * sizeof(int));         // centre
   b += up(27 * n * sizeof(double));     // wts
@@ -195,11 +204,23 @@ void stage_project(ibdns_ctx* c, int mode) {
 }
 
 void stage_flag(ibdns_ctx* c) {
-  if (c->has_flag) TIMED(c, "flag_step", launch_flag_step(c->fl, c->s, c->st));
+  if (!c->has_flag) return;
+  hipError_t e = hipSuccess;
+  TIMED(c, "flag_step", e = launch_flag_step(c->fl, c->s, c->st));
+  if (e != hipSuccess) c->launch_failed = true;
 }
-void stage_advance(ibdns_ctx* c) { TIMED(c, "advance", launch_advance(c->s, c->d.h, c->st)); }
+void stage_advance(ibdns_ctx* c) {
+  TIMED(c, "advance", launch_advance(c->s, c->f.speed_part, project_blocks(c->d), c->d.h, c->st));
+}
 
-int check_launch() { return hipGetLastError() == hipSuccess ? IBDNS_OK : IBDNS_EHIP; }
+int check_launch(ibdns_ctx* c = nullptr) {
+  bool bad = hipGetLastError() != hipSuccess;
+  if (c && c->launch_failed) {
+    bad = true;
+    c->launch_failed = false;
+  }
+  return bad ? IBDNS_EHIP : IBDNS_OK;
+}
 
 int read_status(ibdns_ctx* c) {
   if (hipStreamSynchronize(c->st) != hipSuccess) return IBDNS_EHIP;
@@ -304,6 +325,7 @@ int ibdns_init_domain(const ibdns_domain* dm, const double* zu, const double* zv
   for (auto p : fl) *p = c->carve<double>(d.FS);
   c->f.spec = c->carve<double2>((size_t)d.nx * d.MY * d.nz);
   c->f.partial = c->carve<double>(2 * (size_t)c->nparts);
+  c->f.speed_part = c->carve<double>(project_blocks(d));
   c->tw_y = c->carve<double2>(d.ny);
   c->tw_z = c->carve<double2>(d.nz);
   c->lam_y = c->carve<double>(d.MY);
@@ -393,7 +415,7 @@ int ibdns_init_domain(const ibdns_domain* dm, const double* zu, const double* zv
   launch_outlet(d, c->f, c->s, c->nparts, 0, c->st);
   launch_flux_apply(d, c->f, c->s, c->nparts, c->st);
   stage_project(c, 1);
-  launch_set_dt0(c->s, d.h, c->st);
+  launch_set_dt0(c->s, c->f.speed_part, project_blocks(d), d.h, c->st);
   if (check_launch() != IBDNS_OK || hipStreamSynchronize(c->st) != hipSuccess) {
     delete c;
     return IBDNS_EHIP;
@@ -514,7 +536,10 @@ int ibdns_set_geometry(ibdns_ctx* c, int64_t n_points, const double* X, const do
     F.Fh = c->carve<double>(3 * n);
     double* X0d = c->carve<double>(3 * n);
     F.X0 = X0d;
-    F.f = c->carve<double>(3 * n);
+    double* restd = c->carve<double>(6 * (size_t)n);
+    F.rest = restd;
+    F.xbuf = c->carve<double>(2 * (size_t)flag_bands(ns) * 4 * 3 * ns);
+    F.counter = c->carve<int>(64);
     double* massd = c->carve<double>(n);
     double* dVd = c->carve<double>(n);
     F.mass = massd;
@@ -529,7 +554,6 @@ int ibdns_set_geometry(ibdns_ctx* c, int64_t n_points, const double* X, const do
     ps.centre = c->carve<int>(9 * n);
     ps.wts = c->carve<double>(27 * n);
     c->bbox = c->carve<int>(18);
-    F.bbox = c->bbox;
     // masses and volumes: dA = ds^2 w_a w_b (trapezoid), m = rho dA, dV = dA h
     std::vector<double> wgt(ns, 1.0);
     wgt[0] = wgt[ns - 1] = 0.5;
@@ -588,12 +612,28 @@ int ibdns_set_geometry(ibdns_ctx* c, int64_t n_points, const double* X, const do
         om2 = std::max(om2, r);
       }
     F.dts_max = 1.8 / std::sqrt(om2);
+    // rest lengths |X0_p - X0_q| to the six spring neighbours of every node
+    std::vector<double> rest(6 * (size_t)n, 0.0);
+    {
+      const int nbr[6][2] = {{1, 0}, {-1, 0}, {0, 1}, {0, -1}, {1, 1}, {-1, -1}};
+      for (int b = 0; b < ns; ++b)
+        for (int a = 0; a < ns; ++a)
+          for (int e = 0; e < 6; ++e) {
+            const int a2 = a + nbr[e][0], b2 = b + nbr[e][1];
+            if (a2 < 0 || a2 >= ns || b2 < 0 || b2 >= ns) continue;
+            const double* xp = flag_X0 + 3 * (a + ns * b);
+            const double* xq = flag_X0 + 3 * (a2 + ns * b2);
+            const double dx = xp[0] - xq[0], dy = xp[1] - xq[1], dz = xp[2] - xq[2];
+            rest[6 * (a + ns * b) + e] = std::sqrt(dx * dx + dy * dy + dz * dz);
+          }
+    }
     bool ok = hipMemcpy(F.X, flag_X0, 3 * n * sizeof(double), hipMemcpyHostToDevice) == hipSuccess &&
               hipMemcpy(X0d, flag_X0, 3 * n * sizeof(double), hipMemcpyHostToDevice) == hipSuccess &&
               hipMemset(F.V, 0, 3 * n * sizeof(double)) == hipSuccess &&
               hipMemset(F.Fh, 0, 3 * n * sizeof(double)) == hipSuccess &&
               hipMemcpy(massd, mass.data(), n * sizeof(double), hipMemcpyHostToDevice) == hipSuccess &&
-              hipMemcpy(dVd, vol.data(), n * sizeof(double), hipMemcpyHostToDevice) == hipSuccess;
+              hipMemcpy(dVd, vol.data(), n * sizeof(double), hipMemcpyHostToDevice) == hipSuccess &&
+              hipMemcpy(restd, rest.data(), rest.size() * sizeof(double), hipMemcpyHostToDevice) == hipSuccess;
     if (!ok) return IBDNS_EHIP;
     // tiles covering the flag's support: its extent never exceeds the diagonal sqrt(2) L
     const int ext = (int)std::ceil(std::sqrt(2.0) * 1.01 * L / h) + 4;
@@ -616,7 +656,7 @@ int ibdns_step(ibdns_ctx* c, int32_t n_steps) {
     stage_advance(c);
   }
   c->stepped = true;
-  return check_launch();
+  return check_launch(c);
 }
 
 int ibdns_run_stage(ibdns_ctx* c, int32_t stage) {
@@ -631,7 +671,7 @@ int ibdns_run_stage(ibdns_ctx* c, int32_t stage) {
     default: return IBDNS_EINVAL;
   }
   c->stepped = true;
-  return check_launch();
+  return check_launch(c);
 }
 
 int ibdns_sync(ibdns_ctx* c) {

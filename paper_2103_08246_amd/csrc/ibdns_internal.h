@@ -41,7 +41,7 @@ struct Scalars {
   double dt_fixed;    // > 0: fixed step
   double cfl;
   double pad0;
-  unsigned long long speed_bits;  // running max of the cell speed (bits of a double >= 0)
+  unsigned long long pad2;
   long long step;
   int first;          // 1: next predictor uses H^{n-1} := H^n
   int status;         // sticky StatusBits
@@ -58,6 +58,7 @@ struct Fields {
   double* phi;
   double2* spec;
   double* partial;    // per-block partial sums of the outflow pass (2 per block)
+  double* speed_part; // per-block maxima of the cell speed (projection pass)
 };
 
 // Immersed points of one group (static solid points or flag nodes).
@@ -87,11 +88,12 @@ struct FlagDev {
   double* X;               // ns*ns*3
   double* V;
   double* Fh;              // ns*ns*3 hydrodynamic force density (from the IBM)
-  const double* X0;        // reference lattice (rest lengths, clamp tangent)
+  const double* X0;        // reference lattice (clamp tangent)
   const double* mass;      // ns*ns
   const double* dV;        // ns*ns IBM volumes
-  double* f;               // scratch force ns*ns*3
-  int* bbox;               // 6 ints: node-index box of the flag support (per component max)
+  const double* rest;      // ns*ns*6 rest lengths to the (+a, -a, +b, -b, +a+b, -a-b) neighbours
+  double* xbuf;            // 2 slots x bands x 4 edge rows x ns x 3: band-edge exchange
+  int* counter;            // 64 per-band sub-step counters
 };
 
 // ---- launchers (one per kernel family) ----
@@ -117,10 +119,12 @@ void launch_tri(const Dims& d, const Fields& f, const double* shift_y, const dou
                 hipStream_t st);
 void launch_iffty(const Dims& d, const Fields& f, const double2* tw_y, hipStream_t st);
 void launch_project(const Dims& d, const Fields& f, Scalars* s, int mode, hipStream_t st);
+int project_blocks(const Dims& d);
 
-void launch_flag_step(const FlagDev& fl, Scalars* s, hipStream_t st);
-void launch_advance(Scalars* s, double h, hipStream_t st);
-void launch_set_dt0(Scalars* s, double h, hipStream_t st);
+hipError_t launch_flag_step(const FlagDev& fl, Scalars* s, hipStream_t st);
+int flag_bands(int ns);
+void launch_advance(Scalars* s, const double* partial, int nparts, double h, hipStream_t st);
+void launch_set_dt0(Scalars* s, const double* partial, int nparts, double h, hipStream_t st);
 
 bool fft_size_supported(int n);
 bool tri_size_supported(int nx);

@@ -10,32 +10,45 @@
 //   (second differences at a = 1..ns-2, b = 1..ns-2, mixed difference per
 //   cell; a clamped edge adds the a = 0 term with the ghost X_1 - 2 ds t0);
 //   springs k_s/2 (|X_p - X_q| - l0)^2 on a-edges, b-edges and the
-//   (a,b)-(a+1,b+1) diagonals, rest lengths from the reference lattice;
+//   (a,b)-(a+1,b+1) diagonals, rest lengths of the reference lattice;
 //   load -F dV from the immersed-boundary forcing of the step;
 //   velocity-Verlet sub-steps, n_sub = ceil(dt / dts_max); a = 0 nodes fixed.
-// One workgroup runs all sub-steps; the state lives in global memory (L2).
+//
+// Parallel layout: the lattice is cut into bands of FR spanwise rows, one
+// workgroup per band (co-resident, cooperative launch).  A band keeps its
+// rows plus two halo rows on each side in LDS (the force stencil reaches two
+// rows), its velocities in registers.  After each drift the bands publish
+// their two edge rows to a double-buffered global slot and raise a counter;
+// each band waits (bounded spin) for its two neighbours' counters, then
+// reads their rows into its halo.
 #include "ibdns_internal.h"
 
 namespace ibdns {
 
 namespace {
 
-constexpr int FB = 1024;
+constexpr int FR = 8;            // rows per band
+constexpr int FT_ = 256;         // threads per band
+constexpr int MAXN = (FR * 128 + FT_ - 1) / FT_;  // owned nodes per thread (ns <= 128)
+constexpr long long SPIN_LIMIT = 1LL << 22;   // bounded wait (seconds at most)
 
 struct V3 {
   double x, y, z;
 };
-__device__ __forceinline__ V3 ld3(const double* p, int n) { return {p[3 * n], p[3 * n + 1], p[3 * n + 2]}; }
 
-// Force on node (a, b): bending + springs + external load.
-__device__ V3 node_force(const FlagDev& fl, int a, int b) {
+// Force on node (a, b) from the LDS rows (row r of LDS holds lattice row
+// b = r + rb0) and the per-node rest lengths.
+__device__ V3 node_force(const FlagDev& fl, const double* __restrict__ Xs, int rb0,
+                         const double* __restrict__ rest_s, int own_row0, int a, int b) {
   const int ns = fl.ns;
   const double ds = fl.ds;
   const double inv2 = 1.0 / (ds * ds);
-  auto X = [&](int aa, int bb) { return ld3(fl.X, aa + ns * bb); };
+  auto X = [&](int aa, int bb) -> V3 {
+    const double* p = Xs + 3 * (aa + ns * (bb - rb0));
+    return {p[0], p[1], p[2]};
+  };
   auto w = [&](int q) { return (q == 0 || q == ns - 1) ? 0.5 : 1.0; };
-  double sx = 0.0, sy = 0.0, sz = 0.0;  // sum_r W_r D_r,node R_r
-  // k_aa rows at a' in {a-1, a, a+1}
+  double sx = 0.0, sy = 0.0, sz = 0.0;
   for (int ap = a - 1; ap <= a + 1; ++ap) {
     if (ap < 1 || ap > ns - 2) continue;
     const V3 xm = X(ap - 1, b), x0 = X(ap, b), xp = X(ap + 1, b);
@@ -46,9 +59,9 @@ __device__ V3 node_force(const FlagDev& fl, int a, int b) {
     sz += Wr * coef * ((xm.z - 2.0 * x0.z + xp.z) * inv2);
   }
   if (fl.clamped && a <= 1) {
-    // k_aa(0) = (2 X_1 - 2 X_0 - 2 ds t0) / ds^2, weight ds^2 (1/2) w_b
-    const V3 r0 = ld3(fl.X0, 0 + ns * b), r1 = ld3(fl.X0, 1 + ns * b);
-    double tx = r1.x - r0.x, ty = r1.y - r0.y, tz = r1.z - r0.z;
+    const double* r0 = fl.X0 + 3 * (0 + ns * b);
+    const double* r1 = fl.X0 + 3 * (1 + ns * b);
+    double tx = r1[0] - r0[0], ty = r1[1] - r0[1], tz = r1[2] - r0[2];
     const double tn = sqrt(tx * tx + ty * ty + tz * tz);
     tx /= tn;
     ty /= tn;
@@ -60,7 +73,6 @@ __device__ V3 node_force(const FlagDev& fl, int a, int b) {
     sy += Wr * coef * ((2.0 * x1.y - 2.0 * x0.y) * inv2 - 2.0 * ty / ds);
     sz += Wr * coef * ((2.0 * x1.z - 2.0 * x0.z) * inv2 - 2.0 * tz / ds);
   }
-  // k_bb rows at b' in {b-1, b, b+1}
   for (int bp = b - 1; bp <= b + 1; ++bp) {
     if (bp < 1 || bp > ns - 2) continue;
     const V3 xm = X(a, bp - 1), x0 = X(a, bp), xp = X(a, bp + 1);
@@ -70,7 +82,6 @@ __device__ V3 node_force(const FlagDev& fl, int a, int b) {
     sy += Wr * coef * ((xm.y - 2.0 * x0.y + xp.y) * inv2);
     sz += Wr * coef * ((xm.z - 2.0 * x0.z + xp.z) * inv2);
   }
-  // mixed differences on the four cells around the node
   for (int ap = a - 1; ap <= a; ++ap) {
     if (ap < 0 || ap > ns - 2) continue;
     for (int bp = b - 1; bp <= b; ++bp) {
@@ -85,75 +96,175 @@ __device__ V3 node_force(const FlagDev& fl, int a, int b) {
     }
   }
   V3 f = {-fl.beta * sx, -fl.beta * sy, -fl.beta * sz};
-  // springs
-  const int p = a + ns * b;
-  const V3 xp = ld3(fl.X, p), rp = ld3(fl.X0, p);
+  const V3 xp = X(a, b);
   const int nb[6][2] = {{1, 0}, {-1, 0}, {0, 1}, {0, -1}, {1, 1}, {-1, -1}};
+  const double* rl = rest_s + 6 * (a + ns * (b - own_row0));
   for (int e = 0; e < 6; ++e) {
     const int a2 = a + nb[e][0], b2 = b + nb[e][1];
     if (a2 < 0 || a2 >= ns || b2 < 0 || b2 >= ns) continue;
-    const int q = a2 + ns * b2;
-    const V3 xq = ld3(fl.X, q), rq = ld3(fl.X0, q);
+    const V3 xq = X(a2, b2);
     const double dx = xp.x - xq.x, dy = xp.y - xq.y, dz = xp.z - xq.z;
-    const double ex = rp.x - rq.x, ey = rp.y - rq.y, ez = rp.z - rq.z;
     const double ln = sqrt(dx * dx + dy * dy + dz * dz);
-    const double l0 = sqrt(ex * ex + ey * ey + ez * ez);
-    const double coef = fl.ks * (ln - l0) / ln;
+    const double coef = fl.ks * (ln - rl[e]) / ln;
     f.x -= coef * dx;
     f.y -= coef * dy;
     f.z -= coef * dz;
   }
-  // hydrodynamic load: reaction to the forcing applied to the fluid
-  const double dV = fl.dV[p];
-  f.x += -fl.Fh[3 * p] * dV;
-  f.y += -fl.Fh[3 * p + 1] * dV;
-  f.z += -fl.Fh[3 * p + 2] * dV;
   return f;
 }
 
-__device__ void all_forces(const FlagDev& fl) {
-  const int n = fl.ns * fl.ns;
-  for (int p = threadIdx.x; p < n; p += FB) {
-    const V3 f = node_force(fl, p % fl.ns, p / fl.ns);
-    fl.f[3 * p] = f.x;
-    fl.f[3 * p + 1] = f.y;
-    fl.f[3 * p + 2] = f.z;
-  }
+__global__ void k_flag_prep(FlagDev fl) {
+  const int t = threadIdx.x;
+  if (t < 64) fl.counter[t] = 0;
 }
 
-__global__ void __launch_bounds__(FB) k_flag(FlagDev fl, Scalars* s) {
+__global__ void __launch_bounds__(FT_) k_flag(FlagDev fl, Scalars* s) {
+  const int ns = fl.ns;
+  const int band = blockIdx.x;
+  const int nband = gridDim.x;
+  const int b0 = band * FR;
+  const int b1 = min(b0 + FR, ns);        // own rows [b0, b1)
+  const int rb0 = b0 - 2;                 // LDS row 0 = lattice row b0 - 2
+  __shared__ double Xs[(FR + 4) * 128 * 3];
+  __shared__ double Rs[FR * 128 * 6];
+  __shared__ int abort_flag;
+  const int tid = threadIdx.x;
+  if (tid == 0) abort_flag = 0;
+
+  // LDS fill: own rows, halo rows, rest lengths
+  for (int b = max(rb0, 0); b < min(b1 + 2, ns); ++b)
+    for (int q = tid; q < 3 * ns; q += FT_) Xs[3 * ns * (b - rb0) + q] = fl.X[3 * ns * b + q];
+  for (int q = tid; q < 6 * ns * (b1 - b0); q += FT_) Rs[q] = fl.rest[6 * ns * b0 + q];
+
   const double dt = s->dt;
   const int nsub = (int)ceil(dt / fl.dts_max);
   const double dts = dt / nsub;
-  if (threadIdx.x == 0) s->nsub = nsub;
-  const int n = fl.ns * fl.ns;
-  all_forces(fl);
-  __syncthreads();
-  for (int it = 0; it < nsub; ++it) {
-    for (int p = threadIdx.x; p < n; p += FB) {
-      if (p % fl.ns == 0) continue;  // leading edge fixed
-      const double im = 1.0 / fl.mass[p];
+  if (band == 0 && tid == 0) s->nsub = nsub;
+
+  // owned nodes of this thread
+  const int nown = ns * (b1 - b0);
+  double V[MAXN][3], fe[MAXN][3], im[MAXN];
+  int node[MAXN];
+#pragma unroll
+  for (int k = 0; k < MAXN; ++k) {
+    const int q = tid + k * FT_;
+    node[k] = q < nown ? b0 * ns + q : -1;
+    if (node[k] >= 0) {
+      const int p = node[k];
+      im[k] = 1.0 / fl.mass[p];
+      const double dV = fl.dV[p];
       for (int c = 0; c < 3; ++c) {
-        fl.V[3 * p + c] += (0.5 * dts) * (fl.f[3 * p + c] * im);
-        fl.X[3 * p + c] += dts * fl.V[3 * p + c];
+        V[k][c] = fl.V[3 * p + c];
+        fe[k][c] = -fl.Fh[3 * p + c] * dV;
+      }
+    }
+  }
+  __syncthreads();
+
+  double f[MAXN][3];
+  auto forces = [&]() {
+#pragma unroll
+    for (int k = 0; k < MAXN; ++k) {
+      if (node[k] < 0) continue;
+      const int a = node[k] % ns, b = node[k] / ns;
+      const V3 g = node_force(fl, Xs, rb0, Rs, b0, a, b);
+      f[k][0] = g.x + fe[k][0];
+      f[k][1] = g.y + fe[k][1];
+      f[k][2] = g.z + fe[k][2];
+    }
+  };
+  forces();
+
+  for (int it = 0; it < nsub; ++it) {
+    __syncthreads();  // every thread is done reading Xs (previous force pass)
+    // half kick + drift of the owned free nodes
+#pragma unroll
+    for (int k = 0; k < MAXN; ++k) {
+      if (node[k] < 0 || node[k] % ns == 0) continue;
+      double* xp = Xs + 3 * (node[k] - ns * rb0);
+      for (int c = 0; c < 3; ++c) {
+        V[k][c] += (0.5 * dts) * (f[k][c] * im[k]);
+        xp[c] += dts * V[k][c];
       }
     }
     __syncthreads();
-    all_forces(fl);
+    if (nband > 1) {
+      // publish the two first and two last own rows into slot it & 1
+      double* slot = fl.xbuf + ((size_t)(it & 1) * nband + band) * 4 * 3 * ns;
+      for (int r = 0; r < 4; ++r) {
+        const int b = r < 2 ? b0 + r : b1 - 4 + r;
+        if (b < b0 || b >= b1) continue;
+        for (int q = tid; q < 3 * ns; q += FT_) slot[r * 3 * ns + q] = Xs[3 * ns * (b - rb0) + q];
+      }
+      __threadfence();  // each wave releases its own slot stores at device scope
+      __syncthreads();
+      if (tid == 0) {
+        __threadfence();
+        __hip_atomic_store(&fl.counter[band], it + 1, __ATOMIC_RELEASE, __HIP_MEMORY_SCOPE_AGENT);
+        long long spins = 0;
+        bool ok = true;
+        for (int nbh = band - 1; nbh <= band + 1; nbh += 2) {
+          if (nbh < 0 || nbh >= nband) continue;
+          while (__hip_atomic_load(&fl.counter[nbh], __ATOMIC_ACQUIRE, __HIP_MEMORY_SCOPE_AGENT) < it + 1) {
+            if (++spins > SPIN_LIMIT) {
+              ok = false;
+              break;
+            }
+            __builtin_amdgcn_s_sleep(2);
+          }
+        }
+        if (!ok) {
+          abort_flag = 1;
+          atomicOr(&s->status, (int)ST_RANGE);
+        }
+      }
+      __syncthreads();
+      if (abort_flag) return;   // uniform over the workgroup
+      __threadfence();
+      // halo rows from the neighbours' slots
+      for (int hb = rb0; hb < b1 + 2; ++hb) {
+        if (hb < 0 || hb >= ns || (hb >= b0 && hb < b1)) continue;
+        const int nbh = hb < b0 ? band - 1 : band + 1;
+        const int nb0 = nbh * FR, nb1 = min(nb0 + FR, ns);
+        const int r = (hb - nb0 < 2) ? hb - nb0 : hb - (nb1 - 4);
+        const double* src = fl.xbuf + ((size_t)(it & 1) * nband + nbh) * 4 * 3 * ns + r * 3 * ns;
+        for (int q = tid; q < 3 * ns; q += FT_) Xs[3 * ns * (hb - rb0) + q] = src[q];
+      }
+    }
     __syncthreads();
-    for (int p = threadIdx.x; p < n; p += FB) {
-      if (p % fl.ns == 0) continue;
-      const double im = 1.0 / fl.mass[p];
-      for (int c = 0; c < 3; ++c) fl.V[3 * p + c] += (0.5 * dts) * (fl.f[3 * p + c] * im);
+    forces();
+#pragma unroll
+    for (int k = 0; k < MAXN; ++k) {
+      if (node[k] < 0 || node[k] % ns == 0) continue;
+      for (int c = 0; c < 3; ++c) V[k][c] += (0.5 * dts) * (f[k][c] * im[k]);
+    }
+  }
+  // write back the owned rows
+#pragma unroll
+  for (int k = 0; k < MAXN; ++k) {
+    if (node[k] < 0) continue;
+    const int p = node[k];
+    for (int c = 0; c < 3; ++c) {
+      fl.V[3 * p + c] = V[k][c];
+      fl.X[3 * p + c] = Xs[3 * (p - ns * rb0) + c];
     }
   }
 }
 
-// dt_{n+1} from the cell-speed maximum of the projection, then t, history.
-__global__ void k_advance(Scalars* s, double h) {
-  const double speed = __longlong_as_double((long long)s->speed_bits);
+// dt_{n+1} from the cell-speed maxima of the projection, then t, history.
+__global__ void __launch_bounds__(256) k_advance(Scalars* s, const double* partial, int nparts, double h) {
+  __shared__ double red[256];
+  double m = 0.0;
+  for (int q = threadIdx.x; q < nparts; q += 256) m = fmax(m, partial[q]);
+  red[threadIdx.x] = m;
+  __syncthreads();
+  for (int w = 128; w > 0; w >>= 1) {
+    if ((int)threadIdx.x < w) red[threadIdx.x] = fmax(red[threadIdx.x], red[threadIdx.x + w]);
+    __syncthreads();
+  }
+  if (threadIdx.x != 0) return;
+  const double speed = red[0];
   s->speed_last = speed;
-  s->speed_bits = 0ull;
   double dt_next;
   if (s->dt_fixed > 0.0) {
     dt_next = s->dt_fixed;
@@ -169,11 +280,20 @@ __global__ void k_advance(Scalars* s, double h) {
 }
 
 // dt_0 after the initial projection.
-__global__ void k_set_dt0(Scalars* s, double h) {
-  const double speed = __longlong_as_double((long long)s->speed_bits);
+__global__ void __launch_bounds__(256) k_set_dt0(Scalars* s, const double* partial, int nparts, double h) {
+  __shared__ double red[256];
+  double m = 0.0;
+  for (int q = threadIdx.x; q < nparts; q += 256) m = fmax(m, partial[q]);
+  red[threadIdx.x] = m;
+  __syncthreads();
+  for (int w = 128; w > 0; w >>= 1) {
+    if ((int)threadIdx.x < w) red[threadIdx.x] = fmax(red[threadIdx.x], red[threadIdx.x + w]);
+    __syncthreads();
+  }
+  if (threadIdx.x != 0) return;
+  const double speed = red[0];
   s->speed_last = speed;
-  s->speed_bits = 0ull;
-  double dt0 = s->dt_fixed > 0.0 ? s->dt_fixed : (speed > 0.0 ? s->cfl * h / speed : 1.0);
+  const double dt0 = s->dt_fixed > 0.0 ? s->dt_fixed : (speed > 0.0 ? s->cfl * h / speed : 1.0);
   s->dt = dt0;
   s->dt_prev = dt0;
   s->t = 0.0;
@@ -183,16 +303,25 @@ __global__ void k_set_dt0(Scalars* s, double h) {
 
 }  // namespace
 
-void launch_flag_step(const FlagDev& fl, Scalars* s, hipStream_t st) {
-  hipLaunchKernelGGL(k_flag, dim3(1), dim3(FB), 0, st, fl, s);
+int flag_bands(int ns) { return (ns + FR - 1) / FR; }
+
+hipError_t launch_flag_step(const FlagDev& fl, Scalars* s, hipStream_t st) {
+  const int nb = flag_bands(fl.ns);
+  if (nb > 64) return hipErrorInvalidValue;
+  hipLaunchKernelGGL(k_flag_prep, dim3(1), dim3(64), 0, st, fl);
+  FlagDev a0 = fl;
+  Scalars* a1 = s;
+  void* args[] = {&a0, &a1};
+  // the bands wait on each other: they must be co-resident
+  return hipLaunchCooperativeKernel(reinterpret_cast<const void*>(&k_flag), dim3(nb), dim3(FT_), args, 0, st);
 }
 
-void launch_advance(Scalars* s, double h, hipStream_t st) {
-  hipLaunchKernelGGL(k_advance, dim3(1), dim3(1), 0, st, s, h);
+void launch_advance(Scalars* s, const double* partial, int nparts, double h, hipStream_t st) {
+  hipLaunchKernelGGL(k_advance, dim3(1), dim3(256), 0, st, s, partial, nparts, h);
 }
 
-void launch_set_dt0(Scalars* s, double h, hipStream_t st) {
-  hipLaunchKernelGGL(k_set_dt0, dim3(1), dim3(1), 0, st, s, h);
+void launch_set_dt0(Scalars* s, const double* partial, int nparts, double h, hipStream_t st) {
+  hipLaunchKernelGGL(k_set_dt0, dim3(1), dim3(256), 0, st, s, partial, nparts, h);
 }
 
 }  // namespace ibdns

@@ -456,56 +456,64 @@ __global__ void __launch_bounds__(64 * TRI_WAVES) k_tri(Dims d, Fields f,
 }
 
 // ---------------------------------------------------------------------------
-constexpr int PBX = 64, PBY = 4;
+constexpr int PBX = 64, PBY = 4, PKZ = 16;
 
-// Projection of one cell's faces, pressure update and the per-block maximum
-// of the cell speed |u_c| + |v_c| + |w_c| (face means of the projected field).
-// mode 1 (initial projection) leaves p unchanged.
+// Projection of the faces of a column of cells (z-march over PKZ planes: phi
+// and the projected w of plane k+1 are reused by plane k+1), pressure update,
+// and the per-block maximum of the cell speed |u_c| + |v_c| + |w_c| (face
+// means of the projected field).  mode 1 (initial projection) leaves p.
 __global__ void __launch_bounds__(PBX* PBY) k_project(Dims d, Fields f, Scalars* s, int mode) {
   const int i = blockIdx.x * PBX + threadIdx.x;
   const int j = blockIdx.y * PBY + threadIdx.y;
-  const int k = blockIdx.z;
-  double speed = 0.0;
+  const int kb = blockIdx.z * PKZ;
+  const int ke = min(kb + PKZ, d.nz);
+  double smax = 0.0;
   if (i < d.nx && j < d.ny) {
     const int nx = d.nx;
     const int jm = j == 0 ? d.ny - 1 : j - 1, jp = j == d.ny - 1 ? 0 : j + 1;
-    const int km = k == 0 ? d.nz - 1 : k - 1, kp = k == d.nz - 1 ? 0 : k + 1;
     const double dt = s->dt, inv_h = d.inv_h;
-    const long long c = fidx(d, i, j, k);
-    const double ph = f.phi[c];
-    const double ui = (i >= 1) ? f.ut[c] - dt * (ph - f.phi[c - 1]) * inv_h : f.ut[c];
-    const double uip = (i + 1 <= nx - 1) ? f.ut[c + 1] - dt * (f.phi[c + 1] - ph) * inv_h : f.ut[c + 1];
-    const long long cjm = fidx(d, i, jm, k), cjp = fidx(d, i, jp, k);
-    const long long ckm = fidx(d, i, j, km), ckp = fidx(d, i, j, kp);
-    const double vj = f.vt[c] - dt * (ph - f.phi[cjm]) * inv_h;
-    const double vjp = f.vt[cjp] - dt * (f.phi[cjp] - ph) * inv_h;
-    const double wk = f.wt[c] - dt * (ph - f.phi[ckm]) * inv_h;
-    const double wkp = f.wt[ckp] - dt * (f.phi[ckp] - ph) * inv_h;
-    f.u[c] = ui;
-    f.v[c] = vj;
-    f.w[c] = wk;
-    if (i == nx - 1) {
-      f.u[c + 1] = uip;         // outlet face keeps u~
-      f.v[c + 1] = f.vt[c + 1];  // outlet ghosts keep their provisional values
-      f.w[c + 1] = f.wt[c + 1];
-    }
-    if (mode == 0) f.p[c] = f.p[c] + ph;
-    speed = fabs(0.5 * (ui + uip)) + fabs(0.5 * (vj + vjp)) + fabs(0.5 * (wk + wkp));
-    if (!(speed <= 1.7976931348623157e308)) {
-      atomicOr(&s->status, (int)ST_NONFINITE);
-      speed = 0.0;
+    const int km0 = kb == 0 ? d.nz - 1 : kb - 1;
+    double ph_c = f.phi[fidx(d, i, j, kb)];
+    double wk = f.wt[fidx(d, i, j, kb)] - dt * (ph_c - f.phi[fidx(d, i, j, km0)]) * inv_h;
+    for (int k = kb; k < ke; ++k) {
+      const int kp = k == d.nz - 1 ? 0 : k + 1;
+      const long long c = fidx(d, i, j, k);
+      const long long ckp = fidx(d, i, j, kp);
+      const double ph_p = f.phi[ckp];
+      const double wkp = f.wt[ckp] - dt * (ph_p - ph_c) * inv_h;
+      const double ui = (i >= 1) ? f.ut[c] - dt * (ph_c - f.phi[c - 1]) * inv_h : f.ut[c];
+      const double uip = (i + 1 <= nx - 1) ? f.ut[c + 1] - dt * (f.phi[c + 1] - ph_c) * inv_h : f.ut[c + 1];
+      const long long cjm = fidx(d, i, jm, k), cjp = fidx(d, i, jp, k);
+      const double vj = f.vt[c] - dt * (ph_c - f.phi[cjm]) * inv_h;
+      const double vjp = f.vt[cjp] - dt * (f.phi[cjp] - ph_c) * inv_h;
+      f.u[c] = ui;
+      f.v[c] = vj;
+      f.w[c] = wk;
+      if (i == nx - 1) {
+        f.u[c + 1] = uip;          // outlet face keeps u~
+        f.v[c + 1] = f.vt[c + 1];  // outlet ghosts keep their provisional values
+        f.w[c + 1] = f.wt[c + 1];
+      }
+      if (mode == 0) f.p[c] = f.p[c] + ph_c;
+      double speed = fabs(0.5 * (ui + uip)) + fabs(0.5 * (vj + vjp)) + fabs(0.5 * (wk + wkp));
+      if (!(speed <= 1.7976931348623157e308)) {
+        atomicOr(&s->status, (int)ST_NONFINITE);
+        speed = 0.0;
+      }
+      smax = fmax(smax, speed);
+      ph_c = ph_p;
+      wk = wkp;
     }
   }
-  // block maximum
-  for (int off = 32; off > 0; off >>= 1) speed = fmax(speed, __shfl_xor(speed, off, 64));
+  for (int off = 32; off > 0; off >>= 1) smax = fmax(smax, __shfl_xor(smax, off, 64));
   __shared__ double wmax[PBX * PBY / 64];
   const int tid = threadIdx.y * PBX + threadIdx.x;
-  if ((tid & 63) == 0) wmax[tid >> 6] = speed;
+  if ((tid & 63) == 0) wmax[tid >> 6] = smax;
   __syncthreads();
   if (tid == 0) {
     double mx = wmax[0];
     for (int q = 1; q < PBX * PBY / 64; ++q) mx = fmax(mx, wmax[q]);
-    atomicMax(&s->speed_bits, (unsigned long long)__double_as_longlong(mx));
+    f.speed_part[blockIdx.x + gridDim.x * (blockIdx.y + gridDim.y * blockIdx.z)] = mx;
   }
 }
 
@@ -591,8 +599,12 @@ void launch_tri(const Dims& d, const Fields& f, const double* lam_y, const doubl
   }
 }
 
+int project_blocks(const Dims& d) {
+  return ((d.nx + PBX - 1) / PBX) * ((d.ny + PBY - 1) / PBY) * ((d.nz + PKZ - 1) / PKZ);
+}
+
 void launch_project(const Dims& d, const Fields& f, Scalars* s, int mode, hipStream_t st) {
-  dim3 grid((d.nx + PBX - 1) / PBX, (d.ny + PBY - 1) / PBY, d.nz);
+  dim3 grid((d.nx + PBX - 1) / PBX, (d.ny + PBY - 1) / PBY, (d.nz + PKZ - 1) / PKZ);
   hipLaunchKernelGGL(k_project, grid, dim3(PBX, PBY), 0, st, d, f, s, mode);
 }
 
