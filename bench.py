@@ -43,6 +43,12 @@ def kernel_bytes_per_cell(ny: int) -> dict:
     }
 
 
+def max_divergence(u, v, w, h):
+    """max |D u| over the cells of fields in the ABI's host layout (measurement only)."""
+    d = (u[..., 1:] - u[..., :-1]) + (np.roll(v, -1, axis=1) - v) + (np.roll(w, -1, axis=0) - w)
+    return float(np.max(np.abs(d))) / h
+
+
 def make_workload(name: str):
     import synth
     if name in ("grid_flag_768x384x384_re1000", "default"):
@@ -110,6 +116,7 @@ def main():
     ap.add_argument("--warmup", type=int, default=5)
     ap.add_argument("--workload", default="grid_flag_768x384x384_re1000")
     ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--no-mixed", action="store_true")
     ap.add_argument("--cpu-budget", type=float, default=20.0)
     args = ap.parse_args()
     if args.gpus != 1:
@@ -125,29 +132,30 @@ def main():
     noise = synth.ic_noise(w)
     bars = synth.bar_points(w) if w.grid is not None else None
     X0 = synth.flag_reference(w) if w.flag is not None else None
-    run = ib.create(ib.domain_from(w), noise, points=bars,
-                    flag=ib.flag_from(w.flag) if w.flag is not None else None, flag_X0=X0)
-    del noise
-    print(f"# set up; {len(bars[1]) if bars else 0} solid points", file=sys.stderr, flush=True)
-    run.step(args.warmup)
-    ib.sync(run.ctx)
-    print("# warm-up done", file=sys.stderr, flush=True)
 
-    stream = torch.cuda.current_stream()
-    ib.enable_timing(run.ctx, True)
-    ev0 = torch.cuda.Event(enable_timing=True)
-    ev1 = torch.cuda.Event(enable_timing=True)
-    torch.cuda.synchronize()
-    t0 = time.perf_counter()
-    ev0.record(stream)
-    run.step(args.steps)
-    ev1.record(stream)
-    ib.sync(run.ctx)
-    torch.cuda.synchronize()
-    wall = time.perf_counter() - t0
-    gpu_ms = ev0.elapsed_time(ev1)
-    ib.enable_timing(run.ctx, False)
-    times = ib.kernel_times(run.ctx)
+    def measure(precision, timing):
+        run = ib.create(ib.domain_from(w, precision=precision), noise, points=bars,
+                        flag=ib.flag_from(w.flag) if w.flag is not None else None, flag_X0=X0)
+        run.step(args.warmup)
+        ib.sync(run.ctx)
+        stream = torch.cuda.current_stream()
+        ib.enable_timing(run.ctx, timing)
+        ev0 = torch.cuda.Event(enable_timing=True)
+        ev1 = torch.cuda.Event(enable_timing=True)
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        ev0.record(stream)
+        run.step(args.steps)
+        ev1.record(stream)
+        ib.sync(run.ctx)
+        torch.cuda.synchronize()
+        wall = time.perf_counter() - t0
+        ib.enable_timing(run.ctx, False)
+        times = ib.kernel_times(run.ctx) if timing else {}
+        return run, wall, ev0.elapsed_time(ev1), times
+
+    run, wall, gpu_ms, times = measure(ib.FP64, True)
+    print(f"# fp64: {wall * 1e3 / args.steps:.3f} ms/step", file=sys.stderr, flush=True)
     sc = ib.get_scalars(run.ctx)
     ms_per_step = wall * 1e3 / args.steps
     value = w.cells * args.steps / wall / 1e6
@@ -181,6 +189,22 @@ def main():
            "step_hbm_gbs": round(step_bytes / (ms_per_step * 1e-3) / 1e9, 1),
            "gpu_event_ms_per_step": round(gpu_ms / args.steps, 4),
            "kernel_avg_ms": breakdown}
+    if not args.no_mixed:
+        # the same workload with the FP32 RHS/predictor and IB transfer
+        run_m, wall_m, _, _ = measure(ib.MIXED, False)
+        print(f"# mixed: {wall_m * 1e3 / args.steps:.3f} ms/step", file=sys.stderr, flush=True)
+        a = run.fields()
+        b = run_m.fields()
+        num = sum(float(np.sum((x - y) ** 2)) for x, y in zip(b[:3], a[:3]))
+        den = sum(float(np.sum(y ** 2)) for y in a[:3])
+        dmax = max_divergence(b[0], b[1], b[2], w.h)
+        out["mixed"] = {"value": round(w.cells * args.steps / wall_m / 1e6, 1),
+                        "ms_per_step": round(wall_m * 1e3 / args.steps, 4),
+                        "speedup_vs_fp64": round(wall / wall_m, 3),
+                        "vel_rel_l2_vs_fp64": (num / den) ** 0.5, "max_abs_div": dmax,
+                        "after_steps": args.warmup + args.steps}
+        run_m.close()
+    del noise
     run.close()
     if not args.no_cpu_baseline:
         print("# timing the CPU oracle sample", file=sys.stderr, flush=True)

@@ -70,7 +70,10 @@ typedef struct {
   double dt;           /* > 0: fixed time step; <= 0: from the CFL number         */
   double cfl;          /* CFL number used when dt <= 0                           */
   double noise_amp;    /* amplitude A of the initial-condition noise             */
-  int32_t precision;   /* IBDNS_FP64 (only FP64 is implemented)                  */
+  int32_t precision;   /* IBDNS_FP64, or IBDNS_MIXED: the RHS/predictor and the  */
+                       /* immersed-boundary transfer compute and store H and the */
+                       /* provisional velocity in FP32; state, Poisson solve,   */
+                       /* projection and flag stay FP64                         */
   uint32_t flags;      /* IBDNS_TEST_* bits, 0 in production                      */
 } ibdns_domain;
 

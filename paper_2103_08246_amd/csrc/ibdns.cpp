@@ -95,6 +95,7 @@ size_t fluid_bytes(const ibdns_domain& dm) {
   dd.ny = dm.ny;
   dd.nz = dm.nz;
   b += up(project_blocks(dd) * sizeof(double));
+  b += up(3 * (size_t)dm.ny * dm.nz * sizeof(double));  // outlet planes
   b += up(dm.ny * sizeof(double2)) + up(dm.nz * sizeof(double2));
   b += up(MY * sizeof(double)) + up(dm.nz * sizeof(double));
   return b;
@@ -144,7 +145,7 @@ int validate(const ibdns_domain* d) {
   if (std::fabs(d->ly / d->ny - h) > 1e-12 * h || std::fabs(d->lz / d->nz - h) > 1e-12 * h)
     return IBDNS_EINVAL;
   if (d->dt <= 0 && !(d->cfl > 0 && d->cfl < 1)) return IBDNS_EINVAL;
-  if (d->precision != IBDNS_FP64) return IBDNS_EINVAL;
+  if (d->precision != IBDNS_FP64 && d->precision != IBDNS_MIXED) return IBDNS_EINVAL;
   if ((long long)(((d->nx + 1 + 15) / 16) * 16) * d->ny * d->nz >= (1LL << 31)) return IBDNS_EINVAL;
   return IBDNS_OK;
 }
@@ -248,6 +249,11 @@ double* field_ptr(ibdns_ctx* c, int which, int* nxh) {
   }
 }
 
+bool is_tilde(int which) {
+  return which == IBDNS_ARR_UT || which == IBDNS_ARR_VT || which == IBDNS_ARR_WT ||
+         which == IBDNS_ARR_HU || which == IBDNS_ARR_HV || which == IBDNS_ARR_HW;
+}
+
 int copy_field(ibdns_ctx* c, double* dev, int nxh, double* host, bool to_host) {
   const size_t w = (size_t)nxh * sizeof(double);
   const size_t sp = (size_t)c->d.P * sizeof(double);
@@ -255,6 +261,23 @@ int copy_field(ibdns_ctx* c, double* dev, int nxh, double* host, bool to_host) {
   hipError_t e = to_host ? hipMemcpy2D(host, w, dev, sp, w, rows, hipMemcpyDeviceToHost)
                          : hipMemcpy2D(dev, sp, host, w, w, rows, hipMemcpyHostToDevice);
   return e == hipSuccess ? IBDNS_OK : IBDNS_EHIP;
+}
+
+// FP32 provisional arrays (mixed precision): float rows of pitch P, widened
+// or narrowed on the host.
+int copy_field_f32(ibdns_ctx* c, double* dev, int nxh, double* host, bool to_host) {
+  const size_t rows = (size_t)c->d.ny * c->d.nz;
+  std::vector<float> tmp(rows * nxh);
+  const size_t w = (size_t)nxh * sizeof(float);
+  const size_t sp = (size_t)c->d.P * sizeof(float);
+  if (to_host) {
+    if (hipMemcpy2D(tmp.data(), w, dev, sp, w, rows, hipMemcpyDeviceToHost) != hipSuccess) return IBDNS_EHIP;
+    for (size_t q = 0; q < tmp.size(); ++q) host[q] = tmp[q];
+    return IBDNS_OK;
+  }
+  for (size_t q = 0; q < tmp.size(); ++q) tmp[q] = (float)host[q];
+  return hipMemcpy2D(dev, sp, tmp.data(), w, w, rows, hipMemcpyHostToDevice) == hipSuccess ? IBDNS_OK
+                                                                                          : IBDNS_EHIP;
 }
 
 double roma_host(double r) {
@@ -317,6 +340,7 @@ int ibdns_init_domain(const ibdns_domain* dm, const double* zu, const double* zv
   d.nu = 1.0 / dm->re;
   d.u_in = dm->u_in;
   d.flags = dm->flags;
+  d.mixed = dm->precision == IBDNS_MIXED ? 1 : 0;
   c->nparts = outlet_blocks(d);
 
   c->s = c->carve<Scalars>(1);
@@ -326,6 +350,7 @@ int ibdns_init_domain(const ibdns_domain* dm, const double* zu, const double* zv
   c->f.spec = c->carve<double2>((size_t)d.nx * d.MY * d.nz);
   c->f.partial = c->carve<double>(2 * (size_t)c->nparts);
   c->f.speed_part = c->carve<double>(project_blocks(d));
+  c->f.bnd = c->carve<double>(3 * (size_t)d.ny * d.nz);
   c->tw_y = c->carve<double2>(d.ny);
   c->tw_z = c->carve<double2>(d.nz);
   c->lam_y = c->carve<double>(d.MY);
@@ -404,14 +429,7 @@ int ibdns_init_domain(const ibdns_domain* dm, const double* zu, const double* zv
     return IBDNS_EHIP;
   }
   // initial projection with dt = 1, pressure untouched, then dt_0
-  const size_t fbytes = (size_t)d.FS * sizeof(double);
-  ok = hipMemcpyAsync(c->f.ut, c->f.u, fbytes, hipMemcpyDeviceToDevice, c->st) == hipSuccess &&
-       hipMemcpyAsync(c->f.vt, c->f.v, fbytes, hipMemcpyDeviceToDevice, c->st) == hipSuccess &&
-       hipMemcpyAsync(c->f.wt, c->f.w, fbytes, hipMemcpyDeviceToDevice, c->st) == hipSuccess;
-  if (!ok) {
-    delete c;
-    return IBDNS_EHIP;
-  }
+  launch_state_to_tilde(d, c->f, c->st);
   launch_outlet(d, c->f, c->s, c->nparts, 0, c->st);
   launch_flux_apply(d, c->f, c->s, c->nparts, c->st);
   stage_project(c, 1);
@@ -722,7 +740,23 @@ int ibdns_get_array(ibdns_ctx* c, int32_t which, double* host) {
   if (!c || !host) return IBDNS_EINVAL;
   if (hipStreamSynchronize(c->st) != hipSuccess) return IBDNS_EHIP;
   int nxh = 0;
-  if (double* dev = field_ptr(c, which, &nxh)) return copy_field(c, dev, nxh, host, true);
+  if (double* dev = field_ptr(c, which, &nxh)) {
+    if (!(c->d.mixed && is_tilde(which))) return copy_field(c, dev, nxh, host, true);
+    int r = copy_field_f32(c, dev, nxh, host, true);
+    if (r || which != IBDNS_ARR_UT) return r;
+    // boundary faces of u~ are FP64: inlet from u, outlet from its plane
+    const size_t rows = (size_t)c->d.ny * c->d.nz;
+    std::vector<double> in(rows), out(rows);
+    if (hipMemcpy2D(in.data(), sizeof(double), c->f.u, (size_t)c->d.P * sizeof(double), sizeof(double),
+                    rows, hipMemcpyDeviceToHost) != hipSuccess ||
+        hipMemcpy(out.data(), c->f.bnd, rows * sizeof(double), hipMemcpyDeviceToHost) != hipSuccess)
+      return IBDNS_EHIP;
+    for (size_t q = 0; q < rows; ++q) {
+      host[q * nxh] = in[q];
+      host[q * nxh + c->d.nx] = out[q];
+    }
+    return IBDNS_OK;
+  }
   if (which == IBDNS_ARR_POINT_F) {
     if (!c->nbars) return IBDNS_EINVAL;
     return hipMemcpy(host, c->bars.F, 3 * c->nbars * sizeof(double), hipMemcpyDeviceToHost) == hipSuccess
@@ -740,8 +774,16 @@ int ibdns_set_array(ibdns_ctx* c, int32_t which, const double* host) {
   if (!c || !host) return IBDNS_EINVAL;
   if (hipStreamSynchronize(c->st) != hipSuccess) return IBDNS_EHIP;
   int nxh = 0;
-  if (double* dev = field_ptr(c, which, &nxh))
-    return copy_field(c, dev, nxh, const_cast<double*>(host), false);
+  if (double* dev = field_ptr(c, which, &nxh)) {
+    double* h = const_cast<double*>(host);
+    int r = (c->d.mixed && is_tilde(which)) ? copy_field_f32(c, dev, nxh, h, false)
+                                            : copy_field(c, dev, nxh, h, false);
+    if (r || which != IBDNS_ARR_UT) return r;
+    // the outlet face of u~ also lives in its FP64 plane
+    const size_t rows = (size_t)c->d.ny * c->d.nz;
+    return hipMemcpy2D(c->f.bnd, sizeof(double), host + c->d.nx, (size_t)nxh * sizeof(double),
+                       sizeof(double), rows, hipMemcpyHostToDevice) == hipSuccess ? IBDNS_OK : IBDNS_EHIP;
+  }
   if (which == IBDNS_ARR_V_GHOST || which == IBDNS_ARR_W_GHOST) {
     double* dev = (which == IBDNS_ARR_V_GHOST ? c->f.v : c->f.w) + c->d.nx;
     return hipMemcpy2D(dev, (size_t)c->d.P * sizeof(double), host, sizeof(double), sizeof(double),

@@ -4,7 +4,10 @@
 //   field arrays u, v, w, p, H (3), provisional u~ (3), phi: doubles at
 //   a[i + P * (j + ny * k)], P = x pitch >= nx + 1 (a multiple of 16 doubles);
 //   u uses i = 0..nx (faces), v and w use i = 0..nx-1 plus the outlet ghost at
-//   i = nx, p and phi use i = 0..nx-1.
+//   i = nx, p and phi use i = 0..nx-1.  In mixed precision H and u~ hold
+//   floats at the same indices (the arrays keep their double-sized slots);
+//   the outlet values of u~, v~, w~ are always kept in FP64 planes (bnd), and
+//   the inlet face is read from u.
 //   spectrum: complex half spectrum of the Poisson right-hand side,
 //   s[i + nx * (m + MY * l)], MY = ny/2 + 1 (y wavenumber m, z wavenumber l or
 //   plane k between the two FFT passes), x fastest so that every x-line of a
@@ -25,6 +28,7 @@ struct Dims {
   long long FS;      // field size P * ny * nz
   double h, inv_h, nu, u_in;
   uint32_t flags;    // IBDNS_TEST_* bits
+  int mixed;         // 1: H and u~ stored and computed in FP32
 };
 
 __host__ __device__ inline long long fidx(const Dims& d, int i, int j, int k) {
@@ -59,6 +63,7 @@ struct Fields {
   double2* spec;
   double* partial;    // per-block partial sums of the outflow pass (2 per block)
   double* speed_part; // per-block maxima of the cell speed (projection pass)
+  double* bnd;        // 3 FP64 planes (ny*nz): u~, v~, w~ at the outlet i = nx
 };
 
 // Immersed points of one group (static solid points or flag nodes).
@@ -119,6 +124,7 @@ void launch_tri(const Dims& d, const Fields& f, const double* shift_y, const dou
                 hipStream_t st);
 void launch_iffty(const Dims& d, const Fields& f, const double2* tw_y, hipStream_t st);
 void launch_project(const Dims& d, const Fields& f, Scalars* s, int mode, hipStream_t st);
+void launch_state_to_tilde(const Dims& d, const Fields& f, hipStream_t st);
 int project_blocks(const Dims& d);
 
 hipError_t launch_flag_step(const FlagDev& fl, Scalars* s, hipStream_t st);

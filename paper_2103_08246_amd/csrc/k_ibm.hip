@@ -54,19 +54,22 @@ __global__ void k_point_stencil(Dims d, PointSet ps, Scalars* s) {
   }
 }
 
-__device__ __forceinline__ double* comp_field(const Fields& f, int comp) {
-  return comp == 0 ? f.ut : (comp == 1 ? f.vt : f.wt);
+template <class T>
+__device__ __forceinline__ T* comp_field(const Fields& f, int comp) {
+  return reinterpret_cast<T*>(comp == 0 ? f.ut : (comp == 1 ? f.vt : f.wt));
 }
 
 // Interpolation and force density; also flags a support that leaves the
-// evolved x range (u faces 1..nx-1, v and w cells 0..nx-1).
+// evolved x range (u faces 1..nx-1, v and w cells 0..nx-1).  The sum runs in
+// the field type T (FP32 in mixed precision).
+template <class T>
 __global__ void k_point_interp(Dims d, Fields f, PointSet ps, Scalars* s) {
   const int q = blockIdx.x * blockDim.x + threadIdx.x;
   const int comp = blockIdx.y;
   if (q >= ps.n) return;
   const int* cen = ps.centre + ((size_t)comp * ps.n + q) * 3;
   const double* wt = ps.wts + ((size_t)comp * ps.n + q) * 9;
-  const double* fld = comp_field(f, comp);
+  const T* fld = comp_field<T>(f, comp);
   const int lo = comp == 0 ? 1 : 0;
   if (cen[0] - 1 < lo || cen[0] + 1 > d.nx - 1) {
     atomicOr(&s->status, (int)ST_RANGE);
@@ -74,14 +77,14 @@ __global__ void k_point_interp(Dims d, Fields f, PointSet ps, Scalars* s) {
     ps.amount[(size_t)comp * ps.n + q] = 0.0;
     return;
   }
-  double U = 0.0;
+  T U = 0;
   for (int dk = 0; dk < 3; ++dk) {
     const int kk = wrap(cen[2] + dk - 1, d.nz);
     for (int dj = 0; dj < 3; ++dj) {
       const int jj = wrap(cen[1] + dj - 1, d.ny);
       for (int di = 0; di < 3; ++di) {
         const int ii = cen[0] + di - 1;
-        U += fld[fidx(d, ii, jj, kk)] * (wt[di] * wt[3 + dj] * wt[6 + dk]);
+        U += fld[fidx(d, ii, jj, kk)] * (T)(wt[di] * wt[3 + dj] * wt[6 + dk]);
       }
     }
   }
@@ -94,21 +97,22 @@ __global__ void k_point_interp(Dims d, Fields f, PointSet ps, Scalars* s) {
 }
 
 // Static points: one thread per touched grid node, gathering its CSR row.
+template <class T>
 __global__ void k_spread_csr(Dims d, Fields f, PointSet ps, SpreadCSR csr, int comp) {
   const int r = blockIdx.x * blockDim.x + threadIdx.x;
   if (r >= csr.nrows) return;
   const double* amt = ps.amount + (size_t)comp * ps.n;
   const double* wts = ps.wts + (size_t)comp * ps.n * 9;
-  double acc = 0.0;
+  T acc = 0;
   const int e0 = csr.row_ptr[r], e1 = csr.row_ptr[r + 1];
   for (int e = e0; e < e1; ++e) {
     const int code = csr.entry[e];
     const int q = code / 27, tap = code % 27;
     const int dk = tap / 9, dj = (tap / 3) % 3, di = tap % 3;
     const double* wt = wts + (size_t)q * 9;
-    acc += amt[q] * (wt[di] * wt[3 + dj] * wt[6 + dk]);
+    acc += (T)amt[q] * (T)(wt[di] * wt[3 + dj] * wt[6 + dk]);
   }
-  double* fld = comp_field(f, comp);
+  T* fld = comp_field<T>(f, comp);
   fld[csr.row_node[r]] += acc;
 }
 
@@ -152,6 +156,7 @@ constexpr int TN = TS * TS * TS;    // threads per tile
 // box.  The points are scanned in chunks, those whose support meets the tile
 // are compacted (in increasing order) into LDS, and every thread gathers the
 // contributions to its node.
+template <class T>
 __global__ void __launch_bounds__(TN) k_spread_tiles(Dims d, Fields f, PointSet ps, const int* bbox,
                                                      int ntx, int nty, int ntz, int comp,
                                                      Scalars* s) {
@@ -172,7 +177,7 @@ __global__ void __launch_bounds__(TN) k_spread_tiles(Dims d, Fields f, PointSet 
   const int* cenb = ps.centre + (size_t)comp * ps.n * 3;
   const double* wts = ps.wts + (size_t)comp * ps.n * 9;
   const double* amt = ps.amount + (size_t)comp * ps.n;
-  double acc = 0.0;
+  T acc = 0;
   for (int base = 0; base < ps.n; base += TN) {
     const int q = base + threadIdx.x;
     int hit = 0;
@@ -199,7 +204,7 @@ __global__ void __launch_bounds__(TN) k_spread_tiles(Dims d, Fields f, PointSet 
       const int di = ni - c[0] + 1, dj = nj - c[1] + 1, dk = nk - c[2] + 1;
       if (di >= 0 && di < 3 && dj >= 0 && dj < 3 && dk >= 0 && dk < 3) {
         const double* wt = wts + (size_t)p * 9;
-        acc += amt[p] * (wt[di] * wt[3 + dj] * wt[6 + dk]);
+        acc += (T)amt[p] * (T)(wt[di] * wt[3 + dj] * wt[6 + dk]);
       }
     }
     __syncthreads();
@@ -207,7 +212,7 @@ __global__ void __launch_bounds__(TN) k_spread_tiles(Dims d, Fields f, PointSet 
   if (ni <= bb[3] && nj <= bb[4] && nk <= bb[5]) {
     const int lo = comp == 0 ? 1 : 0;
     if (ni >= lo && ni <= d.nx - 1) {
-      double* fld = comp_field(f, comp);
+      T* fld = comp_field<T>(f, comp);
       fld[fidx(d, ni, wrap(nj, d.ny), wrap(nk, d.nz))] += acc;
     }
   }
@@ -223,7 +228,10 @@ void launch_point_stencil(const Dims& d, const PointSet& ps, Scalars* s, hipStre
 void launch_point_interp(const Dims& d, const Fields& f, const PointSet& ps, Scalars* s,
                          hipStream_t st) {
   if (ps.n == 0) return;
-  hipLaunchKernelGGL(k_point_interp, dim3((ps.n + 255) / 256, 3), dim3(256), 0, st, d, f, ps, s);
+  if (d.mixed)
+    hipLaunchKernelGGL(k_point_interp<float>, dim3((ps.n + 255) / 256, 3), dim3(256), 0, st, d, f, ps, s);
+  else
+    hipLaunchKernelGGL(k_point_interp<double>, dim3((ps.n + 255) / 256, 3), dim3(256), 0, st, d, f, ps, s);
 }
 
 void launch_spread_csr(const Dims& d, const Fields& f, const PointSet& ps, const SpreadCSR* csr3,
@@ -231,8 +239,12 @@ void launch_spread_csr(const Dims& d, const Fields& f, const PointSet& ps, const
   if (ps.n == 0) return;
   for (int c = 0; c < 3; ++c) {
     if (csr3[c].nrows == 0) continue;
-    hipLaunchKernelGGL(k_spread_csr, dim3((csr3[c].nrows + 255) / 256), dim3(256), 0, st, d, f, ps,
-                       csr3[c], c);
+    if (d.mixed)
+      hipLaunchKernelGGL(k_spread_csr<float>, dim3((csr3[c].nrows + 255) / 256), dim3(256), 0, st, d, f,
+                         ps, csr3[c], c);
+    else
+      hipLaunchKernelGGL(k_spread_csr<double>, dim3((csr3[c].nrows + 255) / 256), dim3(256), 0, st, d, f,
+                         ps, csr3[c], c);
   }
 }
 
@@ -245,8 +257,12 @@ void launch_spread_tiles(const Dims& d, const Fields& f, const PointSet& ps, con
                          int ntx, int nty, int ntz, Scalars* s, hipStream_t st) {
   if (ps.n == 0) return;
   for (int c = 0; c < 3; ++c)
-    hipLaunchKernelGGL(k_spread_tiles, dim3(ntx * nty * ntz), dim3(TN), 0, st, d, f, ps, bbox, ntx,
-                       nty, ntz, c, s);
+    if (d.mixed)
+      hipLaunchKernelGGL(k_spread_tiles<float>, dim3(ntx * nty * ntz), dim3(TN), 0, st, d, f, ps, bbox,
+                         ntx, nty, ntz, c, s);
+    else
+      hipLaunchKernelGGL(k_spread_tiles<double>, dim3(ntx * nty * ntz), dim3(TN), 0, st, d, f, ps, bbox,
+                         ntx, nty, ntz, c, s);
 }
 
 }  // namespace ibdns

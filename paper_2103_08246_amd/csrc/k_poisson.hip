@@ -162,11 +162,14 @@ constexpr int FT = 256;  // threads per FFT workgroup
 
 // r = D u~ / dt for a 16-column x tile of one z plane, then the y FFT of the
 // 16 real columns as 8 complex lines, unpacked into the half spectrum.
-template <int NY>
+template <int NY, class T>
 __global__ void __launch_bounds__(FT) k_div_ffty(Dims d, Fields f, const Scalars* __restrict__ s,
                                                  const double2* __restrict__ tw) {
   constexpr int TXC = 16, NL = 8, LS = NY + 1, MY = NY / 2 + 1;
   __shared__ double2 buf[NL * LS];
+  const T* __restrict__ ut = reinterpret_cast<const T*>(f.ut);
+  const T* __restrict__ vt = reinterpret_cast<const T*>(f.vt);
+  const T* __restrict__ wt = reinterpret_cast<const T*>(f.wt);
   const int i0 = blockIdx.x * TXC;
   const int k = blockIdx.y;
   const int kp = (k + 1 == d.nz) ? 0 : k + 1;
@@ -178,8 +181,11 @@ __global__ void __launch_bounds__(FT) k_div_ffty(Dims d, Fields f, const Scalars
     if (i < d.nx) {
       const int jp = (j + 1 == NY) ? 0 : j + 1;
       const long long c = fidx(d, i, j, k);
-      r = (((f.ut[c + 1] - f.ut[c]) + (f.vt[fidx(d, i, jp, k)] - f.vt[c])) +
-           (f.wt[fidx(d, i, j, kp)] - f.wt[c])) / d.h / dt;
+      // boundary faces: the inlet from u, the outlet from the FP64 plane
+      const double u1 = (i + 1 == d.nx) ? f.bnd[j + (long long)NY * k] : (double)ut[c + 1];
+      const double u0 = (i == 0) ? f.u[c] : (double)ut[c];
+      r = (((u1 - u0) + ((double)vt[fidx(d, i, jp, k)] - (double)vt[c])) +
+           ((double)wt[fidx(d, i, j, kp)] - (double)wt[c])) / d.h / dt;
     }
     double2* slot = &buf[(ix >> 1) * LS + j];
     if (ix & 1)
@@ -462,37 +468,45 @@ constexpr int PBX = 64, PBY = 4, PKZ = 16;
 // and the projected w of plane k+1 are reused by plane k+1), pressure update,
 // and the per-block maximum of the cell speed |u_c| + |v_c| + |w_c| (face
 // means of the projected field).  mode 1 (initial projection) leaves p.
+template <class T>
 __global__ void __launch_bounds__(PBX* PBY) k_project(Dims d, Fields f, Scalars* s, int mode) {
   const int i = blockIdx.x * PBX + threadIdx.x;
   const int j = blockIdx.y * PBY + threadIdx.y;
   const int kb = blockIdx.z * PKZ;
   const int ke = min(kb + PKZ, d.nz);
+  const T* __restrict__ ut = reinterpret_cast<const T*>(f.ut);
+  const T* __restrict__ vt = reinterpret_cast<const T*>(f.vt);
+  const T* __restrict__ wt = reinterpret_cast<const T*>(f.wt);
   double smax = 0.0;
   if (i < d.nx && j < d.ny) {
     const int nx = d.nx;
+    const long long nplane = (long long)d.ny * d.nz;
     const int jm = j == 0 ? d.ny - 1 : j - 1, jp = j == d.ny - 1 ? 0 : j + 1;
     const double dt = s->dt, inv_h = d.inv_h;
     const int km0 = kb == 0 ? d.nz - 1 : kb - 1;
     double ph_c = f.phi[fidx(d, i, j, kb)];
-    double wk = f.wt[fidx(d, i, j, kb)] - dt * (ph_c - f.phi[fidx(d, i, j, km0)]) * inv_h;
+    double wk = (double)wt[fidx(d, i, j, kb)] - dt * (ph_c - f.phi[fidx(d, i, j, km0)]) * inv_h;
     for (int k = kb; k < ke; ++k) {
       const int kp = k == d.nz - 1 ? 0 : k + 1;
       const long long c = fidx(d, i, j, k);
       const long long ckp = fidx(d, i, j, kp);
       const double ph_p = f.phi[ckp];
-      const double wkp = f.wt[ckp] - dt * (ph_p - ph_c) * inv_h;
-      const double ui = (i >= 1) ? f.ut[c] - dt * (ph_c - f.phi[c - 1]) * inv_h : f.ut[c];
-      const double uip = (i + 1 <= nx - 1) ? f.ut[c + 1] - dt * (f.phi[c + 1] - ph_c) * inv_h : f.ut[c + 1];
+      const double wkp = (double)wt[ckp] - dt * (ph_p - ph_c) * inv_h;
+      // inlet face keeps U (read from u), outlet face keeps u~ (FP64 plane)
+      const double ui = (i >= 1) ? (double)ut[c] - dt * (ph_c - f.phi[c - 1]) * inv_h : f.u[c];
+      const long long qb = j + (long long)d.ny * k;
+      const double uip = (i + 1 <= nx - 1) ? (double)ut[c + 1] - dt * (f.phi[c + 1] - ph_c) * inv_h
+                                           : f.bnd[qb];
       const long long cjm = fidx(d, i, jm, k), cjp = fidx(d, i, jp, k);
-      const double vj = f.vt[c] - dt * (ph_c - f.phi[cjm]) * inv_h;
-      const double vjp = f.vt[cjp] - dt * (f.phi[cjp] - ph_c) * inv_h;
+      const double vj = (double)vt[c] - dt * (ph_c - f.phi[cjm]) * inv_h;
+      const double vjp = (double)vt[cjp] - dt * (f.phi[cjp] - ph_c) * inv_h;
       f.u[c] = ui;
       f.v[c] = vj;
       f.w[c] = wk;
       if (i == nx - 1) {
-        f.u[c + 1] = uip;          // outlet face keeps u~
-        f.v[c + 1] = f.vt[c + 1];  // outlet ghosts keep their provisional values
-        f.w[c + 1] = f.wt[c + 1];
+        f.u[c + 1] = uip;                  // outlet face keeps u~
+        f.v[c + 1] = f.bnd[nplane + qb];   // outlet ghosts keep their provisional values
+        f.w[c + 1] = f.bnd[2 * nplane + qb];
       }
       if (mode == 0) f.p[c] = f.p[c] + ph_c;
       double speed = fabs(0.5 * (ui + uip)) + fabs(0.5 * (vj + vjp)) + fabs(0.5 * (wk + wkp));
@@ -517,7 +531,28 @@ __global__ void __launch_bounds__(PBX* PBY) k_project(Dims d, Fields f, Scalars*
   }
 }
 
+// u~ := u (in the storage type of u~), used before the initial projection.
+template <class T>
+__global__ void k_state_to_tilde(Dims d, Fields f) {
+  T* ut = reinterpret_cast<T*>(f.ut);
+  T* vt = reinterpret_cast<T*>(f.vt);
+  T* wt = reinterpret_cast<T*>(f.wt);
+  for (long long q = (long long)blockIdx.x * blockDim.x + threadIdx.x; q < d.FS;
+       q += (long long)gridDim.x * blockDim.x) {
+    ut[q] = (T)f.u[q];
+    vt[q] = (T)f.v[q];
+    wt[q] = (T)f.w[q];
+  }
+}
+
 }  // namespace
+
+void launch_state_to_tilde(const Dims& d, const Fields& f, hipStream_t st) {
+  if (d.mixed)
+    hipLaunchKernelGGL(k_state_to_tilde<float>, dim3(4096), dim3(256), 0, st, d, f);
+  else
+    hipLaunchKernelGGL(k_state_to_tilde<double>, dim3(4096), dim3(256), 0, st, d, f);
+}
 
 bool fft_size_supported(int n) {
   switch (n) {
@@ -549,9 +584,15 @@ bool fft_size_supported(int n) {
 void launch_div_ffty(const Dims& d, const Fields& f, const Scalars* s, const double2* tw_y,
                      hipStream_t st) {
   dim3 grid((d.nx + 15) / 16, d.nz);
-#define CALL(NY) hipLaunchKernelGGL(k_div_ffty<NY>, grid, dim3(FT), 0, st, d, f, s, tw_y)
-  IBDNS_FFT_SWITCH(d.ny, CALL)
+  if (d.mixed) {
+#define CALL(NY) hipLaunchKernelGGL((k_div_ffty<NY, float>), grid, dim3(FT), 0, st, d, f, s, tw_y)
+    IBDNS_FFT_SWITCH(d.ny, CALL)
 #undef CALL
+  } else {
+#define CALL(NY) hipLaunchKernelGGL((k_div_ffty<NY, double>), grid, dim3(FT), 0, st, d, f, s, tw_y)
+    IBDNS_FFT_SWITCH(d.ny, CALL)
+#undef CALL
+  }
 }
 
 void launch_fftz(const Dims& d, const Fields& f, const double2* tw_z, int sign, hipStream_t st) {
@@ -605,7 +646,10 @@ int project_blocks(const Dims& d) {
 
 void launch_project(const Dims& d, const Fields& f, Scalars* s, int mode, hipStream_t st) {
   dim3 grid((d.nx + PBX - 1) / PBX, (d.ny + PBY - 1) / PBY, (d.nz + PKZ - 1) / PKZ);
-  hipLaunchKernelGGL(k_project, grid, dim3(PBX, PBY), 0, st, d, f, s, mode);
+  if (d.mixed)
+    hipLaunchKernelGGL(k_project<float>, grid, dim3(PBX, PBY), 0, st, d, f, s, mode);
+  else
+    hipLaunchKernelGGL(k_project<double>, grid, dim3(PBX, PBY), 0, st, d, f, s, mode);
 }
 
 }  // namespace ibdns

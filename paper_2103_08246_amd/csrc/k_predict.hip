@@ -14,15 +14,23 @@ namespace {
 constexpr int TX = 64, TY = 8, KZ = 16;
 constexpr int LX = TX + 2, LY = TY + 2, LP = LX * LY;   // LDS plane with a 1-cell x-y halo
 
-__device__ __forceinline__ double sq(double a) { return a * a; }
+template <class T>
+__device__ __forceinline__ T sq(T a) { return a * a; }
 __device__ __forceinline__ int wrapi(int a, int n) { return a < 0 ? a + n : (a >= n ? a - n : a); }
 
 // One workgroup per 64 x 8 (x, y) tile and KZ planes in z.  u, v, w of planes
 // k-1, k, k+1 and p of plane k sit in LDS (ring of three planes, refilled one
 // plane per step); each thread evaluates u face i (i >= 1), v cell i and w
 // cell i of its column.
+template <class T>
 __global__ void __launch_bounds__(TX* TY) k_predict(Dims d, Fields f, const Scalars* __restrict__ s) {
-  __shared__ double su[3][LP], sv[3][LP], sw[3][LP], spp[LP];
+  __shared__ T su[3][LP], sv[3][LP], sw[3][LP], spp[LP];
+  T* __restrict__ hu = reinterpret_cast<T*>(f.hu);
+  T* __restrict__ hv = reinterpret_cast<T*>(f.hv);
+  T* __restrict__ hw = reinterpret_cast<T*>(f.hw);
+  T* __restrict__ ut = reinterpret_cast<T*>(f.ut);
+  T* __restrict__ vt = reinterpret_cast<T*>(f.vt);
+  T* __restrict__ wt = reinterpret_cast<T*>(f.wt);
   const int tx = threadIdx.x, ty = threadIdx.y, tid = ty * TX + tx;
   const int i0 = blockIdx.x * TX, j0 = blockIdx.y * TY;
   const int kb = blockIdx.z * KZ, ke = min(kb + KZ, d.nz);
@@ -40,12 +48,12 @@ __global__ void __launch_bounds__(TX* TY) k_predict(Dims d, Fields f, const Scal
     for (int e = tid; e < LP; e += TX * TY) {
       const int lx = e % LX, ly = e / LX;
       const int gi = i0 - 1 + lx, gj = wrapi(j0 - 1 + ly, d.ny);
-      double a = 0.0, b = 0.0, c = 0.0;
+      T a = 0, b = 0, c = 0;
       if (gi >= 0 && gi <= nx) {
         const long long o = fidx(d, gi, gj, kk);
-        a = u[o];
-        b = v[o];
-        c = w[o];
+        a = (T)u[o];
+        b = (T)v[o];
+        c = (T)w[o];
       }
       su[slot][e] = a;
       sv[slot][e] = b;
@@ -56,23 +64,25 @@ __global__ void __launch_bounds__(TX* TY) k_predict(Dims d, Fields f, const Scal
     for (int e = tid; e < LP; e += TX * TY) {
       const int lx = e % LX, ly = e / LX;
       const int gi = i0 - 1 + lx, gj = wrapi(j0 - 1 + ly, d.ny);
-      spp[e] = (gi >= 0 && gi < nx) ? p[fidx(d, gi, gj, kk)] : 0.0;
+      spp[e] = (gi >= 0 && gi < nx) ? (T)p[fidx(d, gi, gj, kk)] : (T)0;
     }
   };
 
-  const double dt = s->dt;
-  const double omega = dt / s->dt_prev;
-  const double c1 = 1.0 + 0.5 * omega;
-  const double c2 = 0.5 * omega;
+  const double dt64 = s->dt;
+  const double omega = dt64 / s->dt_prev;
+  const T dt = (T)dt64;
+  const T c1 = (T)(1.0 + 0.5 * omega);
+  const T c2 = (T)(0.5 * omega);
   const bool first = s->first != 0;
-  const double inv_h = d.inv_h;
-  const double c_d = d.nu / (d.h * d.h);
+  const T inv_h = (T)d.inv_h;
+  const T c_d = (T)(d.nu / (d.h * d.h));
+  const T half = (T)0.5, two = (T)2;
 
   load_plane(kb - 1, 0);
   load_plane(kb, 1);
   load_plane(kb + 1, 2);
   load_p(kb);
-  double p_km = active ? p[fidx(d, i, j, wrapi(kb - 1, d.nz))] : 0.0;
+  T p_km = active ? (T)p[fidx(d, i, j, wrapi(kb - 1, d.nz))] : (T)0;
   __syncthreads();
 
   const int o0 = (ty + 1) * LX + (tx + 1);
@@ -81,73 +91,73 @@ __global__ void __launch_bounds__(TX* TY) k_predict(Dims d, Fields f, const Scal
     auto U = [&](int dx, int dy, int sl) { return su[sl][o0 + dy * LX + dx]; };
     auto V = [&](int dx, int dy, int sl) { return sv[sl][o0 + dy * LX + dx]; };
     auto W = [&](int dx, int dy, int sl) { return sw[sl][o0 + dy * LX + dx]; };
-    const double p_c = spp[o0];
+    const T p_c = spp[o0];
     if (active) {
       const long long c = fidx(d, i, j, k);
       // ---------------- u face i ----------------
       if (i >= 1) {
-        const double u0 = U(0, 0, sc);
-        const double uxm = U(-1, 0, sc), uxp = U(1, 0, sc);
-        const double uym = U(0, -1, sc), uyp = U(0, 1, sc);
-        const double uzm = U(0, 0, sm), uzp = U(0, 0, sn);
-        const double fxx_p = sq(0.5 * (u0 + uxp));
-        const double fxx_m = sq(0.5 * (uxm + u0));
-        const double fxy_0 = 0.5 * (uym + u0) * (0.5 * (V(-1, 0, sc) + V(0, 0, sc)));
-        const double fxy_p = 0.5 * (u0 + uyp) * (0.5 * (V(-1, 1, sc) + V(0, 1, sc)));
-        const double fxz_0 = 0.5 * (uzm + u0) * (0.5 * (W(-1, 0, sc) + W(0, 0, sc)));
-        const double fxz_p = 0.5 * (u0 + uzp) * (0.5 * (W(-1, 0, sn) + W(0, 0, sn)));
-        const double adv = ((fxx_p - fxx_m) + (fxy_p - fxy_0) + (fxz_p - fxz_0)) * inv_h;
-        const double lap = (uxp + uxm - 2.0 * u0) + (uyp + uym - 2.0 * u0) + (uzp + uzm - 2.0 * u0);
-        const double H = -adv + c_d * lap;
-        const double Hold = first ? H : f.hu[c];
-        f.hu[c] = H;
-        const double gp = (p_c - spp[o0 - 1]) * inv_h;
-        f.ut[c] = u0 + dt * (c1 * H - c2 * Hold - gp);
+        const T u0 = U(0, 0, sc);
+        const T uxm = U(-1, 0, sc), uxp = U(1, 0, sc);
+        const T uym = U(0, -1, sc), uyp = U(0, 1, sc);
+        const T uzm = U(0, 0, sm), uzp = U(0, 0, sn);
+        const T fxx_p = sq(half * (u0 + uxp));
+        const T fxx_m = sq(half * (uxm + u0));
+        const T fxy_0 = half * (uym + u0) * (half * (V(-1, 0, sc) + V(0, 0, sc)));
+        const T fxy_p = half * (u0 + uyp) * (half * (V(-1, 1, sc) + V(0, 1, sc)));
+        const T fxz_0 = half * (uzm + u0) * (half * (W(-1, 0, sc) + W(0, 0, sc)));
+        const T fxz_p = half * (u0 + uzp) * (half * (W(-1, 0, sn) + W(0, 0, sn)));
+        const T adv = ((fxx_p - fxx_m) + (fxy_p - fxy_0) + (fxz_p - fxz_0)) * inv_h;
+        const T lap = (uxp + uxm - two * u0) + (uyp + uym - two * u0) + (uzp + uzm - two * u0);
+        const T H = -adv + c_d * lap;
+        const T Hold = first ? H : hu[c];
+        hu[c] = H;
+        const T gp = (p_c - spp[o0 - 1]) * inv_h;
+        ut[c] = u0 + dt * (c1 * H - c2 * Hold - gp);
       } else {
-        f.ut[c] = U(0, 0, sc);  // inlet face keeps U
-        f.hu[c] = 0.0;
+        ut[c] = U(0, 0, sc);  // inlet face keeps U
+        hu[c] = (T)0;
       }
       // ---------------- v cell i ----------------
       {
-        const double v0 = V(0, 0, sc);
-        const double vxm = i == 0 ? (hook ? v0 : -v0) : V(-1, 0, sc);
-        const double vxp = (i == nx - 1 && hook) ? v0 : V(1, 0, sc);  // i+1 = nx: ghost
-        const double vym = V(0, -1, sc), vyp = V(0, 1, sc);
-        const double vzm = V(0, 0, sm), vzp = V(0, 0, sn);
-        const double fxy_p = 0.5 * (U(1, -1, sc) + U(1, 0, sc)) * (0.5 * (v0 + vxp));
-        const double fxy_0 = 0.5 * (U(0, -1, sc) + U(0, 0, sc)) * (0.5 * (vxm + v0));
-        const double fyy_0 = sq(0.5 * (v0 + vyp));
-        const double fyy_m = sq(0.5 * (vym + v0));
-        const double fyz_0 = 0.5 * (vzm + v0) * (0.5 * (W(0, -1, sc) + W(0, 0, sc)));
-        const double fyz_p = 0.5 * (v0 + vzp) * (0.5 * (W(0, -1, sn) + W(0, 0, sn)));
-        const double adv = ((fxy_p - fxy_0) + (fyy_0 - fyy_m) + (fyz_p - fyz_0)) * inv_h;
-        const double lap = (vxp + vxm - 2.0 * v0) + (vyp + vym - 2.0 * v0) + (vzp + vzm - 2.0 * v0);
-        const double H = -adv + c_d * lap;
-        const double Hold = first ? H : f.hv[c];
-        f.hv[c] = H;
-        const double gp = (p_c - spp[o0 - LX]) * inv_h;
-        f.vt[c] = v0 + dt * (c1 * H - c2 * Hold - gp);
+        const T v0 = V(0, 0, sc);
+        const T vxm = i == 0 ? (hook ? v0 : -v0) : V(-1, 0, sc);
+        const T vxp = (i == nx - 1 && hook) ? v0 : V(1, 0, sc);  // i+1 = nx: ghost
+        const T vym = V(0, -1, sc), vyp = V(0, 1, sc);
+        const T vzm = V(0, 0, sm), vzp = V(0, 0, sn);
+        const T fxy_p = half * (U(1, -1, sc) + U(1, 0, sc)) * (half * (v0 + vxp));
+        const T fxy_0 = half * (U(0, -1, sc) + U(0, 0, sc)) * (half * (vxm + v0));
+        const T fyy_0 = sq(half * (v0 + vyp));
+        const T fyy_m = sq(half * (vym + v0));
+        const T fyz_0 = half * (vzm + v0) * (half * (W(0, -1, sc) + W(0, 0, sc)));
+        const T fyz_p = half * (v0 + vzp) * (half * (W(0, -1, sn) + W(0, 0, sn)));
+        const T adv = ((fxy_p - fxy_0) + (fyy_0 - fyy_m) + (fyz_p - fyz_0)) * inv_h;
+        const T lap = (vxp + vxm - two * v0) + (vyp + vym - two * v0) + (vzp + vzm - two * v0);
+        const T H = -adv + c_d * lap;
+        const T Hold = first ? H : hv[c];
+        hv[c] = H;
+        const T gp = (p_c - spp[o0 - LX]) * inv_h;
+        vt[c] = v0 + dt * (c1 * H - c2 * Hold - gp);
       }
       // ---------------- w cell i ----------------
       {
-        const double w0 = W(0, 0, sc);
-        const double wxm = i == 0 ? (hook ? w0 : -w0) : W(-1, 0, sc);
-        const double wxp = (i == nx - 1 && hook) ? w0 : W(1, 0, sc);
-        const double wym = W(0, -1, sc), wyp = W(0, 1, sc);
-        const double wzm = W(0, 0, sm), wzp = W(0, 0, sn);
-        const double fxz_p = 0.5 * (U(1, 0, sm) + U(1, 0, sc)) * (0.5 * (w0 + wxp));
-        const double fxz_0 = 0.5 * (U(0, 0, sm) + U(0, 0, sc)) * (0.5 * (wxm + w0));
-        const double fyz_p = 0.5 * (V(0, 1, sm) + V(0, 1, sc)) * (0.5 * (w0 + wyp));
-        const double fyz_0 = 0.5 * (V(0, 0, sm) + V(0, 0, sc)) * (0.5 * (wym + w0));
-        const double fzz_0 = sq(0.5 * (w0 + wzp));
-        const double fzz_m = sq(0.5 * (wzm + w0));
-        const double adv = ((fxz_p - fxz_0) + (fyz_p - fyz_0) + (fzz_0 - fzz_m)) * inv_h;
-        const double lap = (wxp + wxm - 2.0 * w0) + (wyp + wym - 2.0 * w0) + (wzp + wzm - 2.0 * w0);
-        const double H = -adv + c_d * lap;
-        const double Hold = first ? H : f.hw[c];
-        f.hw[c] = H;
-        const double gp = (p_c - p_km) * inv_h;
-        f.wt[c] = w0 + dt * (c1 * H - c2 * Hold - gp);
+        const T w0 = W(0, 0, sc);
+        const T wxm = i == 0 ? (hook ? w0 : -w0) : W(-1, 0, sc);
+        const T wxp = (i == nx - 1 && hook) ? w0 : W(1, 0, sc);
+        const T wym = W(0, -1, sc), wyp = W(0, 1, sc);
+        const T wzm = W(0, 0, sm), wzp = W(0, 0, sn);
+        const T fxz_p = half * (U(1, 0, sm) + U(1, 0, sc)) * (half * (w0 + wxp));
+        const T fxz_0 = half * (U(0, 0, sm) + U(0, 0, sc)) * (half * (wxm + w0));
+        const T fyz_p = half * (V(0, 1, sm) + V(0, 1, sc)) * (half * (w0 + wyp));
+        const T fyz_0 = half * (V(0, 0, sm) + V(0, 0, sc)) * (half * (wym + w0));
+        const T fzz_0 = sq(half * (w0 + wzp));
+        const T fzz_m = sq(half * (wzm + w0));
+        const T adv = ((fxz_p - fxz_0) + (fyz_p - fyz_0) + (fzz_0 - fzz_m)) * inv_h;
+        const T lap = (wxp + wxm - two * w0) + (wyp + wym - two * w0) + (wzp + wzm - two * w0);
+        const T H = -adv + c_d * lap;
+        const T Hold = first ? H : hw[c];
+        hw[c] = H;
+        const T gp = (p_c - p_km) * inv_h;
+        wt[c] = w0 + dt * (c1 * H - c2 * Hold - gp);
       }
     }
     p_km = p_c;
@@ -163,8 +173,12 @@ __global__ void __launch_bounds__(TX* TY) k_predict(Dims d, Fields f, const Scal
 constexpr int OB = 256;
 
 // Convective outflow on the outlet plane (u at i = nx, v and w ghosts at
-// i = nx; the hook keeps the ghosts), plus per-block partial sums of u~ at the
-// outlet and of u at the inlet.
+// i = nx; the test hook keeps the ghosts) into the FP64 boundary planes
+// f.bnd (u~, v~, w~ at i = nx), plus per-block partial sums of u~ at the
+// outlet and of u at the inlet.  update == 0 (initial projection) only copies
+// the current values and sums.  With T = double the provisional arrays also
+// receive the outlet values.
+template <class T>
 __global__ void __launch_bounds__(OB) k_outlet(Dims d, Fields f, const Scalars* __restrict__ s,
                                                int update) {
   const int tid = threadIdx.x;
@@ -176,23 +190,29 @@ __global__ void __launch_bounds__(OB) k_outlet(Dims d, Fields f, const Scalars* 
     const int j = (int)(q % d.ny), k = (int)(q / d.ny);
     const double c = s->dt * d.u_in / d.h;
     const long long o = fidx(d, nx, j, k), o1 = fidx(d, nx - 1, j, k);
-    const double un = f.u[o];
-    const double ut = update ? un - c * (un - f.u[o1]) : f.ut[o];
-    f.ut[o] = ut;
-    if (update) f.hu[o] = 0.0;
-    if (!update) {
-      // initial projection: sums only
-    } else if (d.flags & 1u) {
-      f.vt[o] = f.v[o];
-      f.wt[o] = f.w[o];
+    const double un = f.u[o], vn = f.v[o], wn = f.w[o];
+    double ut, vt, wt;
+    if (!update || (d.flags & 1u)) {
+      ut = update ? un - c * (un - f.u[o1]) : un;
+      vt = vn;
+      wt = wn;
     } else {
-      const double vn = f.v[o], wn = f.w[o];
-      f.vt[o] = vn - c * (vn - f.v[o1]);
-      f.wt[o] = wn - c * (wn - f.w[o1]);
+      ut = un - c * (un - f.u[o1]);
+      vt = vn - c * (vn - f.v[o1]);
+      wt = wn - c * (wn - f.w[o1]);
+    }
+    f.bnd[q] = ut;
+    f.bnd[nplane + q] = vt;
+    f.bnd[2 * nplane + q] = wt;
+    if (sizeof(T) == sizeof(double)) {
+      f.ut[o] = ut;
+      f.vt[o] = vt;
+      f.wt[o] = wt;
     }
     if (update) {
-      f.hv[o] = 0.0;
-      f.hw[o] = 0.0;
+      reinterpret_cast<T*>(f.hu)[o] = (T)0;
+      reinterpret_cast<T*>(f.hv)[o] = (T)0;
+      reinterpret_cast<T*>(f.hw)[o] = (T)0;
     }
     sout = ut;
     sin_ = f.u[fidx(d, 0, j, k)];
@@ -214,8 +234,10 @@ __global__ void __launch_bounds__(OB) k_outlet(Dims d, Fields f, const Scalars* 
   }
 }
 
-// corr = (sum u_0 - sum u~_nx) / (ny nz) added to u~ at the outlet; every block
-// reduces the partials in the same fixed order.
+// corr = (sum u_0 - sum u~_nx) / (ny nz) added to u~ at the outlet (FP64
+// plane; also the FP64 provisional array); every block reduces the partials
+// in the same fixed order.
+template <class T>
 __global__ void __launch_bounds__(OB) k_flux_apply(Dims d, Fields f, Scalars* s, int nparts) {
   const int tid = threadIdx.x;
   __shared__ double ra[OB], rb[OB];
@@ -238,8 +260,12 @@ __global__ void __launch_bounds__(OB) k_flux_apply(Dims d, Fields f, Scalars* s,
   if (blockIdx.x == 0 && tid == 0) s->corr = corr;
   const long long nplane = (long long)d.ny * d.nz;
   for (long long q = (long long)blockIdx.x * OB + tid; q < nplane; q += (long long)gridDim.x * OB) {
-    const int j = (int)(q % d.ny), k = (int)(q / d.ny);
-    f.ut[fidx(d, d.nx, j, k)] += corr;
+    const double v = f.bnd[q] + corr;
+    f.bnd[q] = v;
+    if (sizeof(T) == sizeof(double)) {
+      const int j = (int)(q % d.ny), k = (int)(q / d.ny);
+      f.ut[fidx(d, d.nx, j, k)] = v;
+    }
   }
 }
 
@@ -249,17 +275,26 @@ int outlet_blocks(const Dims& d) { return (int)(((long long)d.ny * d.nz + OB - 1
 
 void launch_predict(const Dims& d, const Fields& f, const Scalars* s, hipStream_t st) {
   dim3 grid((d.nx + TX - 1) / TX, (d.ny + TY - 1) / TY, (d.nz + KZ - 1) / KZ);
-  hipLaunchKernelGGL(k_predict, grid, dim3(TX, TY), 0, st, d, f, s);
+  if (d.mixed)
+    hipLaunchKernelGGL(k_predict<float>, grid, dim3(TX, TY), 0, st, d, f, s);
+  else
+    hipLaunchKernelGGL(k_predict<double>, grid, dim3(TX, TY), 0, st, d, f, s);
 }
 
 void launch_outlet(const Dims& d, const Fields& f, const Scalars* s, int nblocks, int update,
                    hipStream_t st) {
-  hipLaunchKernelGGL(k_outlet, dim3(nblocks), dim3(OB), 0, st, d, f, s, update);
+  if (d.mixed)
+    hipLaunchKernelGGL(k_outlet<float>, dim3(nblocks), dim3(OB), 0, st, d, f, s, update);
+  else
+    hipLaunchKernelGGL(k_outlet<double>, dim3(nblocks), dim3(OB), 0, st, d, f, s, update);
 }
 
 void launch_flux_apply(const Dims& d, const Fields& f, Scalars* s, int nblocks, hipStream_t st) {
   int g = nblocks < 64 ? nblocks : 64;
-  hipLaunchKernelGGL(k_flux_apply, dim3(g), dim3(OB), 0, st, d, f, s, nblocks);
+  if (d.mixed)
+    hipLaunchKernelGGL(k_flux_apply<float>, dim3(g), dim3(OB), 0, st, d, f, s, nblocks);
+  else
+    hipLaunchKernelGGL(k_flux_apply<double>, dim3(g), dim3(OB), 0, st, d, f, s, nblocks);
 }
 
 }  // namespace ibdns

@@ -35,7 +35,9 @@ def test_workspace_size_validation():
            ib.make_domain(64, 32, 32, 4.0, 2.5, 2.0, 200.0, dt=1e-3),     # anisotropic h
            ib.make_domain(4, 32, 32, 0.25, 2.0, 2.0, 200.0, dt=1e-3),     # nx too small
            ib.make_domain(64, 32, 32, 4.0, 2.0, 2.0, 200.0, dt=0.0, cfl=1.5),
-           ib.make_domain(64, 32, 32, 4.0, 2.0, 2.0, 200.0, dt=1e-3, precision=ib.MIXED)]
+           ib.make_domain(64, 32, 32, 4.0, 2.0, 2.0, 200.0, dt=1e-3, precision=7)]
+    assert ib.workspace_size(ib.make_domain(64, 32, 32, 4.0, 2.0, 2.0, 200.0, dt=1e-3,
+                                            precision=ib.MIXED), 0, 16) == n
     for d in bad:
         with pytest.raises(ib.IbdnsError) as e:
             ib.workspace_size(d)

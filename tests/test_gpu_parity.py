@@ -77,6 +77,7 @@ def test_projection_stage_random(dims):
         ut = 1.0 + 0.3 * rng.standard_normal((nz, ny, nx + 1))
         vt = 0.3 * rng.standard_normal((nz, ny, nx + 1))
         wt = 0.3 * rng.standard_normal((nz, ny, nx + 1))
+        ut[..., 0] = 1.0          # the inlet face of u~ is always U (state u at i = 0)
         from oracle import fluid
         fluid.flux_correct(ut)
         for arr, a in ((ib.ARR_UT, ut), (ib.ARR_VT, vt[..., :nx]), (ib.ARR_WT, wt[..., :nx])):
