@@ -58,6 +58,40 @@ def make_workload(name: str):
     raise SystemExit(f"unknown workload {name}")
 
 
+def batch_leg(ib, torch, ws_list, precision, steps, warmup, keep=False):
+    """Run an ensemble through one batch (autotuned tiles, hipGraph replay)."""
+    import synth
+    runs = []
+    for w in ws_list:
+        noise = synth.ic_noise(w)
+        bars = synth.bar_points(w) if w.grid is not None else None
+        X0 = synth.flag_reference(w) if w.flag is not None else None
+        runs.append(ib.create(ib.domain_from(w, precision=precision), noise, points=bars,
+                              flag=ib.flag_from(w.flag) if w.flag is not None else None,
+                              flag_X0=X0))
+    b = ib.Batch(runs)
+    variant = b.autotune()
+    b.use_graph(True)
+    b.step(warmup)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    b.step(steps)
+    torch.cuda.synchronize()
+    wall = time.perf_counter() - t0
+    for r in runs:
+        ib.sync(r.ctx)
+    cells = sum(w.cells for w in ws_list)
+    out = {"runs": len(ws_list), "cells": cells, "steps": steps,
+           "value": round(cells * steps / wall / 1e6, 1), "ms_per_step": round(wall * 1e3 / steps, 4),
+           "precision": "mixed" if precision else "fp64", "graph": True, "tile_variant": variant}
+    if keep:
+        return out, b, runs
+    b.close()
+    for r in runs:
+        r.close()
+    return out, None, None
+
+
 def cpu_baseline(w, budget_s: float = 20.0) -> dict:
     """Time the oracle (as it stands) on a bounded sample of the workload.
 
@@ -117,6 +151,8 @@ def main():
     ap.add_argument("--workload", default="grid_flag_768x384x384_re1000")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-mixed", action="store_true")
+    ap.add_argument("--no-batch", action="store_true")
+    ap.add_argument("--batch-steps", type=int, default=20)
     ap.add_argument("--cpu-budget", type=float, default=20.0)
     args = ap.parse_args()
     if args.gpus != 1:
@@ -206,6 +242,38 @@ def main():
         run_m.close()
     del noise
     run.close()
+    if not args.no_batch:
+        import synth as _s
+        ens24 = _s.ensemble_24()
+        res, _, _ = batch_leg(ib, torch, ens24, ib.FP64, args.batch_steps, 3)
+        res["workload"] = "ensemble 8x96x48x48 + 8x128x64x64 + 8x192x96x96, bars + 24x24 flags, Re 500"
+        print(f"# batch24 fp64: {res['ms_per_step']} ms/step", file=sys.stderr, flush=True)
+        out["batched"] = {"ensemble_24": res}
+        ens6 = _s.ensemble_6_384()
+        r64, b64, runs64 = batch_leg(ib, torch, ens6, ib.FP64, args.batch_steps, 3, keep=True)
+        rmx, bmx, runsmx = batch_leg(ib, torch, ens6, ib.MIXED, args.batch_steps, 3, keep=True)
+        errs, divs = [], []
+        for ra, rb, w6 in zip(runs64, runsmx, ens6):
+            a = ra.fields()
+            c = rb.fields()
+            num = sum(float(np.sum((x - y) ** 2)) for x, y in zip(c[:3], a[:3]))
+            den = sum(float(np.sum(y ** 2)) for y in a[:3])
+            errs.append((num / den) ** 0.5)
+            divs.append(max_divergence(c[0], c[1], c[2], w6.h))
+        for bb, rr in ((b64, runs64), (bmx, runsmx)):
+            bb.close()
+            for r in rr:
+                r.close()
+        rmx["speedup_vs_fp64_batch"] = round(r64["ms_per_step"] / rmx["ms_per_step"], 3)
+        rmx["vel_rel_l2_vs_fp64_max"] = max(errs)
+        rmx["max_abs_div"] = max(divs)
+        rmx["after_steps"] = args.batch_steps + 3
+        for r in (r64, rmx):
+            r["workload"] = "6 x 384x192x192, bars + 64x64 flags at 3..10 M, Re 1000"
+        print(f"# batch6: fp64 {r64['ms_per_step']} / mixed {rmx['ms_per_step']} ms/step",
+              file=sys.stderr, flush=True)
+        out["batched"]["ensemble_6_384_fp64"] = r64
+        out["batched"]["ensemble_6_384_mixed"] = rmx
     if not args.no_cpu_baseline:
         print("# timing the CPU oracle sample", file=sys.stderr, flush=True)
         out["cpu_baseline"] = cpu_baseline(w, args.cpu_budget)

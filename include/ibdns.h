@@ -141,6 +141,43 @@ int ibdns_destroy(ibdns_ctx* ctx);
 const char* ibdns_strerror(int status);
 
 /* ------------------------------------------------------------------------
+ * Batched ensembles: independent runs (uneven sizes allowed), each created by
+ * ibdns_init_domain + ibdns_set_geometry on the same stream and precision,
+ * advanced together.  Every stage is one launch over all runs, except the FFT
+ * and tridiagonal stages, which take one launch per distinct transform size.
+ * ---------------------------------------------------------------------- */
+
+typedef struct ibdns_batch ibdns_batch; /* opaque, library-owned host object */
+
+/* Device workspace bytes of a batch of n_runs (1..256) runs (run tables). */
+int ibdns_batch_workspace_size(int32_t n_runs, size_t* bytes);
+
+/* Create a batch over n_runs existing contexts (caller keeps them alive and
+ * does not step them individually meanwhile).  dev_ws: caller-owned device
+ * memory of at least ibdns_batch_workspace_size bytes, 256-byte aligned.
+ * EINVAL if the runs use different streams or precisions. */
+int ibdns_batch_create(ibdns_ctx* const* runs, int32_t n_runs, void* dev_ws, size_t ws_bytes,
+                       ibdns_batch** out);
+
+/* Advance every run of the batch by n_steps steps, asynchronously. */
+int ibdns_batch_step(ibdns_batch* b, int32_t n_steps);
+
+/* enable != 0: the next ibdns_batch_step captures one step into a hipGraph
+ * and every later step replays it; 0 drops the graph. */
+int ibdns_batch_use_graph(ibdns_batch* b, int32_t enable);
+
+/* Time every predictor tile shape over the whole batch and keep the fastest
+ * (*variant_out receives its index).  Only before the first step (the trial
+ * launches rewrite H): ESTATE otherwise. */
+int ibdns_batch_autotune(ibdns_batch* b, int32_t* variant_out);
+
+/* Single-run form of the tile-shape autotuner (same rule). */
+int ibdns_autotune(ibdns_ctx* ctx, int32_t* variant_out);
+
+/* Release the batch (not the runs, not the workspace). */
+int ibdns_batch_destroy(ibdns_batch* b);
+
+/* ------------------------------------------------------------------------
  * Diagnostic entry points (tests and profiling).
  * ---------------------------------------------------------------------- */
 

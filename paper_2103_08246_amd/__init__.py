@@ -28,7 +28,9 @@ EXPORTED = ("ibdns_workspace_size", "ibdns_init_domain", "ibdns_set_geometry", "
             "ibdns_sync", "ibdns_get_fields", "ibdns_get_flag", "ibdns_destroy",
             "ibdns_strerror", "ibdns_run_stage", "ibdns_get_array", "ibdns_set_array",
             "ibdns_get_scalars", "ibdns_set_time", "ibdns_get_maps", "ibdns_enable_timing",
-            "ibdns_kernel_times")
+            "ibdns_kernel_times", "ibdns_batch_workspace_size", "ibdns_batch_create",
+            "ibdns_batch_step", "ibdns_batch_use_graph", "ibdns_batch_autotune", "ibdns_autotune",
+            "ibdns_batch_destroy")
 
 
 class Domain(ctypes.Structure):
@@ -86,6 +88,14 @@ def _load():
     lib.ibdns_enable_timing.argtypes = [P, ctypes.c_int32]
     lib.ibdns_kernel_times.argtypes = [P, ctypes.c_int32, ctypes.POINTER(ctypes.c_char_p), D,
                                        ctypes.POINTER(ctypes.c_int64)]
+    lib.ibdns_batch_workspace_size.argtypes = [ctypes.c_int32, ctypes.POINTER(ctypes.c_size_t)]
+    lib.ibdns_batch_create.argtypes = [ctypes.POINTER(P), ctypes.c_int32, P, ctypes.c_size_t,
+                                       ctypes.POINTER(P)]
+    lib.ibdns_batch_step.argtypes = [P, ctypes.c_int32]
+    lib.ibdns_batch_use_graph.argtypes = [P, ctypes.c_int32]
+    lib.ibdns_batch_autotune.argtypes = [P, ctypes.POINTER(ctypes.c_int32)]
+    lib.ibdns_autotune.argtypes = [P, ctypes.POINTER(ctypes.c_int32)]
+    lib.ibdns_batch_destroy.argtypes = [P]
     return lib
 
 
@@ -285,3 +295,41 @@ def domain_from(w, precision=FP64, flags=0) -> Domain:
 def flag_from(f) -> FlagParams:
     """FlagParams from any object with ns, length, mass_ratio, bending, stretch, le_bc."""
     return FlagParams(f.ns, f.length, f.mass_ratio, f.bending, f.stretch, f.le_bc)
+
+
+def autotune(ctx) -> int:
+    v = ctypes.c_int32(-1)
+    _check(_lib.ibdns_autotune(ctx, ctypes.byref(v)), "autotune")
+    return v.value
+
+
+class Batch:
+    """Independent runs advanced together (one launch per stage over all runs)."""
+
+    def __init__(self, runs, device="cuda:0"):
+        import torch
+        self.runs = list(runs)
+        n = len(self.runs)
+        size = ctypes.c_size_t(0)
+        _check(_lib.ibdns_batch_workspace_size(n, ctypes.byref(size)), "batch_workspace_size")
+        self.ws = torch.empty(size.value, dtype=torch.uint8, device=device)
+        arr = (ctypes.c_void_p * n)(*[r.ctx.value for r in self.runs])
+        self.handle = ctypes.c_void_p()
+        _check(_lib.ibdns_batch_create(arr, n, ctypes.c_void_p(self.ws.data_ptr()), size.value,
+                                       ctypes.byref(self.handle)), "batch_create")
+
+    def autotune(self) -> int:
+        v = ctypes.c_int32(-1)
+        _check(_lib.ibdns_batch_autotune(self.handle, ctypes.byref(v)), "batch_autotune")
+        return v.value
+
+    def use_graph(self, on=True):
+        _check(_lib.ibdns_batch_use_graph(self.handle, 1 if on else 0), "batch_use_graph")
+
+    def step(self, n=1):
+        _check(_lib.ibdns_batch_step(self.handle, n), "batch_step")
+
+    def close(self):
+        if self.handle is not None and self.handle.value:
+            _check(_lib.ibdns_batch_destroy(self.handle), "batch_destroy")
+            self.handle = None

@@ -62,6 +62,7 @@ struct ibdns_ctx {
   int* bbox = nullptr;
   bool geometry_set = false;
   bool launch_failed = false;
+  int variant = 0;  // predictor tile shape
   bool stepped = false;
   // timing
   bool timing = false;
@@ -178,7 +179,7 @@ void rec_end(ibdns_ctx* c, const char* name, hipEvent_t a) {
   } while (0)
 
 void stage_predict(ibdns_ctx* c) {
-  TIMED(c, "predict", launch_predict(c->d, c->f, c->s, c->st));
+  TIMED(c, "predict", launch_predict(c->d, c->f, c->s, c->variant, c->st));
   TIMED(c, "outlet", launch_outlet(c->d, c->f, c->s, c->nparts, 1, c->st));
 }
 void stage_flux(ibdns_ctx* c) { TIMED(c, "flux_apply", launch_flux_apply(c->d, c->f, c->s, c->nparts, c->st)); }
@@ -869,6 +870,324 @@ int ibdns_kernel_times(ibdns_ctx* c, int32_t n, const char** names, double* tota
     if (launches) launches[q] = c->totals[q].second.second;
   }
   return m;
+}
+
+}  // extern "C"
+
+// ============================================================================
+// Batched ensembles: independent runs (uneven sizes) advanced together, one
+// launch per stage over all runs (one per distinct transform size for the
+// FFT and tridiagonal stages), optionally captured into a hipGraph.
+// ============================================================================
+
+struct ibdns_batch {
+  std::vector<ibdns_ctx*> runs;
+  hipStream_t st = nullptr;
+  int mixed = 0;
+  char* ws = nullptr;
+  size_t ws_bytes = 0, used = 0;
+  RunDesc* table = nullptr;
+  struct L {
+    BatchLaunch bl{};
+    int total = 0;
+    int key = 0;
+  };
+  std::vector<L> predict;  // one per tile variant
+  L outlet, flux, stencil, interp_bars, interp_flag, spread_csr, bbox, spread_tiles, project,
+      flag_prep, flag_bands, advance;
+  std::vector<L> div_g, fftz_g, tri_g, iffty_g;
+  int variant = 0;
+  bool use_graph = false;
+  hipGraph_t graph = nullptr;
+  hipGraphExec_t exec = nullptr;
+
+  template <class T>
+  T* carve(size_t count) {
+    size_t bytes = up(count * sizeof(T));
+    if (used + bytes > ws_bytes) return nullptr;
+    T* p = reinterpret_cast<T*>(ws + used);
+    used += bytes;
+    return p;
+  }
+};
+
+namespace {
+
+constexpr int BATCH_MAX_RUNS = 256;
+constexpr int BATCH_MAX_LAUNCHES = 64;
+
+RunDesc make_desc(ibdns_ctx* c) {
+  RunDesc r{};
+  r.d = c->d;
+  r.f = c->f;
+  r.s = c->s;
+  r.bars = c->bars;
+  for (int q = 0; q < 3; ++q) r.csr[q] = c->csr[q];
+  r.flag = c->flagpts;
+  r.bbox = c->bbox;
+  r.ntx = c->ntx;
+  r.nty = c->nty;
+  r.ntz = c->ntz;
+  r.fl = c->fl;
+  r.tw_y = c->tw_y;
+  r.tw_z = c->tw_z;
+  r.lam_y = c->lam_y;
+  r.lam_z = c->lam_z;
+  r.nparts = c->nparts;
+  r.nspeed = project_blocks(c->d);
+  r.has_flag = c->has_flag ? 1 : 0;
+  return r;
+}
+
+// Build one batched launch over the runs selected by `pick`, with per-run
+// block counts `nb`; the run-index and offset tables go to the batch
+// workspace.  Returns false if the workspace is exhausted.
+template <class Pick, class NB>
+bool make_launch(ibdns_batch* b, ibdns_batch::L& L, Pick pick, NB nb) {
+  std::vector<int> ridx, off;
+  int tot = 0;
+  for (int r = 0; r < (int)b->runs.size(); ++r) {
+    if (!pick(r)) continue;
+    const int n = nb(r);
+    if (n <= 0) continue;
+    ridx.push_back(r);
+    off.push_back(tot);
+    tot += n;
+  }
+  off.push_back(tot);
+  L.total = tot;
+  L.bl.runs = b->table;
+  L.bl.n = (int)ridx.size();
+  if (ridx.empty()) return true;
+  int* dr = b->carve<int>(ridx.size());
+  int* doff = b->carve<int>(off.size());
+  if (!dr || !doff) return false;
+  if (hipMemcpy(dr, ridx.data(), ridx.size() * sizeof(int), hipMemcpyHostToDevice) != hipSuccess ||
+      hipMemcpy(doff, off.data(), off.size() * sizeof(int), hipMemcpyHostToDevice) != hipSuccess)
+    return false;
+  L.bl.ridx = dr;
+  L.bl.off = doff;
+  return true;
+}
+
+template <class Key, class NB>
+bool make_groups(ibdns_batch* b, std::vector<ibdns_batch::L>& out, Key key, NB nb) {
+  std::vector<int> keys;
+  for (int r = 0; r < (int)b->runs.size(); ++r)
+    if (std::find(keys.begin(), keys.end(), key(r)) == keys.end()) keys.push_back(key(r));
+  for (int k : keys) {
+    ibdns_batch::L L;
+    L.key = k;
+    if (!make_launch(b, L, [&](int r) { return key(r) == k; }, nb)) return false;
+    out.push_back(L);
+  }
+  return true;
+}
+
+void batch_step_once(ibdns_batch* b, hipStream_t st) {
+  const int mx = b->mixed;
+  auto go = [](const ibdns_batch::L& L) { return L.bl.n > 0 && L.total > 0; };
+  const ibdns_batch::L& P = b->predict[b->variant];
+  if (go(P)) launch_predict_batch(P.bl, P.total, mx, b->variant, st);
+  if (go(b->outlet)) launch_outlet_batch(b->outlet.bl, b->outlet.total, mx, st);
+  if (go(b->flux)) launch_flux_apply_batch(b->flux.bl, b->flux.total, mx, st);
+  if (go(b->stencil)) launch_point_stencil_batch(b->stencil.bl, b->stencil.total, st);
+  if (go(b->interp_bars)) launch_point_interp_batch(b->interp_bars.bl, b->interp_bars.total, 0, mx, st);
+  if (go(b->interp_flag)) launch_point_interp_batch(b->interp_flag.bl, b->interp_flag.total, 1, mx, st);
+  if (go(b->spread_csr)) launch_spread_csr_batch(b->spread_csr.bl, b->spread_csr.total, mx, st);
+  if (go(b->bbox)) launch_point_bbox_batch(b->bbox.bl, b->bbox.total, st);
+  if (go(b->spread_tiles)) launch_spread_tiles_batch(b->spread_tiles.bl, b->spread_tiles.total, mx, st);
+  for (auto& L : b->div_g)
+    if (go(L)) launch_div_ffty_batch(L.bl, L.total, L.key, mx, st);
+  for (auto& L : b->fftz_g)
+    if (go(L)) launch_fftz_batch(L.bl, L.total, L.key, -1, st);
+  for (auto& L : b->tri_g)
+    if (go(L)) launch_tri_batch(L.bl, L.total, L.key, st);
+  for (auto& L : b->fftz_g)
+    if (go(L)) launch_fftz_batch(L.bl, L.total, L.key, 1, st);
+  for (auto& L : b->iffty_g)
+    if (go(L)) launch_iffty_batch(L.bl, L.total, L.key, st);
+  if (go(b->project)) launch_project_batch(b->project.bl, b->project.total, mx, st);
+  if (go(b->flag_bands))
+    launch_flag_batch(b->flag_prep.bl, b->flag_prep.total, b->flag_bands.bl, b->flag_bands.total, st);
+  if (go(b->advance)) launch_advance_batch(b->advance.bl, b->advance.total, st);
+}
+
+void batch_drop_graph(ibdns_batch* b) {
+  if (b->exec) hipGraphExecDestroy(b->exec);
+  if (b->graph) hipGraphDestroy(b->graph);
+  b->exec = nullptr;
+  b->graph = nullptr;
+}
+
+}  // namespace
+
+extern "C" {
+
+int ibdns_batch_workspace_size(int32_t n_runs, size_t* bytes) {
+  if (!bytes || n_runs < 1 || n_runs > BATCH_MAX_RUNS) return IBDNS_EINVAL;
+  *bytes = up(n_runs * sizeof(RunDesc)) + BATCH_MAX_LAUNCHES * 2 * up((n_runs + 1) * sizeof(int)) + ALIGN;
+  return IBDNS_OK;
+}
+
+int ibdns_batch_create(ibdns_ctx* const* runs, int32_t n_runs, void* dev_ws, size_t ws_bytes,
+                       ibdns_batch** out) {
+  if (!out) return IBDNS_EINVAL;
+  *out = nullptr;
+  size_t need = 0;
+  if (ibdns_batch_workspace_size(n_runs, &need) != IBDNS_OK || !runs) return IBDNS_EINVAL;
+  if (!dev_ws || (reinterpret_cast<uintptr_t>(dev_ws) % ALIGN) != 0) return IBDNS_EINVAL;
+  if (ws_bytes < need) return IBDNS_ENOMEM;
+  for (int r = 0; r < n_runs; ++r) {
+    if (!runs[r]) return IBDNS_EINVAL;
+    if (runs[r]->st != runs[0]->st || runs[r]->d.mixed != runs[0]->d.mixed) return IBDNS_EINVAL;
+    if (runs[r]->has_flag && flag_bands(runs[r]->fl.ns) > 64) return IBDNS_EINVAL;
+  }
+  ibdns_batch* b = new ibdns_batch();
+  b->runs.assign(runs, runs + n_runs);
+  b->st = runs[0]->st;
+  b->mixed = runs[0]->d.mixed;
+  b->ws = reinterpret_cast<char*>(dev_ws);
+  b->ws_bytes = ws_bytes;
+  b->table = b->carve<RunDesc>(n_runs);
+  std::vector<RunDesc> host(n_runs);
+  for (int r = 0; r < n_runs; ++r) host[r] = make_desc(runs[r]);
+  bool ok = b->table && hipMemcpy(b->table, host.data(), n_runs * sizeof(RunDesc), hipMemcpyHostToDevice) == hipSuccess;
+  auto all = [](int) { return true; };
+  auto R = [&](int r) -> ibdns_ctx* { return b->runs[r]; };
+  b->predict.resize(predict_variants());
+  for (int v = 0; v < predict_variants() && ok; ++v)
+    ok = make_launch(b, b->predict[v], all, [&](int r) { return predict_blocks(R(r)->d, v); });
+  ok = ok && make_launch(b, b->outlet, all, [&](int r) { return R(r)->nparts; });
+  ok = ok && make_launch(b, b->flux, all, [&](int r) { return flux_apply_blocks(R(r)->nparts); });
+  auto hasf = [&](int r) { return R(r)->has_flag; };
+  auto hasb = [&](int r) { return R(r)->nbars > 0; };
+  ok = ok && make_launch(b, b->stencil, hasf, [&](int r) { return stencil_blocks(R(r)->flagpts.n); });
+  ok = ok && make_launch(b, b->interp_bars, hasb, [&](int r) { return stencil_blocks(R(r)->bars.n); });
+  ok = ok && make_launch(b, b->interp_flag, hasf, [&](int r) { return stencil_blocks(R(r)->flagpts.n); });
+  ok = ok && make_launch(b, b->spread_csr, hasb, [&](int r) { return spread_csr_blocks(R(r)->csr); });
+  ok = ok && make_launch(b, b->bbox, hasf, [&](int) { return 3; });
+  ok = ok && make_launch(b, b->spread_tiles, hasf, [&](int r) { return 3 * R(r)->ntx * R(r)->nty * R(r)->ntz; });
+  ok = ok && make_groups(b, b->div_g, [&](int r) { return R(r)->d.ny; }, [&](int r) { return div_ffty_blocks(R(r)->d); });
+  ok = ok && make_groups(b, b->fftz_g, [&](int r) { return R(r)->d.nz; }, [&](int r) { return fftz_blocks(R(r)->d); });
+  ok = ok && make_groups(b, b->tri_g, [&](int r) { return tri_chunk(R(r)->d.nx); }, [&](int r) { return tri_blocks(R(r)->d); });
+  ok = ok && make_groups(b, b->iffty_g, [&](int r) { return R(r)->d.ny; }, [&](int r) { return iffty_blocks(R(r)->d); });
+  ok = ok && make_launch(b, b->project, all, [&](int r) { return project_blocks(R(r)->d); });
+  ok = ok && make_launch(b, b->flag_prep, hasf, [&](int) { return 1; });
+  ok = ok && make_launch(b, b->flag_bands, hasf, [&](int r) { return flag_bands(R(r)->fl.ns); });
+  ok = ok && make_launch(b, b->advance, all, [&](int) { return 1; });
+  if (!ok) {
+    delete b;
+    return IBDNS_ENOMEM;
+  }
+  *out = b;
+  return IBDNS_OK;
+}
+
+int ibdns_batch_step(ibdns_batch* b, int32_t n_steps) {
+  if (!b || n_steps < 0) return IBDNS_EINVAL;
+  for (auto* c : b->runs) c->stepped = true;
+  if (b->use_graph && !b->exec) {
+    // capture one step on a private stream (the legacy default stream cannot
+    // be captured); the graph is replayed on the batch's stream
+    hipStream_t cs = nullptr;
+    if (hipStreamCreateWithFlags(&cs, hipStreamNonBlocking) != hipSuccess) return IBDNS_EHIP;
+    bool ok = hipStreamBeginCapture(cs, hipStreamCaptureModeThreadLocal) == hipSuccess;
+    if (ok) {
+      batch_step_once(b, cs);
+      ok = hipStreamEndCapture(cs, &b->graph) == hipSuccess;
+    }
+    ok = ok && hipGraphInstantiate(&b->exec, b->graph, nullptr, nullptr, 0) == hipSuccess;
+    hipStreamDestroy(cs);
+    if (!ok) {
+      batch_drop_graph(b);
+      hipGetLastError();
+      return IBDNS_EHIP;
+    }
+  }
+  for (int n = 0; n < n_steps; ++n) {
+    if (b->exec) {
+      if (hipGraphLaunch(b->exec, b->st) != hipSuccess) return IBDNS_EHIP;
+    } else {
+      batch_step_once(b, b->st);
+    }
+  }
+  return check_launch();
+}
+
+int ibdns_batch_use_graph(ibdns_batch* b, int32_t enable) {
+  if (!b) return IBDNS_EINVAL;
+  if (!enable) batch_drop_graph(b);
+  b->use_graph = enable != 0;
+  return IBDNS_OK;
+}
+
+int ibdns_batch_autotune(ibdns_batch* b, int32_t* variant_out) {
+  if (!b) return IBDNS_EINVAL;
+  for (auto* c : b->runs)
+    if (c->stepped) return IBDNS_ESTATE;  // the trial launches rewrite H (harmless only before step 1)
+  hipEvent_t e0, e1;
+  hipEventCreate(&e0);
+  hipEventCreate(&e1);
+  float best = 1e30f;
+  int bestv = 0;
+  for (int v = 0; v < predict_variants(); ++v) {
+    const ibdns_batch::L& P = b->predict[v];
+    if (P.total <= 0) continue;
+    launch_predict_batch(P.bl, P.total, b->mixed, v, b->st);  // warm-up
+    hipEventRecord(e0, b->st);
+    for (int rep = 0; rep < 3; ++rep) launch_predict_batch(P.bl, P.total, b->mixed, v, b->st);
+    hipEventRecord(e1, b->st);
+    hipEventSynchronize(e1);
+    float ms = 0.0f;
+    hipEventElapsedTime(&ms, e0, e1);
+    if (ms < best) {
+      best = ms;
+      bestv = v;
+    }
+  }
+  hipEventDestroy(e0);
+  hipEventDestroy(e1);
+  b->variant = bestv;
+  batch_drop_graph(b);
+  if (variant_out) *variant_out = bestv;
+  return check_launch();
+}
+
+int ibdns_autotune(ibdns_ctx* c, int32_t* variant_out) {
+  if (!c) return IBDNS_EINVAL;
+  if (c->stepped) return IBDNS_ESTATE;
+  hipEvent_t e0, e1;
+  hipEventCreate(&e0);
+  hipEventCreate(&e1);
+  float best = 1e30f;
+  int bestv = 0;
+  for (int v = 0; v < predict_variants(); ++v) {
+    launch_predict(c->d, c->f, c->s, v, c->st);
+    hipEventRecord(e0, c->st);
+    for (int rep = 0; rep < 3; ++rep) launch_predict(c->d, c->f, c->s, v, c->st);
+    hipEventRecord(e1, c->st);
+    hipEventSynchronize(e1);
+    float ms = 0.0f;
+    hipEventElapsedTime(&ms, e0, e1);
+    if (ms < best) {
+      best = ms;
+      bestv = v;
+    }
+  }
+  hipEventDestroy(e0);
+  hipEventDestroy(e1);
+  c->variant = bestv;
+  if (variant_out) *variant_out = bestv;
+  return check_launch();
+}
+
+int ibdns_batch_destroy(ibdns_batch* b) {
+  if (!b) return IBDNS_EINVAL;
+  hipStreamSynchronize(b->st);
+  batch_drop_graph(b);
+  delete b;
+  return IBDNS_OK;
 }
 
 }  // extern "C"

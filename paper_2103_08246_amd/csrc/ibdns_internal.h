@@ -101,8 +101,65 @@ struct FlagDev {
   int* counter;            // 64 per-band sub-step counters
 };
 
+// Block coordinates of a kernel body: the single-run kernels pass blockIdx /
+// gridDim, the batched kernels a local block of one run.
+struct Blk {
+  int x, y, z;
+  int gx, gy, gz;
+};
+
+__device__ inline Blk blk_from_grid() {
+  return {(int)blockIdx.x, (int)blockIdx.y, (int)blockIdx.z, (int)gridDim.x, (int)gridDim.y,
+          (int)gridDim.z};
+}
+
+__device__ inline Blk blk_linear(int lb, int gx, int gy, int gz) {
+  return {lb % gx, (lb / gx) % gy, lb / (gx * gy), gx, gy, gz};
+}
+
+// Everything a batched launch needs about one run (copied to device memory).
+struct RunDesc {
+  Dims d;
+  Fields f;
+  Scalars* s;
+  PointSet bars;
+  SpreadCSR csr[3];
+  PointSet flag;
+  int* bbox;
+  int ntx, nty, ntz;
+  FlagDev fl;
+  const double2* tw_y;
+  const double2* tw_z;
+  const double* lam_y;
+  const double* lam_z;
+  int nparts;    // outlet partial-sum blocks
+  int nspeed;    // projection blocks (speed maxima)
+  int has_flag;
+};
+
+// A batched launch covers the runs ridx[0..n-1] of a RunDesc table; run r owns
+// the linear blocks [off[r], off[r+1]).
+struct BatchLaunch {
+  const RunDesc* runs;
+  const int* ridx;
+  const int* off;
+  int n;
+};
+
+__device__ inline int batch_run(const BatchLaunch& b, int blk, int* local) {
+  int lo = 0, hi = b.n - 1;
+  while (lo < hi) {  // last r with off[r] <= blk
+    const int mid = (lo + hi + 1) / 2;
+    if (b.off[mid] <= blk) lo = mid; else hi = mid - 1;
+  }
+  *local = blk - b.off[lo];
+  return b.ridx[lo];
+}
+
 // ---- launchers (one per kernel family) ----
-void launch_predict(const Dims& d, const Fields& f, const Scalars* s, hipStream_t st);
+int predict_variants();
+int predict_blocks(const Dims& d, int variant);
+void launch_predict(const Dims& d, const Fields& f, const Scalars* s, int variant, hipStream_t st);
 void launch_outlet(const Dims& d, const Fields& f, const Scalars* s, int nblocks, int update,
                    hipStream_t st);
 void launch_flux_apply(const Dims& d, const Fields& f, Scalars* s, int nblocks, hipStream_t st);
@@ -131,6 +188,31 @@ hipError_t launch_flag_step(const FlagDev& fl, Scalars* s, hipStream_t st);
 int flag_bands(int ns);
 void launch_advance(Scalars* s, const double* partial, int nparts, double h, hipStream_t st);
 void launch_set_dt0(Scalars* s, const double* partial, int nparts, double h, hipStream_t st);
+
+// batched launchers (one launch covers all runs of a BatchLaunch)
+int flux_apply_blocks(int nparts);
+int stencil_blocks(int npts);
+int spread_csr_blocks(const SpreadCSR* csr3);
+int div_ffty_blocks(const Dims& d);
+int fftz_blocks(const Dims& d);
+int iffty_blocks(const Dims& d);
+int tri_blocks(const Dims& d);
+int tri_chunk(int nx);
+void launch_predict_batch(const BatchLaunch& bl, int nblocks, int mixed, int variant, hipStream_t st);
+void launch_outlet_batch(const BatchLaunch& bl, int nblocks, int mixed, hipStream_t st);
+void launch_flux_apply_batch(const BatchLaunch& bl, int nblocks, int mixed, hipStream_t st);
+void launch_point_stencil_batch(const BatchLaunch& bl, int nblocks, hipStream_t st);
+void launch_point_interp_batch(const BatchLaunch& bl, int nblocks, int which, int mixed, hipStream_t st);
+void launch_spread_csr_batch(const BatchLaunch& bl, int nblocks, int mixed, hipStream_t st);
+void launch_point_bbox_batch(const BatchLaunch& bl, int nblocks, hipStream_t st);
+void launch_spread_tiles_batch(const BatchLaunch& bl, int nblocks, int mixed, hipStream_t st);
+void launch_div_ffty_batch(const BatchLaunch& bl, int nblocks, int ny, int mixed, hipStream_t st);
+void launch_fftz_batch(const BatchLaunch& bl, int nblocks, int nz, int sign, hipStream_t st);
+void launch_tri_batch(const BatchLaunch& bl, int nblocks, int C, hipStream_t st);
+void launch_iffty_batch(const BatchLaunch& bl, int nblocks, int ny, hipStream_t st);
+void launch_project_batch(const BatchLaunch& bl, int nblocks, int mixed, hipStream_t st);
+void launch_flag_batch(const BatchLaunch& prep, int nprep, const BatchLaunch& bands, int nbands, hipStream_t st);
+void launch_advance_batch(const BatchLaunch& bl, int nblocks, hipStream_t st);
 
 bool fft_size_supported(int n);
 bool tri_size_supported(int nx);

@@ -118,10 +118,8 @@ __global__ void k_flag_prep(FlagDev fl) {
   if (t < 64) fl.counter[t] = 0;
 }
 
-__global__ void __launch_bounds__(FT_) k_flag(FlagDev fl, Scalars* s) {
+__device__ __forceinline__ void flag_body(const FlagDev& fl, Scalars* s, const int band, const int nband) {
   const int ns = fl.ns;
-  const int band = blockIdx.x;
-  const int nband = gridDim.x;
   const int b0 = band * FR;
   const int b1 = min(b0 + FR, ns);        // own rows [b0, b1)
   const int rb0 = b0 - 2;                 // LDS row 0 = lattice row b0 - 2
@@ -251,8 +249,22 @@ __global__ void __launch_bounds__(FT_) k_flag(FlagDev fl, Scalars* s) {
   }
 }
 
+__global__ void __launch_bounds__(FT_) k_flag(FlagDev fl, Scalars* s) { flag_body(fl, s, blockIdx.x, gridDim.x); }
+
+// Batched: run r owns bands [off[r], off[r+1]); counters are reset by kb_flag_prep.
+__global__ void kb_flag_prep(BatchLaunch bl) {
+  int lb;
+  const RunDesc& R = bl.runs[batch_run(bl, blockIdx.x, &lb)];
+  if (threadIdx.x < 64) R.fl.counter[threadIdx.x] = 0;
+}
+__global__ void __launch_bounds__(FT_) kb_flag(BatchLaunch bl) {
+  int lb;
+  const RunDesc& R = bl.runs[batch_run(bl, blockIdx.x, &lb)];
+  flag_body(R.fl, R.s, lb, (R.fl.ns + FR - 1) / FR);
+}
+
 // dt_{n+1} from the cell-speed maxima of the projection, then t, history.
-__global__ void __launch_bounds__(256) k_advance(Scalars* s, const double* partial, int nparts, double h) {
+__device__ __forceinline__ void advance_body(Scalars* s, const double* partial, int nparts, double h) {
   __shared__ double red[256];
   double m = 0.0;
   for (int q = threadIdx.x; q < nparts; q += 256) m = fmax(m, partial[q]);
@@ -277,6 +289,15 @@ __global__ void __launch_bounds__(256) k_advance(Scalars* s, const double* parti
   s->dt = dt_next;
   s->step += 1;
   s->first = 0;
+}
+
+__global__ void __launch_bounds__(256) k_advance(Scalars* s, const double* partial, int nparts, double h) {
+  advance_body(s, partial, nparts, h);
+}
+__global__ void __launch_bounds__(256) kb_advance(BatchLaunch bl) {
+  int lb;
+  const RunDesc& R = bl.runs[batch_run(bl, blockIdx.x, &lb)];
+  advance_body(R.s, R.f.speed_part, R.nspeed, R.d.h);
 }
 
 // dt_0 after the initial projection.
@@ -322,6 +343,19 @@ void launch_advance(Scalars* s, const double* partial, int nparts, double h, hip
 
 void launch_set_dt0(Scalars* s, const double* partial, int nparts, double h, hipStream_t st) {
   hipLaunchKernelGGL(k_set_dt0, dim3(1), dim3(256), 0, st, s, partial, nparts, h);
+}
+
+}  // namespace ibdns
+
+namespace ibdns {
+
+void launch_flag_batch(const BatchLaunch& prep, int nprep, const BatchLaunch& bands, int nbands, hipStream_t st) {
+  hipLaunchKernelGGL(kb_flag_prep, dim3(nprep), dim3(64), 0, st, prep);
+  hipLaunchKernelGGL(kb_flag, dim3(nbands), dim3(FT_), 0, st, bands);
+}
+
+void launch_advance_batch(const BatchLaunch& bl, int nblocks, hipStream_t st) {
+  hipLaunchKernelGGL(kb_advance, dim3(nblocks), dim3(256), 0, st, bl);
 }
 
 }  // namespace ibdns

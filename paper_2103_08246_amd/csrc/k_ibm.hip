@@ -34,9 +34,9 @@ __device__ __forceinline__ double origin(int comp, int dir, double h) {
 }
 
 // Centre node and 1-D delta factors of every point for every component.
-__global__ void k_point_stencil(Dims d, PointSet ps, Scalars* s) {
-  const int q = blockIdx.x * blockDim.x + threadIdx.x;
-  const int comp = blockIdx.y;
+__device__ __forceinline__ void point_stencil_body(const Dims& d, const PointSet& ps, Scalars* s, int bx,
+                                                   int comp) {
+  const int q = bx * 256 + threadIdx.x;
   if (q >= ps.n) return;
   int* cen = ps.centre + ((size_t)comp * ps.n + q) * 3;
   double* wt = ps.wts + ((size_t)comp * ps.n + q) * 9;
@@ -63,9 +63,9 @@ __device__ __forceinline__ T* comp_field(const Fields& f, int comp) {
 // evolved x range (u faces 1..nx-1, v and w cells 0..nx-1).  The sum runs in
 // the field type T (FP32 in mixed precision).
 template <class T>
-__global__ void k_point_interp(Dims d, Fields f, PointSet ps, Scalars* s) {
-  const int q = blockIdx.x * blockDim.x + threadIdx.x;
-  const int comp = blockIdx.y;
+__device__ __forceinline__ void point_interp_body(const Dims& d, const Fields& f, const PointSet& ps,
+                                                  Scalars* s, int bx, int comp) {
+  const int q = bx * 256 + threadIdx.x;
   if (q >= ps.n) return;
   const int* cen = ps.centre + ((size_t)comp * ps.n + q) * 3;
   const double* wt = ps.wts + ((size_t)comp * ps.n + q) * 9;
@@ -98,8 +98,10 @@ __global__ void k_point_interp(Dims d, Fields f, PointSet ps, Scalars* s) {
 
 // Static points: one thread per touched grid node, gathering its CSR row.
 template <class T>
-__global__ void k_spread_csr(Dims d, Fields f, PointSet ps, SpreadCSR csr, int comp) {
-  const int r = blockIdx.x * blockDim.x + threadIdx.x;
+__device__ __forceinline__ void spread_csr_body(const Dims& d, const Fields& f, const PointSet& ps,
+                                                const SpreadCSR& csr, int comp, int bx) {
+  (void)d;
+  const int r = bx * 256 + threadIdx.x;
   if (r >= csr.nrows) return;
   const double* amt = ps.amount + (size_t)comp * ps.n;
   const double* wts = ps.wts + (size_t)comp * ps.n * 9;
@@ -118,8 +120,7 @@ __global__ void k_spread_csr(Dims d, Fields f, PointSet ps, SpreadCSR csr, int c
 
 // Bounding box (in unwrapped node indices) of the 3x3x3 supports of a point
 // set, per component: bbox[6*comp + 0..2] = min, [3..5] = max.
-__global__ void __launch_bounds__(256) k_point_bbox(PointSet ps, int* bbox) {
-  const int comp = blockIdx.x;
+__device__ __forceinline__ void point_bbox_body(const PointSet& ps, int* bbox, int comp) {
   __shared__ int mn[3][256], mx[3][256];
   int lo[3] = {1 << 30, 1 << 30, 1 << 30}, hi[3] = {-(1 << 30), -(1 << 30), -(1 << 30)};
   for (int q = threadIdx.x; q < ps.n; q += 256) {
@@ -157,13 +158,13 @@ constexpr int TN = TS * TS * TS;    // threads per tile
 // are compacted (in increasing order) into LDS, and every thread gathers the
 // contributions to its node.
 template <class T>
-__global__ void __launch_bounds__(TN) k_spread_tiles(Dims d, Fields f, PointSet ps, const int* bbox,
-                                                     int ntx, int nty, int ntz, int comp,
-                                                     Scalars* s) {
+__device__ __forceinline__ void spread_tiles_body(const Dims& d, const Fields& f, const PointSet& ps,
+                                                  const int* bbox, int ntx, int nty, int ntz, int comp,
+                                                  Scalars* s, int bx) {
   const int* bb = bbox + 6 * comp;
-  const int tx = blockIdx.x % ntx, ty = (blockIdx.x / ntx) % nty, tz = blockIdx.x / (ntx * nty);
+  const int tx = bx % ntx, ty = (bx / ntx) % nty, tz = bx / (ntx * nty);
   const int x0 = bb[0] + tx * TS, y0 = bb[1] + ty * TS, z0 = bb[2] + tz * TS;
-  if (blockIdx.x == 0 && threadIdx.x == 0) {
+  if (bx == 0 && threadIdx.x == 0) {
     // the launch must cover the whole box
     if ((bb[3] - bb[0]) >= ntx * TS || (bb[4] - bb[1]) >= nty * TS || (bb[5] - bb[2]) >= ntz * TS)
       atomicOr(&s->status, (int)ST_RANGE);
@@ -218,6 +219,65 @@ __global__ void __launch_bounds__(TN) k_spread_tiles(Dims d, Fields f, PointSet 
   }
 }
 
+__global__ void __launch_bounds__(256) k_point_stencil(Dims d, PointSet ps, Scalars* s) {
+  point_stencil_body(d, ps, s, blockIdx.x, blockIdx.y);
+}
+template <class T>
+__global__ void __launch_bounds__(256) k_point_interp(Dims d, Fields f, PointSet ps, Scalars* s) {
+  point_interp_body<T>(d, f, ps, s, blockIdx.x, blockIdx.y);
+}
+template <class T>
+__global__ void __launch_bounds__(256) k_spread_csr(Dims d, Fields f, PointSet ps, SpreadCSR csr, int comp) {
+  spread_csr_body<T>(d, f, ps, csr, comp, blockIdx.x);
+}
+__global__ void __launch_bounds__(256) k_point_bbox(PointSet ps, int* bbox) {
+  point_bbox_body(ps, bbox, blockIdx.x);
+}
+template <class T>
+__global__ void __launch_bounds__(TN) k_spread_tiles(Dims d, Fields f, PointSet ps, const int* bbox, int ntx,
+                                                     int nty, int ntz, int comp, Scalars* s) {
+  spread_tiles_body<T>(d, f, ps, bbox, ntx, nty, ntz, comp, s, blockIdx.x);
+}
+
+// ---- batched forms: run r owns [off[r], off[r+1]) blocks ----
+__host__ __device__ inline int pts_blocks(int n) { return (n + 255) / 256; }
+
+// which = 0: static points, 1: flag nodes; blocks: 3 components x point blocks
+__global__ void __launch_bounds__(256) kb_point_stencil(BatchLaunch bl) {
+  int lb;
+  const RunDesc& R = bl.runs[batch_run(bl, blockIdx.x, &lb)];
+  const int nb = pts_blocks(R.flag.n);
+  point_stencil_body(R.d, R.flag, R.s, lb % nb, lb / nb);
+}
+template <class T>
+__global__ void __launch_bounds__(256) kb_point_interp(BatchLaunch bl, int which) {
+  int lb;
+  const RunDesc& R = bl.runs[batch_run(bl, blockIdx.x, &lb)];
+  const PointSet& ps = which ? R.flag : R.bars;
+  const int nb = pts_blocks(ps.n);
+  point_interp_body<T>(R.d, R.f, ps, R.s, lb % nb, lb / nb);
+}
+template <class T>
+__global__ void __launch_bounds__(256) kb_spread_csr(BatchLaunch bl) {
+  int lb;
+  const RunDesc& R = bl.runs[batch_run(bl, blockIdx.x, &lb)];
+  int comp = 0;
+  while (comp < 2 && lb >= pts_blocks(R.csr[comp].nrows)) lb -= pts_blocks(R.csr[comp++].nrows);
+  spread_csr_body<T>(R.d, R.f, R.bars, R.csr[comp], comp, lb);
+}
+__global__ void __launch_bounds__(256) kb_point_bbox(BatchLaunch bl) {
+  int lb;
+  const RunDesc& R = bl.runs[batch_run(bl, blockIdx.x, &lb)];
+  point_bbox_body(R.flag, R.bbox, lb);
+}
+template <class T>
+__global__ void __launch_bounds__(TN) kb_spread_tiles(BatchLaunch bl) {
+  int lb;
+  const RunDesc& R = bl.runs[batch_run(bl, blockIdx.x, &lb)];
+  const int nt = R.ntx * R.nty * R.ntz;
+  spread_tiles_body<T>(R.d, R.f, R.flag, R.bbox, R.ntx, R.nty, R.ntz, lb / nt, R.s, lb % nt);
+}
+
 }  // namespace
 
 void launch_point_stencil(const Dims& d, const PointSet& ps, Scalars* s, hipStream_t st) {
@@ -263,6 +323,40 @@ void launch_spread_tiles(const Dims& d, const Fields& f, const PointSet& ps, con
     else
       hipLaunchKernelGGL(k_spread_tiles<double>, dim3(ntx * nty * ntz), dim3(TN), 0, st, d, f, ps, bbox,
                          ntx, nty, ntz, c, s);
+}
+
+}  // namespace ibdns
+
+namespace ibdns {
+
+int stencil_blocks(int npts) { return 3 * pts_blocks(npts); }
+int spread_csr_blocks(const SpreadCSR* csr3) {
+  return pts_blocks(csr3[0].nrows) + pts_blocks(csr3[1].nrows) + pts_blocks(csr3[2].nrows);
+}
+
+void launch_point_stencil_batch(const BatchLaunch& bl, int nblocks, hipStream_t st) {
+  hipLaunchKernelGGL(kb_point_stencil, dim3(nblocks), dim3(256), 0, st, bl);
+}
+void launch_point_interp_batch(const BatchLaunch& bl, int nblocks, int which, int mixed, hipStream_t st) {
+  if (mixed)
+    hipLaunchKernelGGL(kb_point_interp<float>, dim3(nblocks), dim3(256), 0, st, bl, which);
+  else
+    hipLaunchKernelGGL(kb_point_interp<double>, dim3(nblocks), dim3(256), 0, st, bl, which);
+}
+void launch_spread_csr_batch(const BatchLaunch& bl, int nblocks, int mixed, hipStream_t st) {
+  if (mixed)
+    hipLaunchKernelGGL(kb_spread_csr<float>, dim3(nblocks), dim3(256), 0, st, bl);
+  else
+    hipLaunchKernelGGL(kb_spread_csr<double>, dim3(nblocks), dim3(256), 0, st, bl);
+}
+void launch_point_bbox_batch(const BatchLaunch& bl, int nblocks, hipStream_t st) {
+  hipLaunchKernelGGL(kb_point_bbox, dim3(nblocks), dim3(256), 0, st, bl);
+}
+void launch_spread_tiles_batch(const BatchLaunch& bl, int nblocks, int mixed, hipStream_t st) {
+  if (mixed)
+    hipLaunchKernelGGL(kb_spread_tiles<float>, dim3(nblocks), dim3(TN), 0, st, bl);
+  else
+    hipLaunchKernelGGL(kb_spread_tiles<double>, dim3(nblocks), dim3(TN), 0, st, bl);
 }
 
 }  // namespace ibdns

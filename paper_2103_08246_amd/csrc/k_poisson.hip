@@ -163,15 +163,15 @@ constexpr int FT = 256;  // threads per FFT workgroup
 // r = D u~ / dt for a 16-column x tile of one z plane, then the y FFT of the
 // 16 real columns as 8 complex lines, unpacked into the half spectrum.
 template <int NY, class T>
-__global__ void __launch_bounds__(FT) k_div_ffty(Dims d, Fields f, const Scalars* __restrict__ s,
-                                                 const double2* __restrict__ tw) {
+__device__ __forceinline__ void div_ffty_body(const Dims& d, const Fields& f, const Scalars* __restrict__ s,
+                                              const double2* __restrict__ tw, const int bx, const int by) {
   constexpr int TXC = 16, NL = 8, LS = NY + 1, MY = NY / 2 + 1;
   __shared__ double2 buf[NL * LS];
   const T* __restrict__ ut = reinterpret_cast<const T*>(f.ut);
   const T* __restrict__ vt = reinterpret_cast<const T*>(f.vt);
   const T* __restrict__ wt = reinterpret_cast<const T*>(f.wt);
-  const int i0 = blockIdx.x * TXC;
-  const int k = blockIdx.y;
+  const int i0 = bx * TXC;
+  const int k = by;
   const int kp = (k + 1 == d.nz) ? 0 : k + 1;
   const double dt = s->dt;
   for (int e = threadIdx.x; e < TXC * NY; e += FT) {
@@ -212,11 +212,12 @@ __global__ void __launch_bounds__(FT) k_div_ffty(Dims d, Fields f, const Scalars
 
 // Complex z FFT (sign SIGN) of an 8-column x tile of one y wavenumber m, in place.
 template <int NZ, int SIGN>
-__global__ void __launch_bounds__(FT) k_fftz(Dims d, Fields f, const double2* __restrict__ tw) {
+__device__ __forceinline__ void fftz_body(const Dims& d, const Fields& f, const double2* __restrict__ tw,
+                                          const int bx, const int by) {
   constexpr int TXC = 8, NL = 8, LS = NZ + 1;
   __shared__ double2 buf[NL * LS];
-  const int i0 = blockIdx.x * TXC;
-  const int m = blockIdx.y;
+  const int i0 = bx * TXC;
+  const int m = by;
   const long long lstride = (long long)d.nx * d.MY;
   double2* base = f.spec + (long long)d.nx * m;
   for (int e = threadIdx.x; e < TXC * NZ; e += FT) {
@@ -236,11 +237,12 @@ __global__ void __launch_bounds__(FT) k_fftz(Dims d, Fields f, const double2* __
 // Inverse y FFT of a 16-column tile of one z plane to phi (unnormalised; the
 // 1/(ny nz) factor is applied in k_tri).
 template <int NY>
-__global__ void __launch_bounds__(FT) k_iffty(Dims d, Fields f, const double2* __restrict__ tw) {
+__device__ __forceinline__ void iffty_body(const Dims& d, const Fields& f, const double2* __restrict__ tw,
+                                           const int bx, const int by) {
   constexpr int TXC = 16, NL = 8, LS = NY + 1, MY = NY / 2 + 1;
   __shared__ double2 buf[NL * LS];
-  const int i0 = blockIdx.x * TXC;
-  const int k = blockIdx.y;
+  const int i0 = bx * TXC;
+  const int k = by;
   for (int e = threadIdx.x; e < NL * MY; e += FT) {
     const int L = e % NL, m = e / NL;
     const int ie = i0 + 2 * L, io = ie + 1;
@@ -289,10 +291,8 @@ __device__ __forceinline__ void tri_coef(int g, int nx, double shift, bool singu
 }
 
 template <int C>
-__global__ void __launch_bounds__(64 * TRI_WAVES) k_tri(Dims d, Fields f,
-                                                       const double* __restrict__ lam_y,
-                                                       const double* __restrict__ lam_z,
-                                                       double scale) {
+__device__ __forceinline__ void tri_body(const Dims& d, const Fields& f, const double* __restrict__ lam_y,
+                                         const double* __restrict__ lam_z, double scale, const int bx) {
   constexpr int LSP = C + 1;     // LDS chunk stride (padding against bank conflicts)
   constexpr int R = 128;         // reduced rows (2 per lane)
   __shared__ double2 lb[TRI_WAVES][64 * LSP];
@@ -301,7 +301,7 @@ __global__ void __launch_bounds__(64 * TRI_WAVES) k_tri(Dims d, Fields f,
   __shared__ double cps[64 * C];   // c' of the singular line (one per grid)
   const int wv = threadIdx.x / 64, lane = threadIdx.x % 64;
   const long long nlines = (long long)d.MY * d.nz;
-  const long long line = (long long)blockIdx.x * TRI_WAVES + wv;
+  const long long line = (long long)bx * TRI_WAVES + wv;
   const bool active = line < nlines;
   const int m = active ? (int)(line % d.MY) : 0;
   const int l = active ? (int)(line / d.MY) : 0;
@@ -469,10 +469,11 @@ constexpr int PBX = 64, PBY = 4, PKZ = 16;
 // and the per-block maximum of the cell speed |u_c| + |v_c| + |w_c| (face
 // means of the projected field).  mode 1 (initial projection) leaves p.
 template <class T>
-__global__ void __launch_bounds__(PBX* PBY) k_project(Dims d, Fields f, Scalars* s, int mode) {
-  const int i = blockIdx.x * PBX + threadIdx.x;
-  const int j = blockIdx.y * PBY + threadIdx.y;
-  const int kb = blockIdx.z * PKZ;
+__device__ __forceinline__ void project_body(const Dims& d, const Fields& f, Scalars* s, int mode, const Blk bk) {
+  const int tx = threadIdx.x % PBX, ty = threadIdx.x / PBX;
+  const int i = bk.x * PBX + tx;
+  const int j = bk.y * PBY + ty;
+  const int kb = bk.z * PKZ;
   const int ke = min(kb + PKZ, d.nz);
   const T* __restrict__ ut = reinterpret_cast<const T*>(f.ut);
   const T* __restrict__ vt = reinterpret_cast<const T*>(f.vt);
@@ -521,14 +522,75 @@ __global__ void __launch_bounds__(PBX* PBY) k_project(Dims d, Fields f, Scalars*
   }
   for (int off = 32; off > 0; off >>= 1) smax = fmax(smax, __shfl_xor(smax, off, 64));
   __shared__ double wmax[PBX * PBY / 64];
-  const int tid = threadIdx.y * PBX + threadIdx.x;
+  const int tid = threadIdx.x;
   if ((tid & 63) == 0) wmax[tid >> 6] = smax;
   __syncthreads();
   if (tid == 0) {
     double mx = wmax[0];
     for (int q = 1; q < PBX * PBY / 64; ++q) mx = fmax(mx, wmax[q]);
-    f.speed_part[blockIdx.x + gridDim.x * (blockIdx.y + gridDim.y * blockIdx.z)] = mx;
+    f.speed_part[bk.x + bk.gx * (bk.y + bk.gy * bk.z)] = mx;
   }
+}
+
+template <int NY, class T>
+__global__ void __launch_bounds__(FT) k_div_ffty(Dims d, Fields f, const Scalars* __restrict__ s,
+                                                 const double2* __restrict__ tw) {
+  div_ffty_body<NY, T>(d, f, s, tw, blockIdx.x, blockIdx.y);
+}
+template <int NZ, int SIGN>
+__global__ void __launch_bounds__(FT) k_fftz(Dims d, Fields f, const double2* __restrict__ tw) {
+  fftz_body<NZ, SIGN>(d, f, tw, blockIdx.x, blockIdx.y);
+}
+template <int NY>
+__global__ void __launch_bounds__(FT) k_iffty(Dims d, Fields f, const double2* __restrict__ tw) {
+  iffty_body<NY>(d, f, tw, blockIdx.x, blockIdx.y);
+}
+template <int C>
+__global__ void __launch_bounds__(64 * TRI_WAVES) k_tri(Dims d, Fields f, const double* __restrict__ lam_y,
+                                                       const double* __restrict__ lam_z, double scale) {
+  tri_body<C>(d, f, lam_y, lam_z, scale, blockIdx.x);
+}
+template <class T>
+__global__ void __launch_bounds__(PBX* PBY) k_project(Dims d, Fields f, Scalars* s, int mode) {
+  project_body<T>(d, f, s, mode, blk_from_grid());
+}
+
+// ---- batched forms (all runs of the launch share the template size) ----
+template <int NY, class T>
+__global__ void __launch_bounds__(FT) kb_div_ffty(BatchLaunch bl) {
+  int lb;
+  const RunDesc& R = bl.runs[batch_run(bl, blockIdx.x, &lb)];
+  const int gx = (R.d.nx + 15) / 16;
+  div_ffty_body<NY, T>(R.d, R.f, R.s, R.tw_y, lb % gx, lb / gx);
+}
+template <int NZ, int SIGN>
+__global__ void __launch_bounds__(FT) kb_fftz(BatchLaunch bl) {
+  int lb;
+  const RunDesc& R = bl.runs[batch_run(bl, blockIdx.x, &lb)];
+  const int gx = (R.d.nx + 7) / 8;
+  fftz_body<NZ, SIGN>(R.d, R.f, R.tw_z, lb % gx, lb / gx);
+}
+template <int NY>
+__global__ void __launch_bounds__(FT) kb_iffty(BatchLaunch bl) {
+  int lb;
+  const RunDesc& R = bl.runs[batch_run(bl, blockIdx.x, &lb)];
+  const int gx = (R.d.nx + 15) / 16;
+  iffty_body<NY>(R.d, R.f, R.tw_y, lb % gx, lb / gx);
+}
+template <int C>
+__global__ void __launch_bounds__(64 * TRI_WAVES) kb_tri(BatchLaunch bl) {
+  int lb;
+  const RunDesc& R = bl.runs[batch_run(bl, blockIdx.x, &lb)];
+  const double scale = (R.d.h * R.d.h) / ((double)R.d.ny * (double)R.d.nz);
+  tri_body<C>(R.d, R.f, R.lam_y, R.lam_z, scale, lb);
+}
+template <class T>
+__global__ void __launch_bounds__(PBX* PBY) kb_project(BatchLaunch bl, int mode) {
+  int lb;
+  const RunDesc& R = bl.runs[batch_run(bl, blockIdx.x, &lb)];
+  const Dims& d = R.d;
+  project_body<T>(d, R.f, R.s, mode,
+                  blk_linear(lb, (d.nx + PBX - 1) / PBX, (d.ny + PBY - 1) / PBY, (d.nz + PKZ - 1) / PKZ));
 }
 
 // u~ := u (in the storage type of u~), used before the initial projection.
@@ -647,9 +709,73 @@ int project_blocks(const Dims& d) {
 void launch_project(const Dims& d, const Fields& f, Scalars* s, int mode, hipStream_t st) {
   dim3 grid((d.nx + PBX - 1) / PBX, (d.ny + PBY - 1) / PBY, (d.nz + PKZ - 1) / PKZ);
   if (d.mixed)
-    hipLaunchKernelGGL(k_project<float>, grid, dim3(PBX, PBY), 0, st, d, f, s, mode);
+    hipLaunchKernelGGL(k_project<float>, grid, dim3(PBX * PBY), 0, st, d, f, s, mode);
   else
-    hipLaunchKernelGGL(k_project<double>, grid, dim3(PBX, PBY), 0, st, d, f, s, mode);
+    hipLaunchKernelGGL(k_project<double>, grid, dim3(PBX * PBY), 0, st, d, f, s, mode);
+}
+
+}  // namespace ibdns
+
+namespace ibdns {
+
+int div_ffty_blocks(const Dims& d) { return ((d.nx + 15) / 16) * d.nz; }
+int fftz_blocks(const Dims& d) { return ((d.nx + 7) / 8) * d.MY; }
+int iffty_blocks(const Dims& d) { return ((d.nx + 15) / 16) * d.nz; }
+int tri_blocks(const Dims& d) { return (int)(((long long)d.MY * d.nz + TRI_WAVES - 1) / TRI_WAVES); }
+int tri_chunk(int nx) {
+  int C = (nx + 63) / 64;
+  return C < 2 ? 2 : C;
+}
+
+void launch_div_ffty_batch(const BatchLaunch& bl, int nblocks, int ny, int mixed, hipStream_t st) {
+  if (mixed) {
+#define CALL(NY) hipLaunchKernelGGL((kb_div_ffty<NY, float>), dim3(nblocks), dim3(FT), 0, st, bl)
+    IBDNS_FFT_SWITCH(ny, CALL)
+#undef CALL
+  } else {
+#define CALL(NY) hipLaunchKernelGGL((kb_div_ffty<NY, double>), dim3(nblocks), dim3(FT), 0, st, bl)
+    IBDNS_FFT_SWITCH(ny, CALL)
+#undef CALL
+  }
+}
+
+void launch_fftz_batch(const BatchLaunch& bl, int nblocks, int nz, int sign, hipStream_t st) {
+  if (sign < 0) {
+#define CALL(NZ) hipLaunchKernelGGL((kb_fftz<NZ, -1>), dim3(nblocks), dim3(FT), 0, st, bl)
+    IBDNS_FFT_SWITCH(nz, CALL)
+#undef CALL
+  } else {
+#define CALL(NZ) hipLaunchKernelGGL((kb_fftz<NZ, 1>), dim3(nblocks), dim3(FT), 0, st, bl)
+    IBDNS_FFT_SWITCH(nz, CALL)
+#undef CALL
+  }
+}
+
+void launch_iffty_batch(const BatchLaunch& bl, int nblocks, int ny, hipStream_t st) {
+#define CALL(NY) hipLaunchKernelGGL(kb_iffty<NY>, dim3(nblocks), dim3(FT), 0, st, bl)
+  IBDNS_FFT_SWITCH(ny, CALL)
+#undef CALL
+}
+
+void launch_tri_batch(const BatchLaunch& bl, int nblocks, int C, hipStream_t st) {
+  const dim3 g(nblocks), b(64 * TRI_WAVES);
+  switch (C) {
+    case 2: hipLaunchKernelGGL(kb_tri<2>, g, b, 0, st, bl); break;
+    case 3: hipLaunchKernelGGL(kb_tri<3>, g, b, 0, st, bl); break;
+    case 4: hipLaunchKernelGGL(kb_tri<4>, g, b, 0, st, bl); break;
+    case 5: hipLaunchKernelGGL(kb_tri<5>, g, b, 0, st, bl); break;
+    case 6: hipLaunchKernelGGL(kb_tri<6>, g, b, 0, st, bl); break;
+    case 8: hipLaunchKernelGGL(kb_tri<8>, g, b, 0, st, bl); break;
+    case 12: hipLaunchKernelGGL(kb_tri<12>, g, b, 0, st, bl); break;
+    default: break;
+  }
+}
+
+void launch_project_batch(const BatchLaunch& bl, int nblocks, int mixed, hipStream_t st) {
+  if (mixed)
+    hipLaunchKernelGGL(kb_project<float>, dim3(nblocks), dim3(PBX * PBY), 0, st, bl, 0);
+  else
+    hipLaunchKernelGGL(kb_project<double>, dim3(nblocks), dim3(PBX * PBY), 0, st, bl, 0);
 }
 
 }  // namespace ibdns

@@ -11,19 +11,21 @@ namespace ibdns {
 
 namespace {
 
-constexpr int TX = 64, TY = 8, KZ = 16;
-constexpr int LX = TX + 2, LY = TY + 2, LP = LX * LY;   // LDS plane with a 1-cell x-y halo
+// Tile shapes (x, y, z-planes) the autotuner chooses from; 0 is the default.
+#define IBDNS_PREDICT_VARIANTS(X) X(0, 64, 8, 16) X(1, 64, 4, 32) X(2, 64, 8, 32) X(3, 32, 8, 16) X(4, 64, 16, 8)
 
 template <class T>
 __device__ __forceinline__ T sq(T a) { return a * a; }
 __device__ __forceinline__ int wrapi(int a, int n) { return a < 0 ? a + n : (a >= n ? a - n : a); }
 
-// One workgroup per 64 x 8 (x, y) tile and KZ planes in z.  u, v, w of planes
+// One workgroup per TX x TY (x, y) tile and KZ planes in z.  u, v, w of planes
 // k-1, k, k+1 and p of plane k sit in LDS (ring of three planes, refilled one
 // plane per step); each thread evaluates u face i (i >= 1), v cell i and w
 // cell i of its column.
-template <class T>
-__global__ void __launch_bounds__(TX* TY) k_predict(Dims d, Fields f, const Scalars* __restrict__ s) {
+template <class T, int TX, int TY, int KZ>
+__device__ __forceinline__ void predict_body(const Dims& d, const Fields& f, const Scalars* __restrict__ s,
+                                             const Blk bk) {
+  constexpr int LX = TX + 2, LY = TY + 2, LP = LX * LY;   // LDS plane with a 1-cell x-y halo
   __shared__ T su[3][LP], sv[3][LP], sw[3][LP], spp[LP];
   T* __restrict__ hu = reinterpret_cast<T*>(f.hu);
   T* __restrict__ hv = reinterpret_cast<T*>(f.hv);
@@ -31,9 +33,10 @@ __global__ void __launch_bounds__(TX* TY) k_predict(Dims d, Fields f, const Scal
   T* __restrict__ ut = reinterpret_cast<T*>(f.ut);
   T* __restrict__ vt = reinterpret_cast<T*>(f.vt);
   T* __restrict__ wt = reinterpret_cast<T*>(f.wt);
-  const int tx = threadIdx.x, ty = threadIdx.y, tid = ty * TX + tx;
-  const int i0 = blockIdx.x * TX, j0 = blockIdx.y * TY;
-  const int kb = blockIdx.z * KZ, ke = min(kb + KZ, d.nz);
+  const int tid = threadIdx.x;          // 1-D workgroup of TX * TY threads
+  const int tx = tid % TX, ty = tid / TX;
+  const int i0 = bk.x * TX, j0 = bk.y * TY;
+  const int kb = bk.z * KZ, ke = min(kb + KZ, d.nz);
   const int i = i0 + tx, j = j0 + ty;
   const int nx = d.nx;
   const bool active = i < nx && j < d.ny;
@@ -170,7 +173,22 @@ __global__ void __launch_bounds__(TX* TY) k_predict(Dims d, Fields f, const Scal
   }
 }
 
+template <class T, int TX, int TY, int KZ>
+__global__ void __launch_bounds__(TX* TY) k_predict(Dims d, Fields f, const Scalars* __restrict__ s) {
+  predict_body<T, TX, TY, KZ>(d, f, s, blk_from_grid());
+}
+
+template <class T, int TX, int TY, int KZ>
+__global__ void __launch_bounds__(TX* TY) kb_predict(BatchLaunch bl) {
+  int lb;
+  const RunDesc& R = bl.runs[batch_run(bl, blockIdx.x, &lb)];
+  const Dims& d = R.d;
+  predict_body<T, TX, TY, KZ>(d, R.f, R.s,
+                              blk_linear(lb, (d.nx + TX - 1) / TX, (d.ny + TY - 1) / TY, (d.nz + KZ - 1) / KZ));
+}
+
 constexpr int OB = 256;
+__host__ __device__ inline int flux_blocks(int nparts) { return nparts < 64 ? nparts : 64; }
 
 // Convective outflow on the outlet plane (u at i = nx, v and w ghosts at
 // i = nx; the test hook keeps the ghosts) into the FP64 boundary planes
@@ -179,10 +197,10 @@ constexpr int OB = 256;
 // the current values and sums.  With T = double the provisional arrays also
 // receive the outlet values.
 template <class T>
-__global__ void __launch_bounds__(OB) k_outlet(Dims d, Fields f, const Scalars* __restrict__ s,
-                                               int update) {
+__device__ __forceinline__ void outlet_body(const Dims& d, const Fields& f, const Scalars* __restrict__ s,
+                                            int update, const int bx) {
   const int tid = threadIdx.x;
-  const long long q = (long long)blockIdx.x * OB + tid;
+  const long long q = (long long)bx * OB + tid;
   const long long nplane = (long long)d.ny * d.nz;
   const int nx = d.nx;
   double sout = 0.0, sin_ = 0.0;
@@ -229,16 +247,29 @@ __global__ void __launch_bounds__(OB) k_outlet(Dims d, Fields f, const Scalars* 
     __syncthreads();
   }
   if (tid == 0) {
-    f.partial[2 * blockIdx.x] = ra[0];
-    f.partial[2 * blockIdx.x + 1] = rb[0];
+    f.partial[2 * bx] = ra[0];
+    f.partial[2 * bx + 1] = rb[0];
   }
+}
+
+template <class T>
+__global__ void __launch_bounds__(OB) k_outlet(Dims d, Fields f, const Scalars* __restrict__ s, int update) {
+  outlet_body<T>(d, f, s, update, blockIdx.x);
+}
+
+template <class T>
+__global__ void __launch_bounds__(OB) kb_outlet(BatchLaunch bl, int update) {
+  int lb;
+  const RunDesc& R = bl.runs[batch_run(bl, blockIdx.x, &lb)];
+  outlet_body<T>(R.d, R.f, R.s, update, lb);
 }
 
 // corr = (sum u_0 - sum u~_nx) / (ny nz) added to u~ at the outlet (FP64
 // plane; also the FP64 provisional array); every block reduces the partials
 // in the same fixed order.
 template <class T>
-__global__ void __launch_bounds__(OB) k_flux_apply(Dims d, Fields f, Scalars* s, int nparts) {
+__device__ __forceinline__ void flux_apply_body(const Dims& d, const Fields& f, Scalars* s, int nparts,
+                                                const int bx, const int gx) {
   const int tid = threadIdx.x;
   __shared__ double ra[OB], rb[OB];
   double a = 0.0, b = 0.0;
@@ -257,9 +288,9 @@ __global__ void __launch_bounds__(OB) k_flux_apply(Dims d, Fields f, Scalars* s,
     __syncthreads();
   }
   const double corr = (rb[0] - ra[0]) / ((double)d.ny * (double)d.nz);
-  if (blockIdx.x == 0 && tid == 0) s->corr = corr;
+  if (bx == 0 && tid == 0) s->corr = corr;
   const long long nplane = (long long)d.ny * d.nz;
-  for (long long q = (long long)blockIdx.x * OB + tid; q < nplane; q += (long long)gridDim.x * OB) {
+  for (long long q = (long long)bx * OB + tid; q < nplane; q += (long long)gx * OB) {
     const double v = f.bnd[q] + corr;
     f.bnd[q] = v;
     if (sizeof(T) == sizeof(double)) {
@@ -269,16 +300,65 @@ __global__ void __launch_bounds__(OB) k_flux_apply(Dims d, Fields f, Scalars* s,
   }
 }
 
+template <class T>
+__global__ void __launch_bounds__(OB) k_flux_apply(Dims d, Fields f, Scalars* s, int nparts) {
+  flux_apply_body<T>(d, f, s, nparts, blockIdx.x, gridDim.x);
+}
+
+template <class T>
+__global__ void __launch_bounds__(OB) kb_flux_apply(BatchLaunch bl) {
+  int lb;
+  const RunDesc& R = bl.runs[batch_run(bl, blockIdx.x, &lb)];
+  flux_apply_body<T>(R.d, R.f, R.s, R.nparts, lb, flux_blocks(R.nparts));
+}
+
 }  // namespace
 
 int outlet_blocks(const Dims& d) { return (int)(((long long)d.ny * d.nz + OB - 1) / OB); }
+int flux_apply_blocks(int nparts) { return flux_blocks(nparts); }
 
-void launch_predict(const Dims& d, const Fields& f, const Scalars* s, hipStream_t st) {
-  dim3 grid((d.nx + TX - 1) / TX, (d.ny + TY - 1) / TY, (d.nz + KZ - 1) / KZ);
-  if (d.mixed)
-    hipLaunchKernelGGL(k_predict<float>, grid, dim3(TX, TY), 0, st, d, f, s);
-  else
-    hipLaunchKernelGGL(k_predict<double>, grid, dim3(TX, TY), 0, st, d, f, s);
+int predict_variants() { return 5; }
+
+int predict_blocks(const Dims& d, int variant) {
+  switch (variant) {
+#define X(V, TX_, TY_, KZ_) \
+    case V: return ((d.nx + TX_ - 1) / TX_) * ((d.ny + TY_ - 1) / TY_) * ((d.nz + KZ_ - 1) / KZ_);
+    IBDNS_PREDICT_VARIANTS(X)
+#undef X
+    default: return 0;
+  }
+}
+
+void launch_predict(const Dims& d, const Fields& f, const Scalars* s, int variant, hipStream_t st) {
+  switch (variant) {
+#define X(V, TX_, TY_, KZ_)                                                                          \
+    case V: {                                                                                        \
+      dim3 grid((d.nx + TX_ - 1) / TX_, (d.ny + TY_ - 1) / TY_, (d.nz + KZ_ - 1) / KZ_);              \
+      if (d.mixed)                                                                                   \
+        hipLaunchKernelGGL((k_predict<float, TX_, TY_, KZ_>), grid, dim3(TX_ * TY_), 0, st, d, f, s);  \
+      else                                                                                           \
+        hipLaunchKernelGGL((k_predict<double, TX_, TY_, KZ_>), grid, dim3(TX_ * TY_), 0, st, d, f, s); \
+      break;                                                                                         \
+    }
+    IBDNS_PREDICT_VARIANTS(X)
+#undef X
+    default: break;
+  }
+}
+
+void launch_predict_batch(const BatchLaunch& bl, int nblocks, int mixed, int variant, hipStream_t st) {
+  switch (variant) {
+#define X(V, TX_, TY_, KZ_)                                                                         \
+    case V:                                                                                         \
+      if (mixed)                                                                                    \
+        hipLaunchKernelGGL((kb_predict<float, TX_, TY_, KZ_>), dim3(nblocks), dim3(TX_ * TY_), 0, st, bl);  \
+      else                                                                                          \
+        hipLaunchKernelGGL((kb_predict<double, TX_, TY_, KZ_>), dim3(nblocks), dim3(TX_ * TY_), 0, st, bl); \
+      break;
+    IBDNS_PREDICT_VARIANTS(X)
+#undef X
+    default: break;
+  }
 }
 
 void launch_outlet(const Dims& d, const Fields& f, const Scalars* s, int nblocks, int update,
@@ -289,12 +369,26 @@ void launch_outlet(const Dims& d, const Fields& f, const Scalars* s, int nblocks
     hipLaunchKernelGGL(k_outlet<double>, dim3(nblocks), dim3(OB), 0, st, d, f, s, update);
 }
 
+void launch_outlet_batch(const BatchLaunch& bl, int nblocks, int mixed, hipStream_t st) {
+  if (mixed)
+    hipLaunchKernelGGL(kb_outlet<float>, dim3(nblocks), dim3(OB), 0, st, bl, 1);
+  else
+    hipLaunchKernelGGL(kb_outlet<double>, dim3(nblocks), dim3(OB), 0, st, bl, 1);
+}
+
 void launch_flux_apply(const Dims& d, const Fields& f, Scalars* s, int nblocks, hipStream_t st) {
-  int g = nblocks < 64 ? nblocks : 64;
+  const int g = flux_blocks(nblocks);
   if (d.mixed)
     hipLaunchKernelGGL(k_flux_apply<float>, dim3(g), dim3(OB), 0, st, d, f, s, nblocks);
   else
     hipLaunchKernelGGL(k_flux_apply<double>, dim3(g), dim3(OB), 0, st, d, f, s, nblocks);
+}
+
+void launch_flux_apply_batch(const BatchLaunch& bl, int nblocks, int mixed, hipStream_t st) {
+  if (mixed)
+    hipLaunchKernelGGL(kb_flux_apply<float>, dim3(nblocks), dim3(OB), 0, st, bl);
+  else
+    hipLaunchKernelGGL(kb_flux_apply<double>, dim3(nblocks), dim3(OB), 0, st, bl);
 }
 
 }  // namespace ibdns
