@@ -153,6 +153,8 @@ def main():
     ap.add_argument("--no-mixed", action="store_true")
     ap.add_argument("--no-batch", action="store_true")
     ap.add_argument("--batch-steps", type=int, default=20)
+    ap.add_argument("--copy-calib", action="store_true",
+                    help="also run a plain device copy of 1 GiB (calibrates HBM counters)")
     ap.add_argument("--cpu-budget", type=float, default=20.0)
     args = ap.parse_args()
     if args.gpus != 1:
@@ -172,6 +174,7 @@ def main():
     def measure(precision, timing):
         run = ib.create(ib.domain_from(w, precision=precision), noise, points=bars,
                         flag=ib.flag_from(w.flag) if w.flag is not None else None, flag_X0=X0)
+        run.variant = ib.autotune(run.ctx)   # predictor tile shape, picked by timing
         run.step(args.warmup)
         ib.sync(run.ctx)
         stream = torch.cuda.current_stream()
@@ -220,7 +223,8 @@ def main():
            "config": {"workload": w.name, "cells": w.cells, "grid": [w.nx, w.ny, w.nz],
                       "re": w.re, "cfl": w.cfl, "solid_points": 0 if bars is None else len(bars[1]),
                       "flag_nodes": 0 if w.flag is None else w.flag.ns ** 2,
-                      "precision": "fp64", "flag_substeps": sc["nsub"], "dt": sc["dt"]},
+                      "precision": "fp64", "flag_substeps": sc["nsub"], "dt": sc["dt"],
+                      "predict_variant": run.variant},
            "roofline": roofline,
            "step_hbm_gbs": round(step_bytes / (ms_per_step * 1e-3) / 1e9, 1),
            "gpu_event_ms_per_step": round(gpu_ms / args.steps, 4),
@@ -242,6 +246,14 @@ def main():
         run_m.close()
     del noise
     run.close()
+    if args.copy_calib:
+        src = torch.empty(1 << 27, dtype=torch.float64, device="cuda")   # 1 GiB
+        dst = torch.empty_like(src)
+        src.fill_(1.0)
+        torch.cuda.synchronize()
+        dst.copy_(src)
+        torch.cuda.synchronize()
+        del src, dst
     if not args.no_batch:
         import synth as _s
         ens24 = _s.ensemble_24()

@@ -131,7 +131,7 @@ size_t flag_bytes(int ns) {
   b += up(3 * n * sizeof(double));      // amount
   b += up(9 * n * sizeof(int));         // centre
   b += up(27 * n * sizeof(double));     // wts
-  b += up(18 * sizeof(int));            // bbox
+  b += up((18 + 18 * ((n + 63) / 64)) * sizeof(int));  // bounding boxes: all points, groups of 64
   return b;
 }
 
@@ -572,7 +572,7 @@ int ibdns_set_geometry(ibdns_ctx* c, int64_t n_points, const double* X, const do
     ps.amount = c->carve<double>(3 * n);
     ps.centre = c->carve<int>(9 * n);
     ps.wts = c->carve<double>(27 * n);
-    c->bbox = c->carve<int>(18);
+    c->bbox = c->carve<int>(18 + 18 * ((n + 63) / 64));
     // masses and volumes: dA = ds^2 w_a w_b (trapezoid), m = rho dA, dV = dA h
     std::vector<double> wgt(ns, 1.0);
     wgt[0] = wgt[ns - 1] = 0.5;
@@ -1122,10 +1122,21 @@ int ibdns_batch_use_graph(ibdns_batch* b, int32_t enable) {
   return IBDNS_OK;
 }
 
+// The trial launches of the autotuners run before step 1 and rewrite H^n and
+// u~, which step 1 recomputes.  They are timed with the Adams-Bashforth read of
+// H^{n-1} switched on (first = 0), as in every later step; step 1 itself
+// starts with first = 1 again.
+static bool set_first(ibdns_ctx* c, int v) {
+  return hipStreamSynchronize(c->st) == hipSuccess &&
+         hipMemcpy(&c->s->first, &v, sizeof(int), hipMemcpyHostToDevice) == hipSuccess;
+}
+
 int ibdns_batch_autotune(ibdns_batch* b, int32_t* variant_out) {
   if (!b) return IBDNS_EINVAL;
   for (auto* c : b->runs)
     if (c->stepped) return IBDNS_ESTATE;  // the trial launches rewrite H (harmless only before step 1)
+  for (auto* c : b->runs)
+    if (!set_first(c, 0)) return IBDNS_EHIP;
   hipEvent_t e0, e1;
   hipEventCreate(&e0);
   hipEventCreate(&e1);
@@ -1148,6 +1159,9 @@ int ibdns_batch_autotune(ibdns_batch* b, int32_t* variant_out) {
   }
   hipEventDestroy(e0);
   hipEventDestroy(e1);
+  hipStreamSynchronize(b->st);
+  for (auto* c : b->runs)
+    if (!set_first(c, 1)) return IBDNS_EHIP;
   b->variant = bestv;
   batch_drop_graph(b);
   if (variant_out) *variant_out = bestv;
@@ -1157,6 +1171,7 @@ int ibdns_batch_autotune(ibdns_batch* b, int32_t* variant_out) {
 int ibdns_autotune(ibdns_ctx* c, int32_t* variant_out) {
   if (!c) return IBDNS_EINVAL;
   if (c->stepped) return IBDNS_ESTATE;
+  if (!set_first(c, 0)) return IBDNS_EHIP;
   hipEvent_t e0, e1;
   hipEventCreate(&e0);
   hipEventCreate(&e1);
@@ -1177,6 +1192,7 @@ int ibdns_autotune(ibdns_ctx* c, int32_t* variant_out) {
   }
   hipEventDestroy(e0);
   hipEventDestroy(e1);
+  if (!set_first(c, 1)) return IBDNS_EHIP;
   c->variant = bestv;
   if (variant_out) *variant_out = bestv;
   return check_launch();

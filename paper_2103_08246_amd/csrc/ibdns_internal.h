@@ -117,6 +117,18 @@ __device__ inline Blk blk_linear(int lb, int gx, int gy, int gz) {
   return {lb % gx, (lb / gx) % gy, lb / (gx * gy), gx, gy, gz};
 }
 
+// XCD-aware order: workgroups are dispatched round-robin over the 8 XCDs
+// (each with its own L2), so dispatch id b runs on XCD b % 8.  Map it to a
+// logical tile so that every XCD walks one contiguous range of tiles.
+// Bijective on [0, n).  Measured on the 768 x 384 x 384 step, it pays for the
+// z FFT (8-column tiles: the 128-byte column segments of neighbouring tiles
+// share L2 lines) and costs 2-4 % on the stencil kernels, which keep the
+// plain round-robin order.
+__device__ inline int xcd_remap(int b, int n) {
+  const int q = n >> 3, r = n & 7, x = b & 7, k = b >> 3;
+  return x * q + (x < r ? x : r) + k;
+}
+
 // Everything a batched launch needs about one run (copied to device memory).
 struct RunDesc {
   Dims d;

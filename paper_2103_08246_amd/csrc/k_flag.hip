@@ -194,16 +194,19 @@ __device__ __forceinline__ void flag_body(const FlagDev& fl, Scalars* s, const i
         if (b < b0 || b >= b1) continue;
         for (int q = tid; q < 3 * ns; q += FT_) slot[r * 3 * ns + q] = Xs[3 * ns * (b - rb0) + q];
       }
-      __threadfence();  // each wave releases its own slot stores at device scope
+      // The barrier orders every wave's slot stores before thread 0's release
+      // store of the counter (release covers all stores that happen before
+      // it); the neighbours' counters are polled with relaxed loads and one
+      // acquire fence follows, whose effect the second barrier extends to the
+      // whole workgroup.  One L2 write-back and one invalidate per sub-step.
       __syncthreads();
       if (tid == 0) {
-        __threadfence();
         __hip_atomic_store(&fl.counter[band], it + 1, __ATOMIC_RELEASE, __HIP_MEMORY_SCOPE_AGENT);
         long long spins = 0;
         bool ok = true;
         for (int nbh = band - 1; nbh <= band + 1; nbh += 2) {
           if (nbh < 0 || nbh >= nband) continue;
-          while (__hip_atomic_load(&fl.counter[nbh], __ATOMIC_ACQUIRE, __HIP_MEMORY_SCOPE_AGENT) < it + 1) {
+          while (__hip_atomic_load(&fl.counter[nbh], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) < it + 1) {
             if (++spins > SPIN_LIMIT) {
               ok = false;
               break;
@@ -211,6 +214,7 @@ __device__ __forceinline__ void flag_body(const FlagDev& fl, Scalars* s, const i
             __builtin_amdgcn_s_sleep(2);
           }
         }
+        __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "agent");
         if (!ok) {
           abort_flag = 1;
           atomicOr(&s->status, (int)ST_RANGE);
@@ -218,7 +222,6 @@ __device__ __forceinline__ void flag_body(const FlagDev& fl, Scalars* s, const i
       }
       __syncthreads();
       if (abort_flag) return;   // uniform over the workgroup
-      __threadfence();
       // halo rows from the neighbours' slots
       for (int hb = rb0; hb < b1 + 2; ++hb) {
         if (hb < 0 || hb >= ns || (hb >= b0 && hb < b1)) continue;

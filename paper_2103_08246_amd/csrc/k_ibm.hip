@@ -118,50 +118,78 @@ __device__ __forceinline__ void spread_csr_body(const Dims& d, const Fields& f, 
   fld[csr.row_node[r]] += acc;
 }
 
-// Bounding box (in unwrapped node indices) of the 3x3x3 supports of a point
-// set, per component: bbox[6*comp + 0..2] = min, [3..5] = max.
+// Bounding boxes (in unwrapped node indices) of the 3x3x3 supports of a
+// moving point set, per component: bbox[6 comp + 0..2] = min, [3..5] = max
+// over all points, and bbox[18 + 6 (comp G + g) + ...] the same over point
+// group g = points [64 g, 64 g + 64), G = ceil(n / 64).  One workgroup of 16
+// wavefronts per component; one wavefront per group.
+constexpr int PG = 64;              // points per group
+constexpr int BBT = 1024;           // threads of the bounding-box workgroup
+
 __device__ __forceinline__ void point_bbox_body(const PointSet& ps, int* bbox, int comp) {
-  __shared__ int mn[3][256], mx[3][256];
+  __shared__ int mn[BBT / 64][3], mx[BBT / 64][3];
+  const int ng = (ps.n + PG - 1) / PG;
+  const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
+  int* gb = bbox + 18 + 6 * comp * ng;
   int lo[3] = {1 << 30, 1 << 30, 1 << 30}, hi[3] = {-(1 << 30), -(1 << 30), -(1 << 30)};
-  for (int q = threadIdx.x; q < ps.n; q += 256) {
-    const int* cen = ps.centre + ((size_t)comp * ps.n + q) * 3;
-    for (int a = 0; a < 3; ++a) {
-      lo[a] = min(lo[a], cen[a] - 1);
-      hi[a] = max(hi[a], cen[a] + 1);
-    }
-  }
-  for (int a = 0; a < 3; ++a) {
-    mn[a][threadIdx.x] = lo[a];
-    mx[a][threadIdx.x] = hi[a];
-  }
-  __syncthreads();
-  for (int w = 128; w > 0; w >>= 1) {
-    if ((int)threadIdx.x < w)
+  for (int g = wv; g < ng; g += BBT / 64) {
+    const int q = g * PG + lane;
+    int l[3] = {1 << 30, 1 << 30, 1 << 30}, h[3] = {-(1 << 30), -(1 << 30), -(1 << 30)};
+    if (q < ps.n) {
+      const int* cen = ps.centre + ((size_t)comp * ps.n + q) * 3;
       for (int a = 0; a < 3; ++a) {
-        mn[a][threadIdx.x] = min(mn[a][threadIdx.x], mn[a][threadIdx.x + w]);
-        mx[a][threadIdx.x] = max(mx[a][threadIdx.x], mx[a][threadIdx.x + w]);
+        l[a] = cen[a] - 1;
+        h[a] = cen[a] + 1;
       }
-    __syncthreads();
-  }
-  if (threadIdx.x == 0)
-    for (int a = 0; a < 3; ++a) {
-      bbox[6 * comp + a] = mn[a][0];
-      bbox[6 * comp + 3 + a] = mx[a][0];
     }
+    for (int a = 0; a < 3; ++a)
+      for (int o = 32; o >= 1; o >>= 1) {
+        l[a] = min(l[a], __shfl_xor(l[a], o));
+        h[a] = max(h[a], __shfl_xor(h[a], o));
+      }
+    if (lane == 0)
+      for (int a = 0; a < 3; ++a) {
+        gb[6 * g + a] = l[a];
+        gb[6 * g + 3 + a] = h[a];
+      }
+    for (int a = 0; a < 3; ++a) {
+      lo[a] = min(lo[a], l[a]);
+      hi[a] = max(hi[a], h[a]);
+    }
+  }
+  if (lane == 0)
+    for (int a = 0; a < 3; ++a) {
+      mn[wv][a] = lo[a];
+      mx[wv][a] = hi[a];
+    }
+  __syncthreads();
+  if (threadIdx.x < 3) {
+    const int a = threadIdx.x;
+    int l = mn[0][a], h = mx[0][a];
+    for (int w = 1; w < BBT / 64; ++w) {
+      l = min(l, mn[w][a]);
+      h = max(h, mx[w][a]);
+    }
+    bbox[6 * comp + a] = l;
+    bbox[6 * comp + 3 + a] = h;
+  }
 }
 
 constexpr int TS = 8;               // tile edge (nodes)
 constexpr int TN = TS * TS * TS;    // threads per tile
 
 // Moving points: one workgroup per 8x8x8 tile of nodes inside the bounding
-// box.  The points are scanned in chunks, those whose support meets the tile
-// are compacted (in increasing order) into LDS, and every thread gathers the
-// contributions to its node.
+// box.  The point groups whose box meets the tile are listed in increasing
+// order; eight groups at a time, the points whose support meets the tile are
+// compacted (in increasing order) into LDS, and every thread gathers the
+// contributions to its node in increasing point order.
 template <class T>
 __device__ __forceinline__ void spread_tiles_body(const Dims& d, const Fields& f, const PointSet& ps,
                                                   const int* bbox, int ntx, int nty, int ntz, int comp,
                                                   Scalars* s, int bx) {
   const int* bb = bbox + 6 * comp;
+  const int ng = (ps.n + PG - 1) / PG;
+  const int* gb = bbox + 18 + 6 * comp * ng;
   const int tx = bx % ntx, ty = (bx / ntx) % nty, tz = bx / (ntx * nty);
   const int x0 = bb[0] + tx * TS, y0 = bb[1] + ty * TS, z0 = bb[2] + tz * TS;
   if (bx == 0 && threadIdx.x == 0) {
@@ -172,43 +200,87 @@ __device__ __forceinline__ void spread_tiles_body(const Dims& d, const Fields& f
   if (x0 > bb[3] || y0 > bb[4] || z0 > bb[5]) return;
   const int lx = threadIdx.x % TS, ly = (threadIdx.x / TS) % TS, lz = threadIdx.x / (TS * TS);
   const int ni = x0 + lx, nj = y0 + ly, nk = z0 + lz;  // unwrapped node of this thread
+  const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
+  constexpr int NW = TN / 64;
 
-  __shared__ int list[TN];
-  __shared__ int scan[TN];
+  __shared__ int glist[TN];
+  __shared__ int gcount[NW], pcount[NW];
+  __shared__ int4 sc[TN];            // centre node of each staged point
+  __shared__ double sw[TN][9];       // its 1-D factors (x, y, z taps)
+  __shared__ double sa[TN];          // its amount
   const int* cenb = ps.centre + (size_t)comp * ps.n * 3;
   const double* wts = ps.wts + (size_t)comp * ps.n * 9;
   const double* amt = ps.amount + (size_t)comp * ps.n;
   T acc = 0;
-  for (int base = 0; base < ps.n; base += TN) {
-    const int q = base + threadIdx.x;
-    int hit = 0;
-    if (q < ps.n) {
-      const int* c = cenb + (size_t)q * 3;
-      hit = (c[0] + 1 >= x0 && c[0] - 1 < x0 + TS && c[1] + 1 >= y0 && c[1] - 1 < y0 + TS &&
-             c[2] + 1 >= z0 && c[2] - 1 < z0 + TS) ? 1 : 0;
+  for (int gbase = 0; gbase < ng; gbase += TN) {
+    // list the groups of this chunk whose support box meets the tile
+    const int g = gbase + threadIdx.x;
+    bool hit = false;
+    if (g < ng) {
+      const int* q = gb + 6 * g;
+      hit = q[3] >= x0 && q[0] < x0 + TS && q[4] >= y0 && q[1] < y0 + TS && q[5] >= z0 && q[2] < z0 + TS;
     }
-    scan[threadIdx.x] = hit;
+    const unsigned long long m = __ballot(hit);
+    if (lane == 0) gcount[wv] = __popcll(m);
     __syncthreads();
-    // inclusive scan (Hillis-Steele)
-    for (int off = 1; off < TN; off <<= 1) {
-      const int v = (int)threadIdx.x >= off ? scan[threadIdx.x - off] : 0;
-      __syncthreads();
-      scan[threadIdx.x] += v;
-      __syncthreads();
+    int off = 0, total = 0;
+    for (int w = 0; w < NW; ++w) {
+      off += w < wv ? gcount[w] : 0;
+      total += gcount[w];
     }
-    const int nhit = scan[TN - 1];
-    if (hit) list[scan[threadIdx.x] - 1] = q;
+    if (hit) glist[off + __popcll(m & ((1ull << lane) - 1ull))] = g;
     __syncthreads();
-    for (int e = 0; e < nhit; ++e) {
-      const int p = list[e];
-      const int* c = cenb + (size_t)p * 3;
-      const int di = ni - c[0] + 1, dj = nj - c[1] + 1, dk = nk - c[2] + 1;
-      if (di >= 0 && di < 3 && dj >= 0 && dj < 3 && dk >= 0 && dk < 3) {
-        const double* wt = wts + (size_t)p * 9;
-        acc += (T)amt[p] * (T)(wt[di] * wt[3 + dj] * wt[6 + dk]);
+    for (int b0 = 0; b0 < total; b0 += NW) {
+      // wavefront w takes group glist[b0 + w] and keeps the points whose support meets the tile
+      bool keep = false;
+      int q = 0, cx = 0, cy = 0, cz = 0;
+      if (b0 + wv < total) {
+        q = glist[b0 + wv] * PG + lane;
+        if (q < ps.n) {
+          const int* c = cenb + (size_t)q * 3;
+          cx = c[0];
+          cy = c[1];
+          cz = c[2];
+          keep = cx + 1 >= x0 && cx - 1 < x0 + TS && cy + 1 >= y0 && cy - 1 < y0 + TS && cz + 1 >= z0 &&
+                 cz - 1 < z0 + TS;
+        }
       }
+      const unsigned long long mk = __ballot(keep);
+      if (lane == 0) pcount[wv] = __popcll(mk);
+      __syncthreads();
+      int poff = 0, np = 0;
+      for (int w = 0; w < NW; ++w) {
+        poff += w < wv ? pcount[w] : 0;
+        np += pcount[w];
+      }
+      if (keep) {
+        const int e = poff + __popcll(mk & ((1ull << lane) - 1ull));
+        sc[e] = make_int4(cx, cy, cz, 0);
+        const double* wt = wts + (size_t)q * 9;
+        for (int t = 0; t < 9; ++t) sw[e][t] = wt[t];
+        sa[e] = amt[q];
+      }
+      __syncthreads();
+      int e = 0;
+      for (; e + 4 <= np; e += 4) {
+        int4 c[4];
+#pragma unroll
+        for (int u = 0; u < 4; ++u) c[u] = sc[e + u];
+#pragma unroll
+        for (int u = 0; u < 4; ++u) {
+          const int di = ni - c[u].x + 1, dj = nj - c[u].y + 1, dk = nk - c[u].z + 1;
+          if ((unsigned)di < 3u && (unsigned)dj < 3u && (unsigned)dk < 3u)
+            acc += (T)sa[e + u] * (T)(sw[e + u][di] * sw[e + u][3 + dj] * sw[e + u][6 + dk]);
+        }
+      }
+      for (; e < np; ++e) {
+        const int4 c = sc[e];
+        const int di = ni - c.x + 1, dj = nj - c.y + 1, dk = nk - c.z + 1;
+        if ((unsigned)di < 3u && (unsigned)dj < 3u && (unsigned)dk < 3u)
+          acc += (T)sa[e] * (T)(sw[e][di] * sw[e][3 + dj] * sw[e][6 + dk]);
+      }
+      __syncthreads();
     }
-    __syncthreads();
   }
   if (ni <= bb[3] && nj <= bb[4] && nk <= bb[5]) {
     const int lo = comp == 0 ? 1 : 0;
@@ -230,7 +302,7 @@ template <class T>
 __global__ void __launch_bounds__(256) k_spread_csr(Dims d, Fields f, PointSet ps, SpreadCSR csr, int comp) {
   spread_csr_body<T>(d, f, ps, csr, comp, blockIdx.x);
 }
-__global__ void __launch_bounds__(256) k_point_bbox(PointSet ps, int* bbox) {
+__global__ void __launch_bounds__(BBT) k_point_bbox(PointSet ps, int* bbox) {
   point_bbox_body(ps, bbox, blockIdx.x);
 }
 template <class T>
@@ -265,7 +337,7 @@ __global__ void __launch_bounds__(256) kb_spread_csr(BatchLaunch bl) {
   while (comp < 2 && lb >= pts_blocks(R.csr[comp].nrows)) lb -= pts_blocks(R.csr[comp++].nrows);
   spread_csr_body<T>(R.d, R.f, R.bars, R.csr[comp], comp, lb);
 }
-__global__ void __launch_bounds__(256) kb_point_bbox(BatchLaunch bl) {
+__global__ void __launch_bounds__(BBT) kb_point_bbox(BatchLaunch bl) {
   int lb;
   const RunDesc& R = bl.runs[batch_run(bl, blockIdx.x, &lb)];
   point_bbox_body(R.flag, R.bbox, lb);
@@ -310,7 +382,7 @@ void launch_spread_csr(const Dims& d, const Fields& f, const PointSet& ps, const
 
 void launch_point_bbox(const PointSet& ps, int* bbox, hipStream_t st) {
   if (ps.n == 0) return;
-  hipLaunchKernelGGL(k_point_bbox, dim3(3), dim3(256), 0, st, ps, bbox);
+  hipLaunchKernelGGL(k_point_bbox, dim3(3), dim3(BBT), 0, st, ps, bbox);
 }
 
 void launch_spread_tiles(const Dims& d, const Fields& f, const PointSet& ps, const int* bbox,
@@ -350,7 +422,7 @@ void launch_spread_csr_batch(const BatchLaunch& bl, int nblocks, int mixed, hipS
     hipLaunchKernelGGL(kb_spread_csr<double>, dim3(nblocks), dim3(256), 0, st, bl);
 }
 void launch_point_bbox_batch(const BatchLaunch& bl, int nblocks, hipStream_t st) {
-  hipLaunchKernelGGL(kb_point_bbox, dim3(nblocks), dim3(256), 0, st, bl);
+  hipLaunchKernelGGL(kb_point_bbox, dim3(nblocks), dim3(BBT), 0, st, bl);
 }
 void launch_spread_tiles_batch(const BatchLaunch& bl, int nblocks, int mixed, hipStream_t st) {
   if (mixed)

@@ -100,8 +100,16 @@ struct DFT<8, SIGN> {
   }
 };
 
-// One Stockham pass of radix R over NL lines of length N (line stride LS) in
-// LDS: butterfly i of a line reads x[i + q N/R], applies the twiddles
+// LDS layout of the FFT lines: one padding slot per 16 elements, and a line
+// stride congruent to 9 modulo 16 slots, so that the radix-8 scatter of the
+// first pass and the column-wise staging of 8 lines hit distinct banks.
+__device__ __forceinline__ constexpr int lp(int e) { return e + (e >> 4); }
+__host__ __device__ constexpr int line_stride(int n) {
+  return lp(n) + ((9 - lp(n) % 16) + 16) % 16;
+}
+
+// One Stockham pass of radix R over NL lines of length N (line stride LS,
+// element e at slot lp(e)) in LDS: butterfly i of a line reads x[i + q N/R], applies the twiddles
 // w^(q k), k = i mod P, and writes y[(i/P) P R + k + q P].  All inputs are
 // loaded before the barrier, so the pass runs in place.
 template <int N, int R, int P, int SIGN, int NL, int NT, int LS>
@@ -117,7 +125,7 @@ __device__ __forceinline__ void stockham_pass(double2* buf, const double2* __res
       const int line = g / T, i = g % T;
       const double2* x = buf + line * LS;
 #pragma unroll
-      for (int q = 0; q < R; ++q) v[b][q] = x[i + q * T];
+      for (int q = 0; q < R; ++q) v[b][q] = x[lp(i + q * T)];
     }
   }
   __syncthreads();
@@ -139,7 +147,7 @@ __device__ __forceinline__ void stockham_pass(double2* buf, const double2* __res
       const int j = (i / P) * P * R + k;
       double2* y = buf + line * LS;
 #pragma unroll
-      for (int q = 0; q < R; ++q) y[j + q * P] = v[b][q];
+      for (int q = 0; q < R; ++q) y[lp(j + q * P)] = v[b][q];
     }
   }
   __syncthreads();
@@ -165,7 +173,7 @@ constexpr int FT = 256;  // threads per FFT workgroup
 template <int NY, class T>
 __device__ __forceinline__ void div_ffty_body(const Dims& d, const Fields& f, const Scalars* __restrict__ s,
                                               const double2* __restrict__ tw, const int bx, const int by) {
-  constexpr int TXC = 16, NL = 8, LS = NY + 1, MY = NY / 2 + 1;
+  constexpr int TXC = 16, NL = 8, LS = line_stride(NY), MY = NY / 2 + 1;
   __shared__ double2 buf[NL * LS];
   const T* __restrict__ ut = reinterpret_cast<const T*>(f.ut);
   const T* __restrict__ vt = reinterpret_cast<const T*>(f.vt);
@@ -187,7 +195,7 @@ __device__ __forceinline__ void div_ffty_body(const Dims& d, const Fields& f, co
       r = (((u1 - u0) + ((double)vt[fidx(d, i, jp, k)] - (double)vt[c])) +
            ((double)wt[fidx(d, i, j, kp)] - (double)wt[c])) / d.h / dt;
     }
-    double2* slot = &buf[(ix >> 1) * LS + j];
+    double2* slot = &buf[(ix >> 1) * LS + lp(j)];
     if (ix & 1)
       slot->y = r;
     else
@@ -199,8 +207,8 @@ __device__ __forceinline__ void div_ffty_body(const Dims& d, const Fields& f, co
     const int ix = e % TXC, m = e / TXC;
     const int i = i0 + ix;
     const int L = ix >> 1;
-    const double2 A = buf[L * LS + m];
-    const double2 B = buf[L * LS + (m == 0 ? 0 : NY - m)];
+    const double2 A = buf[L * LS + lp(m)];
+    const double2 B = buf[L * LS + lp(m == 0 ? 0 : NY - m)];
     double2 out;
     if ((ix & 1) == 0)
       out = make_double2(0.5 * (A.x + B.x), 0.5 * (A.y - B.y));   // (Z_m + conj Z_{N-m}) / 2
@@ -214,7 +222,7 @@ __device__ __forceinline__ void div_ffty_body(const Dims& d, const Fields& f, co
 template <int NZ, int SIGN>
 __device__ __forceinline__ void fftz_body(const Dims& d, const Fields& f, const double2* __restrict__ tw,
                                           const int bx, const int by) {
-  constexpr int TXC = 8, NL = 8, LS = NZ + 1;
+  constexpr int TXC = 8, NL = 8, LS = line_stride(NZ);
   __shared__ double2 buf[NL * LS];
   const int i0 = bx * TXC;
   const int m = by;
@@ -223,14 +231,14 @@ __device__ __forceinline__ void fftz_body(const Dims& d, const Fields& f, const 
   for (int e = threadIdx.x; e < TXC * NZ; e += FT) {
     const int ix = e % TXC, k = e / TXC;
     const int i = i0 + ix;
-    buf[ix * LS + k] = (i < d.nx) ? base[i + lstride * k] : make_double2(0.0, 0.0);
+    buf[ix * LS + lp(k)] = (i < d.nx) ? base[i + lstride * k] : make_double2(0.0, 0.0);
   }
   __syncthreads();
   FFTPasses<NZ, 1, SIGN, NL, FT, LS>::run(buf, tw);
   for (int e = threadIdx.x; e < TXC * NZ; e += FT) {
     const int ix = e % TXC, k = e / TXC;
     const int i = i0 + ix;
-    if (i < d.nx) base[i + lstride * k] = buf[ix * LS + k];
+    if (i < d.nx) base[i + lstride * k] = buf[ix * LS + lp(k)];
   }
 }
 
@@ -239,7 +247,7 @@ __device__ __forceinline__ void fftz_body(const Dims& d, const Fields& f, const 
 template <int NY>
 __device__ __forceinline__ void iffty_body(const Dims& d, const Fields& f, const double2* __restrict__ tw,
                                            const int bx, const int by) {
-  constexpr int TXC = 16, NL = 8, LS = NY + 1, MY = NY / 2 + 1;
+  constexpr int TXC = 16, NL = 8, LS = line_stride(NY), MY = NY / 2 + 1;
   __shared__ double2 buf[NL * LS];
   const int i0 = bx * TXC;
   const int k = by;
@@ -253,9 +261,9 @@ __device__ __forceinline__ void iffty_body(const Dims& d, const Fields& f, const
       xe.y = 0.0;
       xo.y = 0.0;
     }
-    buf[L * LS + m] = make_double2(xe.x - xo.y, xe.y + xo.x);          // Xe + i Xo
+    buf[L * LS + lp(m)] = make_double2(xe.x - xo.y, xe.y + xo.x);          // Xe + i Xo
     if (m > 0 && 2 * m < NY)
-      buf[L * LS + NY - m] = make_double2(xe.x + xo.y, xo.x - xe.y);   // conj(Xe) + i conj(Xo)
+      buf[L * LS + lp(NY - m)] = make_double2(xe.x + xo.y, xo.x - xe.y);   // conj(Xe) + i conj(Xo)
   }
   __syncthreads();
   FFTPasses<NY, 1, 1, NL, FT, LS>::run(buf, tw);
@@ -263,7 +271,7 @@ __device__ __forceinline__ void iffty_body(const Dims& d, const Fields& f, const
     const int ix = e % TXC, j = e / TXC;
     const int i = i0 + ix;
     if (i < d.nx) {
-      const double2 z = buf[(ix >> 1) * LS + j];
+      const double2 z = buf[(ix >> 1) * LS + lp(j)];
       f.phi[fidx(d, i, j, k)] = (ix & 1) ? z.y : z.x;
     }
   }
@@ -532,18 +540,22 @@ __device__ __forceinline__ void project_body(const Dims& d, const Fields& f, Sca
   }
 }
 
+// Single-run kernels: 1-D grids; the z FFT takes its tiles in XCD-aware order.
 template <int NY, class T>
 __global__ void __launch_bounds__(FT) k_div_ffty(Dims d, Fields f, const Scalars* __restrict__ s,
                                                  const double2* __restrict__ tw) {
-  div_ffty_body<NY, T>(d, f, s, tw, blockIdx.x, blockIdx.y);
+  const int gx = (d.nx + 15) / 16, b = blockIdx.x;
+  div_ffty_body<NY, T>(d, f, s, tw, b % gx, b / gx);
 }
 template <int NZ, int SIGN>
 __global__ void __launch_bounds__(FT) k_fftz(Dims d, Fields f, const double2* __restrict__ tw) {
-  fftz_body<NZ, SIGN>(d, f, tw, blockIdx.x, blockIdx.y);
+  const int gx = (d.nx + 7) / 8, b = xcd_remap(blockIdx.x, gridDim.x);
+  fftz_body<NZ, SIGN>(d, f, tw, b % gx, b / gx);
 }
 template <int NY>
 __global__ void __launch_bounds__(FT) k_iffty(Dims d, Fields f, const double2* __restrict__ tw) {
-  iffty_body<NY>(d, f, tw, blockIdx.x, blockIdx.y);
+  const int gx = (d.nx + 15) / 16, b = blockIdx.x;
+  iffty_body<NY>(d, f, tw, b % gx, b / gx);
 }
 template <int C>
 __global__ void __launch_bounds__(64 * TRI_WAVES) k_tri(Dims d, Fields f, const double* __restrict__ lam_y,
@@ -552,7 +564,8 @@ __global__ void __launch_bounds__(64 * TRI_WAVES) k_tri(Dims d, Fields f, const 
 }
 template <class T>
 __global__ void __launch_bounds__(PBX* PBY) k_project(Dims d, Fields f, Scalars* s, int mode) {
-  project_body<T>(d, f, s, mode, blk_from_grid());
+  const int gx = (d.nx + PBX - 1) / PBX, gy = (d.ny + PBY - 1) / PBY, gz = (d.nz + PKZ - 1) / PKZ;
+  project_body<T>(d, f, s, mode, blk_linear(blockIdx.x, gx, gy, gz));
 }
 
 // ---- batched forms (all runs of the launch share the template size) ----
@@ -566,7 +579,7 @@ __global__ void __launch_bounds__(FT) kb_div_ffty(BatchLaunch bl) {
 template <int NZ, int SIGN>
 __global__ void __launch_bounds__(FT) kb_fftz(BatchLaunch bl) {
   int lb;
-  const RunDesc& R = bl.runs[batch_run(bl, blockIdx.x, &lb)];
+  const RunDesc& R = bl.runs[batch_run(bl, xcd_remap(blockIdx.x, gridDim.x), &lb)];
   const int gx = (R.d.nx + 7) / 8;
   fftz_body<NZ, SIGN>(R.d, R.f, R.tw_z, lb % gx, lb / gx);
 }
@@ -645,7 +658,7 @@ bool fft_size_supported(int n) {
 
 void launch_div_ffty(const Dims& d, const Fields& f, const Scalars* s, const double2* tw_y,
                      hipStream_t st) {
-  dim3 grid((d.nx + 15) / 16, d.nz);
+  dim3 grid(((d.nx + 15) / 16) * d.nz);
   if (d.mixed) {
 #define CALL(NY) hipLaunchKernelGGL((k_div_ffty<NY, float>), grid, dim3(FT), 0, st, d, f, s, tw_y)
     IBDNS_FFT_SWITCH(d.ny, CALL)
@@ -658,7 +671,7 @@ void launch_div_ffty(const Dims& d, const Fields& f, const Scalars* s, const dou
 }
 
 void launch_fftz(const Dims& d, const Fields& f, const double2* tw_z, int sign, hipStream_t st) {
-  dim3 grid((d.nx + 7) / 8, d.MY);
+  dim3 grid(((d.nx + 7) / 8) * d.MY);
   if (sign < 0) {
 #define CALL(NZ) hipLaunchKernelGGL((k_fftz<NZ, -1>), grid, dim3(FT), 0, st, d, f, tw_z)
     IBDNS_FFT_SWITCH(d.nz, CALL)
@@ -671,7 +684,7 @@ void launch_fftz(const Dims& d, const Fields& f, const double2* tw_z, int sign, 
 }
 
 void launch_iffty(const Dims& d, const Fields& f, const double2* tw_y, hipStream_t st) {
-  dim3 grid((d.nx + 15) / 16, d.nz);
+  dim3 grid(((d.nx + 15) / 16) * d.nz);
 #define CALL(NY) hipLaunchKernelGGL(k_iffty<NY>, grid, dim3(FT), 0, st, d, f, tw_y)
   IBDNS_FFT_SWITCH(d.ny, CALL)
 #undef CALL
@@ -707,7 +720,7 @@ int project_blocks(const Dims& d) {
 }
 
 void launch_project(const Dims& d, const Fields& f, Scalars* s, int mode, hipStream_t st) {
-  dim3 grid((d.nx + PBX - 1) / PBX, (d.ny + PBY - 1) / PBY, (d.nz + PKZ - 1) / PKZ);
+  dim3 grid(((d.nx + PBX - 1) / PBX) * ((d.ny + PBY - 1) / PBY) * ((d.nz + PKZ - 1) / PKZ));
   if (d.mixed)
     hipLaunchKernelGGL(k_project<float>, grid, dim3(PBX * PBY), 0, st, d, f, s, mode);
   else

@@ -175,7 +175,8 @@ __device__ __forceinline__ void predict_body(const Dims& d, const Fields& f, con
 
 template <class T, int TX, int TY, int KZ>
 __global__ void __launch_bounds__(TX* TY) k_predict(Dims d, Fields f, const Scalars* __restrict__ s) {
-  predict_body<T, TX, TY, KZ>(d, f, s, blk_from_grid());
+  const int gx = (d.nx + TX - 1) / TX, gy = (d.ny + TY - 1) / TY, gz = (d.nz + KZ - 1) / KZ;
+  predict_body<T, TX, TY, KZ>(d, f, s, blk_linear(blockIdx.x, gx, gy, gz));
 }
 
 template <class T, int TX, int TY, int KZ>
@@ -333,7 +334,7 @@ void launch_predict(const Dims& d, const Fields& f, const Scalars* s, int varian
   switch (variant) {
 #define X(V, TX_, TY_, KZ_)                                                                          \
     case V: {                                                                                        \
-      dim3 grid((d.nx + TX_ - 1) / TX_, (d.ny + TY_ - 1) / TY_, (d.nz + KZ_ - 1) / KZ_);              \
+      dim3 grid(((d.nx + TX_ - 1) / TX_) * ((d.ny + TY_ - 1) / TY_) * ((d.nz + KZ_ - 1) / KZ_));      \
       if (d.mixed)                                                                                   \
         hipLaunchKernelGGL((k_predict<float, TX_, TY_, KZ_>), grid, dim3(TX_ * TY_), 0, st, d, f, s);  \
       else                                                                                           \
