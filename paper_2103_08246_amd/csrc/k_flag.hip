@@ -27,7 +27,7 @@ namespace ibdns {
 
 namespace {
 
-constexpr int FR = 8;            // rows per band
+constexpr int FR = 4;            // rows per band
 constexpr int FT_ = 256;         // threads per band
 constexpr int MAXN = (FR * 128 + FT_ - 1) / FT_;  // owned nodes per thread (ns <= 128)
 constexpr long long SPIN_LIMIT = 1LL << 22;   // bounded wait (seconds at most)
@@ -267,18 +267,32 @@ __global__ void __launch_bounds__(FT_) kb_flag(BatchLaunch bl) {
 }
 
 // dt_{n+1} from the cell-speed maxima of the projection, then t, history.
-__device__ __forceinline__ void advance_body(Scalars* s, const double* partial, int nparts, double h) {
-  __shared__ double red[256];
-  double m = 0.0;
-  for (int q = threadIdx.x; q < nparts; q += 256) m = fmax(m, partial[q]);
-  red[threadIdx.x] = m;
-  __syncthreads();
-  for (int w = 128; w > 0; w >>= 1) {
-    if ((int)threadIdx.x < w) red[threadIdx.x] = fmax(red[threadIdx.x], red[threadIdx.x + w]);
-    __syncthreads();
+constexpr int RT = 1024;  // threads of the one-workgroup reductions
+
+// Maximum of the per-block speed maxima (non-negative), valid in thread 0.
+__device__ __forceinline__ double block_max(const double* __restrict__ partial, int nparts) {
+  __shared__ double red[RT / 64];
+  double m0 = 0.0, m1 = 0.0, m2 = 0.0, m3 = 0.0;
+  int q = threadIdx.x;
+  for (; q + 3 * RT < nparts; q += 4 * RT) {
+    m0 = fmax(m0, partial[q]);
+    m1 = fmax(m1, partial[q + RT]);
+    m2 = fmax(m2, partial[q + 2 * RT]);
+    m3 = fmax(m3, partial[q + 3 * RT]);
   }
+  for (; q < nparts; q += RT) m0 = fmax(m0, partial[q]);
+  double m = fmax(fmax(m0, m1), fmax(m2, m3));
+  for (int o = 32; o > 0; o >>= 1) m = fmax(m, __shfl_xor(m, o, 64));
+  if ((threadIdx.x & 63) == 0) red[threadIdx.x >> 6] = m;
+  __syncthreads();
+  if (threadIdx.x == 0)
+    for (int w = 1; w < RT / 64; ++w) m = fmax(m, red[w]);
+  return m;
+}
+
+__device__ __forceinline__ void advance_body(Scalars* s, const double* partial, int nparts, double h) {
+  const double speed = block_max(partial, nparts);
   if (threadIdx.x != 0) return;
-  const double speed = red[0];
   s->speed_last = speed;
   double dt_next;
   if (s->dt_fixed > 0.0) {
@@ -294,28 +308,19 @@ __device__ __forceinline__ void advance_body(Scalars* s, const double* partial, 
   s->first = 0;
 }
 
-__global__ void __launch_bounds__(256) k_advance(Scalars* s, const double* partial, int nparts, double h) {
+__global__ void __launch_bounds__(RT) k_advance(Scalars* s, const double* partial, int nparts, double h) {
   advance_body(s, partial, nparts, h);
 }
-__global__ void __launch_bounds__(256) kb_advance(BatchLaunch bl) {
+__global__ void __launch_bounds__(RT) kb_advance(BatchLaunch bl) {
   int lb;
   const RunDesc& R = bl.runs[batch_run(bl, blockIdx.x, &lb)];
   advance_body(R.s, R.f.speed_part, R.nspeed, R.d.h);
 }
 
 // dt_0 after the initial projection.
-__global__ void __launch_bounds__(256) k_set_dt0(Scalars* s, const double* partial, int nparts, double h) {
-  __shared__ double red[256];
-  double m = 0.0;
-  for (int q = threadIdx.x; q < nparts; q += 256) m = fmax(m, partial[q]);
-  red[threadIdx.x] = m;
-  __syncthreads();
-  for (int w = 128; w > 0; w >>= 1) {
-    if ((int)threadIdx.x < w) red[threadIdx.x] = fmax(red[threadIdx.x], red[threadIdx.x + w]);
-    __syncthreads();
-  }
+__global__ void __launch_bounds__(RT) k_set_dt0(Scalars* s, const double* partial, int nparts, double h) {
+  const double speed = block_max(partial, nparts);
   if (threadIdx.x != 0) return;
-  const double speed = red[0];
   s->speed_last = speed;
   const double dt0 = s->dt_fixed > 0.0 ? s->dt_fixed : (speed > 0.0 ? s->cfl * h / speed : 1.0);
   s->dt = dt0;
@@ -341,11 +346,11 @@ hipError_t launch_flag_step(const FlagDev& fl, Scalars* s, hipStream_t st) {
 }
 
 void launch_advance(Scalars* s, const double* partial, int nparts, double h, hipStream_t st) {
-  hipLaunchKernelGGL(k_advance, dim3(1), dim3(256), 0, st, s, partial, nparts, h);
+  hipLaunchKernelGGL(k_advance, dim3(1), dim3(RT), 0, st, s, partial, nparts, h);
 }
 
 void launch_set_dt0(Scalars* s, const double* partial, int nparts, double h, hipStream_t st) {
-  hipLaunchKernelGGL(k_set_dt0, dim3(1), dim3(256), 0, st, s, partial, nparts, h);
+  hipLaunchKernelGGL(k_set_dt0, dim3(1), dim3(RT), 0, st, s, partial, nparts, h);
 }
 
 }  // namespace ibdns
@@ -358,7 +363,7 @@ void launch_flag_batch(const BatchLaunch& prep, int nprep, const BatchLaunch& ba
 }
 
 void launch_advance_batch(const BatchLaunch& bl, int nblocks, hipStream_t st) {
-  hipLaunchKernelGGL(kb_advance, dim3(nblocks), dim3(256), 0, st, bl);
+  hipLaunchKernelGGL(kb_advance, dim3(nblocks), dim3(RT), 0, st, bl);
 }
 
 }  // namespace ibdns

@@ -10,17 +10,20 @@
 // Kernels:
 //   k_div_ffty  divergence of u~ fused with the real-to-complex y FFT of r
 //               (two real x-columns packed into one complex line);
-//   k_fftz      complex z FFT in place on the half spectrum (both signs);
+//   k_fftz      complex z FFT in place on the half spectrum (both signs),
+//               persistent workgroups that prefetch their next tile;
 //   k_tri       one wavefront per x-line: each lane eliminates a contiguous
 //               chunk down to its two end unknowns, the 128-row reduced system
-//               is solved by cyclic reduction in LDS, then back-substitution;
-//               the singular line is solved by a serial Thomas sweep;
+//               is solved by cyclic reduction in LDS, then back-substitution
+//               (the singular line too, pinned, then its mean removed);
 //   k_iffty     complex-to-real inverse y FFT to phi;
 //   k_project   projection, pressure update and the CFL maximum (max of the
-//               cell speed per block, one atomicMax per block).
+//               cell speed per block, written to a per-block slot).
 // FFTs: mixed-radix (8, 4, 2, 3) Stockham passes over lines held in LDS, one
 // register-staged butterfly set per thread and pass, twiddles from a table
 // exp(-2 pi i m / N) built on the host.
+#include <algorithm>
+
 #include "ibdns_internal.h"
 
 namespace ibdns {
@@ -100,27 +103,27 @@ struct DFT<8, SIGN> {
   }
 };
 
-// LDS layout of the FFT lines: one padding slot per 16 elements, and a line
-// stride congruent to 9 modulo 16 slots, so that the radix-8 scatter of the
-// first pass and the column-wise staging of 8 lines hit distinct banks.
-__device__ __forceinline__ constexpr int lp(int e) { return e + (e >> 4); }
-__host__ __device__ constexpr int line_stride(int n) {
-  return lp(n) + ((9 - lp(n) % 16) + 16) % 16;
-}
+// LDS layout of the FFT lines: element e of a line sits at slot
+// e ^ ((e >> 3) & 7), a permutation inside each aligned group of 8 (all
+// supported lengths are multiples of 8).  Runs of 8 consecutive elements and
+// the radix-8 scatter of stride 8 then both land on 8 distinct 16-byte bank
+// groups; the odd line stride does the same for the 8-line staging.
+__device__ __forceinline__ constexpr int lp(int e) { return e ^ ((e >> 3) & 7); }
+__host__ __device__ constexpr int line_stride(int n) { return n + 1; }
 
 // One Stockham pass of radix R over NL lines of length N (line stride LS,
 // element e at slot lp(e)) in LDS: butterfly i of a line reads x[i + q N/R], applies the twiddles
 // w^(q k), k = i mod P, and writes y[(i/P) P R + k + q P].  All inputs are
 // loaded before the barrier, so the pass runs in place.
 template <int N, int R, int P, int SIGN, int NL, int NT, int LS>
-__device__ __forceinline__ void stockham_pass(double2* buf, const double2* __restrict__ tw) {
+__device__ __forceinline__ void stockham_pass(double2* buf, const double2* __restrict__ tw, const int tid) {
   constexpr int T = N / R;
   constexpr int TOT = T * NL;
   constexpr int NB = (TOT + NT - 1) / NT;
   double2 v[NB][R];
 #pragma unroll
   for (int b = 0; b < NB; ++b) {
-    const int g = threadIdx.x + b * NT;
+    const int g = tid + b * NT;
     if (g < TOT) {
       const int line = g / T, i = g % T;
       const double2* x = buf + line * LS;
@@ -131,7 +134,7 @@ __device__ __forceinline__ void stockham_pass(double2* buf, const double2* __res
   __syncthreads();
 #pragma unroll
   for (int b = 0; b < NB; ++b) {
-    const int g = threadIdx.x + b * NT;
+    const int g = tid + b * NT;
     if (g < TOT) {
       const int line = g / T, i = g % T;
       const int k = i % P;
@@ -155,13 +158,15 @@ __device__ __forceinline__ void stockham_pass(double2* buf, const double2* __res
 
 template <int N, int P, int SIGN, int NL, int NT, int LS>
 struct FFTPasses {
-  static __device__ __forceinline__ void run(double2* buf, const double2* __restrict__ tw) {
+  static_assert(N % 8 == 0, "the LDS swizzle permutes aligned groups of 8");
+  static __device__ __forceinline__ void run(double2* buf, const double2* __restrict__ tw,
+                                             const int tid = threadIdx.x) {
     constexpr int REM = N / P;
     if constexpr (REM > 1) {
       constexpr int R = (REM % 8 == 0) ? 8 : (REM % 4 == 0) ? 4 : (REM % 2 == 0) ? 2 : 3;
       static_assert(REM % R == 0, "FFT length must be 2^a 3^b");
-      stockham_pass<N, R, P, SIGN, NL, NT, LS>(buf, tw);
-      FFTPasses<N, P * R, SIGN, NL, NT, LS>::run(buf, tw);
+      stockham_pass<N, R, P, SIGN, NL, NT, LS>(buf, tw, tid);
+      FFTPasses<N, P * R, SIGN, NL, NT, LS>::run(buf, tw, tid);
     }
   }
 };
@@ -242,6 +247,58 @@ __device__ __forceinline__ void fftz_body(const Dims& d, const Fields& f, const 
   }
 }
 
+// Persistent form of the z FFT: workgroup w takes tiles w, w + G, w + 2G, ...
+// (G workgroups, XCD-contiguous within each round) and loads the next tile
+// into registers while it transforms the current one in LDS.
+template <int NZ, int SIGN>
+__device__ __forceinline__ void fftz_stream_body(const Dims& d, const Fields& f, const double2* __restrict__ tw,
+                                                 const int w, const int G) {
+  constexpr int TXC = 8, NL = 8, LS = line_stride(NZ);
+  constexpr int NEL = (TXC * NZ + FT - 1) / FT;
+  __shared__ double2 buf[NL * LS];
+  const int gx = (d.nx + TXC - 1) / TXC;
+  const int ntiles = gx * d.MY;
+  const long long lstride = (long long)d.nx * d.MY;
+  double2 pre[NEL];
+  auto fetch = [&](int t) {
+    const int i0 = (t % gx) * TXC, m = t / gx;
+    const double2* base = f.spec + (long long)d.nx * m;
+#pragma unroll
+    for (int q = 0; q < NEL; ++q) {
+      const int e = threadIdx.x + q * FT;
+      const int ix = e % TXC, k = e / TXC;
+      pre[q] = (e < TXC * NZ && i0 + ix < d.nx) ? base[i0 + ix + lstride * k] : make_double2(0.0, 0.0);
+    }
+  };
+  int t = xcd_remap(w, G);
+  if (t < ntiles) fetch(t);
+  for (int round = 0; t < ntiles; ++round) {
+    __syncthreads();  // the previous tile's results have left LDS
+#pragma unroll
+    for (int q = 0; q < NEL; ++q) {
+      const int e = threadIdx.x + q * FT;
+      if (e < TXC * NZ) buf[(e % TXC) * LS + lp(e / TXC)] = pre[q];
+    }
+    __syncthreads();
+    const int tn = (round + 1) * G + xcd_remap(w, G);
+    if (tn < ntiles) fetch(tn);  // in flight during the passes below
+    // opaque copies of the twiddle pointer and thread index per round keep the
+    // compiler from hoisting every pass's twiddles and LDS offsets out of the
+    // loop into registers
+    const double2* twr = tw;
+    int tid = threadIdx.x;
+    asm volatile("" : "+s"(twr), "+v"(tid));
+    FFTPasses<NZ, 1, SIGN, NL, FT, LS>::run(buf, twr, tid);
+    const int i0 = (t % gx) * TXC, m = t / gx;
+    double2* base = f.spec + (long long)d.nx * m;
+    for (int e = threadIdx.x; e < TXC * NZ; e += FT) {
+      const int ix = e % TXC, k = e / TXC;
+      if (i0 + ix < d.nx) base[i0 + ix + lstride * k] = buf[ix * LS + lp(k)];
+    }
+    t = tn;
+  }
+}
+
 // Inverse y FFT of a 16-column tile of one z plane to phi (unnormalised; the
 // 1/(ny nz) factor is applied in k_tri).
 template <int NY>
@@ -298,76 +355,67 @@ __device__ __forceinline__ void tri_coef(int g, int nx, double shift, bool singu
   }
 }
 
+// The lines of a workgroup are independent: one wavefront per line, and the
+// LDS exchanges inside a line only need wavefront-level ordering (the LDS
+// executes a wavefront's accesses in issue order).
+__device__ __forceinline__ void wave_sync() {
+  __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+  __builtin_amdgcn_wave_barrier();
+  __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+}
+
+// 1/x for the well-scaled pivots of the x systems: hardware estimate and two
+// Newton steps (within an ulp or so of the correctly rounded quotient).
+__device__ __forceinline__ double rcp64(double x) {
+  double r = __builtin_amdgcn_rcp(x);
+  r = fma(r, fma(-x, r, 1.0), r);
+  r = fma(r, fma(-x, r, 1.0), r);
+  return r;
+}
+
+// Storage slot of reduced row r (rows 2 lane and 2 lane + 1 of a lane land
+// in the two halves, so that every access of the reduction is unit-stride).
+__device__ __forceinline__ int rpos(int r) { return (r & 1) * 64 + (r >> 1); }
+
 template <int C>
 __device__ __forceinline__ void tri_body(const Dims& d, const Fields& f, const double* __restrict__ lam_y,
                                          const double* __restrict__ lam_z, double scale, const int bx) {
-  constexpr int LSP = C + 1;     // LDS chunk stride (padding against bank conflicts)
+  constexpr int LSP = C + 1;     // LDS chunk stride (odd: lanes hit distinct banks)
   constexpr int R = 128;         // reduced rows (2 per lane)
   __shared__ double2 lb[TRI_WAVES][64 * LSP];
   __shared__ double rA[TRI_WAVES][R], rB[TRI_WAVES][R], rC[TRI_WAVES][R];
   __shared__ double2 rD[TRI_WAVES][R];
-  __shared__ double cps[64 * C];   // c' of the singular line (one per grid)
   const int wv = threadIdx.x / 64, lane = threadIdx.x % 64;
   const long long nlines = (long long)d.MY * d.nz;
   const long long line = (long long)bx * TRI_WAVES + wv;
-  const bool active = line < nlines;
-  const int m = active ? (int)(line % d.MY) : 0;
-  const int l = active ? (int)(line / d.MY) : 0;
+  if (line >= nlines) return;   // the whole wavefront
+  const int m = (int)(line % d.MY);
+  const int l = (int)(line / d.MY);
   const int nx = d.nx;
-  double2* g = f.spec + (active ? line : 0) * (long long)nx;
+  // the (0, 0) mode is singular: its row 0 becomes phi_0 = 0 and its x-mean is
+  // removed afterwards
+  const bool singular = m == 0 && l == 0;
+  double2* g = f.spec + line * (long long)nx;
   double2* L = lb[wv];
+  double* A_ = rA[wv];
+  double* B_ = rB[wv];
+  double* C_ = rC[wv];
+  double2* D_ = rD[wv];
 
   for (int t = 0; t < C; ++t) {
     const int e = lane + 64 * t;
-    L[(e / C) * LSP + e % C] = (active && e < nx) ? cscale(g[e], scale) : make_double2(0.0, 0.0);
+    L[(e / C) * LSP + e % C] = (e < nx && !(singular && e == 0)) ? cscale(g[e], scale) : make_double2(0.0, 0.0);
   }
-  __syncthreads();
-  const double shift = active ? (d.h * d.h) * (lam_z[l] + lam_y[m]) : -1.0;
-  const bool singular = active && m == 0 && l == 0;
+  wave_sync();
+  const double shift = (d.h * d.h) * (lam_z[l] + lam_y[m]);
   double2 x[C];
-
-  if (singular) {
-    // serial Thomas sweep of the singular line (row 0 replaced by phi_0 = 0),
-    // then removal of the x-mean; c' kept in LDS
-    if (lane == 0) {
-      double cp = 0.0;
-      double2 dp = make_double2(0.0, 0.0);
-      for (int e = 0; e < nx; ++e) {
-        double a, b, c;
-        tri_coef(e, nx, shift, true, a, b, c);
-        const double2 dd = (e == 0) ? make_double2(0.0, 0.0) : L[(e / C) * LSP + e % C];
-        const double den = b - a * cp;
-        cp = c / den;
-        dp = make_double2((dd.x - a * dp.x) / den, (dd.y - a * dp.y) / den);
-        cps[e] = cp;
-        L[(e / C) * LSP + e % C] = dp;
-      }
-      double2 xn = make_double2(0.0, 0.0);
-      for (int e = nx - 1; e >= 0; --e) {
-        const double2 dpe = L[(e / C) * LSP + e % C];
-        const double2 xe = (e == nx - 1) ? dpe : make_double2(dpe.x - cps[e] * xn.x, dpe.y - cps[e] * xn.y);
-        L[(e / C) * LSP + e % C] = xe;
-        xn = xe;
-      }
-      double2 sum = make_double2(0.0, 0.0);
-      for (int e = 0; e < nx; ++e) sum = cadd(sum, L[(e / C) * LSP + e % C]);
-      const double2 mean = make_double2(sum.x / nx, sum.y / nx);
-      for (int e = 0; e < nx; ++e) L[(e / C) * LSP + e % C] = csub(L[(e / C) * LSP + e % C], mean);
-    }
-    // same number of barriers as the cyclic reduction of the other waves
-    for (int st = 1; st < R; st <<= 1) {
-      __syncthreads();
-      __syncthreads();
-    }
-#pragma unroll
-    for (int t = 0; t < C; ++t) x[t] = L[lane * LSP + t];
-  } else {
+  {
     const int s0 = lane * C;
     double a[C], b[C], c[C];
     double2 dd[C];
 #pragma unroll
     for (int t = 0; t < C; ++t) {
-      tri_coef(s0 + t, nx, shift, false, a[t], b[t], c[t]);
+      tri_coef(s0 + t, nx, shift, singular, a[t], b[t], c[t]);
       dd[t] = L[lane * LSP + t];
     }
     double cp[C], be[C], ga[C];
@@ -383,7 +431,7 @@ __device__ __forceinline__ void tri_body(const Dims& d, const Fields& f, const d
 #pragma unroll
     for (int t = 1; t <= C - 2; ++t) {
       const double den = (t == 1) ? b[1] : b[t] - a[t] * cp[t - 1];
-      const double inv = 1.0 / den;
+      const double inv = rcp64(den);
       cp[t] = c[t] * inv;
       if (t == 1) {
         al[t] = cscale(dd[1], inv);
@@ -417,55 +465,70 @@ __device__ __forceinline__ void tri_body(const Dims& d, const Fields& f, const d
       A1 = a[1]; B1 = b[1]; C1 = c[1]; D1 = dd[1];
     }
     const int r0 = 2 * lane, r1 = 2 * lane + 1;
-    rA[wv][r0] = A0; rB[wv][r0] = B0; rC[wv][r0] = C0; rD[wv][r0] = D0;
-    rA[wv][r1] = A1; rB[wv][r1] = B1; rC[wv][r1] = C1; rD[wv][r1] = D1;
-    // cyclic reduction (PCR) of the reduced system
+    A_[rpos(r0)] = A0; B_[rpos(r0)] = B0; C_[rpos(r0)] = C0; D_[rpos(r0)] = D0;
+    A_[rpos(r1)] = A1; B_[rpos(r1)] = B1; C_[rpos(r1)] = C1; D_[rpos(r1)] = D1;
+    // parallel cyclic reduction of the reduced system
     for (int st = 1; st < R; st <<= 1) {
-      __syncthreads();
+      wave_sync();
       double nA[2], nB[2], nC[2];
       double2 nD[2];
 #pragma unroll
       for (int q = 0; q < 2; ++q) {
         const int r = 2 * lane + q;
         const int rm = r - st, rp = r + st;
-        double Aq = 0.0, Cq = 0.0, Bq = rB[wv][r];
-        double2 Dq = rD[wv][r];
+        const double Ar = A_[rpos(r)], Cr = C_[rpos(r)];
+        double Aq = 0.0, Cq = 0.0, Bq = B_[rpos(r)];
+        double2 Dq = D_[rpos(r)];
         if (rm >= 0) {
-          const double k1 = rA[wv][r] / rB[wv][rm];
-          Aq = -rA[wv][rm] * k1;
-          Bq -= rC[wv][rm] * k1;
-          Dq = csub(Dq, cscale(rD[wv][rm], k1));
+          const double k1 = Ar * rcp64(B_[rpos(rm)]);
+          Aq = -A_[rpos(rm)] * k1;
+          Bq -= C_[rpos(rm)] * k1;
+          Dq = csub(Dq, cscale(D_[rpos(rm)], k1));
         }
         if (rp < R) {
-          const double k2 = rC[wv][r] / rB[wv][rp];
-          Cq = -rC[wv][rp] * k2;
-          Bq -= rA[wv][rp] * k2;
-          Dq = csub(Dq, cscale(rD[wv][rp], k2));
+          const double k2 = Cr * rcp64(B_[rpos(rp)]);
+          Cq = -C_[rpos(rp)] * k2;
+          Bq -= A_[rpos(rp)] * k2;
+          Dq = csub(Dq, cscale(D_[rpos(rp)], k2));
         }
         nA[q] = Aq; nB[q] = Bq; nC[q] = Cq; nD[q] = Dq;
       }
-      __syncthreads();
+      wave_sync();
 #pragma unroll
       for (int q = 0; q < 2; ++q) {
         const int r = 2 * lane + q;
-        rA[wv][r] = nA[q]; rB[wv][r] = nB[q]; rC[wv][r] = nC[q]; rD[wv][r] = nD[q];
+        A_[rpos(r)] = nA[q]; B_[rpos(r)] = nB[q]; C_[rpos(r)] = nC[q]; D_[rpos(r)] = nD[q];
       }
     }
-    const double2 xs = cscale(rD[wv][r0], 1.0 / rB[wv][r0]);
-    const double2 xe = cscale(rD[wv][r1], 1.0 / rB[wv][r1]);
+    wave_sync();
+    const double2 xs = cscale(D_[rpos(r0)], rcp64(B_[rpos(r0)]));
+    const double2 xe = cscale(D_[rpos(r1)], rcp64(B_[rpos(r1)]));
     x[0] = xs;
     x[C - 1] = xe;
 #pragma unroll
     for (int t = 1; t <= C - 2; ++t)
       x[t] = make_double2(al[t].x + be[t] * xs.x + ga[t] * xe.x, al[t].y + be[t] * xs.y + ga[t] * xe.y);
   }
-  __syncthreads();
+  if (singular) {  // remove the x-mean (fixed summation order: lanes, then a butterfly)
+    double2 sm = make_double2(0.0, 0.0);
+#pragma unroll
+    for (int t = 0; t < C; ++t)
+      if (lane * C + t < nx) sm = cadd(sm, x[t]);
+    for (int o = 1; o < 64; o <<= 1) {
+      sm.x += __shfl_xor(sm.x, o, 64);
+      sm.y += __shfl_xor(sm.y, o, 64);
+    }
+    const double2 mean = make_double2(sm.x / nx, sm.y / nx);
+#pragma unroll
+    for (int t = 0; t < C; ++t) x[t] = csub(x[t], mean);
+  }
+  wave_sync();
 #pragma unroll
   for (int t = 0; t < C; ++t) L[lane * LSP + t] = x[t];
-  __syncthreads();
+  wave_sync();
   for (int t = 0; t < C; ++t) {
     const int e = lane + 64 * t;
-    if (active && e < nx) g[e] = L[(e / C) * LSP + e % C];
+    if (e < nx) g[e] = L[(e / C) * LSP + e % C];
   }
 }
 
@@ -548,9 +611,9 @@ __global__ void __launch_bounds__(FT) k_div_ffty(Dims d, Fields f, const Scalars
   div_ffty_body<NY, T>(d, f, s, tw, b % gx, b / gx);
 }
 template <int NZ, int SIGN>
-__global__ void __launch_bounds__(FT) k_fftz(Dims d, Fields f, const double2* __restrict__ tw) {
-  const int gx = (d.nx + 7) / 8, b = xcd_remap(blockIdx.x, gridDim.x);
-  fftz_body<NZ, SIGN>(d, f, tw, b % gx, b / gx);
+__global__ void __launch_bounds__(FT) k_fftz(Dims d, Fields f,
+                                                                             const double2* __restrict__ tw) {
+  fftz_stream_body<NZ, SIGN>(d, f, tw, blockIdx.x, gridDim.x);
 }
 template <int NY>
 __global__ void __launch_bounds__(FT) k_iffty(Dims d, Fields f, const double2* __restrict__ tw) {
@@ -670,14 +733,35 @@ void launch_div_ffty(const Dims& d, const Fields& f, const Scalars* s, const dou
   }
 }
 
+// Workgroups of a persistent launch: as many as fit on the device at once
+// (occupancy queried once per kernel), at most one per tile.
+template <class K>
+static int resident_grid(K kernel, int threads, int ntiles) {
+  static int cus = 0;
+  if (cus == 0) {
+    int dev = 0;
+    hipGetDevice(&dev);
+    hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev);
+    if (cus <= 0) cus = 1;
+  }
+  int per_cu = 0;
+  if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, kernel, threads, 0) != hipSuccess || per_cu <= 0)
+    per_cu = 1;
+  return std::min(ntiles, per_cu * cus);
+}
+
 void launch_fftz(const Dims& d, const Fields& f, const double2* tw_z, int sign, hipStream_t st) {
-  dim3 grid(((d.nx + 7) / 8) * d.MY);
+  const int ntiles = ((d.nx + 7) / 8) * d.MY;
   if (sign < 0) {
-#define CALL(NZ) hipLaunchKernelGGL((k_fftz<NZ, -1>), grid, dim3(FT), 0, st, d, f, tw_z)
+#define CALL(NZ)                                                                         \
+  hipLaunchKernelGGL((k_fftz<NZ, -1>), dim3(resident_grid(k_fftz<NZ, -1>, FT, ntiles)), dim3(FT), 0, st, \
+                     d, f, tw_z)
     IBDNS_FFT_SWITCH(d.nz, CALL)
 #undef CALL
   } else {
-#define CALL(NZ) hipLaunchKernelGGL((k_fftz<NZ, 1>), grid, dim3(FT), 0, st, d, f, tw_z)
+#define CALL(NZ)                                                                        \
+  hipLaunchKernelGGL((k_fftz<NZ, 1>), dim3(resident_grid(k_fftz<NZ, 1>, FT, ntiles)), dim3(FT), 0, st, \
+                     d, f, tw_z)
     IBDNS_FFT_SWITCH(d.nz, CALL)
 #undef CALL
   }

@@ -12,7 +12,8 @@ namespace ibdns {
 namespace {
 
 // Tile shapes (x, y, z-planes) the autotuner chooses from; 0 is the default.
-#define IBDNS_PREDICT_VARIANTS(X) X(0, 64, 8, 16) X(1, 64, 4, 32) X(2, 64, 8, 32) X(3, 32, 8, 16) X(4, 64, 16, 8)
+#define IBDNS_PREDICT_VARIANTS(X) \
+  X(0, 64, 8, 16) X(1, 64, 4, 32) X(2, 64, 8, 32) X(3, 32, 8, 16) X(4, 64, 16, 8) X(5, 64, 16, 16) X(6, 32, 16, 32)
 
 template <class T>
 __device__ __forceinline__ T sq(T a) { return a * a; }
@@ -46,29 +47,59 @@ __device__ __forceinline__ void predict_body(const Dims& d, const Fields& f, con
   const double* __restrict__ w = f.w;
   const double* __restrict__ p = f.p;
 
-  auto load_plane = [&](int kk_unwrapped, int slot) {
+  // Plane loads go through registers: the loads of plane k+2 (and p of
+  // plane k+1) are issued before the work on plane k and land in LDS after it.
+  constexpr int NT = TX * TY, NE = (LP + NT - 1) / NT;
+  T ru[NE], rv[NE], rw[NE], rp[NE];
+  auto fetch_plane = [&](int kk_unwrapped) {
     const int kk = wrapi(kk_unwrapped, d.nz);
-    for (int e = tid; e < LP; e += TX * TY) {
+#pragma unroll
+    for (int q = 0; q < NE; ++q) {
+      const int e = tid + q * NT;
       const int lx = e % LX, ly = e / LX;
       const int gi = i0 - 1 + lx, gj = wrapi(j0 - 1 + ly, d.ny);
       T a = 0, b = 0, c = 0;
-      if (gi >= 0 && gi <= nx) {
+      if (e < LP && gi >= 0 && gi <= nx) {
         const long long o = fidx(d, gi, gj, kk);
         a = (T)u[o];
         b = (T)v[o];
         c = (T)w[o];
       }
-      su[slot][e] = a;
-      sv[slot][e] = b;
-      sw[slot][e] = c;
+      ru[q] = a;
+      rv[q] = b;
+      rw[q] = c;
     }
   };
-  auto load_p = [&](int kk) {
-    for (int e = tid; e < LP; e += TX * TY) {
+  auto fetch_p = [&](int kk) {
+#pragma unroll
+    for (int q = 0; q < NE; ++q) {
+      const int e = tid + q * NT;
       const int lx = e % LX, ly = e / LX;
       const int gi = i0 - 1 + lx, gj = wrapi(j0 - 1 + ly, d.ny);
-      spp[e] = (gi >= 0 && gi < nx) ? (T)p[fidx(d, gi, gj, kk)] : (T)0;
+      rp[q] = (e < LP && gi >= 0 && gi < nx) ? (T)p[fidx(d, gi, gj, kk)] : (T)0;
     }
+  };
+  auto commit_plane = [&](int slot) {
+#pragma unroll
+    for (int q = 0; q < NE; ++q) {
+      const int e = tid + q * NT;
+      if (e < LP) {
+        su[slot][e] = ru[q];
+        sv[slot][e] = rv[q];
+        sw[slot][e] = rw[q];
+      }
+    }
+  };
+  auto commit_p = [&]() {
+#pragma unroll
+    for (int q = 0; q < NE; ++q) {
+      const int e = tid + q * NT;
+      if (e < LP) spp[e] = rp[q];
+    }
+  };
+  auto load_plane = [&](int kk_unwrapped, int slot) {
+    fetch_plane(kk_unwrapped);
+    commit_plane(slot);
   };
 
   const double dt64 = s->dt;
@@ -84,7 +115,8 @@ __device__ __forceinline__ void predict_body(const Dims& d, const Fields& f, con
   load_plane(kb - 1, 0);
   load_plane(kb, 1);
   load_plane(kb + 1, 2);
-  load_p(kb);
+  fetch_p(kb);
+  commit_p();
   T p_km = active ? (T)p[fidx(d, i, j, wrapi(kb - 1, d.nz))] : (T)0;
   __syncthreads();
 
@@ -95,6 +127,11 @@ __device__ __forceinline__ void predict_body(const Dims& d, const Fields& f, con
     auto V = [&](int dx, int dy, int sl) { return sv[sl][o0 + dy * LX + dx]; };
     auto W = [&](int dx, int dy, int sl) { return sw[sl][o0 + dy * LX + dx]; };
     const T p_c = spp[o0];
+    const bool more = k + 1 < ke;
+    if (more) {
+      fetch_plane(k + 2);
+      fetch_p(k + 1);
+    }
     if (active) {
       const long long c = fidx(d, i, j, k);
       // ---------------- u face i ----------------
@@ -165,9 +202,9 @@ __device__ __forceinline__ void predict_body(const Dims& d, const Fields& f, con
     }
     p_km = p_c;
     __syncthreads();
-    if (k + 1 < ke) {
-      load_plane(k + 2, sm);
-      load_p(k + 1);
+    if (more) {
+      commit_plane(sm);
+      commit_p();
     }
     __syncthreads();
   }
