@@ -14,6 +14,7 @@ Prints one JSON line.  --gpus above 1 is rejected: this build runs on one GPU.
 from __future__ import annotations
 
 import argparse
+import hashlib
 import json
 import math
 import os
@@ -204,10 +205,17 @@ def main():
     dom = max((k for k in times if k in bpc), key=lambda k: times[k][0])
     avg_ms = times[dom][0] / times[dom][1]
     achieved = bpc[dom] * w.cells / (avg_ms * 1e-3) / 1e9
+    # HBM bytes per launch from the committed counter runs, while they still
+    # describe this kernel: same source file, same tile shape
     traffic = None
     tf = os.path.join(ROOT, "profiles", f"traffic_{dom}.json")
     if os.path.exists(tf):
-        traffic = json.load(open(tf)).get("hbm_bytes_per_launch")
+        rec = json.load(open(tf))
+        src = os.path.join(ROOT, "paper_2103_08246_amd", "csrc", f"k_{dom}.hip")
+        same_src = os.path.exists(src) and hashlib.sha256(open(src, "rb").read()).hexdigest() == \
+            rec.get("source_sha256")
+        if same_src and rec.get("variant") == run.variant:
+            traffic = rec.get("hbm_bytes_per_launch")
     roofline = {"bound": "hbm", "kernel": dom, "achieved": round(achieved, 1),
                 "peak": HBM_PEAK_GBS, "unit": "GB/s", "frac": round(achieved / HBM_PEAK_GBS, 4),
                 "traffic": traffic,

@@ -255,13 +255,35 @@ bool is_tilde(int which) {
          which == IBDNS_ARR_HU || which == IBDNS_ARR_HV || which == IBDNS_ARR_HW;
 }
 
+// Copy columns [off, off + w) of a device array of `rows` rows with pitch
+// `pitch` elements to or from a dense host array of row stride hpitch.  Whole
+// row blocks move as plain linear copies through a host staging buffer (a
+// write reads the block first, so the other columns keep their values).
+template <class E>
+int pitched_copy(E* dev, size_t pitch, size_t off, size_t w, size_t rows, E* host, size_t hpitch,
+                 bool to_host) {
+  const size_t chunk = std::max<size_t>(1, (size_t(32) << 20) / (pitch * sizeof(E)));
+  std::vector<E> st(std::min(rows, chunk) * pitch);
+  for (size_t r0 = 0; r0 < rows; r0 += chunk) {
+    const size_t nr = std::min(chunk, rows - r0);
+    const size_t bytes = nr * pitch * sizeof(E);
+    if (hipMemcpy(st.data(), dev + r0 * pitch, bytes, hipMemcpyDeviceToHost) != hipSuccess) return IBDNS_EHIP;
+    for (size_t r = 0; r < nr; ++r) {
+      E* srow = st.data() + r * pitch + off;
+      E* hrow = host + (r0 + r) * hpitch;
+      if (to_host)
+        std::copy(srow, srow + w, hrow);
+      else
+        std::copy(hrow, hrow + w, srow);
+    }
+    if (!to_host && hipMemcpy(dev + r0 * pitch, st.data(), bytes, hipMemcpyHostToDevice) != hipSuccess)
+      return IBDNS_EHIP;
+  }
+  return IBDNS_OK;
+}
+
 int copy_field(ibdns_ctx* c, double* dev, int nxh, double* host, bool to_host) {
-  const size_t w = (size_t)nxh * sizeof(double);
-  const size_t sp = (size_t)c->d.P * sizeof(double);
-  const size_t rows = (size_t)c->d.ny * c->d.nz;
-  hipError_t e = to_host ? hipMemcpy2D(host, w, dev, sp, w, rows, hipMemcpyDeviceToHost)
-                         : hipMemcpy2D(dev, sp, host, w, w, rows, hipMemcpyHostToDevice);
-  return e == hipSuccess ? IBDNS_OK : IBDNS_EHIP;
+  return pitched_copy<double>(dev, c->d.P, 0, nxh, (size_t)c->d.ny * c->d.nz, host, nxh, to_host);
 }
 
 // FP32 provisional arrays (mixed precision): float rows of pitch P, widened
@@ -269,16 +291,14 @@ int copy_field(ibdns_ctx* c, double* dev, int nxh, double* host, bool to_host) {
 int copy_field_f32(ibdns_ctx* c, double* dev, int nxh, double* host, bool to_host) {
   const size_t rows = (size_t)c->d.ny * c->d.nz;
   std::vector<float> tmp(rows * nxh);
-  const size_t w = (size_t)nxh * sizeof(float);
-  const size_t sp = (size_t)c->d.P * sizeof(float);
+  float* devf = reinterpret_cast<float*>(dev);
   if (to_host) {
-    if (hipMemcpy2D(tmp.data(), w, dev, sp, w, rows, hipMemcpyDeviceToHost) != hipSuccess) return IBDNS_EHIP;
+    if (int r = pitched_copy<float>(devf, c->d.P, 0, nxh, rows, tmp.data(), nxh, true)) return r;
     for (size_t q = 0; q < tmp.size(); ++q) host[q] = tmp[q];
     return IBDNS_OK;
   }
   for (size_t q = 0; q < tmp.size(); ++q) tmp[q] = (float)host[q];
-  return hipMemcpy2D(dev, sp, tmp.data(), w, w, rows, hipMemcpyHostToDevice) == hipSuccess ? IBDNS_OK
-                                                                                          : IBDNS_EHIP;
+  return pitched_copy<float>(devf, c->d.P, 0, nxh, rows, tmp.data(), nxh, false);
 }
 
 double roma_host(double r) {
@@ -748,8 +768,7 @@ int ibdns_get_array(ibdns_ctx* c, int32_t which, double* host) {
     // boundary faces of u~ are FP64: inlet from u, outlet from its plane
     const size_t rows = (size_t)c->d.ny * c->d.nz;
     std::vector<double> in(rows), out(rows);
-    if (hipMemcpy2D(in.data(), sizeof(double), c->f.u, (size_t)c->d.P * sizeof(double), sizeof(double),
-                    rows, hipMemcpyDeviceToHost) != hipSuccess ||
+    if (pitched_copy<double>(c->f.u, c->d.P, 0, 1, rows, in.data(), 1, true) != IBDNS_OK ||
         hipMemcpy(out.data(), c->f.bnd, rows * sizeof(double), hipMemcpyDeviceToHost) != hipSuccess)
       return IBDNS_EHIP;
     for (size_t q = 0; q < rows; ++q) {
@@ -764,9 +783,8 @@ int ibdns_get_array(ibdns_ctx* c, int32_t which, double* host) {
                ? IBDNS_OK : IBDNS_EHIP;
   }
   if (which == IBDNS_ARR_V_GHOST || which == IBDNS_ARR_W_GHOST) {
-    double* dev = (which == IBDNS_ARR_V_GHOST ? c->f.v : c->f.w) + c->d.nx;
-    return hipMemcpy2D(host, sizeof(double), dev, (size_t)c->d.P * sizeof(double), sizeof(double),
-                       (size_t)c->d.ny * c->d.nz, hipMemcpyDeviceToHost) == hipSuccess ? IBDNS_OK : IBDNS_EHIP;
+    double* dev = which == IBDNS_ARR_V_GHOST ? c->f.v : c->f.w;
+    return pitched_copy<double>(dev, c->d.P, c->d.nx, 1, (size_t)c->d.ny * c->d.nz, host, 1, true);
   }
   return IBDNS_EINVAL;
 }
@@ -782,13 +800,15 @@ int ibdns_set_array(ibdns_ctx* c, int32_t which, const double* host) {
     if (r || which != IBDNS_ARR_UT) return r;
     // the outlet face of u~ also lives in its FP64 plane
     const size_t rows = (size_t)c->d.ny * c->d.nz;
-    return hipMemcpy2D(c->f.bnd, sizeof(double), host + c->d.nx, (size_t)nxh * sizeof(double),
-                       sizeof(double), rows, hipMemcpyHostToDevice) == hipSuccess ? IBDNS_OK : IBDNS_EHIP;
+    std::vector<double> out(rows);
+    for (size_t q = 0; q < rows; ++q) out[q] = host[q * nxh + c->d.nx];
+    return hipMemcpy(c->f.bnd, out.data(), rows * sizeof(double), hipMemcpyHostToDevice) == hipSuccess
+               ? IBDNS_OK : IBDNS_EHIP;
   }
   if (which == IBDNS_ARR_V_GHOST || which == IBDNS_ARR_W_GHOST) {
-    double* dev = (which == IBDNS_ARR_V_GHOST ? c->f.v : c->f.w) + c->d.nx;
-    return hipMemcpy2D(dev, (size_t)c->d.P * sizeof(double), host, sizeof(double), sizeof(double),
-                       (size_t)c->d.ny * c->d.nz, hipMemcpyHostToDevice) == hipSuccess ? IBDNS_OK : IBDNS_EHIP;
+    double* dev = which == IBDNS_ARR_V_GHOST ? c->f.v : c->f.w;
+    return pitched_copy<double>(dev, c->d.P, c->d.nx, 1, (size_t)c->d.ny * c->d.nz, const_cast<double*>(host), 1,
+                                false);
   }
   return IBDNS_EINVAL;
 }

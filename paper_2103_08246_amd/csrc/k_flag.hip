@@ -28,7 +28,7 @@ namespace ibdns {
 namespace {
 
 constexpr int FR = 4;            // rows per band
-constexpr int FT_ = 256;         // threads per band
+constexpr int FT_ = 512;         // threads per band (one node per thread for ns <= 128)
 constexpr int MAXN = (FR * 128 + FT_ - 1) / FT_;  // owned nodes per thread (ns <= 128)
 constexpr long long SPIN_LIMIT = 1LL << 22;   // bounded wait (seconds at most)
 
@@ -192,13 +192,17 @@ __device__ __forceinline__ void flag_body(const FlagDev& fl, Scalars* s, const i
       for (int r = 0; r < 4; ++r) {
         const int b = r < 2 ? b0 + r : b1 - 4 + r;
         if (b < b0 || b >= b1) continue;
-        for (int q = tid; q < 3 * ns; q += FT_) slot[r * 3 * ns + q] = Xs[3 * ns * (b - rb0) + q];
+        for (int q = tid; q < 3 * ns; q += FT_)
+          __hip_atomic_store(&slot[r * 3 * ns + q], Xs[3 * ns * (b - rb0) + q], __ATOMIC_RELAXED,
+                             __HIP_MEMORY_SCOPE_AGENT);
       }
       // The barrier orders every wave's slot stores before thread 0's release
       // store of the counter (release covers all stores that happen before
       // it); the neighbours' counters are polled with relaxed loads and one
       // acquire fence follows, whose effect the second barrier extends to the
-      // whole workgroup.  One L2 write-back and one invalidate per sub-step.
+      // whole workgroup.  One L2 write-back and one invalidate per sub-step;
+      // the slots themselves are written and read as device-coherent relaxed
+      // atomics, so the write-back finds no dirty slot lines.
       __syncthreads();
       if (tid == 0) {
         __hip_atomic_store(&fl.counter[band], it + 1, __ATOMIC_RELEASE, __HIP_MEMORY_SCOPE_AGENT);
@@ -229,7 +233,8 @@ __device__ __forceinline__ void flag_body(const FlagDev& fl, Scalars* s, const i
         const int nb0 = nbh * FR, nb1 = min(nb0 + FR, ns);
         const int r = (hb - nb0 < 2) ? hb - nb0 : hb - (nb1 - 4);
         const double* src = fl.xbuf + ((size_t)(it & 1) * nband + nbh) * 4 * 3 * ns + r * 3 * ns;
-        for (int q = tid; q < 3 * ns; q += FT_) Xs[3 * ns * (hb - rb0) + q] = src[q];
+        for (int q = tid; q < 3 * ns; q += FT_)
+          Xs[3 * ns * (hb - rb0) + q] = __hip_atomic_load(&src[q], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
       }
     }
     __syncthreads();
