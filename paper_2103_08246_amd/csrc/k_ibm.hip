@@ -296,11 +296,13 @@ __global__ void __launch_bounds__(256) k_point_stencil(Dims d, PointSet ps, Scal
 }
 template <class T>
 __global__ void __launch_bounds__(256) k_point_interp(Dims d, Fields f, PointSet ps, Scalars* s) {
-  point_interp_body<T>(d, f, ps, s, blockIdx.x, blockIdx.y);
+  point_interp_body<T>(d, f, ps, s, xcd_remap(blockIdx.x, gridDim.x), blockIdx.y);
 }
+// Rows are in grid order: XCD-contiguous row ranges keep each point's delta
+// factors in one L2 instead of all eight.
 template <class T>
 __global__ void __launch_bounds__(256) k_spread_csr(Dims d, Fields f, PointSet ps, SpreadCSR csr, int comp) {
-  spread_csr_body<T>(d, f, ps, csr, comp, blockIdx.x);
+  spread_csr_body<T>(d, f, ps, csr, comp, xcd_remap(blockIdx.x, gridDim.x));
 }
 __global__ void __launch_bounds__(BBT) k_point_bbox(PointSet ps, int* bbox) {
   point_bbox_body(ps, bbox, blockIdx.x);

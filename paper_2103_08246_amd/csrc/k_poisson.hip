@@ -549,6 +549,13 @@ __device__ __forceinline__ void project_body(const Dims& d, const Fields& f, Sca
   const T* __restrict__ ut = reinterpret_cast<const T*>(f.ut);
   const T* __restrict__ vt = reinterpret_cast<const T*>(f.vt);
   const T* __restrict__ wt = reinterpret_cast<const T*>(f.wt);
+  // distinct arrays: the next plane's loads may be issued before this plane's stores
+  const double* __restrict__ phi = f.phi;
+  const double* __restrict__ bnd = f.bnd;
+  double* __restrict__ uo = f.u;
+  double* __restrict__ vo = f.v;
+  double* __restrict__ wo = f.w;
+  double* __restrict__ po = f.p;
   double smax = 0.0;
   if (i < d.nx && j < d.ny) {
     const int nx = d.nx;
@@ -556,31 +563,32 @@ __device__ __forceinline__ void project_body(const Dims& d, const Fields& f, Sca
     const int jm = j == 0 ? d.ny - 1 : j - 1, jp = j == d.ny - 1 ? 0 : j + 1;
     const double dt = s->dt, inv_h = d.inv_h;
     const int km0 = kb == 0 ? d.nz - 1 : kb - 1;
-    double ph_c = f.phi[fidx(d, i, j, kb)];
-    double wk = (double)wt[fidx(d, i, j, kb)] - dt * (ph_c - f.phi[fidx(d, i, j, km0)]) * inv_h;
+    double ph_c = phi[fidx(d, i, j, kb)];
+    double wk = (double)wt[fidx(d, i, j, kb)] - dt * (ph_c - phi[fidx(d, i, j, km0)]) * inv_h;
+#pragma unroll 2
     for (int k = kb; k < ke; ++k) {
       const int kp = k == d.nz - 1 ? 0 : k + 1;
       const long long c = fidx(d, i, j, k);
       const long long ckp = fidx(d, i, j, kp);
-      const double ph_p = f.phi[ckp];
+      const double ph_p = phi[ckp];
       const double wkp = (double)wt[ckp] - dt * (ph_p - ph_c) * inv_h;
       // inlet face keeps U (read from u), outlet face keeps u~ (FP64 plane)
-      const double ui = (i >= 1) ? (double)ut[c] - dt * (ph_c - f.phi[c - 1]) * inv_h : f.u[c];
+      const double ui = (i >= 1) ? (double)ut[c] - dt * (ph_c - phi[c - 1]) * inv_h : uo[c];
       const long long qb = j + (long long)d.ny * k;
-      const double uip = (i + 1 <= nx - 1) ? (double)ut[c + 1] - dt * (f.phi[c + 1] - ph_c) * inv_h
-                                           : f.bnd[qb];
+      const double uip = (i + 1 <= nx - 1) ? (double)ut[c + 1] - dt * (phi[c + 1] - ph_c) * inv_h
+                                           : bnd[qb];
       const long long cjm = fidx(d, i, jm, k), cjp = fidx(d, i, jp, k);
-      const double vj = (double)vt[c] - dt * (ph_c - f.phi[cjm]) * inv_h;
-      const double vjp = (double)vt[cjp] - dt * (f.phi[cjp] - ph_c) * inv_h;
-      f.u[c] = ui;
-      f.v[c] = vj;
-      f.w[c] = wk;
+      const double vj = (double)vt[c] - dt * (ph_c - phi[cjm]) * inv_h;
+      const double vjp = (double)vt[cjp] - dt * (phi[cjp] - ph_c) * inv_h;
+      uo[c] = ui;
+      vo[c] = vj;
+      wo[c] = wk;
       if (i == nx - 1) {
-        f.u[c + 1] = uip;                  // outlet face keeps u~
-        f.v[c + 1] = f.bnd[nplane + qb];   // outlet ghosts keep their provisional values
-        f.w[c + 1] = f.bnd[2 * nplane + qb];
+        uo[c + 1] = uip;                 // outlet face keeps u~
+        vo[c + 1] = bnd[nplane + qb];    // outlet ghosts keep their provisional values
+        wo[c + 1] = bnd[2 * nplane + qb];
       }
-      if (mode == 0) f.p[c] = f.p[c] + ph_c;
+      if (mode == 0) po[c] = po[c] + ph_c;
       double speed = fabs(0.5 * (ui + uip)) + fabs(0.5 * (vj + vjp)) + fabs(0.5 * (wk + wkp));
       if (!(speed <= 1.7976931348623157e308)) {
         atomicOr(&s->status, (int)ST_NONFINITE);
