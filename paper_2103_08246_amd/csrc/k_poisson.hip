@@ -379,156 +379,175 @@ __device__ __forceinline__ int rpos(int r) { return (r & 1) * 64 + (r >> 1); }
 
 template <int C>
 __device__ __forceinline__ void tri_body(const Dims& d, const Fields& f, const double* __restrict__ lam_y,
-                                         const double* __restrict__ lam_z, double scale, const int bx) {
+                                         const double* __restrict__ lam_z, double scale, const long long first,
+                                         const long long stride) {
   constexpr int LSP = C + 1;     // LDS chunk stride (odd: lanes hit distinct banks)
   constexpr int R = 128;         // reduced rows (2 per lane)
   __shared__ double2 lb[TRI_WAVES][64 * LSP];
   __shared__ double rA[TRI_WAVES][R], rB[TRI_WAVES][R], rC[TRI_WAVES][R];
   __shared__ double2 rD[TRI_WAVES][R];
-  const int wv = threadIdx.x / 64, lane = threadIdx.x % 64;
+  const int wv = threadIdx.x / 64, lane0 = threadIdx.x % 64;
   const long long nlines = (long long)d.MY * d.nz;
-  const long long line = (long long)bx * TRI_WAVES + wv;
-  if (line >= nlines) return;   // the whole wavefront
-  const int m = (int)(line % d.MY);
-  const int l = (int)(line / d.MY);
   const int nx = d.nx;
-  // the (0, 0) mode is singular: its row 0 becomes phi_0 = 0 and its x-mean is
-  // removed afterwards
-  const bool singular = m == 0 && l == 0;
-  double2* g = f.spec + line * (long long)nx;
   double2* L = lb[wv];
   double* A_ = rA[wv];
   double* B_ = rB[wv];
   double* C_ = rC[wv];
   double2* D_ = rD[wv];
-
-  for (int t = 0; t < C; ++t) {
-    const int e = lane + 64 * t;
-    L[(e / C) * LSP + e % C] = (e < nx && !(singular && e == 0)) ? cscale(g[e], scale) : make_double2(0.0, 0.0);
-  }
-  wave_sync();
-  const double shift = (d.h * d.h) * (lam_z[l] + lam_y[m]);
-  double2 x[C];
-  {
-    const int s0 = lane * C;
-    double a[C], b[C], c[C];
-    double2 dd[C];
+  // lines first, first + stride, ...: the next line is loaded into registers
+  // while the current one is solved
+  double2 pre[C];
+  auto fetch = [&](long long ln) {
+    const double2* gl = f.spec + ln * (long long)nx;
 #pragma unroll
     for (int t = 0; t < C; ++t) {
-      tri_coef(s0 + t, nx, shift, singular, a[t], b[t], c[t]);
-      dd[t] = L[lane * LSP + t];
+      const int e = lane0 + 64 * t;
+      pre[t] = e < nx ? gl[e] : make_double2(0.0, 0.0);
     }
-    double cp[C], be[C], ga[C];
-    double2 al[C];
+  };
+  if (first < nlines) fetch(first);
+  for (long long line = first; line < nlines; line += stride) {
+    // an opaque copy of the lane index per line keeps the compiler from
+    // hoisting every line-invariant coefficient and LDS offset into registers
+    int lane = lane0;
+    asm volatile("" : "+v"(lane));
+    const int m = (int)(line % d.MY);
+    const int l = (int)(line / d.MY);
+    // the (0, 0) mode is singular: its row 0 becomes phi_0 = 0 and its x-mean
+    // is removed afterwards
+    const bool singular = m == 0 && l == 0;
+    double2* g = f.spec + line * (long long)nx;
 #pragma unroll
     for (int t = 0; t < C; ++t) {
-      cp[t] = 0.0;
-      be[t] = 0.0;
-      ga[t] = 0.0;
-      al[t] = make_double2(0.0, 0.0);
-    }
-    // interior rows t = 1..C-2: x_t = al_t + be_t x_s + ga_t x_e
-#pragma unroll
-    for (int t = 1; t <= C - 2; ++t) {
-      const double den = (t == 1) ? b[1] : b[t] - a[t] * cp[t - 1];
-      const double inv = rcp64(den);
-      cp[t] = c[t] * inv;
-      if (t == 1) {
-        al[t] = cscale(dd[1], inv);
-        be[t] = -a[1] * inv;
-        ga[t] = (t == C - 2 ? -c[t] : 0.0) * inv;
-      } else {
-        al[t] = cscale(csub(dd[t], cscale(al[t - 1], a[t])), inv);
-        be[t] = (-a[t] * be[t - 1]) * inv;
-        ga[t] = ((t == C - 2 ? -c[t] : 0.0) - a[t] * ga[t - 1]) * inv;
-      }
-    }
-#pragma unroll
-    for (int t = C - 3; t >= 1; --t) {
-      al[t] = csub(al[t], cscale(al[t + 1], cp[t]));
-      be[t] = be[t] - cp[t] * be[t + 1];
-      ga[t] = ga[t] - cp[t] * ga[t + 1];
-    }
-    double A0, B0, C0, A1, B1, C1;
-    double2 D0, D1;
-    if constexpr (C >= 3) {
-      A0 = a[0];
-      B0 = b[0] + c[0] * be[1];
-      C0 = c[0] * ga[1];
-      D0 = csub(dd[0], cscale(al[1], c[0]));
-      A1 = a[C - 1] * be[C - 2];
-      B1 = b[C - 1] + a[C - 1] * ga[C - 2];
-      C1 = c[C - 1];
-      D1 = csub(dd[C - 1], cscale(al[C - 2], a[C - 1]));
-    } else {
-      A0 = a[0]; B0 = b[0]; C0 = c[0]; D0 = dd[0];
-      A1 = a[1]; B1 = b[1]; C1 = c[1]; D1 = dd[1];
-    }
-    const int r0 = 2 * lane, r1 = 2 * lane + 1;
-    A_[rpos(r0)] = A0; B_[rpos(r0)] = B0; C_[rpos(r0)] = C0; D_[rpos(r0)] = D0;
-    A_[rpos(r1)] = A1; B_[rpos(r1)] = B1; C_[rpos(r1)] = C1; D_[rpos(r1)] = D1;
-    // parallel cyclic reduction of the reduced system
-    for (int st = 1; st < R; st <<= 1) {
-      wave_sync();
-      double nA[2], nB[2], nC[2];
-      double2 nD[2];
-#pragma unroll
-      for (int q = 0; q < 2; ++q) {
-        const int r = 2 * lane + q;
-        const int rm = r - st, rp = r + st;
-        const double Ar = A_[rpos(r)], Cr = C_[rpos(r)];
-        double Aq = 0.0, Cq = 0.0, Bq = B_[rpos(r)];
-        double2 Dq = D_[rpos(r)];
-        if (rm >= 0) {
-          const double k1 = Ar * rcp64(B_[rpos(rm)]);
-          Aq = -A_[rpos(rm)] * k1;
-          Bq -= C_[rpos(rm)] * k1;
-          Dq = csub(Dq, cscale(D_[rpos(rm)], k1));
-        }
-        if (rp < R) {
-          const double k2 = Cr * rcp64(B_[rpos(rp)]);
-          Cq = -C_[rpos(rp)] * k2;
-          Bq -= A_[rpos(rp)] * k2;
-          Dq = csub(Dq, cscale(D_[rpos(rp)], k2));
-        }
-        nA[q] = Aq; nB[q] = Bq; nC[q] = Cq; nD[q] = Dq;
-      }
-      wave_sync();
-#pragma unroll
-      for (int q = 0; q < 2; ++q) {
-        const int r = 2 * lane + q;
-        A_[rpos(r)] = nA[q]; B_[rpos(r)] = nB[q]; C_[rpos(r)] = nC[q]; D_[rpos(r)] = nD[q];
-      }
+      const int e = lane + 64 * t;
+      L[(e / C) * LSP + e % C] = (e < nx && !(singular && e == 0)) ? cscale(pre[t], scale) : make_double2(0.0, 0.0);
     }
     wave_sync();
-    const double2 xs = cscale(D_[rpos(r0)], rcp64(B_[rpos(r0)]));
-    const double2 xe = cscale(D_[rpos(r1)], rcp64(B_[rpos(r1)]));
-    x[0] = xs;
-    x[C - 1] = xe;
+    if (line + stride < nlines) fetch(line + stride);
+    const double shift = (d.h * d.h) * (lam_z[l] + lam_y[m]);
+    double2 x[C];
+    {
+      const int s0 = lane * C;
+      double a[C], b[C], c[C];
+      double2 dd[C];
 #pragma unroll
-    for (int t = 1; t <= C - 2; ++t)
-      x[t] = make_double2(al[t].x + be[t] * xs.x + ga[t] * xe.x, al[t].y + be[t] * xs.y + ga[t] * xe.y);
-  }
-  if (singular) {  // remove the x-mean (fixed summation order: lanes, then a butterfly)
-    double2 sm = make_double2(0.0, 0.0);
+      for (int t = 0; t < C; ++t) {
+        tri_coef(s0 + t, nx, shift, singular, a[t], b[t], c[t]);
+        dd[t] = L[lane * LSP + t];
+      }
+      double cp[C], be[C], ga[C];
+      double2 al[C];
 #pragma unroll
-    for (int t = 0; t < C; ++t)
-      if (lane * C + t < nx) sm = cadd(sm, x[t]);
-    for (int o = 1; o < 64; o <<= 1) {
-      sm.x += __shfl_xor(sm.x, o, 64);
-      sm.y += __shfl_xor(sm.y, o, 64);
+      for (int t = 0; t < C; ++t) {
+        cp[t] = 0.0;
+        be[t] = 0.0;
+        ga[t] = 0.0;
+        al[t] = make_double2(0.0, 0.0);
+      }
+      // interior rows t = 1..C-2: x_t = al_t + be_t x_s + ga_t x_e
+#pragma unroll
+      for (int t = 1; t <= C - 2; ++t) {
+        const double den = (t == 1) ? b[1] : b[t] - a[t] * cp[t - 1];
+        const double inv = rcp64(den);
+        cp[t] = c[t] * inv;
+        if (t == 1) {
+          al[t] = cscale(dd[1], inv);
+          be[t] = -a[1] * inv;
+          ga[t] = (t == C - 2 ? -c[t] : 0.0) * inv;
+        } else {
+          al[t] = cscale(csub(dd[t], cscale(al[t - 1], a[t])), inv);
+          be[t] = (-a[t] * be[t - 1]) * inv;
+          ga[t] = ((t == C - 2 ? -c[t] : 0.0) - a[t] * ga[t - 1]) * inv;
+        }
+      }
+#pragma unroll
+      for (int t = C - 3; t >= 1; --t) {
+        al[t] = csub(al[t], cscale(al[t + 1], cp[t]));
+        be[t] = be[t] - cp[t] * be[t + 1];
+        ga[t] = ga[t] - cp[t] * ga[t + 1];
+      }
+      double A0, B0, C0, A1, B1, C1;
+      double2 D0, D1;
+      if constexpr (C >= 3) {
+        A0 = a[0];
+        B0 = b[0] + c[0] * be[1];
+        C0 = c[0] * ga[1];
+        D0 = csub(dd[0], cscale(al[1], c[0]));
+        A1 = a[C - 1] * be[C - 2];
+        B1 = b[C - 1] + a[C - 1] * ga[C - 2];
+        C1 = c[C - 1];
+        D1 = csub(dd[C - 1], cscale(al[C - 2], a[C - 1]));
+      } else {
+        A0 = a[0]; B0 = b[0]; C0 = c[0]; D0 = dd[0];
+        A1 = a[1]; B1 = b[1]; C1 = c[1]; D1 = dd[1];
+      }
+      const int r0 = 2 * lane, r1 = 2 * lane + 1;
+      A_[rpos(r0)] = A0; B_[rpos(r0)] = B0; C_[rpos(r0)] = C0; D_[rpos(r0)] = D0;
+      A_[rpos(r1)] = A1; B_[rpos(r1)] = B1; C_[rpos(r1)] = C1; D_[rpos(r1)] = D1;
+      // parallel cyclic reduction of the reduced system
+      for (int st = 1; st < R; st <<= 1) {
+        wave_sync();
+        double nA[2], nB[2], nC[2];
+        double2 nD[2];
+#pragma unroll
+        for (int q = 0; q < 2; ++q) {
+          const int r = 2 * lane + q;
+          const int rm = r - st, rp = r + st;
+          const double Ar = A_[rpos(r)], Cr = C_[rpos(r)];
+          double Aq = 0.0, Cq = 0.0, Bq = B_[rpos(r)];
+          double2 Dq = D_[rpos(r)];
+          if (rm >= 0) {
+            const double k1 = Ar * rcp64(B_[rpos(rm)]);
+            Aq = -A_[rpos(rm)] * k1;
+            Bq -= C_[rpos(rm)] * k1;
+            Dq = csub(Dq, cscale(D_[rpos(rm)], k1));
+          }
+          if (rp < R) {
+            const double k2 = Cr * rcp64(B_[rpos(rp)]);
+            Cq = -C_[rpos(rp)] * k2;
+            Bq -= A_[rpos(rp)] * k2;
+            Dq = csub(Dq, cscale(D_[rpos(rp)], k2));
+          }
+          nA[q] = Aq; nB[q] = Bq; nC[q] = Cq; nD[q] = Dq;
+        }
+        wave_sync();
+#pragma unroll
+        for (int q = 0; q < 2; ++q) {
+          const int r = 2 * lane + q;
+          A_[rpos(r)] = nA[q]; B_[rpos(r)] = nB[q]; C_[rpos(r)] = nC[q]; D_[rpos(r)] = nD[q];
+        }
+      }
+      wave_sync();
+      const double2 xs = cscale(D_[rpos(r0)], rcp64(B_[rpos(r0)]));
+      const double2 xe = cscale(D_[rpos(r1)], rcp64(B_[rpos(r1)]));
+      x[0] = xs;
+      x[C - 1] = xe;
+#pragma unroll
+      for (int t = 1; t <= C - 2; ++t)
+        x[t] = make_double2(al[t].x + be[t] * xs.x + ga[t] * xe.x, al[t].y + be[t] * xs.y + ga[t] * xe.y);
     }
-    const double2 mean = make_double2(sm.x / nx, sm.y / nx);
+    if (singular) {  // remove the x-mean (fixed summation order: lanes, then a butterfly)
+      double2 sm = make_double2(0.0, 0.0);
 #pragma unroll
-    for (int t = 0; t < C; ++t) x[t] = csub(x[t], mean);
-  }
-  wave_sync();
+      for (int t = 0; t < C; ++t)
+        if (lane * C + t < nx) sm = cadd(sm, x[t]);
+      for (int o = 1; o < 64; o <<= 1) {
+        sm.x += __shfl_xor(sm.x, o, 64);
+        sm.y += __shfl_xor(sm.y, o, 64);
+      }
+      const double2 mean = make_double2(sm.x / nx, sm.y / nx);
 #pragma unroll
-  for (int t = 0; t < C; ++t) L[lane * LSP + t] = x[t];
-  wave_sync();
-  for (int t = 0; t < C; ++t) {
-    const int e = lane + 64 * t;
-    if (e < nx) g[e] = L[(e / C) * LSP + e % C];
+      for (int t = 0; t < C; ++t) x[t] = csub(x[t], mean);
+    }
+    wave_sync();
+#pragma unroll
+    for (int t = 0; t < C; ++t) L[lane * LSP + t] = x[t];
+    wave_sync();
+    for (int t = 0; t < C; ++t) {
+      const int e = lane + 64 * t;
+      if (e < nx) g[e] = L[(e / C) * LSP + e % C];
+    }
+    wave_sync();  // the line has left LDS
   }
 }
 
@@ -631,7 +650,8 @@ __global__ void __launch_bounds__(FT) k_iffty(Dims d, Fields f, const double2* _
 template <int C>
 __global__ void __launch_bounds__(64 * TRI_WAVES) k_tri(Dims d, Fields f, const double* __restrict__ lam_y,
                                                        const double* __restrict__ lam_z, double scale) {
-  tri_body<C>(d, f, lam_y, lam_z, scale, blockIdx.x);
+  tri_body<C>(d, f, lam_y, lam_z, scale, (long long)blockIdx.x * TRI_WAVES + threadIdx.x / 64,
+              (long long)gridDim.x * TRI_WAVES);
 }
 template <class T>
 __global__ void __launch_bounds__(PBX* PBY) k_project(Dims d, Fields f, Scalars* s, int mode) {
@@ -666,7 +686,8 @@ __global__ void __launch_bounds__(64 * TRI_WAVES) kb_tri(BatchLaunch bl) {
   int lb;
   const RunDesc& R = bl.runs[batch_run(bl, blockIdx.x, &lb)];
   const double scale = (R.d.h * R.d.h) / ((double)R.d.ny * (double)R.d.nz);
-  tri_body<C>(R.d, R.f, R.lam_y, R.lam_z, scale, lb);
+  const long long nl = (long long)R.d.MY * R.d.nz;
+  tri_body<C>(R.d, R.f, R.lam_y, R.lam_z, scale, (long long)lb * TRI_WAVES + threadIdx.x / 64, nl);
 }
 template <class T>
 __global__ void __launch_bounds__(PBX* PBY) kb_project(BatchLaunch bl, int mode) {
@@ -791,20 +812,26 @@ bool tri_size_supported(int nx) {
 void launch_tri(const Dims& d, const Fields& f, const double* lam_y, const double* lam_z,
                 hipStream_t st) {
   const long long nlines = (long long)d.MY * d.nz;
-  dim3 grid((unsigned)((nlines + TRI_WAVES - 1) / TRI_WAVES));
+  const int nblk = (int)((nlines + TRI_WAVES - 1) / TRI_WAVES);
   const double scale = (d.h * d.h) / ((double)d.ny * (double)d.nz);
   int C = (d.nx + 63) / 64;
   if (C < 2) C = 2;
+  // persistent: as many workgroups as are resident, each wavefront walking
+  // lines with a stride of the whole grid
+#define CALL(CC)                                                                                        \
+  hipLaunchKernelGGL(k_tri<CC>, dim3(resident_grid(k_tri<CC>, 64 * TRI_WAVES, nblk)), dim3(64 * TRI_WAVES), 0, \
+                     st, d, f, lam_y, lam_z, scale)
   switch (C) {
-    case 2: hipLaunchKernelGGL(k_tri<2>, grid, dim3(64 * TRI_WAVES), 0, st, d, f, lam_y, lam_z, scale); break;
-    case 3: hipLaunchKernelGGL(k_tri<3>, grid, dim3(64 * TRI_WAVES), 0, st, d, f, lam_y, lam_z, scale); break;
-    case 4: hipLaunchKernelGGL(k_tri<4>, grid, dim3(64 * TRI_WAVES), 0, st, d, f, lam_y, lam_z, scale); break;
-    case 5: hipLaunchKernelGGL(k_tri<5>, grid, dim3(64 * TRI_WAVES), 0, st, d, f, lam_y, lam_z, scale); break;
-    case 6: hipLaunchKernelGGL(k_tri<6>, grid, dim3(64 * TRI_WAVES), 0, st, d, f, lam_y, lam_z, scale); break;
-    case 8: hipLaunchKernelGGL(k_tri<8>, grid, dim3(64 * TRI_WAVES), 0, st, d, f, lam_y, lam_z, scale); break;
-    case 12: hipLaunchKernelGGL(k_tri<12>, grid, dim3(64 * TRI_WAVES), 0, st, d, f, lam_y, lam_z, scale); break;
+    case 2: CALL(2); break;
+    case 3: CALL(3); break;
+    case 4: CALL(4); break;
+    case 5: CALL(5); break;
+    case 6: CALL(6); break;
+    case 8: CALL(8); break;
+    case 12: CALL(12); break;
     default: break;
   }
+#undef CALL
 }
 
 int project_blocks(const Dims& d) {
