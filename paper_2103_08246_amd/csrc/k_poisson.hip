@@ -30,8 +30,13 @@ namespace ibdns {
 
 namespace {
 
+// Complex arithmetic, butterflies and passes carry no implicit multiply-add
+// fusion (the one fused multiply-add per product term of a complex product is
+// written out), so every kernel that inlines them computes bitwise the same
+// transform.
+#pragma clang fp contract(off)
 __device__ __forceinline__ double2 cmul(double2 a, double2 b) {
-  return make_double2(a.x * b.x - a.y * b.y, a.x * b.y + a.y * b.x);
+  return make_double2(fma(a.x, b.x, -(a.y * b.y)), fma(a.x, b.y, a.y * b.x));
 }
 __device__ __forceinline__ double2 cadd(double2 a, double2 b) { return make_double2(a.x + b.x, a.y + b.y); }
 __device__ __forceinline__ double2 csub(double2 a, double2 b) { return make_double2(a.x - b.x, a.y - b.y); }
@@ -111,10 +116,41 @@ struct DFT<8, SIGN> {
 __device__ __forceinline__ constexpr int lp(int e) { return e ^ ((e >> 3) & 7); }
 __host__ __device__ constexpr int line_stride(int n) { return n + 1; }
 
+// Twiddles from an LDS table of the first octant, oc[r] = (cos, sin)(2 pi r / N)
+// for r = 0..N/8: exp(-2 pi i m / N) for any 0 <= m < N by the octant
+// symmetries.  The passes then issue no vector-memory loads, so global loads
+// of the next tile can stay in flight across them.
+template <int N>
+__device__ __forceinline__ double2 twiddle(const double2* __restrict__ oc, const int m) {
+  constexpr int Q = N / 8;
+  const int o = m / Q, r = m - o * Q;
+  const bool odd = (o & 1) != 0;
+  const double2 v = oc[odd ? Q - r : r];
+  double c = odd ? v.y : v.x, sn = odd ? v.x : v.y;   // angle reduced to the first quadrant
+  if (o & 2) {                                       // a quarter turn
+    const double t = c;
+    c = -sn;
+    sn = t;
+  }
+  if (o & 4) {                                       // a half turn
+    c = -c;
+    sn = -sn;
+  }
+  return make_double2(c, -sn);
+}
+
+// Fill the octant table from the host-built table tw[m] = exp(-2 pi i m / N).
+template <int N>
+__device__ __forceinline__ void load_octant(double2* oc, const double2* __restrict__ tw, const int tid,
+                                            const int nthreads) {
+  for (int r = tid; r <= N / 8; r += nthreads) oc[r] = make_double2(tw[r].x, -tw[r].y);
+}
+
 // One Stockham pass of radix R over NL lines of length N (line stride LS,
-// element e at slot lp(e)) in LDS: butterfly i of a line reads x[i + q N/R], applies the twiddles
-// w^(q k), k = i mod P, and writes y[(i/P) P R + k + q P].  All inputs are
-// loaded before the barrier, so the pass runs in place.
+// element e at slot lp(e)) in LDS, twiddles from the octant table tw:
+// butterfly i of a line reads x[i + q N/R], applies the twiddles w^(q k),
+// k = i mod P, and writes y[(i/P) P R + k + q P].  All inputs are loaded
+// before the barrier, so the pass runs in place.
 template <int N, int R, int P, int SIGN, int NL, int NT, int LS>
 __device__ __forceinline__ void stockham_pass(double2* buf, const double2* __restrict__ tw, const int tid) {
   constexpr int T = N / R;
@@ -141,7 +177,7 @@ __device__ __forceinline__ void stockham_pass(double2* buf, const double2* __res
       if constexpr (P > 1) {
 #pragma unroll
         for (int q = 1; q < R; ++q) {
-          double2 w = tw[(q * k) * (N / (P * R))];
+          double2 w = twiddle<N>(tw, (q * k) * (N / (P * R)));
           if (SIGN > 0) w.y = -w.y;
           v[b][q] = cmul(v[b][q], w);
         }
@@ -171,6 +207,13 @@ struct FFTPasses {
   }
 };
 
+#pragma clang fp contract(fast)
+
+// d - a s for complex d, a and real s (free to fuse)
+__device__ __forceinline__ double2 cfms(double2 d, double2 a, double s) {
+  return make_double2(d.x - a.x * s, d.y - a.y * s);
+}
+
 constexpr int FT = 256;  // threads per FFT workgroup
 
 // r = D u~ / dt for a 16-column x tile of one z plane, then the y FFT of the
@@ -180,6 +223,8 @@ __device__ __forceinline__ void div_ffty_body(const Dims& d, const Fields& f, co
                                               const double2* __restrict__ tw, const int bx, const int by) {
   constexpr int TXC = 16, NL = 8, LS = line_stride(NY), MY = NY / 2 + 1;
   __shared__ double2 buf[NL * LS];
+  __shared__ double2 oc[NY / 8 + 1];
+  load_octant<NY>(oc, tw, threadIdx.x, FT);
   const T* __restrict__ ut = reinterpret_cast<const T*>(f.ut);
   const T* __restrict__ vt = reinterpret_cast<const T*>(f.vt);
   const T* __restrict__ wt = reinterpret_cast<const T*>(f.wt);
@@ -207,7 +252,7 @@ __device__ __forceinline__ void div_ffty_body(const Dims& d, const Fields& f, co
       slot->x = r;
   }
   __syncthreads();
-  FFTPasses<NY, 1, -1, NL, FT, LS>::run(buf, tw);
+  FFTPasses<NY, 1, -1, NL, FT, LS>::run(buf, oc);
   for (int e = threadIdx.x; e < TXC * MY; e += FT) {
     const int ix = e % TXC, m = e / TXC;
     const int i = i0 + ix;
@@ -229,6 +274,8 @@ __device__ __forceinline__ void fftz_body(const Dims& d, const Fields& f, const 
                                           const int bx, const int by) {
   constexpr int TXC = 8, NL = 8, LS = line_stride(NZ);
   __shared__ double2 buf[NL * LS];
+  __shared__ double2 oc[NZ / 8 + 1];
+  load_octant<NZ>(oc, tw, threadIdx.x, FT);
   const int i0 = bx * TXC;
   const int m = by;
   const long long lstride = (long long)d.nx * d.MY;
@@ -239,7 +286,7 @@ __device__ __forceinline__ void fftz_body(const Dims& d, const Fields& f, const 
     buf[ix * LS + lp(k)] = (i < d.nx) ? base[i + lstride * k] : make_double2(0.0, 0.0);
   }
   __syncthreads();
-  FFTPasses<NZ, 1, SIGN, NL, FT, LS>::run(buf, tw);
+  FFTPasses<NZ, 1, SIGN, NL, FT, LS>::run(buf, oc);
   for (int e = threadIdx.x; e < TXC * NZ; e += FT) {
     const int ix = e % TXC, k = e / TXC;
     const int i = i0 + ix;
@@ -256,6 +303,8 @@ __device__ __forceinline__ void fftz_stream_body(const Dims& d, const Fields& f,
   constexpr int TXC = 8, NL = 8, LS = line_stride(NZ);
   constexpr int NEL = (TXC * NZ + FT - 1) / FT;
   __shared__ double2 buf[NL * LS];
+  __shared__ double2 oc[NZ / 8 + 1];
+  load_octant<NZ>(oc, tw, threadIdx.x, FT);  // ordered by the first barrier of the loop
   const int gx = (d.nx + TXC - 1) / TXC;
   const int ntiles = gx * d.MY;
   const long long lstride = (long long)d.nx * d.MY;
@@ -282,13 +331,11 @@ __device__ __forceinline__ void fftz_stream_body(const Dims& d, const Fields& f,
     __syncthreads();
     const int tn = (round + 1) * G + xcd_remap(w, G);
     if (tn < ntiles) fetch(tn);  // in flight during the passes below
-    // opaque copies of the twiddle pointer and thread index per round keep the
-    // compiler from hoisting every pass's twiddles and LDS offsets out of the
-    // loop into registers
-    const double2* twr = tw;
+    // an opaque copy of the thread index per round keeps the compiler from
+    // hoisting every pass's LDS offsets out of the loop into registers
     int tid = threadIdx.x;
-    asm volatile("" : "+s"(twr), "+v"(tid));
-    FFTPasses<NZ, 1, SIGN, NL, FT, LS>::run(buf, twr, tid);
+    asm volatile("" : "+v"(tid));
+    FFTPasses<NZ, 1, SIGN, NL, FT, LS>::run(buf, oc, tid);
     const int i0 = (t % gx) * TXC, m = t / gx;
     double2* base = f.spec + (long long)d.nx * m;
     for (int e = threadIdx.x; e < TXC * NZ; e += FT) {
@@ -306,6 +353,8 @@ __device__ __forceinline__ void iffty_body(const Dims& d, const Fields& f, const
                                            const int bx, const int by) {
   constexpr int TXC = 16, NL = 8, LS = line_stride(NY), MY = NY / 2 + 1;
   __shared__ double2 buf[NL * LS];
+  __shared__ double2 oc[NY / 8 + 1];
+  load_octant<NY>(oc, tw, threadIdx.x, FT);
   const int i0 = bx * TXC;
   const int k = by;
   for (int e = threadIdx.x; e < NL * MY; e += FT) {
@@ -323,7 +372,7 @@ __device__ __forceinline__ void iffty_body(const Dims& d, const Fields& f, const
       buf[L * LS + lp(NY - m)] = make_double2(xe.x + xo.y, xo.x - xe.y);   // conj(Xe) + i conj(Xo)
   }
   __syncthreads();
-  FFTPasses<NY, 1, 1, NL, FT, LS>::run(buf, tw);
+  FFTPasses<NY, 1, 1, NL, FT, LS>::run(buf, oc);
   for (int e = threadIdx.x; e < TXC * NY; e += FT) {
     const int ix = e % TXC, j = e / TXC;
     const int i = i0 + ix;
@@ -455,14 +504,14 @@ __device__ __forceinline__ void tri_body(const Dims& d, const Fields& f, const d
           be[t] = -a[1] * inv;
           ga[t] = (t == C - 2 ? -c[t] : 0.0) * inv;
         } else {
-          al[t] = cscale(csub(dd[t], cscale(al[t - 1], a[t])), inv);
+          al[t] = cscale(cfms(dd[t], al[t - 1], a[t]), inv);
           be[t] = (-a[t] * be[t - 1]) * inv;
           ga[t] = ((t == C - 2 ? -c[t] : 0.0) - a[t] * ga[t - 1]) * inv;
         }
       }
 #pragma unroll
       for (int t = C - 3; t >= 1; --t) {
-        al[t] = csub(al[t], cscale(al[t + 1], cp[t]));
+        al[t] = cfms(al[t], al[t + 1], cp[t]);
         be[t] = be[t] - cp[t] * be[t + 1];
         ga[t] = ga[t] - cp[t] * ga[t + 1];
       }
@@ -472,11 +521,11 @@ __device__ __forceinline__ void tri_body(const Dims& d, const Fields& f, const d
         A0 = a[0];
         B0 = b[0] + c[0] * be[1];
         C0 = c[0] * ga[1];
-        D0 = csub(dd[0], cscale(al[1], c[0]));
+        D0 = cfms(dd[0], al[1], c[0]);
         A1 = a[C - 1] * be[C - 2];
         B1 = b[C - 1] + a[C - 1] * ga[C - 2];
         C1 = c[C - 1];
-        D1 = csub(dd[C - 1], cscale(al[C - 2], a[C - 1]));
+        D1 = cfms(dd[C - 1], al[C - 2], a[C - 1]);
       } else {
         A0 = a[0]; B0 = b[0]; C0 = c[0]; D0 = dd[0];
         A1 = a[1]; B1 = b[1]; C1 = c[1]; D1 = dd[1];
@@ -500,13 +549,13 @@ __device__ __forceinline__ void tri_body(const Dims& d, const Fields& f, const d
             const double k1 = Ar * rcp64(B_[rpos(rm)]);
             Aq = -A_[rpos(rm)] * k1;
             Bq -= C_[rpos(rm)] * k1;
-            Dq = csub(Dq, cscale(D_[rpos(rm)], k1));
+            Dq = cfms(Dq, D_[rpos(rm)], k1);
           }
           if (rp < R) {
             const double k2 = Cr * rcp64(B_[rpos(rp)]);
             Cq = -C_[rpos(rp)] * k2;
             Bq -= A_[rpos(rp)] * k2;
-            Dq = csub(Dq, cscale(D_[rpos(rp)], k2));
+            Dq = cfms(Dq, D_[rpos(rp)], k2);
           }
           nA[q] = Aq; nB[q] = Bq; nC[q] = Cq; nD[q] = Dq;
         }
