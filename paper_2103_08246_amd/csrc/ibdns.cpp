@@ -64,6 +64,10 @@ struct ibdns_ctx {
   bool launch_failed = false;
   int variant = 0;  // predictor tile shape
   bool stepped = false;
+  // the flag update overlaps the pressure solve: a second stream, forked
+  // after the immersed-boundary stage and joined before the time advance
+  hipStream_t side = nullptr;
+  hipEvent_t ev_fork = nullptr, ev_join = nullptr;
   // timing
   bool timing = false;
   std::vector<Timed> recs;
@@ -156,27 +160,28 @@ int validate(const ibdns_domain* d) {
     if ((x) != hipSuccess) return IBDNS_EHIP; \
   } while (0)
 
-void rec_begin(ibdns_ctx* c, const char* name, hipEvent_t* a) {
+void rec_begin(ibdns_ctx* c, const char* name, hipEvent_t* a, hipStream_t st) {
   (void)name;
   if (!c->timing) return;
   hipEventCreate(a);
-  hipEventRecord(*a, c->st);
+  hipEventRecord(*a, st);
 }
-void rec_end(ibdns_ctx* c, const char* name, hipEvent_t a) {
+void rec_end(ibdns_ctx* c, const char* name, hipEvent_t a, hipStream_t st) {
   if (!c->timing) return;
   hipEvent_t b;
   hipEventCreate(&b);
-  hipEventRecord(b, c->st);
+  hipEventRecord(b, st);
   c->recs.push_back({name, a, b});
 }
 
-#define TIMED(ctx, name, call)       \
-  do {                               \
-    hipEvent_t ev_a_ = nullptr;      \
-    rec_begin(ctx, name, &ev_a_);    \
-    call;                            \
-    rec_end(ctx, name, ev_a_);       \
+#define TIMED_ON(ctx, stream, name, call)     \
+  do {                                        \
+    hipEvent_t ev_a_ = nullptr;               \
+    rec_begin(ctx, name, &ev_a_, stream);     \
+    call;                                     \
+    rec_end(ctx, name, ev_a_, stream);        \
   } while (0)
+#define TIMED(ctx, name, call) TIMED_ON(ctx, (ctx)->st, name, call)
 
 void stage_predict(ibdns_ctx* c) {
   TIMED(c, "predict", launch_predict(c->d, c->f, c->s, c->variant, c->st));
@@ -184,16 +189,26 @@ void stage_predict(ibdns_ctx* c) {
 }
 void stage_flux(ibdns_ctx* c) { TIMED(c, "flux_apply", launch_flux_apply(c->d, c->f, c->s, c->nparts, c->st)); }
 
-void stage_ibm(ibdns_ctx* c) {
+// Immersed boundary, first half: index maps and interpolation of every
+// point from the same provisional field, hence the forcing of every point.
+void stage_ibm_interp(ibdns_ctx* c) {
   if (c->has_flag) TIMED(c, "flag_stencil", launch_point_stencil(c->d, c->flagpts, c->s, c->st));
   if (c->nbars) TIMED(c, "bars_interp", launch_point_interp(c->d, c->f, c->bars, c->s, c->st));
   if (c->has_flag) TIMED(c, "flag_interp", launch_point_interp(c->d, c->f, c->flagpts, c->s, c->st));
+}
+// Second half: spreading onto the grid (from the maps and amounts of the
+// first half; the flag positions are not read again).
+void stage_ibm_spread(ibdns_ctx* c) {
   if (c->nbars) TIMED(c, "bars_spread", launch_spread_csr(c->d, c->f, c->bars, c->csr, c->st));
   if (c->has_flag) {
     TIMED(c, "flag_bbox", launch_point_bbox(c->flagpts, c->bbox, c->st));
     TIMED(c, "flag_spread",
           launch_spread_tiles(c->d, c->f, c->flagpts, c->bbox, c->ntx, c->nty, c->ntz, c->s, c->st));
   }
+}
+void stage_ibm(ibdns_ctx* c) {
+  stage_ibm_interp(c);
+  stage_ibm_spread(c);
 }
 
 void stage_project(ibdns_ctx* c, int mode) {
@@ -210,6 +225,27 @@ void stage_flag(ibdns_ctx* c) {
   hipError_t e = hipSuccess;
   TIMED(c, "flag_step", e = launch_flag_step(c->fl, c->s, c->st));
   if (e != hipSuccess) c->launch_failed = true;
+}
+
+// Flag update on the side stream, concurrent with the spreading and the
+// pressure solve.  It reads the step's forcing and dt (written before the
+// fork; dt changes only in the advance, after the join) and writes only the
+// flag state and the sub-step count, which nothing on the main stream reads
+// before the join.  Plain launch: its bands are co-resident once dispatched
+// alongside the fluid kernels, and a band that waits for a neighbour not
+// yet dispatched only spins (bounded) until the dispatcher places it.
+bool fork_flag(ibdns_ctx* c) {
+  if (!c->has_flag || !c->side) return false;
+  if (hipEventRecord(c->ev_fork, c->st) != hipSuccess || hipStreamWaitEvent(c->side, c->ev_fork, 0) != hipSuccess) {
+    c->launch_failed = true;
+    return false;
+  }
+  TIMED_ON(c, c->side, "flag_step", launch_flag_step_plain(c->fl, c->s, c->side));
+  if (hipEventRecord(c->ev_join, c->side) != hipSuccess) c->launch_failed = true;
+  return true;
+}
+void join_flag(ibdns_ctx* c) {
+  if (hipStreamWaitEvent(c->st, c->ev_join, 0) != hipSuccess) c->launch_failed = true;
 }
 void stage_advance(ibdns_ctx* c) {
   TIMED(c, "advance", launch_advance(c->s, c->f.speed_part, project_blocks(c->d), c->d.h, c->st));
@@ -678,6 +714,12 @@ int ibdns_set_geometry(ibdns_ctx* c, int64_t n_points, const double* X, const do
     const int ext = (int)std::ceil(std::sqrt(2.0) * 1.01 * L / h) + 4;
     c->ntx = c->nty = c->ntz = (ext + 7) / 8 + 1;
     c->has_flag = true;
+    // default-priority, non-blocking: ordered with the main stream by events only
+    if (!c->side &&
+        (hipStreamCreateWithFlags(&c->side, hipStreamNonBlocking) != hipSuccess ||
+         hipEventCreateWithFlags(&c->ev_fork, hipEventDisableTiming) != hipSuccess ||
+         hipEventCreateWithFlags(&c->ev_join, hipEventDisableTiming) != hipSuccess))
+      return IBDNS_EHIP;
   }
   c->geometry_set = true;
   if (check_launch() != IBDNS_OK || hipStreamSynchronize(c->st) != hipSuccess) return IBDNS_EHIP;
@@ -689,9 +731,14 @@ int ibdns_step(ibdns_ctx* c, int32_t n_steps) {
   for (int n = 0; n < n_steps; ++n) {
     stage_predict(c);
     stage_flux(c);
-    stage_ibm(c);
+    stage_ibm_interp(c);
+    const bool forked = fork_flag(c);
+    stage_ibm_spread(c);
     stage_project(c, 0);
-    stage_flag(c);
+    if (forked)
+      join_flag(c);
+    else
+      stage_flag(c);
     stage_advance(c);
   }
   c->stepped = true;
@@ -749,6 +796,12 @@ int ibdns_get_flag(ibdns_ctx* c, double* X, double* V, double* F) {
 int ibdns_destroy(ibdns_ctx* c) {
   if (!c) return IBDNS_EINVAL;
   hipStreamSynchronize(c->st);
+  if (c->side) {
+    hipStreamSynchronize(c->side);
+    hipStreamDestroy(c->side);
+    hipEventDestroy(c->ev_fork);
+    hipEventDestroy(c->ev_join);
+  }
   for (auto& r : c->recs) {
     hipEventDestroy(r.a);
     hipEventDestroy(r.b);
@@ -920,6 +973,9 @@ struct ibdns_batch {
   bool use_graph = false;
   hipGraph_t graph = nullptr;
   hipGraphExec_t exec = nullptr;
+  // the flag bands run on a side stream, concurrent with the pressure solve
+  hipStream_t side = nullptr;
+  hipEvent_t ev_fork = nullptr, ev_join = nullptr;
 
   template <class T>
   T* carve(size_t count) {
@@ -1014,6 +1070,14 @@ void batch_step_once(ibdns_batch* b, hipStream_t st) {
   if (go(b->stencil)) launch_point_stencil_batch(b->stencil.bl, b->stencil.total, st);
   if (go(b->interp_bars)) launch_point_interp_batch(b->interp_bars.bl, b->interp_bars.total, 0, mx, st);
   if (go(b->interp_flag)) launch_point_interp_batch(b->interp_flag.bl, b->interp_flag.total, 1, mx, st);
+  // fork: the flag update needs only this step's forcing and dt
+  const bool fork = go(b->flag_bands) && b->side;
+  if (fork) {
+    hipEventRecord(b->ev_fork, st);
+    hipStreamWaitEvent(b->side, b->ev_fork, 0);
+    launch_flag_batch(b->flag_prep.bl, b->flag_prep.total, b->flag_bands.bl, b->flag_bands.total, b->side);
+    hipEventRecord(b->ev_join, b->side);
+  }
   if (go(b->spread_csr)) launch_spread_csr_batch(b->spread_csr.bl, b->spread_csr.total, mx, st);
   if (go(b->bbox)) launch_point_bbox_batch(b->bbox.bl, b->bbox.total, st);
   if (go(b->spread_tiles)) launch_spread_tiles_batch(b->spread_tiles.bl, b->spread_tiles.total, mx, st);
@@ -1028,7 +1092,9 @@ void batch_step_once(ibdns_batch* b, hipStream_t st) {
   for (auto& L : b->iffty_g)
     if (go(L)) launch_iffty_batch(L.bl, L.total, L.key, st);
   if (go(b->project)) launch_project_batch(b->project.bl, b->project.total, mx, st);
-  if (go(b->flag_bands))
+  if (fork)
+    hipStreamWaitEvent(st, b->ev_join, 0);
+  else if (go(b->flag_bands))
     launch_flag_batch(b->flag_prep.bl, b->flag_prep.total, b->flag_bands.bl, b->flag_bands.total, st);
   if (go(b->advance)) launch_advance_batch(b->advance.bl, b->advance.total, st);
 }
@@ -1064,6 +1130,12 @@ int ibdns_batch_create(ibdns_ctx* const* runs, int32_t n_runs, void* dev_ws, siz
     if (runs[r]->has_flag && flag_bands(runs[r]->fl.ns) > 64) return IBDNS_EINVAL;
   }
   ibdns_batch* b = new ibdns_batch();
+  if (hipStreamCreateWithFlags(&b->side, hipStreamNonBlocking) != hipSuccess ||
+      hipEventCreateWithFlags(&b->ev_fork, hipEventDisableTiming) != hipSuccess ||
+      hipEventCreateWithFlags(&b->ev_join, hipEventDisableTiming) != hipSuccess) {
+    delete b;
+    return IBDNS_EHIP;
+  }
   b->runs.assign(runs, runs + n_runs);
   b->st = runs[0]->st;
   b->mixed = runs[0]->d.mixed;
@@ -1097,6 +1169,9 @@ int ibdns_batch_create(ibdns_ctx* const* runs, int32_t n_runs, void* dev_ws, siz
   ok = ok && make_launch(b, b->flag_bands, hasf, [&](int r) { return flag_bands(R(r)->fl.ns); });
   ok = ok && make_launch(b, b->advance, all, [&](int) { return 1; });
   if (!ok) {
+    hipStreamDestroy(b->side);
+    hipEventDestroy(b->ev_fork);
+    hipEventDestroy(b->ev_join);
     delete b;
     return IBDNS_ENOMEM;
   }
@@ -1221,7 +1296,11 @@ int ibdns_autotune(ibdns_ctx* c, int32_t* variant_out) {
 int ibdns_batch_destroy(ibdns_batch* b) {
   if (!b) return IBDNS_EINVAL;
   hipStreamSynchronize(b->st);
+  hipStreamSynchronize(b->side);
   batch_drop_graph(b);
+  hipStreamDestroy(b->side);
+  hipEventDestroy(b->ev_fork);
+  hipEventDestroy(b->ev_join);
   delete b;
   return IBDNS_OK;
 }

@@ -197,6 +197,7 @@ void launch_state_to_tilde(const Dims& d, const Fields& f, hipStream_t st);
 int project_blocks(const Dims& d);
 
 hipError_t launch_flag_step(const FlagDev& fl, Scalars* s, hipStream_t st);
+void launch_flag_step_plain(const FlagDev& fl, Scalars* s, hipStream_t st);
 int flag_bands(int ns);
 void launch_advance(Scalars* s, const double* partial, int nparts, double h, hipStream_t st);
 void launch_set_dt0(Scalars* s, const double* partial, int nparts, double h, hipStream_t st);

@@ -15,19 +15,22 @@
 //   velocity-Verlet sub-steps, n_sub = ceil(dt / dts_max); a = 0 nodes fixed.
 //
 // Parallel layout: the lattice is cut into bands of FR spanwise rows, one
-// workgroup per band (co-resident, cooperative launch).  A band keeps its
-// rows plus two halo rows on each side in LDS (the force stencil reaches two
-// rows), its velocities in registers.  After each drift the bands publish
-// their two edge rows to a double-buffered global slot and raise a counter;
-// each band waits (bounded spin) for its two neighbours' counters, then
-// reads their rows into its halo.
+// workgroup per band.  A band keeps its rows plus two halo rows on each side
+// in LDS (the force stencil reaches two rows), its velocities in registers.
+// After each drift the bands publish their two edge rows to a double-buffered
+// global slot and raise a counter; each band waits (bounded spin) for its two
+// neighbours' counters, then reads their rows into its halo.  The time step
+// launches it as a plain kernel on a second stream, concurrent with the
+// spreading and the pressure solve: a band whose neighbour is not yet
+// dispatched spins until the dispatcher places it.  Stand-alone stage runs
+// use a cooperative launch.
 #include "ibdns_internal.h"
 
 namespace ibdns {
 
 namespace {
 
-constexpr int FR = 4;            // rows per band
+constexpr int FR = 8;            // rows per band
 constexpr int FT_ = 512;         // threads per band (one node per thread for ns <= 128)
 constexpr int MAXN = (FR * 128 + FT_ - 1) / FT_;  // owned nodes per thread (ns <= 128)
 constexpr long long SPIN_LIMIT = 1LL << 22;   // bounded wait (seconds at most)
@@ -348,6 +351,11 @@ hipError_t launch_flag_step(const FlagDev& fl, Scalars* s, hipStream_t st) {
   void* args[] = {&a0, &a1};
   // the bands wait on each other: they must be co-resident
   return hipLaunchCooperativeKernel(reinterpret_cast<const void*>(&k_flag), dim3(nb), dim3(FT_), args, 0, st);
+}
+
+void launch_flag_step_plain(const FlagDev& fl, Scalars* s, hipStream_t st) {
+  hipLaunchKernelGGL(k_flag_prep, dim3(1), dim3(64), 0, st, fl);
+  hipLaunchKernelGGL(k_flag, dim3(flag_bands(fl.ns)), dim3(FT_), 0, st, fl, s);
 }
 
 void launch_advance(Scalars* s, const double* partial, int nparts, double h, hipStream_t st) {

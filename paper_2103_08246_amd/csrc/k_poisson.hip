@@ -10,8 +10,7 @@
 // Kernels:
 //   k_div_ffty  divergence of u~ fused with the real-to-complex y FFT of r
 //               (two real x-columns packed into one complex line);
-//   k_fftz      complex z FFT in place on the half spectrum (both signs),
-//               persistent workgroups that prefetch their next tile;
+//   k_fftz      complex z FFT in place on the half spectrum (both signs);
 //   k_tri       one wavefront per x-line: each lane eliminates a contiguous
 //               chunk down to its two end unknowns, the 128-row reduced system
 //               is solved by cyclic reduction in LDS, then back-substitution
@@ -291,58 +290,6 @@ __device__ __forceinline__ void fftz_body(const Dims& d, const Fields& f, const 
     const int ix = e % TXC, k = e / TXC;
     const int i = i0 + ix;
     if (i < d.nx) base[i + lstride * k] = buf[ix * LS + lp(k)];
-  }
-}
-
-// Persistent form of the z FFT: workgroup w takes tiles w, w + G, w + 2G, ...
-// (G workgroups, XCD-contiguous within each round) and loads the next tile
-// into registers while it transforms the current one in LDS.
-template <int NZ, int SIGN>
-__device__ __forceinline__ void fftz_stream_body(const Dims& d, const Fields& f, const double2* __restrict__ tw,
-                                                 const int w, const int G) {
-  constexpr int TXC = 8, NL = 8, LS = line_stride(NZ);
-  constexpr int NEL = (TXC * NZ + FT - 1) / FT;
-  __shared__ double2 buf[NL * LS];
-  __shared__ double2 oc[NZ / 8 + 1];
-  load_octant<NZ>(oc, tw, threadIdx.x, FT);  // ordered by the first barrier of the loop
-  const int gx = (d.nx + TXC - 1) / TXC;
-  const int ntiles = gx * d.MY;
-  const long long lstride = (long long)d.nx * d.MY;
-  double2 pre[NEL];
-  auto fetch = [&](int t) {
-    const int i0 = (t % gx) * TXC, m = t / gx;
-    const double2* base = f.spec + (long long)d.nx * m;
-#pragma unroll
-    for (int q = 0; q < NEL; ++q) {
-      const int e = threadIdx.x + q * FT;
-      const int ix = e % TXC, k = e / TXC;
-      pre[q] = (e < TXC * NZ && i0 + ix < d.nx) ? base[i0 + ix + lstride * k] : make_double2(0.0, 0.0);
-    }
-  };
-  int t = xcd_remap(w, G);
-  if (t < ntiles) fetch(t);
-  for (int round = 0; t < ntiles; ++round) {
-    __syncthreads();  // the previous tile's results have left LDS
-#pragma unroll
-    for (int q = 0; q < NEL; ++q) {
-      const int e = threadIdx.x + q * FT;
-      if (e < TXC * NZ) buf[(e % TXC) * LS + lp(e / TXC)] = pre[q];
-    }
-    __syncthreads();
-    const int tn = (round + 1) * G + xcd_remap(w, G);
-    if (tn < ntiles) fetch(tn);  // in flight during the passes below
-    // an opaque copy of the thread index per round keeps the compiler from
-    // hoisting every pass's LDS offsets out of the loop into registers
-    int tid = threadIdx.x;
-    asm volatile("" : "+v"(tid));
-    FFTPasses<NZ, 1, SIGN, NL, FT, LS>::run(buf, oc, tid);
-    const int i0 = (t % gx) * TXC, m = t / gx;
-    double2* base = f.spec + (long long)d.nx * m;
-    for (int e = threadIdx.x; e < TXC * NZ; e += FT) {
-      const int ix = e % TXC, k = e / TXC;
-      if (i0 + ix < d.nx) base[i0 + ix + lstride * k] = buf[ix * LS + lp(k)];
-    }
-    t = tn;
   }
 }
 
@@ -687,9 +634,9 @@ __global__ void __launch_bounds__(FT) k_div_ffty(Dims d, Fields f, const Scalars
   div_ffty_body<NY, T>(d, f, s, tw, b % gx, b / gx);
 }
 template <int NZ, int SIGN>
-__global__ void __launch_bounds__(FT) k_fftz(Dims d, Fields f,
-                                                                             const double2* __restrict__ tw) {
-  fftz_stream_body<NZ, SIGN>(d, f, tw, blockIdx.x, gridDim.x);
+__global__ void __launch_bounds__(FT) k_fftz(Dims d, Fields f, const double2* __restrict__ tw) {
+  const int gx = (d.nx + 7) / 8, b = xcd_remap(blockIdx.x, gridDim.x);
+  fftz_body<NZ, SIGN>(d, f, tw, b % gx, b / gx);
 }
 template <int NY>
 __global__ void __launch_bounds__(FT) k_iffty(Dims d, Fields f, const double2* __restrict__ tw) {
@@ -829,17 +776,13 @@ static int resident_grid(K kernel, int threads, int ntiles) {
 }
 
 void launch_fftz(const Dims& d, const Fields& f, const double2* tw_z, int sign, hipStream_t st) {
-  const int ntiles = ((d.nx + 7) / 8) * d.MY;
+  const dim3 grid(((d.nx + 7) / 8) * d.MY);
   if (sign < 0) {
-#define CALL(NZ)                                                                         \
-  hipLaunchKernelGGL((k_fftz<NZ, -1>), dim3(resident_grid(k_fftz<NZ, -1>, FT, ntiles)), dim3(FT), 0, st, \
-                     d, f, tw_z)
+#define CALL(NZ) hipLaunchKernelGGL((k_fftz<NZ, -1>), grid, dim3(FT), 0, st, d, f, tw_z)
     IBDNS_FFT_SWITCH(d.nz, CALL)
 #undef CALL
   } else {
-#define CALL(NZ)                                                                        \
-  hipLaunchKernelGGL((k_fftz<NZ, 1>), dim3(resident_grid(k_fftz<NZ, 1>, FT, ntiles)), dim3(FT), 0, st, \
-                     d, f, tw_z)
+#define CALL(NZ) hipLaunchKernelGGL((k_fftz<NZ, 1>), grid, dim3(FT), 0, st, d, f, tw_z)
     IBDNS_FFT_SWITCH(d.nz, CALL)
 #undef CALL
   }
