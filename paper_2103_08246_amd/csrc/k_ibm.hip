@@ -107,7 +107,8 @@ __device__ __forceinline__ void spread_csr_body(const Dims& d, const Fields& f, 
   const double* wts = ps.wts + (size_t)comp * ps.n * 9;
   T acc = 0;
   const int e0 = csr.row_ptr[r], e1 = csr.row_ptr[r + 1];
-  for (int e = e0; e < e1; ++e) {
+#pragma unroll 8
+  for (int e = e0; e < e1; ++e) {  // unrolled: eight entries' gathers in flight
     const int code = csr.entry[e];
     const int q = code / 27, tap = code % 27;
     const int dk = tap / 9, dj = (tap / 3) % 3, di = tap % 3;
