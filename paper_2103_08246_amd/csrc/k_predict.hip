@@ -13,7 +13,8 @@ namespace {
 
 // Tile shapes (x, y, z-planes) the autotuner chooses from; 0 is the default.
 #define IBDNS_PREDICT_VARIANTS(X) \
-  X(0, 64, 8, 16) X(1, 64, 4, 32) X(2, 64, 8, 32) X(3, 32, 8, 16) X(4, 64, 16, 8) X(5, 64, 16, 16) X(6, 32, 16, 32)
+  X(0, 64, 8, 16) X(1, 64, 4, 32) X(2, 64, 8, 32) X(3, 32, 8, 16) X(4, 64, 16, 8) X(5, 64, 16, 16) X(6, 32, 16, 32) \
+  X(7, 128, 8, 32) X(8, 128, 4, 32) X(9, 128, 8, 16) X(10, 256, 4, 16) X(11, 128, 4, 16)
 
 template <class T>
 __device__ __forceinline__ T sq(T a) { return a * a; }
@@ -355,7 +356,11 @@ __global__ void __launch_bounds__(OB) kb_flux_apply(BatchLaunch bl) {
 int outlet_blocks(const Dims& d) { return (int)(((long long)d.ny * d.nz + OB - 1) / OB); }
 int flux_apply_blocks(int nparts) { return flux_blocks(nparts); }
 
-int predict_variants() { return 5; }
+int predict_variants() {
+#define X(V, TX_, TY_, KZ_) +1
+  return 0 IBDNS_PREDICT_VARIANTS(X);
+#undef X
+}
 
 int predict_blocks(const Dims& d, int variant) {
   switch (variant) {
