@@ -227,10 +227,14 @@ int ibdns_set_time(ibdns_ctx* ctx, double dt, double dt_prev, int32_t first_step
  * current positions as floor((X - o_comp)/h + 1/2).  out: n_total*3 int32. */
 int ibdns_get_maps(ibdns_ctx* ctx, int32_t comp, int32_t* out);
 
-/* Per-kernel timing with HIP events recorded on the context's stream.
- * enable != 0 starts accumulating; ibdns_kernel_times fills up to n entries
- * of names/total milliseconds/launch counts (sync first) and returns the
- * number of timed kernels. */
+/* Per-kernel timing with HIP events recorded on the stream each kernel runs on.
+ * enable = IBDNS_TIMING_ALL records around every kernel, IBDNS_TIMING_PREDICT
+ * only around the predictor (two events per step, for timing a run without
+ * perturbing it), 0 stops; a nonzero enable discards earlier records and
+ * starts accumulating afresh.  ibdns_kernel_times fills up to n entries of
+ * names/total milliseconds/launch counts (sync first) and returns the number
+ * of timed kernels.  EINVAL for other values of enable. */
+enum { IBDNS_TIMING_OFF = 0, IBDNS_TIMING_ALL = 1, IBDNS_TIMING_PREDICT = 2 };
 int ibdns_enable_timing(ibdns_ctx* ctx, int32_t enable);
 int ibdns_kernel_times(ibdns_ctx* ctx, int32_t n, const char** names, double* total_ms,
                        int64_t* launches);

@@ -230,8 +230,17 @@ def get_maps(ctx, comp, n_total):
     return out
 
 
-def enable_timing(ctx, on=True):
-    _check(_lib.ibdns_enable_timing(ctx, 1 if on else 0), "enable_timing")
+TIMING_OFF, TIMING_ALL, TIMING_PREDICT = 0, 1, 2
+
+
+def enable_timing(ctx, mode=TIMING_ALL):
+    """mode: TIMING_ALL (every kernel), TIMING_PREDICT (predictor only) or
+    TIMING_OFF; True/False map to TIMING_ALL/TIMING_OFF."""
+    if mode is True:
+        mode = TIMING_ALL
+    elif mode is False:
+        mode = TIMING_OFF
+    _check(_lib.ibdns_enable_timing(ctx, int(mode)), "enable_timing")
 
 
 def kernel_times(ctx, nmax=64):

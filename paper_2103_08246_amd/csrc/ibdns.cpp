@@ -68,8 +68,8 @@ struct ibdns_ctx {
   // after the immersed-boundary stage and joined before the time advance
   hipStream_t side = nullptr;
   hipEvent_t ev_fork = nullptr, ev_join = nullptr;
-  // timing
-  bool timing = false;
+  // timing: IBDNS_TIMING_*
+  int timing = 0;
   std::vector<Timed> recs;
   std::vector<std::pair<std::string, std::pair<double, long long>>> totals;
 
@@ -160,14 +160,16 @@ int validate(const ibdns_domain* d) {
     if ((x) != hipSuccess) return IBDNS_EHIP; \
   } while (0)
 
+bool timed(const ibdns_ctx* c, const char* name) {
+  return c->timing == IBDNS_TIMING_ALL || (c->timing == IBDNS_TIMING_PREDICT && !std::strcmp(name, "predict"));
+}
 void rec_begin(ibdns_ctx* c, const char* name, hipEvent_t* a, hipStream_t st) {
-  (void)name;
-  if (!c->timing) return;
+  if (!timed(c, name)) return;
   hipEventCreate(a);
   hipEventRecord(*a, st);
 }
 void rec_end(ibdns_ctx* c, const char* name, hipEvent_t a, hipStream_t st) {
-  if (!c->timing) return;
+  if (!timed(c, name)) return;
   hipEvent_t b;
   hipEventCreate(&b);
   hipEventRecord(b, st);
@@ -912,8 +914,17 @@ int ibdns_get_maps(ibdns_ctx* c, int32_t comp, int32_t* out) {
 }
 
 int ibdns_enable_timing(ibdns_ctx* c, int32_t enable) {
-  if (!c) return IBDNS_EINVAL;
-  c->timing = enable != 0;
+  if (!c || enable < IBDNS_TIMING_OFF || enable > IBDNS_TIMING_PREDICT) return IBDNS_EINVAL;
+  if (enable != IBDNS_TIMING_OFF) {  // start afresh
+    if (hipStreamSynchronize(c->st) != hipSuccess) return IBDNS_EHIP;
+    for (auto& r : c->recs) {
+      hipEventDestroy(r.a);
+      hipEventDestroy(r.b);
+    }
+    c->recs.clear();
+    c->totals.clear();
+  }
+  c->timing = enable;
   return IBDNS_OK;
 }
 
