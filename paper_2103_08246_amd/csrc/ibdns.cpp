@@ -85,9 +85,17 @@ struct ibdns_ctx {
 
 namespace {
 
+// Row pitch of every field array, in elements: rows start on 128-byte lines
+// for the FP64 arrays (16 doubles) and, in mixed precision, for the FP32
+// provisional arrays too (32 elements).
+int row_pitch(const ibdns_domain& dm) {
+  const int q = dm.precision == IBDNS_MIXED ? 32 : 16;
+  return ((dm.nx + 1 + q - 1) / q) * q;
+}
+
 // Bytes of the fluid part of the workspace.
 size_t fluid_bytes(const ibdns_domain& dm) {
-  const long long P = ((dm.nx + 1 + 15) / 16) * 16;
+  const long long P = row_pitch(dm);
   const long long FS = P * dm.ny * dm.nz;
   const long long MY = dm.ny / 2 + 1;
   const long long nparts = ((long long)dm.ny * dm.nz + 255) / 256;
@@ -151,7 +159,7 @@ int validate(const ibdns_domain* d) {
     return IBDNS_EINVAL;
   if (d->dt <= 0 && !(d->cfl > 0 && d->cfl < 1)) return IBDNS_EINVAL;
   if (d->precision != IBDNS_FP64 && d->precision != IBDNS_MIXED) return IBDNS_EINVAL;
-  if ((long long)(((d->nx + 1 + 15) / 16) * 16) * d->ny * d->nz >= (1LL << 31)) return IBDNS_EINVAL;
+  if ((long long)row_pitch(*d) * d->ny * d->nz >= (1LL << 31)) return IBDNS_EINVAL;
   return IBDNS_OK;
 }
 
@@ -194,9 +202,9 @@ void stage_flux(ibdns_ctx* c) { TIMED(c, "flux_apply", launch_flux_apply(c->d, c
 // Immersed boundary, first half: index maps and interpolation of every
 // point from the same provisional field, hence the forcing of every point.
 void stage_ibm_interp(ibdns_ctx* c) {
-  if (c->has_flag) TIMED(c, "flag_stencil", launch_point_stencil(c->d, c->flagpts, c->s, c->st));
-  if (c->nbars) TIMED(c, "bars_interp", launch_point_interp(c->d, c->f, c->bars, c->s, c->st));
-  if (c->has_flag) TIMED(c, "flag_interp", launch_point_interp(c->d, c->f, c->flagpts, c->s, c->st));
+  if (c->nbars) TIMED(c, "bars_interp", launch_point_interp(c->d, c->f, c->bars, c->s, false, c->st));
+  // the flag's maps move with it: computed in the same launch as its interpolation
+  if (c->has_flag) TIMED(c, "flag_interp", launch_point_interp(c->d, c->f, c->flagpts, c->s, true, c->st));
 }
 // Second half: spreading onto the grid (from the maps and amounts of the
 // first half; the flag positions are not read again).
@@ -390,7 +398,7 @@ int ibdns_init_domain(const ibdns_domain* dm, const double* zu, const double* zv
   d.nx = dm->nx;
   d.ny = dm->ny;
   d.nz = dm->nz;
-  d.P = ((dm->nx + 1 + 15) / 16) * 16;
+  d.P = row_pitch(*dm);
   d.MY = dm->ny / 2 + 1;
   d.PS = (long long)d.P * d.ny;
   d.FS = d.PS * d.nz;
@@ -817,17 +825,18 @@ int ibdns_get_array(ibdns_ctx* c, int32_t which, double* host) {
   if (hipStreamSynchronize(c->st) != hipSuccess) return IBDNS_EHIP;
   int nxh = 0;
   if (double* dev = field_ptr(c, which, &nxh)) {
-    if (!(c->d.mixed && is_tilde(which))) return copy_field(c, dev, nxh, host, true);
-    int r = copy_field_f32(c, dev, nxh, host, true);
+    const bool f32 = c->d.mixed && is_tilde(which);
+    int r = f32 ? copy_field_f32(c, dev, nxh, host, true) : copy_field(c, dev, nxh, host, true);
     if (r || which != IBDNS_ARR_UT) return r;
-    // boundary faces of u~ are FP64: inlet from u, outlet from its plane
+    // the outlet face of u~ lives only in its FP64 plane; in mixed precision
+    // the inlet face is read from u (FP64) as well
     const size_t rows = (size_t)c->d.ny * c->d.nz;
     std::vector<double> in(rows), out(rows);
-    if (pitched_copy<double>(c->f.u, c->d.P, 0, 1, rows, in.data(), 1, true) != IBDNS_OK ||
+    if ((f32 && pitched_copy<double>(c->f.u, c->d.P, 0, 1, rows, in.data(), 1, true) != IBDNS_OK) ||
         hipMemcpy(out.data(), c->f.bnd, rows * sizeof(double), hipMemcpyDeviceToHost) != hipSuccess)
       return IBDNS_EHIP;
     for (size_t q = 0; q < rows; ++q) {
-      host[q * nxh] = in[q];
+      if (f32) host[q * nxh] = in[q];
       host[q * nxh + c->d.nx] = out[q];
     }
     return IBDNS_OK;
@@ -977,7 +986,7 @@ struct ibdns_batch {
     int key = 0;
   };
   std::vector<L> predict;  // one per tile variant
-  L outlet, flux, stencil, interp_bars, interp_flag, spread_csr, bbox, spread_tiles, project,
+  L outlet, flux, interp_bars, interp_flag, spread_csr, bbox, spread_tiles, project,
       flag_prep, flag_bands, advance;
   std::vector<L> div_g, fftz_g, tri_g, iffty_g;
   int variant = 0;
@@ -1078,7 +1087,6 @@ void batch_step_once(ibdns_batch* b, hipStream_t st) {
   if (go(P)) launch_predict_batch(P.bl, P.total, mx, b->variant, st);
   if (go(b->outlet)) launch_outlet_batch(b->outlet.bl, b->outlet.total, mx, st);
   if (go(b->flux)) launch_flux_apply_batch(b->flux.bl, b->flux.total, mx, st);
-  if (go(b->stencil)) launch_point_stencil_batch(b->stencil.bl, b->stencil.total, st);
   if (go(b->interp_bars)) launch_point_interp_batch(b->interp_bars.bl, b->interp_bars.total, 0, mx, st);
   if (go(b->interp_flag)) launch_point_interp_batch(b->interp_flag.bl, b->interp_flag.total, 1, mx, st);
   // fork: the flag update needs only this step's forcing and dt
@@ -1165,7 +1173,6 @@ int ibdns_batch_create(ibdns_ctx* const* runs, int32_t n_runs, void* dev_ws, siz
   ok = ok && make_launch(b, b->flux, all, [&](int r) { return flux_apply_blocks(R(r)->nparts); });
   auto hasf = [&](int r) { return R(r)->has_flag; };
   auto hasb = [&](int r) { return R(r)->nbars > 0; };
-  ok = ok && make_launch(b, b->stencil, hasf, [&](int r) { return stencil_blocks(R(r)->flagpts.n); });
   ok = ok && make_launch(b, b->interp_bars, hasb, [&](int r) { return stencil_blocks(R(r)->bars.n); });
   ok = ok && make_launch(b, b->interp_flag, hasf, [&](int r) { return stencil_blocks(R(r)->flagpts.n); });
   ok = ok && make_launch(b, b->spread_csr, hasb, [&](int r) { return spread_csr_blocks(R(r)->csr); });

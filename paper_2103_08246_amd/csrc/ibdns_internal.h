@@ -178,7 +178,8 @@ void launch_flux_apply(const Dims& d, const Fields& f, Scalars* s, int nblocks, 
 int outlet_blocks(const Dims& d);
 
 void launch_point_stencil(const Dims& d, const PointSet& ps, Scalars* s, hipStream_t st);
-void launch_point_interp(const Dims& d, const Fields& f, const PointSet& ps, Scalars* s,
+// stencil: compute the point maps first (moving points), in the same launch
+void launch_point_interp(const Dims& d, const Fields& f, const PointSet& ps, Scalars* s, bool stencil,
                          hipStream_t st);
 void launch_spread_csr(const Dims& d, const Fields& f, const PointSet& ps,
                        const SpreadCSR* csr3, hipStream_t st);
@@ -214,7 +215,6 @@ int tri_chunk(int nx);
 void launch_predict_batch(const BatchLaunch& bl, int nblocks, int mixed, int variant, hipStream_t st);
 void launch_outlet_batch(const BatchLaunch& bl, int nblocks, int mixed, hipStream_t st);
 void launch_flux_apply_batch(const BatchLaunch& bl, int nblocks, int mixed, hipStream_t st);
-void launch_point_stencil_batch(const BatchLaunch& bl, int nblocks, hipStream_t st);
 void launch_point_interp_batch(const BatchLaunch& bl, int nblocks, int which, int mixed, hipStream_t st);
 void launch_spread_csr_batch(const BatchLaunch& bl, int nblocks, int mixed, hipStream_t st);
 void launch_point_bbox_batch(const BatchLaunch& bl, int nblocks, hipStream_t st);

@@ -296,8 +296,10 @@ __global__ void __launch_bounds__(256) k_point_stencil(Dims d, PointSet ps, Scal
   point_stencil_body(d, ps, s, blockIdx.x, blockIdx.y);
 }
 template <class T>
-__global__ void __launch_bounds__(256) k_point_interp(Dims d, Fields f, PointSet ps, Scalars* s) {
-  point_interp_body<T>(d, f, ps, s, xcd_remap(blockIdx.x, gridDim.x), blockIdx.y);
+__global__ void __launch_bounds__(256) k_point_interp(Dims d, Fields f, PointSet ps, Scalars* s, int stencil) {
+  const int bx = xcd_remap(blockIdx.x, gridDim.x);
+  if (stencil) point_stencil_body(d, ps, s, bx, blockIdx.y);  // moving points: maps of this step first
+  point_interp_body<T>(d, f, ps, s, bx, blockIdx.y);
 }
 // Rows are in grid order: XCD-contiguous row ranges keep each point's delta
 // factors in one L2 instead of all eight.
@@ -310,26 +312,22 @@ __global__ void __launch_bounds__(BBT) k_point_bbox(PointSet ps, int* bbox) {
 }
 template <class T>
 __global__ void __launch_bounds__(TN) k_spread_tiles(Dims d, Fields f, PointSet ps, const int* bbox, int ntx,
-                                                     int nty, int ntz, int comp, Scalars* s) {
-  spread_tiles_body<T>(d, f, ps, bbox, ntx, nty, ntz, comp, s, blockIdx.x);
+                                                     int nty, int ntz, Scalars* s) {
+  const int nt = ntx * nty * ntz;  // one launch for the three components
+  spread_tiles_body<T>(d, f, ps, bbox, ntx, nty, ntz, blockIdx.x / nt, s, blockIdx.x % nt);
 }
 
 // ---- batched forms: run r owns [off[r], off[r+1]) blocks ----
 __host__ __device__ inline int pts_blocks(int n) { return (n + 255) / 256; }
 
 // which = 0: static points, 1: flag nodes; blocks: 3 components x point blocks
-__global__ void __launch_bounds__(256) kb_point_stencil(BatchLaunch bl) {
-  int lb;
-  const RunDesc& R = bl.runs[batch_run(bl, blockIdx.x, &lb)];
-  const int nb = pts_blocks(R.flag.n);
-  point_stencil_body(R.d, R.flag, R.s, lb % nb, lb / nb);
-}
 template <class T>
 __global__ void __launch_bounds__(256) kb_point_interp(BatchLaunch bl, int which) {
   int lb;
   const RunDesc& R = bl.runs[batch_run(bl, blockIdx.x, &lb)];
   const PointSet& ps = which ? R.flag : R.bars;
   const int nb = pts_blocks(ps.n);
+  if (which) point_stencil_body(R.d, ps, R.s, lb % nb, lb / nb);  // the flag moves: maps of this step first
   point_interp_body<T>(R.d, R.f, ps, R.s, lb % nb, lb / nb);
 }
 template <class T>
@@ -360,13 +358,14 @@ void launch_point_stencil(const Dims& d, const PointSet& ps, Scalars* s, hipStre
   hipLaunchKernelGGL(k_point_stencil, dim3((ps.n + 255) / 256, 3), dim3(256), 0, st, d, ps, s);
 }
 
-void launch_point_interp(const Dims& d, const Fields& f, const PointSet& ps, Scalars* s,
+void launch_point_interp(const Dims& d, const Fields& f, const PointSet& ps, Scalars* s, bool stencil,
                          hipStream_t st) {
   if (ps.n == 0) return;
+  const int sten = stencil ? 1 : 0;
   if (d.mixed)
-    hipLaunchKernelGGL(k_point_interp<float>, dim3((ps.n + 255) / 256, 3), dim3(256), 0, st, d, f, ps, s);
+    hipLaunchKernelGGL(k_point_interp<float>, dim3((ps.n + 255) / 256, 3), dim3(256), 0, st, d, f, ps, s, sten);
   else
-    hipLaunchKernelGGL(k_point_interp<double>, dim3((ps.n + 255) / 256, 3), dim3(256), 0, st, d, f, ps, s);
+    hipLaunchKernelGGL(k_point_interp<double>, dim3((ps.n + 255) / 256, 3), dim3(256), 0, st, d, f, ps, s, sten);
 }
 
 void launch_spread_csr(const Dims& d, const Fields& f, const PointSet& ps, const SpreadCSR* csr3,
@@ -391,13 +390,11 @@ void launch_point_bbox(const PointSet& ps, int* bbox, hipStream_t st) {
 void launch_spread_tiles(const Dims& d, const Fields& f, const PointSet& ps, const int* bbox,
                          int ntx, int nty, int ntz, Scalars* s, hipStream_t st) {
   if (ps.n == 0) return;
-  for (int c = 0; c < 3; ++c)
-    if (d.mixed)
-      hipLaunchKernelGGL(k_spread_tiles<float>, dim3(ntx * nty * ntz), dim3(TN), 0, st, d, f, ps, bbox,
-                         ntx, nty, ntz, c, s);
-    else
-      hipLaunchKernelGGL(k_spread_tiles<double>, dim3(ntx * nty * ntz), dim3(TN), 0, st, d, f, ps, bbox,
-                         ntx, nty, ntz, c, s);
+  const dim3 grid(3 * ntx * nty * ntz);
+  if (d.mixed)
+    hipLaunchKernelGGL(k_spread_tiles<float>, grid, dim3(TN), 0, st, d, f, ps, bbox, ntx, nty, ntz, s);
+  else
+    hipLaunchKernelGGL(k_spread_tiles<double>, grid, dim3(TN), 0, st, d, f, ps, bbox, ntx, nty, ntz, s);
 }
 
 }  // namespace ibdns
@@ -409,9 +406,6 @@ int spread_csr_blocks(const SpreadCSR* csr3) {
   return pts_blocks(csr3[0].nrows) + pts_blocks(csr3[1].nrows) + pts_blocks(csr3[2].nrows);
 }
 
-void launch_point_stencil_batch(const BatchLaunch& bl, int nblocks, hipStream_t st) {
-  hipLaunchKernelGGL(kb_point_stencil, dim3(nblocks), dim3(256), 0, st, bl);
-}
 void launch_point_interp_batch(const BatchLaunch& bl, int nblocks, int which, int mixed, hipStream_t st) {
   if (mixed)
     hipLaunchKernelGGL(kb_point_interp<float>, dim3(nblocks), dim3(256), 0, st, bl, which);

@@ -258,19 +258,12 @@ __device__ __forceinline__ void outlet_body(const Dims& d, const Fields& f, cons
       vt = vn - c * (vn - f.v[o1]);
       wt = wn - c * (wn - f.w[o1]);
     }
+    // the provisional outlet face and ghosts live only in these FP64 planes
+    // (the divergence and the projection read them there); H is never
+    // formed at i = nx and keeps the zeros of the workspace
     f.bnd[q] = ut;
     f.bnd[nplane + q] = vt;
     f.bnd[2 * nplane + q] = wt;
-    if (sizeof(T) == sizeof(double)) {
-      f.ut[o] = ut;
-      f.vt[o] = vt;
-      f.wt[o] = wt;
-    }
-    if (update) {
-      reinterpret_cast<T*>(f.hu)[o] = (T)0;
-      reinterpret_cast<T*>(f.hv)[o] = (T)0;
-      reinterpret_cast<T*>(f.hw)[o] = (T)0;
-    }
     sout = ut;
     sin_ = f.u[fidx(d, 0, j, k)];
   }
@@ -330,12 +323,7 @@ __device__ __forceinline__ void flux_apply_body(const Dims& d, const Fields& f, 
   if (bx == 0 && tid == 0) s->corr = corr;
   const long long nplane = (long long)d.ny * d.nz;
   for (long long q = (long long)bx * OB + tid; q < nplane; q += (long long)gx * OB) {
-    const double v = f.bnd[q] + corr;
-    f.bnd[q] = v;
-    if (sizeof(T) == sizeof(double)) {
-      const int j = (int)(q % d.ny), k = (int)(q / d.ny);
-      f.ut[fidx(d, d.nx, j, k)] = v;
-    }
+    f.bnd[q] += corr;
   }
 }
 
