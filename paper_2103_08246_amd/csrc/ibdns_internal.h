@@ -2,7 +2,8 @@
 //
 // Device layout (one run):
 //   field arrays u, v, w, p, H (3), provisional u~ (3), phi: doubles at
-//   a[i + P * (j + ny * k)], P = x pitch >= nx + 1 (a multiple of 16 doubles);
+//   a[i + P * (j + ny * k)], P = x pitch >= nx + 1 (a multiple of 16, of 32
+//   in mixed precision: rows start on 128-byte lines);
 //   u uses i = 0..nx (faces), v and w use i = 0..nx-1 plus the outlet ghost at
 //   i = nx, p and phi use i = 0..nx-1.  In mixed precision H and u~ hold
 //   floats at the same indices (the arrays keep their double-sized slots);

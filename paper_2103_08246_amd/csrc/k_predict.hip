@@ -233,8 +233,7 @@ __host__ __device__ inline int flux_blocks(int nparts) { return nparts < 64 ? np
 // i = nx; the test hook keeps the ghosts) into the FP64 boundary planes
 // f.bnd (u~, v~, w~ at i = nx), plus per-block partial sums of u~ at the
 // outlet and of u at the inlet.  update == 0 (initial projection) only copies
-// the current values and sums.  With T = double the provisional arrays also
-// receive the outlet values.
+// the current values and sums.  The provisional arrays hold no outlet values.
 template <class T>
 __device__ __forceinline__ void outlet_body(const Dims& d, const Fields& f, const Scalars* __restrict__ s,
                                             int update, const int bx) {
@@ -297,8 +296,7 @@ __global__ void __launch_bounds__(OB) kb_outlet(BatchLaunch bl, int update) {
 }
 
 // corr = (sum u_0 - sum u~_nx) / (ny nz) added to u~ at the outlet (FP64
-// plane; also the FP64 provisional array); every block reduces the partials
-// in the same fixed order.
+// plane); every block reduces the partials in the same fixed order.
 template <class T>
 __device__ __forceinline__ void flux_apply_body(const Dims& d, const Fields& f, Scalars* s, int nparts,
                                                 const int bx, const int gx) {
