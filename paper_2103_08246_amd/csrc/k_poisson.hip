@@ -627,11 +627,23 @@ __device__ __forceinline__ void project_body(const Dims& d, const Fields& f, Sca
 }
 
 // Single-run kernels: 1-D grids; the z FFT takes its tiles in XCD-aware order.
+// FP32 provisional rows: a 16-column tile reads half of each 128-byte line, so
+// a workgroup takes the two tiles that share those lines, one after the other.
+template <class T>
+__host__ __device__ constexpr int div_tiles_per_block() { return sizeof(T) == 4 ? 2 : 1; }
 template <int NY, class T>
 __global__ void __launch_bounds__(FT) k_div_ffty(Dims d, Fields f, const Scalars* __restrict__ s,
                                                  const double2* __restrict__ tw) {
-  const int gx = (d.nx + 15) / 16, b = blockIdx.x;
-  div_ffty_body<NY, T>(d, f, s, tw, b % gx, b / gx);
+  constexpr int TPB = div_tiles_per_block<T>();
+  const int gx = (d.nx + 15) / 16, gp = (gx + TPB - 1) / TPB;
+  const int bp = blockIdx.x % gp, k = blockIdx.x / gp;
+  div_ffty_body<NY, T>(d, f, s, tw, TPB * bp, k);
+  if constexpr (TPB == 2) {
+    if (2 * bp + 1 < gx) {
+      __syncthreads();  // the first tile has left LDS
+      div_ffty_body<NY, T>(d, f, s, tw, 2 * bp + 1, k);
+    }
+  }
 }
 template <int NZ, int SIGN>
 __global__ void __launch_bounds__(FT) k_fftz(Dims d, Fields f, const double2* __restrict__ tw) {
@@ -746,12 +758,14 @@ bool fft_size_supported(int n) {
 
 void launch_div_ffty(const Dims& d, const Fields& f, const Scalars* s, const double2* tw_y,
                      hipStream_t st) {
-  dim3 grid(((d.nx + 15) / 16) * d.nz);
+  const int gx = (d.nx + 15) / 16;
   if (d.mixed) {
+    const dim3 grid(((gx + 1) / 2) * d.nz);
 #define CALL(NY) hipLaunchKernelGGL((k_div_ffty<NY, float>), grid, dim3(FT), 0, st, d, f, s, tw_y)
     IBDNS_FFT_SWITCH(d.ny, CALL)
 #undef CALL
   } else {
+    const dim3 grid(gx * d.nz);
 #define CALL(NY) hipLaunchKernelGGL((k_div_ffty<NY, double>), grid, dim3(FT), 0, st, d, f, s, tw_y)
     IBDNS_FFT_SWITCH(d.ny, CALL)
 #undef CALL
