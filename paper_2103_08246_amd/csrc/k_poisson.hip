@@ -114,6 +114,13 @@ struct DFT<8, SIGN> {
 // groups; the odd line stride does the same for the 8-line staging.
 __device__ __forceinline__ constexpr int lp(int e) { return e ^ ((e >> 3) & 7); }
 __host__ __device__ constexpr int line_stride(int n) { return n + 1; }
+// Iterations per batch of a staging loop of n iterations whose loads are
+// issued together: at most umax, in batches of equal size (the last batch may
+// run past n: its extra iterations read a clamped address and store nothing).
+__host__ __device__ constexpr int load_batch(int n, int umax = 8) {
+  const int nb = (n + umax - 1) / umax;
+  return (n + nb - 1) / nb;
+}
 
 // Twiddles from an LDS table of the first octant, oc[r] = (cos, sin)(2 pi r / N)
 // for r = 0..N/8: exp(-2 pi i m / N) for any 0 <= m < N by the octant
@@ -227,31 +234,53 @@ __device__ __forceinline__ void div_ffty_body(const Dims& d, const Fields& f, co
   const T* __restrict__ ut = reinterpret_cast<const T*>(f.ut);
   const T* __restrict__ vt = reinterpret_cast<const T*>(f.vt);
   const T* __restrict__ wt = reinterpret_cast<const T*>(f.wt);
-  const int i0 = bx * TXC;
   const int k = by;
   const int kp = (k + 1 == d.nz) ? 0 : k + 1;
   const double dt = s->dt;
-  for (int e = threadIdx.x; e < TXC * NY; e += FT) {
-    const int ix = e % TXC, j = e / TXC;
-    const int i = i0 + ix;
-    double r = 0.0;
-    if (i < d.nx) {
+  // Every thread keeps one column (FT is a multiple of TXC) and walks the rows
+  // j = tid / TXC + RP n; the loads of U rows are issued before any is used.
+  // Columns past nx read the last column and store 0.
+  static_assert(FT % TXC == 0, "one column per thread");
+  constexpr int RP = FT / TXC, NIT = (NY + RP - 1) / RP, U = load_batch(NIT, 4);
+  const int ix = threadIdx.x % TXC, i = bx * TXC + ix;
+  const bool live = i < d.nx;
+  const int ic = live ? i : d.nx - 1;
+  for (int n0 = 0; n0 < NIT; n0 += U) {
+    T a1[U], a0[U], b1[U], b0[U], c1[U], c0[U];
+#pragma unroll
+    for (int q = 0; q < U; ++q) {
+      const int j = min((n0 + q) * RP + (int)threadIdx.x / TXC, NY - 1);
       const int jp = (j + 1 == NY) ? 0 : j + 1;
-      const long long c = fidx(d, i, j, k);
-      // boundary faces: the inlet from u, the outlet from the FP64 plane
-      const double u1 = (i + 1 == d.nx) ? f.bnd[j + (long long)NY * k] : (double)ut[c + 1];
-      const double u0 = (i == 0) ? f.u[c] : (double)ut[c];
-      r = (((u1 - u0) + ((double)vt[fidx(d, i, jp, k)] - (double)vt[c])) +
-           ((double)wt[fidx(d, i, j, kp)] - (double)wt[c])) / d.h / dt;
+      const long long c = fidx(d, ic, j, k);
+      a1[q] = ut[c + 1];  // i = nx - 1: the ghost slot, replaced below
+      a0[q] = ut[c];
+      b1[q] = vt[fidx(d, ic, jp, k)];
+      b0[q] = vt[c];
+      c1[q] = wt[fidx(d, ic, j, kp)];
+      c0[q] = wt[c];
     }
-    double2* slot = &buf[(ix >> 1) * LS + lp(j)];
-    if (ix & 1)
-      slot->y = r;
-    else
-      slot->x = r;
+#pragma unroll
+    for (int q = 0; q < U; ++q) {
+      const int j = (n0 + q) * RP + (int)threadIdx.x / TXC;
+      if (j < NY) {
+        // boundary faces: the inlet from u, the outlet from the FP64 plane
+        double u1 = (double)a1[q], u0 = (double)a0[q];
+        if (ic + 1 == d.nx) u1 = f.bnd[j + (long long)NY * k];
+        if (ic == 0) u0 = f.u[fidx(d, 0, j, k)];
+        const double r = live ? (((u1 - u0) + ((double)b1[q] - (double)b0[q])) +
+                                 ((double)c1[q] - (double)c0[q])) / d.h / dt
+                              : 0.0;
+        double2* slot = &buf[(ix >> 1) * LS + lp(j)];
+        if (ix & 1)
+          slot->y = r;
+        else
+          slot->x = r;
+      }
+    }
   }
   __syncthreads();
   FFTPasses<NY, 1, -1, NL, FT, LS>::run(buf, oc);
+  const int i0 = bx * TXC;
   for (int e = threadIdx.x; e < TXC * MY; e += FT) {
     const int ix = e % TXC, m = e / TXC;
     const int i = i0 + ix;
@@ -279,10 +308,24 @@ __device__ __forceinline__ void fftz_body(const Dims& d, const Fields& f, const 
   const int m = by;
   const long long lstride = (long long)d.nx * d.MY;
   double2* base = f.spec + (long long)d.nx * m;
-  for (int e = threadIdx.x; e < TXC * NZ; e += FT) {
-    const int ix = e % TXC, k = e / TXC;
-    const int i = i0 + ix;
-    buf[ix * LS + lp(k)] = (i < d.nx) ? base[i + lstride * k] : make_double2(0.0, 0.0);
+  // loads of U elements per thread issued before any is used; out-of-range
+  // elements read a clamped address and store 0
+  constexpr int TOT = TXC * NZ, NIT = (TOT + FT - 1) / FT, U = load_batch(NIT);
+  for (int n0 = 0; n0 < NIT; n0 += U) {
+    double2 v[U];
+#pragma unroll
+    for (int q = 0; q < U; ++q) {
+      const int e = min((int)threadIdx.x + (n0 + q) * FT, TOT - 1);
+      v[q] = base[min(i0 + e % TXC, d.nx - 1) + lstride * (e / TXC)];
+    }
+#pragma unroll
+    for (int q = 0; q < U; ++q) {
+      const int e = threadIdx.x + (n0 + q) * FT;
+      if (e < TOT) {
+        const int ix = e % TXC, k = e / TXC;
+        buf[ix * LS + lp(k)] = (i0 + ix < d.nx) ? v[q] : make_double2(0.0, 0.0);
+      }
+    }
   }
   __syncthreads();
   FFTPasses<NZ, 1, SIGN, NL, FT, LS>::run(buf, oc);
@@ -304,19 +347,34 @@ __device__ __forceinline__ void iffty_body(const Dims& d, const Fields& f, const
   load_octant<NY>(oc, tw, threadIdx.x, FT);
   const int i0 = bx * TXC;
   const int k = by;
-  for (int e = threadIdx.x; e < NL * MY; e += FT) {
-    const int L = e % NL, m = e / NL;
-    const int ie = i0 + 2 * L, io = ie + 1;
-    const long long off = (long long)d.nx * (m + (long long)MY * k);
-    double2 xe = ie < d.nx ? f.spec[ie + off] : make_double2(0.0, 0.0);
-    double2 xo = io < d.nx ? f.spec[io + off] : make_double2(0.0, 0.0);
-    if (m == 0 || 2 * m == NY) {  // real-signal spectrum: these bins are real
-      xe.y = 0.0;
-      xo.y = 0.0;
+  // loads of U element pairs per thread issued before any is used
+  constexpr int TOT = NL * MY, NIT = (TOT + FT - 1) / FT, U = load_batch(NIT);
+  for (int n0 = 0; n0 < NIT; n0 += U) {
+    double2 ve[U], vo[U];
+#pragma unroll
+    for (int q = 0; q < U; ++q) {
+      const int e = min((int)threadIdx.x + (n0 + q) * FT, TOT - 1);
+      const int ie = i0 + 2 * (e % NL);
+      const long long off = (long long)d.nx * (e / NL + (long long)MY * k);
+      ve[q] = f.spec[min(ie, d.nx - 1) + off];
+      vo[q] = f.spec[min(ie + 1, d.nx - 1) + off];
     }
-    buf[L * LS + lp(m)] = make_double2(xe.x - xo.y, xe.y + xo.x);          // Xe + i Xo
-    if (m > 0 && 2 * m < NY)
-      buf[L * LS + lp(NY - m)] = make_double2(xe.x + xo.y, xo.x - xe.y);   // conj(Xe) + i conj(Xo)
+#pragma unroll
+    for (int q = 0; q < U; ++q) {
+      const int e = threadIdx.x + (n0 + q) * FT;
+      if (e >= TOT) continue;
+      const int L = e % NL, m = e / NL;
+      const int ie = i0 + 2 * L, io = ie + 1;
+      double2 xe = ie < d.nx ? ve[q] : make_double2(0.0, 0.0);
+      double2 xo = io < d.nx ? vo[q] : make_double2(0.0, 0.0);
+      if (m == 0 || 2 * m == NY) {  // real-signal spectrum: these bins are real
+        xe.y = 0.0;
+        xo.y = 0.0;
+      }
+      buf[L * LS + lp(m)] = make_double2(xe.x - xo.y, xe.y + xo.x);          // Xe + i Xo
+      if (m > 0 && 2 * m < NY)
+        buf[L * LS + lp(NY - m)] = make_double2(xe.x + xo.y, xo.x - xe.y);   // conj(Xe) + i conj(Xo)
+    }
   }
   __syncthreads();
   FFTPasses<NY, 1, 1, NL, FT, LS>::run(buf, oc);
