@@ -96,27 +96,37 @@ __device__ __forceinline__ void point_interp_body(const Dims& d, const Fields& f
   ps.amount[(size_t)comp * ps.n + q] = dt * F * ps.dV[q] / h3;
 }
 
-// Static points: one thread per touched grid node, gathering its CSR row.
+// Static points: LPR lanes per touched grid node gather its CSR row (lane l
+// takes the entries l, l + LPR, ...), then add their partial sums in a fixed
+// butterfly order.
+constexpr int LPR = 4;           // lanes per row
+constexpr int RPB = 256 / LPR;   // rows per workgroup
+__host__ __device__ inline int csr_blocks(int nrows) { return (nrows + RPB - 1) / RPB; }
+
 template <class T>
 __device__ __forceinline__ void spread_csr_body(const Dims& d, const Fields& f, const PointSet& ps,
                                                 const SpreadCSR& csr, int comp, int bx) {
   (void)d;
-  const int r = bx * 256 + threadIdx.x;
-  if (r >= csr.nrows) return;
+  const int r = bx * RPB + (int)threadIdx.x / LPR, l = threadIdx.x % LPR;
+  if (r >= csr.nrows) return;  // whole aligned lane groups leave together
   const double* amt = ps.amount + (size_t)comp * ps.n;
   const double* wts = ps.wts + (size_t)comp * ps.n * 9;
   T acc = 0;
   const int e0 = csr.row_ptr[r], e1 = csr.row_ptr[r + 1];
-#pragma unroll 8
-  for (int e = e0; e < e1; ++e) {  // unrolled: eight entries' gathers in flight
+#pragma unroll 4
+  for (int e = e0 + l; e < e1; e += LPR) {  // unrolled: four entries' gathers in flight
     const int code = csr.entry[e];
     const int q = code / 27, tap = code % 27;
     const int dk = tap / 9, dj = (tap / 3) % 3, di = tap % 3;
     const double* wt = wts + (size_t)q * 9;
     acc += (T)amt[q] * (T)(wt[di] * wt[3 + dj] * wt[6 + dk]);
   }
-  T* fld = comp_field<T>(f, comp);
-  fld[csr.row_node[r]] += acc;
+#pragma unroll
+  for (int o = 1; o < LPR; o <<= 1) acc += __shfl_xor(acc, o, 64);
+  if (l == 0) {
+    T* fld = comp_field<T>(f, comp);
+    fld[csr.row_node[r]] += acc;
+  }
 }
 
 // Bounding boxes (in unwrapped node indices) of the 3x3x3 supports of a
@@ -335,7 +345,7 @@ __global__ void __launch_bounds__(256) kb_spread_csr(BatchLaunch bl) {
   int lb;
   const RunDesc& R = bl.runs[batch_run(bl, blockIdx.x, &lb)];
   int comp = 0;
-  while (comp < 2 && lb >= pts_blocks(R.csr[comp].nrows)) lb -= pts_blocks(R.csr[comp++].nrows);
+  while (comp < 2 && lb >= csr_blocks(R.csr[comp].nrows)) lb -= csr_blocks(R.csr[comp++].nrows);
   spread_csr_body<T>(R.d, R.f, R.bars, R.csr[comp], comp, lb);
 }
 __global__ void __launch_bounds__(BBT) kb_point_bbox(BatchLaunch bl) {
@@ -374,10 +384,10 @@ void launch_spread_csr(const Dims& d, const Fields& f, const PointSet& ps, const
   for (int c = 0; c < 3; ++c) {
     if (csr3[c].nrows == 0) continue;
     if (d.mixed)
-      hipLaunchKernelGGL(k_spread_csr<float>, dim3((csr3[c].nrows + 255) / 256), dim3(256), 0, st, d, f,
+      hipLaunchKernelGGL(k_spread_csr<float>, dim3(csr_blocks(csr3[c].nrows)), dim3(256), 0, st, d, f,
                          ps, csr3[c], c);
     else
-      hipLaunchKernelGGL(k_spread_csr<double>, dim3((csr3[c].nrows + 255) / 256), dim3(256), 0, st, d, f,
+      hipLaunchKernelGGL(k_spread_csr<double>, dim3(csr_blocks(csr3[c].nrows)), dim3(256), 0, st, d, f,
                          ps, csr3[c], c);
   }
 }
@@ -403,7 +413,7 @@ namespace ibdns {
 
 int stencil_blocks(int npts) { return 3 * pts_blocks(npts); }
 int spread_csr_blocks(const SpreadCSR* csr3) {
-  return pts_blocks(csr3[0].nrows) + pts_blocks(csr3[1].nrows) + pts_blocks(csr3[2].nrows);
+  return csr_blocks(csr3[0].nrows) + csr_blocks(csr3[1].nrows) + csr_blocks(csr3[2].nrows);
 }
 
 void launch_point_interp_batch(const BatchLaunch& bl, int nblocks, int which, int mixed, hipStream_t st) {
