@@ -252,7 +252,8 @@ def main():
            "kernel_avg_ms_note": "separate pass of the same length with events around every kernel"}
     if not args.no_mixed:
         # the same workload with the FP32 RHS/predictor and IB transfer
-        run_m, wall_m, _, _ = measure(ib.MIXED, False)
+        # (with the per-kernel pass too, so that both runs stand at the same step)
+        run_m, wall_m, _, times_m = measure(ib.MIXED, True)
         print(f"# mixed: {wall_m * 1e3 / args.steps:.3f} ms/step", file=sys.stderr, flush=True)
         a = run.fields()
         b = run_m.fields()
@@ -263,7 +264,10 @@ def main():
                         "ms_per_step": round(wall_m * 1e3 / args.steps, 4),
                         "speedup_vs_fp64": round(wall / wall_m, 3),
                         "vel_rel_l2_vs_fp64": (num / den) ** 0.5, "max_abs_div": dmax,
-                        "after_steps": args.warmup + args.steps}
+                        "after_steps": args.warmup + 2 * args.steps,
+                        "predict_variant": run_m.variant,
+                        "kernel_avg_ms": {k: round(v[0] / max(v[1], 1), 4) for k, v in
+                                          sorted(times_m["all"].items(), key=lambda kv: -kv[1][0])}}
         run_m.close()
     del noise
     run.close()
