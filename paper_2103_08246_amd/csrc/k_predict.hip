@@ -14,7 +14,8 @@ namespace {
 // Tile shapes (x, y, z-planes) the autotuner chooses from; 0 is the default.
 #define IBDNS_PREDICT_VARIANTS(X) \
   X(0, 64, 8, 16) X(1, 64, 4, 32) X(2, 64, 8, 32) X(3, 32, 8, 16) X(4, 64, 16, 8) X(5, 64, 16, 16) X(6, 32, 16, 32) \
-  X(7, 128, 8, 32) X(8, 128, 4, 32) X(9, 128, 8, 16) X(10, 256, 4, 16) X(11, 128, 4, 16)
+  X(7, 128, 8, 32) X(8, 128, 4, 32) X(9, 128, 8, 16) X(10, 256, 4, 16) X(11, 128, 4, 16) \
+  X(12, 128, 8, 24) X(13, 128, 8, 48)
 
 template <class T>
 __device__ __forceinline__ T sq(T a) { return a * a; }

@@ -36,7 +36,7 @@ def test_batch_equals_single_runs(graph, tune):
     try:
         if tune:
             v = b.autotune()
-            assert 0 <= v < 12   # twelve predictor tile shapes
+            assert 0 <= v < 14   # fourteen predictor tile shapes
         if graph:
             b.use_graph(True)
         b.step(6)
@@ -75,7 +75,7 @@ def test_single_run_autotune_keeps_parity():
     run, S = build_pair(w)
     try:
         v = ib.autotune(run.ctx)
-        assert 0 <= v < 12   # twelve predictor tile shapes
+        assert 0 <= v < 14   # fourteen predictor tile shapes
         run.step(5)
         S.step(5)
         u, vv, ww, p, t, k = run.fields()
