@@ -72,13 +72,17 @@ __device__ __forceinline__ void predict_body(const Dims& d, const Fields& f, con
       rw[q] = c;
     }
   };
+  // The pressure gradient reads p at x-1 and y-1 only: the x+1 column and the
+  // y+1 row of the halo are not loaded (a whole 128-byte line per row for one
+  // x+1 element).
   auto fetch_p = [&](int kk) {
 #pragma unroll
     for (int q = 0; q < NE; ++q) {
       const int e = tid + q * NT;
       const int lx = e % LX, ly = e / LX;
       const int gi = i0 - 1 + lx, gj = wrapi(j0 - 1 + ly, d.ny);
-      rp[q] = (e < LP && gi >= 0 && gi < nx) ? (T)p[fidx(d, gi, gj, kk)] : (T)0;
+      rp[q] = (e < LP && gi >= 0 && gi < nx && lx < LX - 1 && ly < LY - 1) ? (T)p[fidx(d, gi, gj, kk)]
+                                                                           : (T)0;
     }
   };
   auto commit_plane = [&](int slot) {
