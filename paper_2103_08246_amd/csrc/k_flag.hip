@@ -14,8 +14,9 @@
 //   load -F dV from the immersed-boundary forcing of the step;
 //   velocity-Verlet sub-steps, n_sub = ceil(dt / dts_max); a = 0 nodes fixed.
 //
-// Parallel layout: the lattice is cut into bands of FR spanwise rows, one
-// workgroup per band.  A band keeps its rows plus two halo rows on each side
+// Parallel layout: the lattice is cut into bands of spanwise rows, one
+// workgroup per band, as many rows as keep a band within 1024 nodes (a flag
+// of up to 32 x 32 nodes is one band and exchanges nothing).  A band keeps its rows plus two halo rows on each side
 // in LDS (the force stencil reaches two rows), its velocities in registers.
 // After each drift the bands publish their two edge rows to a double-buffered
 // global slot and raise a counter; each band waits (bounded spin) for its two
@@ -28,11 +29,17 @@
 
 namespace ibdns {
 
+// Rows per band of an ns x ns flag (ns <= 128): at least 8, so at most 16 bands.
+__host__ __device__ inline int band_rows(int ns) {
+  const int r = 1024 / ns;
+  return r < ns ? r : ns;
+}
+
 namespace {
 
-constexpr int FR = 8;            // rows per band
-constexpr int FT_ = 512;         // threads per band (one node per thread for ns <= 128)
-constexpr int MAXN = (FR * 128 + FT_ - 1) / FT_;  // owned nodes per thread (ns <= 128)
+constexpr int BN = 1024;         // nodes per band at most
+constexpr int FT_ = 512;         // threads per band
+constexpr int MAXN = (BN + FT_ - 1) / FT_;  // owned nodes per thread
 constexpr long long SPIN_LIMIT = 1LL << 22;   // bounded wait (seconds at most)
 
 struct V3 {
@@ -123,11 +130,13 @@ __global__ void k_flag_prep(FlagDev fl) {
 
 __device__ __forceinline__ void flag_body(const FlagDev& fl, Scalars* s, const int band, const int nband) {
   const int ns = fl.ns;
-  const int b0 = band * FR;
-  const int b1 = min(b0 + FR, ns);        // own rows [b0, b1)
+  const int rows = band_rows(ns);
+  const int b0 = band * rows;
+  const int b1 = min(b0 + rows, ns);      // own rows [b0, b1)
   const int rb0 = b0 - 2;                 // LDS row 0 = lattice row b0 - 2
-  __shared__ double Xs[(FR + 4) * 128 * 3];
-  __shared__ double Rs[FR * 128 * 6];
+  // own rows plus two halo rows per side: rows * ns <= BN, ns <= 128
+  __shared__ double Xs[(BN + 4 * 128) * 3];
+  __shared__ double Rs[BN * 6];
   __shared__ int abort_flag;
   const int tid = threadIdx.x;
   if (tid == 0) abort_flag = 0;
@@ -233,7 +242,7 @@ __device__ __forceinline__ void flag_body(const FlagDev& fl, Scalars* s, const i
       for (int hb = rb0; hb < b1 + 2; ++hb) {
         if (hb < 0 || hb >= ns || (hb >= b0 && hb < b1)) continue;
         const int nbh = hb < b0 ? band - 1 : band + 1;
-        const int nb0 = nbh * FR, nb1 = min(nb0 + FR, ns);
+        const int nb0 = nbh * rows, nb1 = min(nb0 + rows, ns);
         const int r = (hb - nb0 < 2) ? hb - nb0 : hb - (nb1 - 4);
         const double* src = fl.xbuf + ((size_t)(it & 1) * nband + nbh) * 4 * 3 * ns + r * 3 * ns;
         for (int q = tid; q < 3 * ns; q += FT_)
@@ -271,7 +280,7 @@ __global__ void kb_flag_prep(BatchLaunch bl) {
 __global__ void __launch_bounds__(FT_) kb_flag(BatchLaunch bl) {
   int lb;
   const RunDesc& R = bl.runs[batch_run(bl, blockIdx.x, &lb)];
-  flag_body(R.fl, R.s, lb, (R.fl.ns + FR - 1) / FR);
+  flag_body(R.fl, R.s, lb, (R.fl.ns + band_rows(R.fl.ns) - 1) / band_rows(R.fl.ns));
 }
 
 // dt_{n+1} from the cell-speed maxima of the projection, then t, history.
@@ -340,7 +349,7 @@ __global__ void __launch_bounds__(RT) k_set_dt0(Scalars* s, const double* partia
 
 }  // namespace
 
-int flag_bands(int ns) { return (ns + FR - 1) / FR; }
+int flag_bands(int ns) { return (ns + band_rows(ns) - 1) / band_rows(ns); }
 
 hipError_t launch_flag_step(const FlagDev& fl, Scalars* s, hipStream_t st) {
   const int nb = flag_bands(fl.ns);
