@@ -38,7 +38,7 @@ __host__ __device__ inline int band_rows(int ns) {
 namespace {
 
 constexpr int BN = 1024;         // nodes per band at most
-constexpr int FT_ = 512;         // threads per band
+constexpr int FT_ = 1024;        // threads per band (one node per thread)
 constexpr int MAXN = (BN + FT_ - 1) / FT_;  // owned nodes per thread
 constexpr long long SPIN_LIMIT = 1LL << 22;   // bounded wait (seconds at most)
 
