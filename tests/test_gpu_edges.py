@@ -76,6 +76,30 @@ def test_largest_flag_parity():
         run.close()
 
 
+@pytest.mark.parametrize("ns", [32, 33, 48, 121])
+def test_flag_band_shapes_parity(ns):
+    """Bands of min(ns, 1024 // ns) rows: 32 is one band of 1024 nodes, 33 two
+    bands (31 + 2 rows), 48 three (21 + 21 + 6), 121 sixteen with a last band
+    of one row."""
+    w = synth.Workload(name=f"flag_bands_{ns}", nx=64, ny=32, nz=32, lx=4.0, ly=2.0, lz=2.0,
+                       re=200.0, dt=1e-3, flag=synth.Flag(ns=ns, length=1.0, x_le=1.0, y_c=1.0,
+                                                          z_c=1.0, bending=0.01))
+    run, S = build_pair(w)
+    try:
+        for _ in range(2):
+            run.step(1)
+            S.step(1)
+        u, v, ww, p, t, k = run.fields()
+        uo, vo, wo, po = S.fields()
+        assert rel_l2([u, v, ww], [uo, vo, wo]) < 1e-12
+        X, V, F = run.flag()
+        assert rel_l2([X], [S.X.reshape(X.shape)]) < 1e-13
+        assert rel_l2([V], [S.V.reshape(V.shape)]) < 1e-9
+        assert ib.get_scalars(run.ctx)["nsub"] == S.nsub
+    finally:
+        run.close()
+
+
 def test_flag_support_outside_x_range_is_rejected():
     """Leading edge half a cell behind the inlet: its support leaves the evolved
     x range, and set_geometry refuses it (a flag that drifts out later is
