@@ -27,11 +27,12 @@ def make(w, precision=ib.FP64):
                      flag=ib.flag_from(w.flag) if w.flag is not None else None, flag_X0=X0)
 
 
-@pytest.mark.parametrize("graph,tune", [(False, False), (True, False), (True, True)])
-def test_batch_equals_single_runs(graph, tune):
+@pytest.mark.parametrize("graph,tune,precision", [(False, False, ib.FP64), (True, False, ib.FP64),
+                                                   (True, True, ib.FP64), (True, False, ib.MIXED)])
+def test_batch_equals_single_runs(graph, tune, precision):
     ws = members()
-    single = [make(w) for w in ws]
-    batched = [make(w) for w in ws]
+    single = [make(w, precision) for w in ws]
+    batched = [make(w, precision) for w in ws]
     b = ib.Batch(batched)
     try:
         if tune:
