@@ -183,12 +183,12 @@ int ibdns_batch_destroy(ibdns_batch* b);
 
 /* Stages of one step, in order. */
 enum {
-  IBDNS_STAGE_PREDICT = 0, /* S1-S3: RHS, AB2 predictor, convective outflow */
-  IBDNS_STAGE_FLUX = 1,    /* S4: outflow flux correction                  */
-  IBDNS_STAGE_IBM = 2,     /* S5: interpolation, forcing, spreading        */
-  IBDNS_STAGE_PROJECT = 3, /* S6-S8: divergence, Poisson, projection       */
-  IBDNS_STAGE_FLAG = 4,    /* S10: flag sub-steps                           */
-  IBDNS_STAGE_ADVANCE = 5, /* S9 + S11: next dt, time, history             */
+  IBDNS_STAGE_PREDICT = 0, /* RHS, AB2 predictor, convective outflow (Sec. II.A-B) */
+  IBDNS_STAGE_FLUX = 1,    /* outflow flux correction (outflow = inflow)           */
+  IBDNS_STAGE_IBM = 2,     /* interpolation, direct forcing, spreading (Sec. II.B) */
+  IBDNS_STAGE_PROJECT = 3, /* divergence, Poisson solve, projection, CFL maximum   */
+  IBDNS_STAGE_FLAG = 4,    /* flag sub-steps under the step's forcing (Sec. II.B)  */
+  IBDNS_STAGE_ADVANCE = 5, /* next dt, time, H history                             */
   IBDNS_NUM_STAGES = 6
 };
 
