@@ -218,7 +218,8 @@ def main():
     avg_ms = times["timed_region"][dom][0] / times["timed_region"][dom][1]
     achieved = bpc[dom] * w.cells / (avg_ms * 1e-3) / 1e9
     # HBM bytes per launch from the committed counter runs, while they still
-    # describe this kernel: same source file, same tile shape
+    # describe this kernel: same source file, and a record for the tile shape
+    # the autotuner chose (the counter runs measure every shape it tries)
     traffic = None
     tf = os.path.join(ROOT, "profiles", f"traffic_{dom}.json")
     if os.path.exists(tf):
@@ -228,6 +229,8 @@ def main():
             rec.get("source_sha256")
         if same_src and rec.get("variant") == run.variant:
             traffic = rec.get("hbm_bytes_per_launch")
+        elif same_src and str(run.variant) in rec.get("per_variant", {}):
+            traffic = rec["per_variant"][str(run.variant)]["hbm_bytes_per_launch"]
     roofline = {"bound": "hbm", "kernel": dom, "achieved": round(achieved, 1),
                 "peak": HBM_PEAK_GBS, "unit": "GB/s", "frac": round(achieved / HBM_PEAK_GBS, 4),
                 "traffic": traffic,
