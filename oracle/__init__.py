@@ -23,4 +23,5 @@ from .fluid import (Fields, rhs, predictor, outlet, flux_correct, divergence,  #
                     project, cfl_dt)
 from .poisson import solve_poisson, apply_laplacian  # noqa: F401
 from .flag import FlagModel  # noqa: F401
+from .probes import ProbeStats, probe_positions, station_statistics  # noqa: F401
 from .solver import Solver  # noqa: F401

@@ -17,6 +17,7 @@ advanced by its own solver.  Steps, per time step n:
   S9  dt_{n+1}: fixed, or from the CFL number              (fluid.cfl_dt)
   S10 flag: load f_h = -F_k dV_k from S5, spring-network sub-steps (flag)
   S11 H^{n-1} <- H^n, t += dt_n
+Optionally (Sec. III) virtual probes sample u^{n+1} after S8 (probes).
 
 Initial condition (reading; the paper starts from a uniform stream):
 u = U + A z on every u face i = 1..nx, v = A z and w = A z on every cell,
@@ -32,6 +33,7 @@ from . import fluid
 from .delta import ibm_force
 from .flag import FlagModel
 from .poisson import solve_poisson
+from .probes import ProbeStats, probe_positions
 
 
 class Solver:
@@ -44,7 +46,7 @@ class Solver:
     """
 
     def __init__(self, params, noise=None, bars=None, flag=None, hooks: int = 0,
-                 advection: bool = True):
+                 advection: bool = True, probes=None):
         P = params
         self.nx, self.ny, self.nz = P.nx, P.ny, P.nz
         self.h = P.lx / P.nx
@@ -84,6 +86,12 @@ class Solver:
             self.F_flag = np.zeros_like(self.X)
         self.F_bar = np.zeros((self.bar_X.shape[0], 3))
         self.nsub = 0
+        # virtual probes (dict n_x, x0, dx, yc, zc, dyz, n_lags), sampled after each projection
+        self.probes = None
+        if probes is not None:
+            P_ = probes
+            self.probes = ProbeStats(probe_positions(P_["n_x"], P_["x0"], P_["dx"], P_["yc"], P_["zc"],
+                                                     P_["dyz"]), P_["n_lags"])
         # initial projection with dt = 1 (phi discarded)
         ut, vt, wt = self.f.u.copy(), self.f.v.copy(), self.f.w.copy()
         fluid.flux_correct(ut)
@@ -153,6 +161,8 @@ class Solver:
             ut, vt, wt, H = self.stage_predict()
             self.stage_ibm(ut, vt, wt)
             self.stage_project(ut, vt, wt)
+            if self.probes is not None:
+                self.probes.sample_fields(self.f, self.h)
             dt_next = self._next_dt()
             self.stage_flag()
             self.H_old = H
