@@ -141,6 +141,41 @@ int ibdns_destroy(ibdns_ctx* ctx);
 const char* ibdns_strerror(int status);
 
 /* ------------------------------------------------------------------------
+ * Virtual probes (Sec. III: a stencil of probes around the centreline, from
+ * whose time history the turbulent kinetic energy, the large-scale anisotropy
+ * and the autocorrelations f and g of the streamwise and a transverse
+ * velocity are built).
+ *
+ * 9 n_x probes: probe (p, a, b), p = 0..n_x-1, a, b in {-1, 0, 1}, at
+ * (x0 + p dx, yc + a dyz, zc + b dyz), index q = (b+1) + 3 ((a+1) + 3 p).
+ * After the projection of every ibdns_step each velocity component is
+ * sampled by trilinear interpolation on its own staggered mesh (periodic in y
+ * and z) and accumulated into the probe's record of 10 + 2 n_lags doubles:
+ *   [n, Su, Sv, Sw, Suu, Svv, Sww, Suv, Suw, Svw, Ru(0..L-1), Rv(0..L-1)]
+ * with n the sample count, S sums of the samples and of their products, and
+ * Ru(l), Rv(l) the sums of u(t) u(t-l), v(t) v(t-l) over the samples that
+ * have a sample l steps earlier (L = n_lags; a ring of the last L samples is
+ * kept on the device).  Stage-by-stage runs (ibdns_run_stage) and batches do
+ * not sample.
+ * ---------------------------------------------------------------------- */
+
+/* Device bytes of the probe records, rings and positions. */
+int ibdns_probe_workspace_size(int32_t n_x, int32_t n_lags, size_t* bytes);
+
+/* Place the probes and zero their records.  dev_ws: caller-owned device
+ * memory of at least ibdns_probe_workspace_size bytes, 256-byte aligned, kept
+ * alive until ibdns_destroy or the next ibdns_set_probes.  EINVAL if n_x < 1,
+ * n_lags outside 1..4096, or any probe's interpolation stencil leaves the
+ * sampled x range of a component (u: faces 0..nx; v, w: cells 0..nx-1);
+ * ENOMEM if ws_bytes is short. */
+int ibdns_set_probes(ibdns_ctx* ctx, int32_t n_x, double x0, double dx, double yc, double zc,
+                     double dyz, int32_t n_lags, void* dev_ws, size_t ws_bytes);
+
+/* Copy the 9 n_x probe records (layout above) to a host array.  Synchronises.
+ * ESTATE if no probes are set. */
+int ibdns_get_probe_stats(ibdns_ctx* ctx, double* out);
+
+/* ------------------------------------------------------------------------
  * Batched ensembles: independent runs (uneven sizes allowed), each created by
  * ibdns_init_domain + ibdns_set_geometry on the same stream and precision,
  * advanced together.  Every stage is one launch over all runs, except the FFT

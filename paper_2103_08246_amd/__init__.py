@@ -30,7 +30,8 @@ EXPORTED = ("ibdns_workspace_size", "ibdns_init_domain", "ibdns_set_geometry", "
             "ibdns_get_scalars", "ibdns_set_time", "ibdns_get_maps", "ibdns_enable_timing",
             "ibdns_kernel_times", "ibdns_batch_workspace_size", "ibdns_batch_create",
             "ibdns_batch_step", "ibdns_batch_use_graph", "ibdns_batch_autotune", "ibdns_autotune",
-            "ibdns_batch_destroy")
+            "ibdns_batch_destroy", "ibdns_probe_workspace_size", "ibdns_set_probes",
+            "ibdns_get_probe_stats")
 
 
 class Domain(ctypes.Structure):
@@ -96,6 +97,12 @@ def _load():
     lib.ibdns_batch_autotune.argtypes = [P, ctypes.POINTER(ctypes.c_int32)]
     lib.ibdns_autotune.argtypes = [P, ctypes.POINTER(ctypes.c_int32)]
     lib.ibdns_batch_destroy.argtypes = [P]
+    lib.ibdns_probe_workspace_size.argtypes = [ctypes.c_int32, ctypes.c_int32,
+                                               ctypes.POINTER(ctypes.c_size_t)]
+    dd = ctypes.c_double
+    lib.ibdns_set_probes.argtypes = [P, ctypes.c_int32, dd, dd, dd, dd, dd, ctypes.c_int32, P,
+                                     ctypes.c_size_t]
+    lib.ibdns_get_probe_stats.argtypes = [P, D]
     return lib
 
 
@@ -272,6 +279,27 @@ class Run:
 
     def flag(self, check=True):
         return get_flag(self.ctx, self.ns, check)
+
+    def set_probes(self, n_x, x0, dx, yc, zc, dyz, n_lags, device="cuda:0"):
+        """Place 9 n_x probes (record layout in include/ibdns.h); the workspace
+        tensor is kept on this object."""
+        import torch
+        size = ctypes.c_size_t(0)
+        _check(_lib.ibdns_probe_workspace_size(n_x, n_lags, ctypes.byref(size)),
+               "probe_workspace_size")
+        self.probe_ws = torch.empty(size.value, dtype=torch.uint8, device=device)
+        _check(_lib.ibdns_set_probes(self.ctx, n_x, x0, dx, yc, zc, dyz, n_lags,
+                                     ctypes.c_void_p(self.probe_ws.data_ptr()), size.value),
+               "set_probes")
+        self.probe_shape = (9 * n_x, 10 + 2 * n_lags)
+
+    def probe_stats(self, check=True):
+        # without probes the library answers ESTATE before writing anything
+        out = np.empty(getattr(self, "probe_shape", (1, 1)))
+        code = _lib.ibdns_get_probe_stats(self.ctx, _dptr(out))
+        if check:
+            _check(code, "get_probe_stats")
+        return out
 
     def close(self):
         if self.ctx is not None:

@@ -68,6 +68,8 @@ struct ibdns_ctx {
   // after the immersed-boundary stage and joined before the time advance
   hipStream_t side = nullptr;
   hipEvent_t ev_fork = nullptr, ev_join = nullptr;
+  // virtual probes (caller-owned workspace), sampled after each projection
+  ProbeDev probes{};
   // timing: IBDNS_TIMING_*
   int timing = 0;
   std::vector<Timed> recs;
@@ -745,6 +747,7 @@ int ibdns_step(ibdns_ctx* c, int32_t n_steps) {
     const bool forked = fork_flag(c);
     stage_ibm_spread(c);
     stage_project(c, 0);
+    if (c->probes.n > 0) TIMED(c, "probes", launch_probes(c->d, c->f, c->probes, c->st));
     if (forked)
       join_flag(c);
     else
@@ -800,6 +803,65 @@ int ibdns_get_flag(ibdns_ctx* c, double* X, double* V, double* F) {
   if (X && hipMemcpy(X, c->fl.X, bytes, hipMemcpyDeviceToHost) != hipSuccess) return IBDNS_EHIP;
   if (V && hipMemcpy(V, c->fl.V, bytes, hipMemcpyDeviceToHost) != hipSuccess) return IBDNS_EHIP;
   if (F && hipMemcpy(F, c->fl.Fh, bytes, hipMemcpyDeviceToHost) != hipSuccess) return IBDNS_EHIP;
+  return read_status(c);
+}
+
+int ibdns_probe_workspace_size(int32_t n_x, int32_t n_lags, size_t* bytes) {
+  if (!bytes || n_x < 1 || n_lags < 1 || n_lags > 4096) return IBDNS_EINVAL;
+  const size_t n = 9 * (size_t)n_x;
+  *bytes = up(3 * n * sizeof(double)) + up(n * (10 + 2 * (size_t)n_lags) * sizeof(double)) +
+           up(n * 2 * (size_t)n_lags * sizeof(double));
+  return IBDNS_OK;
+}
+
+int ibdns_set_probes(ibdns_ctx* c, int32_t n_x, double x0, double dx, double yc, double zc, double dyz,
+                     int32_t n_lags, void* dev_ws, size_t ws_bytes) {
+  size_t need = 0;
+  if (!c || ibdns_probe_workspace_size(n_x, n_lags, &need) != IBDNS_OK) return IBDNS_EINVAL;
+  if (!dev_ws || (reinterpret_cast<uintptr_t>(dev_ws) % ALIGN) != 0) return IBDNS_EINVAL;
+  if (ws_bytes < need) return IBDNS_ENOMEM;
+  const Dims& d = c->d;
+  const int n = 9 * n_x;
+  std::vector<double> X(3 * (size_t)n);
+  for (int p = 0; p < n_x; ++p)
+    for (int a = -1; a <= 1; ++a)
+      for (int b = -1; b <= 1; ++b) {
+        const int q = (b + 1) + 3 * ((a + 1) + 3 * p);
+        X[3 * q] = x0 + p * dx;
+        X[3 * q + 1] = yc + a * dyz;
+        X[3 * q + 2] = zc + b * dyz;
+      }
+  // the x stencil (two nodes) must stay on sampled nodes: u faces 0..nx,
+  // v and w cells 0..nx-1 (the same floor the kernel takes)
+  for (int q = 0; q < n; ++q) {
+    for (int dir = 0; dir < 3; ++dir)
+      if (!std::isfinite(X[3 * q + dir])) return IBDNS_EINVAL;
+    const double fu = std::floor(X[3 * q] / d.h), fc = std::floor(X[3 * q] / d.h - 0.5);
+    if (fu < 0.0 || fu + 1.0 > d.nx || fc < 0.0 || fc + 1.0 > d.nx - 1) return IBDNS_EINVAL;
+    for (int dir = 1; dir < 3; ++dir)
+      if (std::fabs(X[3 * q + dir] / d.h) > 1e9) return IBDNS_EINVAL;
+  }
+  char* ws = static_cast<char*>(dev_ws);
+  double* dX = reinterpret_cast<double*>(ws);
+  double* rec = reinterpret_cast<double*>(ws + up(3 * (size_t)n * sizeof(double)));
+  const size_t rec_bytes = (size_t)n * (10 + 2 * (size_t)n_lags) * sizeof(double);
+  double* ring = reinterpret_cast<double*>(ws + up(3 * (size_t)n * sizeof(double)) + up(rec_bytes));
+  if (hipStreamSynchronize(c->st) != hipSuccess ||
+      hipMemcpy(dX, X.data(), X.size() * sizeof(double), hipMemcpyHostToDevice) != hipSuccess ||
+      hipMemset(rec, 0, rec_bytes) != hipSuccess ||
+      hipMemset(ring, 0, (size_t)n * 2 * n_lags * sizeof(double)) != hipSuccess ||
+      hipDeviceSynchronize() != hipSuccess)
+    return IBDNS_EHIP;
+  c->probes = ProbeDev{n, n_lags, dX, rec, ring};
+  return IBDNS_OK;
+}
+
+int ibdns_get_probe_stats(ibdns_ctx* c, double* out) {
+  if (!c || !out) return IBDNS_EINVAL;
+  if (c->probes.n <= 0) return IBDNS_ESTATE;
+  if (hipStreamSynchronize(c->st) != hipSuccess) return IBDNS_EHIP;
+  const size_t bytes = (size_t)c->probes.n * (10 + 2 * (size_t)c->probes.L) * sizeof(double);
+  if (hipMemcpy(out, c->probes.rec, bytes, hipMemcpyDeviceToHost) != hipSuccess) return IBDNS_EHIP;
   return read_status(c);
 }
 

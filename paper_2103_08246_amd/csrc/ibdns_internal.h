@@ -102,6 +102,15 @@ struct FlagDev {
   int* counter;            // 64 per-band sub-step counters
 };
 
+// Virtual probes: n probes at X (3n), records of 10 + 2L doubles, rings of
+// the last L samples of u and v (2L doubles per probe).
+struct ProbeDev {
+  int n, L;
+  const double* X;
+  double* rec;
+  double* ring;
+};
+
 // Block coordinates of a kernel body: the single-run kernels pass blockIdx /
 // gridDim, the batched kernels a local block of one run.
 struct Blk {
@@ -202,6 +211,7 @@ hipError_t launch_flag_step(const FlagDev& fl, Scalars* s, hipStream_t st);
 void launch_flag_step_plain(const FlagDev& fl, Scalars* s, hipStream_t st);
 int flag_bands(int ns);
 void launch_advance(Scalars* s, const double* partial, int nparts, double h, hipStream_t st);
+void launch_probes(const Dims& d, const Fields& f, const ProbeDev& pr, hipStream_t st);
 void launch_set_dt0(Scalars* s, const double* partial, int nparts, double h, hipStream_t st);
 
 // batched launchers (one launch covers all runs of a BatchLaunch)

@@ -124,6 +124,17 @@ def ensemble_6_384() -> list:
             for r, d in enumerate((3.0, 4.0, 5.0, 6.0, 8.0, 10.0))]
 
 
+def probe_layout(w: Workload, n_lags: int = 64) -> dict:
+    """Virtual-probe arrangement of Sec. III on this machine: stations every M/2
+    in x from x = M/2 to Lx - M/2, three by three probes 2M/3 apart around the
+    centreline (M = the grid's mesh, 1 without a grid)."""
+    M = w.grid.mesh if w.grid is not None else 1.0
+    dx, x0 = 0.5 * M, 0.5 * M
+    n_x = int(np.floor((w.lx - 0.5 * M - x0) / dx + 1e-9)) + 1
+    return dict(n_x=n_x, x0=x0, dx=dx, yc=0.5 * w.ly, zc=0.5 * w.lz, dyz=2.0 * M / 3.0,
+                n_lags=n_lags)
+
+
 def scaled(w: Workload, nx: int, ny: int, nz: int, **kw) -> Workload:
     """Same box and physics on another mesh (keeps h isotropic if the ratios are kept)."""
     return replace(w, nx=nx, ny=ny, nz=nz, **kw)

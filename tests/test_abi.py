@@ -50,3 +50,15 @@ def test_strerror():
     import paper_2103_08246_amd as ib
     assert "workspace" in ib.strerror(ib.ENOMEM)
     assert ib.strerror(ib.OK) == "ok"
+
+
+def test_probe_workspace_size():
+    import paper_2103_08246_amd as ib
+    lib = ib.lib()
+    out = ctypes.c_size_t(0)
+    assert lib.ibdns_probe_workspace_size(3, 5, ctypes.byref(out)) == ib.OK
+    n = 27
+    up = lambda b: (b + 255) // 256 * 256   # noqa: E731  (256-byte carving)
+    assert out.value == up(3 * n * 8) + up(n * (10 + 2 * 5) * 8) + up(n * 2 * 5 * 8)
+    for n_x, n_lags in ((0, 5), (3, 0), (3, 4097)):
+        assert lib.ibdns_probe_workspace_size(n_x, n_lags, ctypes.byref(out)) == ib.EINVAL
