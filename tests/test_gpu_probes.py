@@ -16,8 +16,9 @@ def _rel_max(a, b):
     return float(np.max(np.abs(a - b)) / max(1.0, float(np.max(np.abs(b)))))
 
 
-@pytest.mark.parametrize("n_lags", [1, 7])
-def test_probe_records_match_oracle(n_lags):
+@pytest.mark.parametrize("n_lags,steps", [(1, 10), (7, 10), (70, 72)])
+def test_probe_records_match_oracle(n_lags, steps):
+    """70 lags over 72 steps: lanes take lags l and l + 64, and the ring wraps."""
     from oracle.solver import Solver
     w = small_grid_flag()
     pr = synth.probe_layout(w, n_lags)
@@ -28,7 +29,6 @@ def test_probe_records_match_oracle(n_lags):
                     flag=ib.flag_from(w.flag), flag_X0=X0)
     try:
         run.set_probes(pr["n_x"], pr["x0"], pr["dx"], pr["yc"], pr["zc"], pr["dyz"], n_lags)
-        steps = 10
         for _ in range(steps):
             run.step(1)
             S.step(1)
