@@ -34,6 +34,7 @@ from .delta import ibm_force
 from .flag import FlagModel
 from .poisson import solve_poisson
 from .probes import ProbeStats, probe_positions
+from .grid_forcing import GridGeometry, forcing_list as grid_forcing_list, apply as grid_forcing_apply
 
 
 class Solver:
@@ -46,7 +47,7 @@ class Solver:
     """
 
     def __init__(self, params, noise=None, bars=None, flag=None, hooks: int = 0,
-                 advection: bool = True, probes=None):
+                 advection: bool = True, probes=None, grid_forcing=None):
         P = params
         self.nx, self.ny, self.nz = P.nx, P.ny, P.nz
         self.h = P.lx / P.nx
@@ -86,6 +87,14 @@ class Solver:
             self.F_flag = np.zeros_like(self.X)
         self.F_bar = np.zeros((self.bar_X.shape[0], 3))
         self.nsub = 0
+        # Eulerian forcing of the passive grid (dict x_plane, mesh, bar) instead of points
+        self.grid_lists = None
+        if grid_forcing is not None:
+            if self.bar_X.shape[0] > 0:
+                raise ValueError("Eulerian grid forcing replaces the static points")
+            geom = GridGeometry(grid_forcing["x_plane"], grid_forcing["mesh"], grid_forcing["bar"],
+                                P.ly, P.lz)
+            self.grid_lists = [grid_forcing_list(geom, c, nx, ny, nz, self.h) for c in range(3)]
         # virtual probes (dict n_x, x0, dx, yc, zc, dyz, n_lags), sampled after each projection
         self.probes = None
         if probes is not None:
@@ -133,7 +142,10 @@ class Solver:
         return ut, vt, wt, H
 
     def stage_ibm(self, ut, vt, wt):
-        """S5 on the provisional velocity (in place); returns F (K, 3)."""
+        """S5 on the provisional velocity (in place); returns F (K, 3).  With
+        Eulerian grid forcing the grid is forced first, at its nodes."""
+        if self.grid_lists is not None:
+            grid_forcing_apply(ut, vt, wt, self.grid_lists)
         X, Ud, dV = self.markers()
         F = ibm_force(ut, vt, wt, X, Ud, dV, self.h, self.dt, self.nx)
         nb = self.bar_X.shape[0]
