@@ -141,6 +141,45 @@ int ibdns_destroy(ibdns_ctx* ctx);
 const char* ibdns_strerror(int status);
 
 /* ------------------------------------------------------------------------
+ * Eulerian direct forcing of the passive grid (Sec. II.B (i): the fixed grid
+ * is imposed at the Eulerian velocity nodes, Fadlun et al. 2000), an
+ * alternative to passing the grid as static points to ibdns_set_geometry.
+ *
+ * Geometry (Sec. II.A): square rods of side bar at x = x_plane, rods along y
+ * at z = lz/2 + (b + 1/2) mesh (mod lz), b < round(lz/mesh), rods along z at
+ * y = ly/2 + (b + 1/2) mesh (mod ly), b < round(ly/mesh); a point is solid
+ * when |x - x_plane| <= bar/2 and its periodic transverse distance to a rod's
+ * centre line is <= bar/2.  Each step, before the flag's forcing, every
+ * evolved velocity node (u faces 1..nx-1, v and w cells 0..nx-1) that is
+ * solid is set to 0; a fluid node with a solid neighbour among its six grid
+ * neighbours takes u~(Q) delta/(delta + h), where the wall lies at distance
+ * delta from it towards that neighbour (the smallest delta; ties in the order
+ * -x, +x, -y, +y, -z, +z) and Q is the node on its other side (0 if Q is not
+ * an evolved node); all values read are the unforced ones.
+ * ---------------------------------------------------------------------- */
+
+/* Device bytes of the forcing lists of this domain and grid.  EINVAL for an
+ * unsupported domain, non-positive mesh or bar, or a grid that reaches the
+ * x ends. */
+int ibdns_grid_forcing_workspace_size(const ibdns_domain* d, double x_plane, double mesh, double bar,
+                                      size_t* bytes);
+
+/* Build the lists on the host and upload them into dev_ws (caller-owned, at
+ * least ibdns_grid_forcing_workspace_size bytes, 256-byte aligned, kept alive
+ * until ibdns_destroy).  Before the first ibdns_step, once; EINVAL if static
+ * points were set (or are set later: ibdns_set_geometry then refuses them),
+ * ESTATE after a step, ENOMEM if ws_bytes is short. */
+int ibdns_set_grid_forcing(ibdns_ctx* ctx, double x_plane, double mesh, double bar, void* dev_ws,
+                           size_t ws_bytes);
+
+/* The forcing list of component comp (0 u, 1 v, 2 w): *count entries; when
+ * the arrays are not NULL, node and src receive host-layout indices
+ * i + NX (j + ny k) (NX = nx+1 for u, nx for v, w; src -1 for solid nodes) and
+ * weight the weights, in increasing node order.  ESTATE without grid forcing. */
+int ibdns_get_grid_forcing(ibdns_ctx* ctx, int32_t comp, int64_t* count, int64_t* node, int64_t* src,
+                           double* weight);
+
+/* ------------------------------------------------------------------------
  * Virtual probes (Sec. III: a stencil of probes around the centreline, from
  * whose time history the turbulent kinetic energy, the large-scale anisotropy
  * and the autocorrelations f and g of the streamwise and a transverse

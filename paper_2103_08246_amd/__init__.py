@@ -31,7 +31,8 @@ EXPORTED = ("ibdns_workspace_size", "ibdns_init_domain", "ibdns_set_geometry", "
             "ibdns_kernel_times", "ibdns_batch_workspace_size", "ibdns_batch_create",
             "ibdns_batch_step", "ibdns_batch_use_graph", "ibdns_batch_autotune", "ibdns_autotune",
             "ibdns_batch_destroy", "ibdns_probe_workspace_size", "ibdns_set_probes",
-            "ibdns_get_probe_stats")
+            "ibdns_get_probe_stats", "ibdns_grid_forcing_workspace_size", "ibdns_set_grid_forcing",
+            "ibdns_get_grid_forcing")
 
 
 class Domain(ctypes.Structure):
@@ -103,6 +104,11 @@ def _load():
     lib.ibdns_set_probes.argtypes = [P, ctypes.c_int32, dd, dd, dd, dd, dd, ctypes.c_int32, P,
                                      ctypes.c_size_t]
     lib.ibdns_get_probe_stats.argtypes = [P, D]
+    lib.ibdns_grid_forcing_workspace_size.argtypes = [ctypes.POINTER(Domain), dd, dd, dd,
+                                                      ctypes.POINTER(ctypes.c_size_t)]
+    lib.ibdns_set_grid_forcing.argtypes = [P, dd, dd, dd, P, ctypes.c_size_t]
+    I64 = ctypes.POINTER(ctypes.c_int64)
+    lib.ibdns_get_grid_forcing.argtypes = [P, ctypes.c_int32, I64, I64, I64, D]
     return lib
 
 
@@ -301,6 +307,31 @@ class Run:
             _check(code, "get_probe_stats")
         return out
 
+    def set_grid_forcing(self, dom: Domain, x_plane, mesh, bar, device="cuda:0"):
+        """Eulerian forcing of the passive grid (rule in include/ibdns.h); the
+        workspace tensor is kept on this object."""
+        import torch
+        size = ctypes.c_size_t(0)
+        _check(_lib.ibdns_grid_forcing_workspace_size(ctypes.byref(dom), x_plane, mesh, bar,
+                                                      ctypes.byref(size)), "grid_forcing_workspace_size")
+        self.grid_ws = torch.empty(max(size.value, 256), dtype=torch.uint8, device=device)
+        _check(_lib.ibdns_set_grid_forcing(self.ctx, x_plane, mesh, bar,
+                                           ctypes.c_void_p(self.grid_ws.data_ptr()), self.grid_ws.numel()),
+               "set_grid_forcing")
+
+    def grid_forcing(self, comp):
+        """(node, src, weight) of one component's forcing list, host-layout indices."""
+        n = ctypes.c_int64(0)
+        _check(_lib.ibdns_get_grid_forcing(self.ctx, comp, ctypes.byref(n), None, None, None),
+               "get_grid_forcing")
+        node = np.empty(n.value, dtype=np.int64)
+        src = np.empty(n.value, dtype=np.int64)
+        wgt = np.empty(n.value)
+        I64 = ctypes.POINTER(ctypes.c_int64)
+        _check(_lib.ibdns_get_grid_forcing(self.ctx, comp, ctypes.byref(n), node.ctypes.data_as(I64),
+                                           src.ctypes.data_as(I64), _dptr(wgt)), "get_grid_forcing")
+        return node, src, wgt
+
     def close(self):
         if self.ctx is not None:
             destroy(self.ctx)
@@ -308,8 +339,10 @@ class Run:
 
 
 def create(dom: Domain, noise=None, points=None, flag: FlagParams | None = None, flag_X0=None,
-           device="cuda:0", stream=None) -> Run:
-    """Allocate the workspace with torch on ``device`` and build a context."""
+           device="cuda:0", stream=None, grid_forcing=None) -> Run:
+    """Allocate the workspace with torch on ``device`` and build a context.
+    grid_forcing: an object with x_plane, mesh, bar for Eulerian forcing of the
+    passive grid (then points must be None)."""
     import torch
     n_points = 0 if points is None else int(np.asarray(points[1]).size)
     ns = 0 if flag is None else flag.ns
@@ -318,6 +351,8 @@ def create(dom: Domain, noise=None, points=None, flag: FlagParams | None = None,
     st = stream if stream is not None else torch.cuda.current_stream(device)
     ctx = init_domain(dom, noise, ws.data_ptr(), nbytes, st.cuda_stream)
     run = Run(ctx, ws, dom.nx, dom.ny, dom.nz, ns)
+    if grid_forcing is not None:
+        run.set_grid_forcing(dom, grid_forcing.x_plane, grid_forcing.mesh, grid_forcing.bar, device)
     if points is not None or flag is not None:
         set_geometry(ctx, points, flag, flag_X0)
     return run

@@ -70,6 +70,12 @@ struct ibdns_ctx {
   hipEvent_t ev_fork = nullptr, ev_join = nullptr;
   // virtual probes (caller-owned workspace), sampled after each projection
   ProbeDev probes{};
+  // Eulerian forcing of the passive grid (caller-owned workspace); host copy
+  // of the lists: host-layout node, source (-1: solid) and weight
+  GridForceDev gforce{};
+  bool has_gforce = false;
+  std::vector<long long> g_node[3], g_src[3];
+  std::vector<double> g_w[3];
   // timing: IBDNS_TIMING_*
   int timing = 0;
   std::vector<Timed> recs;
@@ -204,6 +210,8 @@ void stage_flux(ibdns_ctx* c) { TIMED(c, "flux_apply", launch_flux_apply(c->d, c
 // Immersed boundary, first half: index maps and interpolation of every
 // point from the same provisional field, hence the forcing of every point.
 void stage_ibm_interp(ibdns_ctx* c) {
+  // Eulerian grid forcing, before the flag's forcing reads u~
+  if (c->has_gforce) TIMED(c, "grid_force", launch_grid_force(c->d, c->f, c->gforce, c->st));
   if (c->nbars) TIMED(c, "bars_interp", launch_point_interp(c->d, c->f, c->bars, c->s, false, c->st));
   // the flag's maps move with it: computed in the same launch as its interpolation
   if (c->has_flag) TIMED(c, "flag_interp", launch_point_interp(c->d, c->f, c->flagpts, c->s, true, c->st));
@@ -517,6 +525,7 @@ int ibdns_set_geometry(ibdns_ctx* c, int64_t n_points, const double* X, const do
   if (c->geometry_set || c->stepped) return IBDNS_ESTATE;
   if (n_points < 0 || (n_points > 0 && (!X || !dV))) return IBDNS_EINVAL;
   if (27 * n_points >= (1LL << 31)) return IBDNS_EINVAL;
+  if (n_points > 0 && c->has_gforce) return IBDNS_EINVAL;   // the grid is forced at its nodes
   const Dims& d = c->d;
   const double h = d.h;
   const int nx = d.nx;
@@ -804,6 +813,208 @@ int ibdns_get_flag(ibdns_ctx* c, double* X, double* V, double* F) {
   if (V && hipMemcpy(V, c->fl.V, bytes, hipMemcpyDeviceToHost) != hipSuccess) return IBDNS_EHIP;
   if (F && hipMemcpy(F, c->fl.Fh, bytes, hipMemcpyDeviceToHost) != hipSuccess) return IBDNS_EHIP;
   return read_status(c);
+}
+
+}  // extern "C"
+
+namespace {
+
+// Eulerian grid forcing lists (the rule stated with the declarations).
+std::vector<double> rod_centres(double L, double M) {
+  std::vector<double> c;
+  const long n = std::lround(L / M);
+  for (long b = 0; b < n; ++b) {
+    double x = 0.5 * L + (b + 0.5) * M;
+    if (x >= L) x -= L;
+    c.push_back(x);
+  }
+  return c;
+}
+double pdist(double a, double c, double L) {
+  const double d = std::fabs(a - c);
+  return std::min(d, L - d);
+}
+
+struct GridLists {
+  std::vector<long long> node[3], src[3];   // host layout i + NX (j + ny k); src -1: solid
+  std::vector<int> pnode[3], psrc[3];        // pitched field indices (device)
+  std::vector<double> w[3];
+};
+
+int build_grid_lists(const ibdns_domain& dm, int P, double xp, double M, double bar, GridLists& out) {
+  const int nx = dm.nx, ny = dm.ny, nz = dm.nz;
+  const double h = dm.lx / nx, half = 0.5 * bar;
+  if (!(M > 0.0) || !(bar > 0.0) || !std::isfinite(xp)) return IBDNS_EINVAL;
+  if (!(xp - half - 2 * h > 0.0) || !(xp + half + 2 * h < dm.lx)) return IBDNS_EINVAL;
+  if ((long long)P * ny * nz >= (1LL << 31)) return IBDNS_EINVAL;
+  const std::vector<double> zc = rod_centres(dm.lz, M), yc = rod_centres(dm.ly, M);
+  for (int comp = 0; comp < 3; ++comp) {
+    const double o[3] = {comp == 0 ? 0.0 : 0.5, comp == 1 ? 0.0 : 0.5, comp == 2 ? 0.0 : 0.5};
+    const int ilo = comp == 0 ? 1 : 0, ihi = nx - 1;
+    const long long NX = comp == 0 ? nx + 1 : nx;
+    std::vector<char> ix(nx + 1), by(ny), bz(nz);
+    for (int i = 0; i <= nx; ++i) ix[i] = std::fabs((i + o[0]) * h - xp) <= half;
+    for (int j = 0; j < ny; ++j) {
+      const double y = (j + o[1]) * h;
+      for (double c : yc) by[j] |= pdist(y, c, dm.ly) <= half;   // inside a rod along z
+    }
+    for (int k = 0; k < nz; ++k) {
+      const double z = (k + o[2]) * h;
+      for (double c : zc) bz[k] |= pdist(z, c, dm.lz) <= half;   // inside a rod along y
+    }
+    auto solid = [&](int i, int j, int k) { return ix[i] && (by[j] || bz[k]); };
+    std::vector<int> cand;   // evolved x indices that are solid or next to the solid band
+    for (int i = ilo; i <= ihi; ++i)
+      if (ix[i] || (i > ilo && ix[i - 1]) || (i < ihi && ix[i + 1])) cand.push_back(i);
+    auto wall = [&](int axis, int i, int j, int k) {
+      if (axis == 0) return std::fabs((i + o[0]) * h - xp) - half;
+      const std::vector<double>& cs = axis == 1 ? yc : zc;
+      const double coord = axis == 1 ? (j + o[1]) * h : (k + o[2]) * h;
+      const double L = axis == 1 ? dm.ly : dm.lz;
+      double best = INFINITY;
+      for (double c : cs) {
+        const double dd = pdist(coord, c, L);
+        if (dd > half) best = std::min(best, dd - half);
+      }
+      return best;
+    };
+    auto add = [&](int i, int j, int k, int iq, int jq, int kq, bool has_src, double wgt) {
+      out.node[comp].push_back(i + NX * (j + (long long)ny * k));
+      out.pnode[comp].push_back((int)(i + (long long)P * (j + (long long)ny * k)));
+      out.src[comp].push_back(has_src ? iq + NX * (jq + (long long)ny * kq) : -1);
+      out.psrc[comp].push_back(has_src ? (int)(iq + (long long)P * (jq + (long long)ny * kq)) : -1);
+      out.w[comp].push_back(wgt);
+    };
+    for (int k = 0; k < nz; ++k)
+      for (int j = 0; j < ny; ++j)
+        for (int i : cand) {
+          if (solid(i, j, k)) {
+            add(i, j, k, 0, 0, 0, false, 0.0);
+            continue;
+          }
+          // solid neighbours in the order -x, +x, -y, +y, -z, +z; the smallest wall distance
+          int best_axis = -1, best_step = 0;
+          double best = 0.0;
+          const int axes[6] = {0, 0, 1, 1, 2, 2}, steps[6] = {-1, 1, -1, 1, -1, 1};
+          for (int q = 0; q < 6; ++q) {
+            const int a = axes[q], st = steps[q];
+            bool sn;
+            if (a == 0) {
+              const int in = i + st;
+              sn = in >= ilo && in <= ihi && solid(in, j, k);
+            } else if (a == 1) {
+              sn = solid(i, (j + st + ny) % ny, k);
+            } else {
+              sn = solid(i, j, (k + st + nz) % nz);
+            }
+            if (!sn) continue;
+            const double dl = wall(a, i, j, k);
+            if (best_axis < 0 || dl < best) {
+              best_axis = a;
+              best_step = st;
+              best = dl;
+            }
+          }
+          if (best_axis < 0) continue;
+          int iq = i, jq = j, kq = k;
+          if (best_axis == 0) {
+            iq = i - best_step;
+            if (iq < ilo || iq > ihi) {
+              add(i, j, k, 0, 0, 0, false, 0.0);
+              continue;
+            }
+          } else if (best_axis == 1) {
+            jq = (j - best_step + ny) % ny;
+          } else {
+            kq = (k - best_step + nz) % nz;
+          }
+          add(i, j, k, iq, jq, kq, true, best / (best + h));
+        }
+  }
+  return IBDNS_OK;
+}
+
+size_t grid_lists_bytes(const GridLists& g) {
+  size_t b = 0, tot = 0;
+  for (int c = 0; c < 3; ++c) {
+    const size_t n = g.pnode[c].size();
+    b += 2 * up(n * sizeof(int)) + up(n * sizeof(double));
+    tot += n;
+  }
+  return b + up(tot * sizeof(double));
+}
+
+}  // namespace
+
+extern "C" {
+
+int ibdns_grid_forcing_workspace_size(const ibdns_domain* d, double x_plane, double mesh, double bar,
+                                      size_t* bytes) {
+  size_t dummy = 0;
+  if (!d || !bytes || ibdns_workspace_size(d, 0, 0, &dummy) != IBDNS_OK) return IBDNS_EINVAL;
+  GridLists g;
+  const int r = build_grid_lists(*d, row_pitch(*d), x_plane, mesh, bar, g);
+  if (r != IBDNS_OK) return r;
+  *bytes = grid_lists_bytes(g);
+  return IBDNS_OK;
+}
+
+int ibdns_set_grid_forcing(ibdns_ctx* c, double x_plane, double mesh, double bar, void* dev_ws,
+                           size_t ws_bytes) {
+  if (!c) return IBDNS_EINVAL;
+  if (c->stepped || c->has_gforce) return IBDNS_ESTATE;
+  if (c->nbars > 0) return IBDNS_EINVAL;
+  if (!dev_ws || (reinterpret_cast<uintptr_t>(dev_ws) % ALIGN) != 0) return IBDNS_EINVAL;
+  GridLists g;
+  const int r = build_grid_lists(c->dom, c->d.P, x_plane, mesh, bar, g);
+  if (r != IBDNS_OK) return r;
+  if (ws_bytes < grid_lists_bytes(g)) return IBDNS_ENOMEM;
+  char* p = static_cast<char*>(dev_ws);
+  GridForceDev dev{};
+  size_t tot = 0;
+  if (hipStreamSynchronize(c->st) != hipSuccess) return IBDNS_EHIP;
+  for (int comp = 0; comp < 3; ++comp) {
+    const size_t n = g.pnode[comp].size();
+    int* dn = reinterpret_cast<int*>(p);
+    p += up(n * sizeof(int));
+    int* ds = reinterpret_cast<int*>(p);
+    p += up(n * sizeof(int));
+    double* dw = reinterpret_cast<double*>(p);
+    p += up(n * sizeof(double));
+    if (n && (hipMemcpy(dn, g.pnode[comp].data(), n * sizeof(int), hipMemcpyHostToDevice) != hipSuccess ||
+              hipMemcpy(ds, g.psrc[comp].data(), n * sizeof(int), hipMemcpyHostToDevice) != hipSuccess ||
+              hipMemcpy(dw, g.w[comp].data(), n * sizeof(double), hipMemcpyHostToDevice) != hipSuccess))
+      return IBDNS_EHIP;
+    dev.n[comp] = (int)n;
+    dev.node[comp] = dn;
+    dev.src[comp] = ds;
+    dev.w[comp] = dw;
+    tot += n;
+  }
+  dev.val = reinterpret_cast<double*>(p);
+  if ((long long)tot >= (1LL << 31)) return IBDNS_EINVAL;
+  c->gforce = dev;
+  c->has_gforce = true;
+  for (int comp = 0; comp < 3; ++comp) {
+    c->g_node[comp] = std::move(g.node[comp]);
+    c->g_src[comp] = std::move(g.src[comp]);
+    c->g_w[comp] = std::move(g.w[comp]);
+  }
+  return IBDNS_OK;
+}
+
+int ibdns_get_grid_forcing(ibdns_ctx* c, int32_t comp, int64_t* count, int64_t* node, int64_t* src,
+                           double* weight) {
+  if (!c || !count || comp < 0 || comp > 2) return IBDNS_EINVAL;
+  if (!c->has_gforce) return IBDNS_ESTATE;
+  const size_t n = c->g_node[comp].size();
+  *count = (int64_t)n;
+  for (size_t q = 0; q < n; ++q) {
+    if (node) node[q] = c->g_node[comp][q];
+    if (src) src[q] = c->g_src[comp][q];
+    if (weight) weight[q] = c->g_w[comp][q];
+  }
+  return IBDNS_OK;
 }
 
 int ibdns_probe_workspace_size(int32_t n_x, int32_t n_lags, size_t* bytes) {
@@ -1209,6 +1420,7 @@ int ibdns_batch_create(ibdns_ctx* const* runs, int32_t n_runs, void* dev_ws, siz
     if (!runs[r]) return IBDNS_EINVAL;
     if (runs[r]->st != runs[0]->st || runs[r]->d.mixed != runs[0]->d.mixed) return IBDNS_EINVAL;
     if (runs[r]->has_flag && flag_bands(runs[r]->fl.ns) > 64) return IBDNS_EINVAL;
+    if (runs[r]->has_gforce) return IBDNS_EINVAL;   // batches force grids as points only
   }
   ibdns_batch* b = new ibdns_batch();
   if (hipStreamCreateWithFlags(&b->side, hipStreamNonBlocking) != hipSuccess ||

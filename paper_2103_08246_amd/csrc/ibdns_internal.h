@@ -111,6 +111,17 @@ struct ProbeDev {
   double* ring;
 };
 
+// Eulerian forcing of the passive grid: per component c, n[c] forced nodes
+// (pitched field indices, increasing), the node each one copies (-1: solid,
+// set to zero) and its weight; val holds the values between the two passes.
+struct GridForceDev {
+  int n[3];
+  const int* node[3];
+  const int* src[3];
+  const double* w[3];
+  double* val;
+};
+
 // Block coordinates of a kernel body: the single-run kernels pass blockIdx /
 // gridDim, the batched kernels a local block of one run.
 struct Blk {
@@ -212,6 +223,7 @@ void launch_flag_step_plain(const FlagDev& fl, Scalars* s, hipStream_t st);
 int flag_bands(int ns);
 void launch_advance(Scalars* s, const double* partial, int nparts, double h, hipStream_t st);
 void launch_probes(const Dims& d, const Fields& f, const ProbeDev& pr, hipStream_t st);
+void launch_grid_force(const Dims& d, const Fields& f, const GridForceDev& g, hipStream_t st);
 void launch_set_dt0(Scalars* s, const double* partial, int nparts, double h, hipStream_t st);
 
 // batched launchers (one launch covers all runs of a BatchLaunch)

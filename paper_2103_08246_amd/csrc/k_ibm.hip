@@ -361,7 +361,49 @@ __global__ void __launch_bounds__(TN) kb_spread_tiles(BatchLaunch bl) {
   spread_tiles_body<T>(R.d, R.f, R.flag, R.bbox, R.ntx, R.nty, R.ntz, lb / nt, R.s, lb % nt);
 }
 
+// Eulerian forcing of the passive grid (paper Sec. II.B (i)): solid nodes
+// take the body velocity 0, interface nodes the linear profile between the
+// wall and the node opposite it, value = weight * u~(src).  Two passes over
+// the three components' lists: every value is read from the unforced field
+// first, then written, so the result does not depend on the order.
+__device__ __forceinline__ bool grid_entry(const GridForceDev& g, long long e, int* comp, int* q) {
+  if (e < g.n[0]) { *comp = 0; *q = (int)e; return true; }
+  e -= g.n[0];
+  if (e < g.n[1]) { *comp = 1; *q = (int)e; return true; }
+  e -= g.n[1];
+  if (e < g.n[2]) { *comp = 2; *q = (int)e; return true; }
+  return false;
+}
+template <class T>
+__global__ void __launch_bounds__(256) k_grid_force_read(Fields f, GridForceDev g) {
+  const long long e = (long long)blockIdx.x * 256 + threadIdx.x;
+  int comp, q;
+  if (!grid_entry(g, e, &comp, &q)) return;
+  const int src = g.src[comp][q];
+  g.val[e] = src < 0 ? 0.0 : g.w[comp][q] * (double)comp_field<T>(f, comp)[src];
+}
+template <class T>
+__global__ void __launch_bounds__(256) k_grid_force_write(Fields f, GridForceDev g) {
+  const long long e = (long long)blockIdx.x * 256 + threadIdx.x;
+  int comp, q;
+  if (!grid_entry(g, e, &comp, &q)) return;
+  comp_field<T>(f, comp)[g.node[comp][q]] = (T)g.val[e];
+}
+
 }  // namespace
+
+void launch_grid_force(const Dims& d, const Fields& f, const GridForceDev& g, hipStream_t st) {
+  const long long tot = (long long)g.n[0] + g.n[1] + g.n[2];
+  if (tot == 0) return;
+  const dim3 grid((unsigned)((tot + 255) / 256));
+  if (d.mixed) {
+    hipLaunchKernelGGL(k_grid_force_read<float>, grid, dim3(256), 0, st, f, g);
+    hipLaunchKernelGGL(k_grid_force_write<float>, grid, dim3(256), 0, st, f, g);
+  } else {
+    hipLaunchKernelGGL(k_grid_force_read<double>, grid, dim3(256), 0, st, f, g);
+    hipLaunchKernelGGL(k_grid_force_write<double>, grid, dim3(256), 0, st, f, g);
+  }
+}
 
 void launch_point_stencil(const Dims& d, const PointSet& ps, Scalars* s, hipStream_t st) {
   if (ps.n == 0) return;
