@@ -153,6 +153,7 @@ def main():
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-mixed", action="store_true")
     ap.add_argument("--no-batch", action="store_true")
+    ap.add_argument("--no-eulerian", action="store_true")
     ap.add_argument("--batch-steps", type=int, default=20)
     ap.add_argument("--copy-calib", action="store_true",
                     help="also run a plain device copy of 1 GiB (calibrates HBM counters)")
@@ -172,12 +173,15 @@ def main():
     bars = synth.bar_points(w) if w.grid is not None else None
     X0 = synth.flag_reference(w) if w.flag is not None else None
 
-    def measure(precision, breakdown):
+    def measure(precision, breakdown, eulerian=False):
         """Timed region: args.steps steps with HIP events around the predictor
         only (two per step).  breakdown: then as many steps again with events
-        around every kernel, for the per-kernel table (not the value)."""
-        run = ib.create(ib.domain_from(w, precision=precision), noise, points=bars,
-                        flag=ib.flag_from(w.flag) if w.flag is not None else None, flag_X0=X0)
+        around every kernel, for the per-kernel table (not the value).
+        eulerian: the grid forced at its nodes instead of as points."""
+        run = ib.create(ib.domain_from(w, precision=precision), noise,
+                        points=None if eulerian else bars,
+                        flag=ib.flag_from(w.flag) if w.flag is not None else None, flag_X0=X0,
+                        grid_forcing=w.grid if eulerian else None)
         run.variant = ib.autotune(run.ctx)   # predictor tile shape, picked by timing
         run.step(args.warmup)
         ib.sync(run.ctx)
@@ -284,6 +288,21 @@ def main():
                         "kernel_avg_ms": {k: round(v[0] / max(v[1], 1), 4) for k, v in
                                           sorted(times_m["all"].items(), key=lambda kv: -kv[1][0])}}
         run_m.close()
+    if w.grid is not None and not args.no_eulerian:
+        # the paper's own treatment of the fixed grid (Sec. II.B (i)): Eulerian
+        # forcing at the velocity nodes instead of the delta points
+        run_e, wall_e, _, times_e = measure(ib.FP64, True, eulerian=True)
+        n_forced = sum(run_e.grid_forcing(c)[0].size for c in range(3))
+        out["grid_eulerian"] = {"value": round(w.cells * args.steps / wall_e / 1e6, 1),
+                                "ms_per_step": round(wall_e * 1e3 / args.steps, 4),
+                                "forced_nodes": int(n_forced),
+                                "kernel_avg_ms": {k: round(v[0] / max(v[1], 1), 4) for k, v in
+                                                  sorted(times_e["all"].items(), key=lambda kv: -kv[1][0])
+                                                  if k in ("grid_force", "flag_interp", "flag_spread",
+                                                           "flag_bbox")},
+                                "note": "FP64, grid forced at its velocity nodes, flag by delta markers"}
+        print(f"# eulerian grid: {wall_e * 1e3 / args.steps:.3f} ms/step", file=sys.stderr, flush=True)
+        run_e.close()
     del noise
     run.close()
     if args.copy_calib:
