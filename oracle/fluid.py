@@ -230,3 +230,81 @@ def cfl_dt(f: Fields, h: float, cfl: float):
     wc = np.abs(0.5 * (w[..., :nx] + _zp(w[..., :nx])))
     smax = float(np.max(uc + vc + wc))
     return cfl * h / smax
+
+
+# ---------------------------------------------------------------------------
+# Crank-Nicolson diffusion with approximate factorisation (Sec. II.B names
+# Crank-Nicolson for the diffusive terms and an approximate factorisation for
+# the provisional velocity).  Reading, delta form:
+#   RHS = dt [(1 + w/2) Hc^n - (w/2) Hc^{n-1} - G p^n + nu L u^n],
+#   Hc = -div(u u) (the convective part only),
+#   (1 - b Dx)(1 - b Dy)(1 - b Dz) du = RHS,  b = nu dt / 2,  Dd = d^2/dd^2 (3-point),
+#   u~ = u^n + du on the evolved nodes,
+# solved as du = X^{-1} Y^{-1} Z^{-1} RHS: the periodic y and z factors first,
+# then the x factor, whose boundary rows take the increments of the boundary
+# values: u: du_0 = 0 (inlet), du_nx = u~_nx - u^n_nx (the convective outflow
+# value); v, w: the inlet ghost du_{-1} = -du_0 and the outlet ghost
+# increment u~_nx - u^n_nx; under the zero-gradient test hook, du_{-1} = du_0
+# and du_nx = du_{nx-1}.
+# ---------------------------------------------------------------------------
+
+def _periodic_solve(b, beta, h, axis):
+    """(1 - beta D) x = b along a periodic axis: the circulant operator is
+    diagonal in the discrete Fourier basis with eigenvalues
+    1 + (4 beta / h^2) sin^2(pi m / n)."""
+    n = b.shape[axis]
+    m = np.arange(n)
+    mu = 1.0 + (4.0 * beta / (h * h)) * np.sin(np.pi * m / n) ** 2
+    shape = [1] * b.ndim
+    shape[axis] = n
+    return np.real(np.fft.ifft(np.fft.fft(b, axis=axis) / mu.reshape(shape), axis=axis))
+
+
+def _x_solve(rhs, r, first_diag, last_diag, last_add):
+    """Tridiagonal (-r, diag, -r) along the last axis (lines of length n) with
+    the first and last diagonal entries given and last_add added to the last
+    row's right-hand side; banded LAPACK solve, every line at once."""
+    from scipy.linalg import solve_banded
+    n = rhs.shape[-1]
+    ab = np.zeros((3, n))
+    ab[0, 1:] = -r
+    ab[1, :] = 1.0 + 2.0 * r
+    ab[1, 0] = first_diag
+    ab[1, -1] = last_diag
+    ab[2, :-1] = -r
+    b = rhs.copy()
+    b[..., -1] += last_add
+    flat = b.reshape(-1, n).T
+    return solve_banded((1, 1), ab, flat).T.reshape(b.shape)
+
+
+def predictor_cn(f: Fields, Hc, Hc_old, D, ut, vt, wt, dt: float, omega: float, h: float, nu: float,
+                 hooks: int = 0):
+    """Provisional velocity with Crank-Nicolson diffusion in approximately
+    factorised delta form (the reading above), in place on ut, vt, wt, whose
+    outlet entries must already hold the convective outflow values.  Hc, Hc_old:
+    convective right-hand sides; D = nu L u^n."""
+    u, v, w, p = f.u, f.v, f.w, f.p
+    nx = u.shape[2] - 1
+    c1 = 1.0 + 0.5 * omega
+    c2 = 0.5 * omega
+    inv_h = 1.0 / h
+    beta = 0.5 * nu * dt
+    r = beta / (h * h)
+    gp = ((p[..., 1:nx] - p[..., 0:nx - 1]) * inv_h, (p - _ym(p)) * inv_h, (p - _zm(p)) * inv_h)
+    sl = (slice(1, nx), slice(0, nx), slice(0, nx))
+    neumann = bool(hooks & HOOK_VW_NEUMANN_X)
+    for c, (st, tl) in enumerate(((u, ut), (v, vt), (w, wt))):
+        s = sl[c]
+        rhs = dt * (c1 * Hc[c][..., s] - c2 * Hc_old[c][..., s] - gp[c] + D[c][..., s])
+        rhs = _periodic_solve(rhs, beta, h, axis=0)      # z
+        rhs = _periodic_solve(rhs, beta, h, axis=1)      # y
+        if c == 0:
+            d_out = tl[..., nx] - st[..., nx]
+            du = _x_solve(rhs, r, 1.0 + 2.0 * r, 1.0 + 2.0 * r, r * d_out)
+        elif neumann:
+            du = _x_solve(rhs, r, 1.0 + r, 1.0 + r, 0.0)
+        else:
+            d_out = tl[..., nx] - st[..., nx]
+            du = _x_solve(rhs, r, 1.0 + 3.0 * r, 1.0 + 2.0 * r, r * d_out)
+        tl[..., s] = st[..., s] + du

@@ -47,7 +47,7 @@ class Solver:
     """
 
     def __init__(self, params, noise=None, bars=None, flag=None, hooks: int = 0,
-                 advection: bool = True, probes=None, grid_forcing=None):
+                 advection: bool = True, probes=None, grid_forcing=None, diffusion: str = "explicit"):
         P = params
         self.nx, self.ny, self.nz = P.nx, P.ny, P.nz
         self.h = P.lx / P.nx
@@ -57,6 +57,9 @@ class Solver:
         self.cfl = P.cfl
         self.hooks = hooks
         self.advection = advection
+        if diffusion not in ("explicit", "cn"):
+            raise ValueError(diffusion)
+        self.diffusion = diffusion
         nx, ny, nz = self.nx, self.ny, self.nz
         A = P.noise_amp
         u = np.full((nz, ny, nx + 1), P.u_in)
@@ -131,9 +134,20 @@ class Solver:
 
     # ---- the step, split so that tests can stop after any stage ----
     def stage_predict(self):
-        """S1-S4: returns (ut, vt, wt, H)."""
+        """S1-S4: returns (ut, vt, wt, H).  With Crank-Nicolson diffusion H is
+        the convective part only and S2 is fluid.predictor_cn, which needs the
+        outflow values of S3 first."""
         f, h, dt = self.f, self.h, self.dt
         omega = dt / self.dt_prev
+        if self.diffusion == "cn":
+            Hc = fluid.rhs(f, h, 0.0, self.hooks, self.advection)
+            D = fluid.rhs(f, h, self.nu, self.hooks, advection=False)
+            Hc_old = Hc if self.H_old is None else self.H_old
+            ut, vt, wt = f.u.copy(), f.v.copy(), f.w.copy()
+            fluid.outlet(f, ut, vt, wt, dt, h, self.u_in, self.hooks)
+            fluid.predictor_cn(f, Hc, Hc_old, D, ut, vt, wt, dt, omega, h, self.nu, self.hooks)
+            fluid.flux_correct(ut)
+            return ut, vt, wt, Hc
         H = fluid.rhs(f, h, self.nu, self.hooks, self.advection)
         H_old = H if self.H_old is None else self.H_old
         ut, vt, wt = fluid.predictor(f, H, H_old, dt, omega, h)
