@@ -75,7 +75,20 @@ typedef struct {
                        /* provisional velocity in FP32; state, Poisson solve,   */
                        /* projection and flag stay FP64                         */
   uint32_t flags;      /* IBDNS_TEST_* bits, 0 in production                      */
+  int32_t diffusion;   /* IBDNS_DIFFUSION_EXPLICIT, or IBDNS_DIFFUSION_CN (below) */
 } ibdns_domain;
+
+/* Diffusion in time.  EXPLICIT: inside the Adams-Bashforth right-hand side.
+ * CN (Sec. II.B: Crank-Nicolson for the diffusive terms, the provisional
+ * velocity by approximate factorisation), delta form per component:
+ *   RHS = dt [(1 + w/2) Hc^n - (w/2) Hc^{n-1} - G p^n + nu L u^n],  Hc = -div(u u),
+ *   (1 - b Dx)(1 - b Dy)(1 - b Dz) du = RHS,  b = nu dt / 2,  u~ = u^n + du,
+ * solved as du = X^{-1} Y^{-1} Z^{-1} RHS (periodic y and z factors first,
+ * then x), the x factor carrying the boundary increments: u: du_0 = 0,
+ * du_nx = outflow value - u^n_nx; v, w: inlet ghost du_{-1} = -du_0, outlet
+ * ghost increment outflow value - u^n_nx (zero-gradient at both ends under
+ * the test hook).  FP64 only (EINVAL with IBDNS_MIXED); batches refuse it. */
+enum { IBDNS_DIFFUSION_EXPLICIT = 0, IBDNS_DIFFUSION_CN = 1 };
 
 /* Flag (Sec. II.A: square of side L, mass ratio rho, bending coefficient beta,
  * hinged at its leading edge; Sec. II.B: spring network, essentially

@@ -18,6 +18,7 @@ LIB_PATH = os.path.join(HERE, "libibdns.so")
 
 OK, EINVAL, ENOMEM, EHIP, EUNSTABLE, ESTATE = 0, -1, -2, -3, -4, -5
 FP64, MIXED = 0, 1
+DIFFUSION_EXPLICIT, DIFFUSION_CN = 0, 1
 LE_HINGED, LE_CLAMPED = 0, 1
 TEST_VW_NEUMANN_X = 1
 STAGE_PREDICT, STAGE_FLUX, STAGE_IBM, STAGE_PROJECT, STAGE_FLAG, STAGE_ADVANCE = range(6)
@@ -40,7 +41,8 @@ class Domain(ctypes.Structure):
                 ("lx", ctypes.c_double), ("ly", ctypes.c_double), ("lz", ctypes.c_double),
                 ("re", ctypes.c_double), ("u_in", ctypes.c_double), ("dt", ctypes.c_double),
                 ("cfl", ctypes.c_double), ("noise_amp", ctypes.c_double),
-                ("precision", ctypes.c_int32), ("flags", ctypes.c_uint32)]
+                ("precision", ctypes.c_int32), ("flags", ctypes.c_uint32),
+                ("diffusion", ctypes.c_int32)]
 
 
 class FlagParams(ctypes.Structure):
@@ -137,8 +139,8 @@ def _dptr(a):
 
 
 def make_domain(nx, ny, nz, lx, ly, lz, re, u_in=1.0, dt=0.0, cfl=0.5, noise_amp=0.0,
-                precision=FP64, flags=0) -> Domain:
-    return Domain(nx, ny, nz, lx, ly, lz, re, u_in, dt, cfl, noise_amp, precision, flags)
+                precision=FP64, flags=0, diffusion=DIFFUSION_EXPLICIT) -> Domain:
+    return Domain(nx, ny, nz, lx, ly, lz, re, u_in, dt, cfl, noise_amp, precision, flags, diffusion)
 
 
 def workspace_size(dom: Domain, n_points: int = 0, flag_ns: int = 0) -> int:
@@ -358,10 +360,10 @@ def create(dom: Domain, noise=None, points=None, flag: FlagParams | None = None,
     return run
 
 
-def domain_from(w, precision=FP64, flags=0) -> Domain:
+def domain_from(w, precision=FP64, flags=0, diffusion=DIFFUSION_EXPLICIT) -> Domain:
     """Domain struct from any object with nx, ny, nz, lx, ly, lz, re, u_in, dt, cfl, noise_amp."""
     return make_domain(w.nx, w.ny, w.nz, w.lx, w.ly, w.lz, w.re, w.u_in, w.dt, w.cfl,
-                       w.noise_amp, precision, flags)
+                       w.noise_amp, precision, flags, diffusion)
 
 
 def flag_from(f) -> FlagParams:

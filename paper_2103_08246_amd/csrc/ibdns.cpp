@@ -68,6 +68,8 @@ struct ibdns_ctx {
   // after the immersed-boundary stage and joined before the time advance
   hipStream_t side = nullptr;
   hipEvent_t ev_fork = nullptr, ev_join = nullptr;
+  // Crank-Nicolson factor tables (used when d.cn)
+  CnTables cnt{};
   // virtual probes (caller-owned workspace), sampled after each projection
   ProbeDev probes{};
   // Eulerian forcing of the passive grid (caller-owned workspace); host copy
@@ -119,6 +121,7 @@ size_t fluid_bytes(const ibdns_domain& dm) {
   b += up(3 * (size_t)dm.ny * dm.nz * sizeof(double));  // outlet planes
   b += up(dm.ny * sizeof(double2)) + up(dm.nz * sizeof(double2));
   b += up(MY * sizeof(double)) + up(dm.nz * sizeof(double));
+  b += up(cn_table_doubles(dm.nx, dm.ny, dm.nz) * sizeof(double));  // Crank-Nicolson factors
   return b;
 }
 
@@ -167,6 +170,8 @@ int validate(const ibdns_domain* d) {
     return IBDNS_EINVAL;
   if (d->dt <= 0 && !(d->cfl > 0 && d->cfl < 1)) return IBDNS_EINVAL;
   if (d->precision != IBDNS_FP64 && d->precision != IBDNS_MIXED) return IBDNS_EINVAL;
+  if (d->diffusion != IBDNS_DIFFUSION_EXPLICIT && d->diffusion != IBDNS_DIFFUSION_CN) return IBDNS_EINVAL;
+  if (d->diffusion == IBDNS_DIFFUSION_CN && d->precision != IBDNS_FP64) return IBDNS_EINVAL;
   if ((long long)row_pitch(*d) * d->ny * d->nz >= (1LL << 31)) return IBDNS_EINVAL;
   return IBDNS_OK;
 }
@@ -204,6 +209,9 @@ void rec_end(ibdns_ctx* c, const char* name, hipEvent_t a, hipStream_t st) {
 void stage_predict(ibdns_ctx* c) {
   TIMED(c, "predict", launch_predict(c->d, c->f, c->s, c->variant, c->st));
   TIMED(c, "outlet", launch_outlet(c->d, c->f, c->s, c->nparts, 1, c->st));
+  // Crank-Nicolson: the predictor wrote the increment's right-hand side; the
+  // factored solves need the outflow values of the outlet kernel
+  if (c->d.cn) TIMED(c, "cn_sweeps", launch_cn(c->d, c->f, c->s, c->cnt, c->st));
 }
 void stage_flux(ibdns_ctx* c) { TIMED(c, "flux_apply", launch_flux_apply(c->d, c->f, c->s, c->nparts, c->st)); }
 
@@ -418,6 +426,7 @@ int ibdns_init_domain(const ibdns_domain* dm, const double* zu, const double* zv
   d.u_in = dm->u_in;
   d.flags = dm->flags;
   d.mixed = dm->precision == IBDNS_MIXED ? 1 : 0;
+  d.cn = dm->diffusion == IBDNS_DIFFUSION_CN ? 1 : 0;
   c->nparts = outlet_blocks(d);
 
   c->s = c->carve<Scalars>(1);
@@ -432,7 +441,9 @@ int ibdns_init_domain(const ibdns_domain* dm, const double* zu, const double* zv
   c->tw_z = c->carve<double2>(d.nz);
   c->lam_y = c->carve<double>(d.MY);
   c->lam_z = c->carve<double>(d.nz);
-  if (!c->lam_z) {
+  double* cnb = c->carve<double>(cn_table_doubles(d.nx, d.ny, d.nz));
+  if (cnb) c->cnt = cn_tables_at(cnb, d.nx, d.ny, d.nz);
+  if (!c->lam_z || !cnb) {
     delete c;
     return IBDNS_ENOMEM;
   }
@@ -1421,6 +1432,7 @@ int ibdns_batch_create(ibdns_ctx* const* runs, int32_t n_runs, void* dev_ws, siz
     if (runs[r]->st != runs[0]->st || runs[r]->d.mixed != runs[0]->d.mixed) return IBDNS_EINVAL;
     if (runs[r]->has_flag && flag_bands(runs[r]->fl.ns) > 64) return IBDNS_EINVAL;
     if (runs[r]->has_gforce) return IBDNS_EINVAL;   // batches force grids as points only
+    if (runs[r]->d.cn) return IBDNS_EINVAL;         // and diffuse explicitly
   }
   ibdns_batch* b = new ibdns_batch();
   if (hipStreamCreateWithFlags(&b->side, hipStreamNonBlocking) != hipSuccess ||

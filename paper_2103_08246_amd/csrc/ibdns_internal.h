@@ -30,6 +30,7 @@ struct Dims {
   double h, inv_h, nu, u_in;
   uint32_t flags;    // IBDNS_TEST_* bits
   int mixed;         // 1: H and u~ stored and computed in FP32
+  int cn;            // 1: Crank-Nicolson diffusion (the predictor writes the increment's RHS)
 };
 
 __host__ __device__ inline long long fidx(const Dims& d, int i, int j, int k) {
@@ -100,6 +101,16 @@ struct FlagDev {
   const double* rest;      // ns*ns*6 rest lengths to the (+a, -a, +b, -b, +a+b, -a-b) neighbours
   double* xbuf;            // 2 slots x bands x 4 edge rows x ns x 3: band-edge exchange
   int* counter;            // 64 per-band sub-step counters
+};
+
+// Crank-Nicolson sweeps: factor tables rebuilt on the device each step (dt
+// lives there).  Periodic directions (Sherman-Morrison on the cyclic system):
+// c' and 1/pivot of the modified tridiagonal, its correction vector q;
+// x direction: c' and 1/pivot for u (nx-1 unknowns) and for v, w (nx).
+// sc: r = nu dt / (2 h^2), then per periodic direction (y, z) the ratio
+// (top-right entry / gamma) and 1 / (1 + v.q).
+struct CnTables {
+  double *y_cp, *y_m, *y_q, *z_cp, *z_m, *z_q, *xu_cp, *xu_m, *xv_cp, *xv_m, *sc;
 };
 
 // Virtual probes: n probes at X (3n), records of 10 + 2L doubles, rings of
@@ -223,6 +234,9 @@ void launch_flag_step_plain(const FlagDev& fl, Scalars* s, hipStream_t st);
 int flag_bands(int ns);
 void launch_advance(Scalars* s, const double* partial, int nparts, double h, hipStream_t st);
 void launch_probes(const Dims& d, const Fields& f, const ProbeDev& pr, hipStream_t st);
+size_t cn_table_doubles(int nx, int ny, int nz);
+CnTables cn_tables_at(double* base, int nx, int ny, int nz);
+void launch_cn(const Dims& d, const Fields& f, const Scalars* s, const CnTables& t, hipStream_t st);
 void launch_grid_force(const Dims& d, const Fields& f, const GridForceDev& g, hipStream_t st);
 void launch_set_dt0(Scalars* s, const double* partial, int nparts, double h, hipStream_t st);
 

@@ -114,6 +114,7 @@ __device__ __forceinline__ void predict_body(const Dims& d, const Fields& f, con
   const T c1 = (T)(1.0 + 0.5 * omega);
   const T c2 = (T)(0.5 * omega);
   const bool first = s->first != 0;
+  const bool cn = d.cn != 0;   // Crank-Nicolson: H is convective only, u~ holds the increment's RHS
   const T inv_h = (T)d.inv_h;
   const T c_d = (T)(d.nu / (d.h * d.h));
   const T half = (T)0.5, two = (T)2;
@@ -154,11 +155,11 @@ __device__ __forceinline__ void predict_body(const Dims& d, const Fields& f, con
         const T fxz_p = half * (u0 + uzp) * (half * (W(-1, 0, sn) + W(0, 0, sn)));
         const T adv = ((fxx_p - fxx_m) + (fxy_p - fxy_0) + (fxz_p - fxz_0)) * inv_h;
         const T lap = (uxp + uxm - two * u0) + (uyp + uym - two * u0) + (uzp + uzm - two * u0);
-        const T H = -adv + c_d * lap;
+        const T H = cn ? -adv : -adv + c_d * lap;
         const T Hold = first ? H : hu[c];
         hu[c] = H;
         const T gp = (p_c - spp[o0 - 1]) * inv_h;
-        ut[c] = u0 + dt * (c1 * H - c2 * Hold - gp);
+        ut[c] = cn ? dt * (c1 * H - c2 * Hold - gp + c_d * lap) : u0 + dt * (c1 * H - c2 * Hold - gp);
       } else {
         ut[c] = U(0, 0, sc);  // inlet face keeps U
         hu[c] = (T)0;
@@ -178,11 +179,11 @@ __device__ __forceinline__ void predict_body(const Dims& d, const Fields& f, con
         const T fyz_p = half * (v0 + vzp) * (half * (W(0, -1, sn) + W(0, 0, sn)));
         const T adv = ((fxy_p - fxy_0) + (fyy_0 - fyy_m) + (fyz_p - fyz_0)) * inv_h;
         const T lap = (vxp + vxm - two * v0) + (vyp + vym - two * v0) + (vzp + vzm - two * v0);
-        const T H = -adv + c_d * lap;
+        const T H = cn ? -adv : -adv + c_d * lap;
         const T Hold = first ? H : hv[c];
         hv[c] = H;
         const T gp = (p_c - spp[o0 - LX]) * inv_h;
-        vt[c] = v0 + dt * (c1 * H - c2 * Hold - gp);
+        vt[c] = cn ? dt * (c1 * H - c2 * Hold - gp + c_d * lap) : v0 + dt * (c1 * H - c2 * Hold - gp);
       }
       // ---------------- w cell i ----------------
       {
@@ -199,11 +200,11 @@ __device__ __forceinline__ void predict_body(const Dims& d, const Fields& f, con
         const T fzz_m = sq(half * (wzm + w0));
         const T adv = ((fxz_p - fxz_0) + (fyz_p - fyz_0) + (fzz_0 - fzz_m)) * inv_h;
         const T lap = (wxp + wxm - two * w0) + (wyp + wym - two * w0) + (wzp + wzm - two * w0);
-        const T H = -adv + c_d * lap;
+        const T H = cn ? -adv : -adv + c_d * lap;
         const T Hold = first ? H : hw[c];
         hw[c] = H;
         const T gp = (p_c - p_km) * inv_h;
-        wt[c] = w0 + dt * (c1 * H - c2 * Hold - gp);
+        wt[c] = cn ? dt * (c1 * H - c2 * Hold - gp + c_d * lap) : w0 + dt * (c1 * H - c2 * Hold - gp);
       }
     }
     p_km = p_c;

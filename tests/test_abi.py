@@ -62,3 +62,16 @@ def test_probe_workspace_size():
     assert out.value == up(3 * n * 8) + up(n * (10 + 2 * 5) * 8) + up(n * 2 * 5 * 8)
     for n_x, n_lags in ((0, 5), (3, 0), (3, 4097)):
         assert lib.ibdns_probe_workspace_size(n_x, n_lags, ctypes.byref(out)) == ib.EINVAL
+
+
+def test_diffusion_mode_validation():
+    import paper_2103_08246_amd as ib
+    out = ctypes.c_size_t(0)
+    lib = ib.lib()
+    cn = ib.make_domain(64, 32, 32, 4.0, 2.0, 2.0, 200.0, dt=1e-3, diffusion=ib.DIFFUSION_CN)
+    assert lib.ibdns_workspace_size(ctypes.byref(cn), 0, 0, ctypes.byref(out)) == ib.OK
+    cn_mixed = ib.make_domain(64, 32, 32, 4.0, 2.0, 2.0, 200.0, dt=1e-3, precision=ib.MIXED,
+                              diffusion=ib.DIFFUSION_CN)
+    assert lib.ibdns_workspace_size(ctypes.byref(cn_mixed), 0, 0, ctypes.byref(out)) == ib.EINVAL
+    bad = ib.make_domain(64, 32, 32, 4.0, 2.0, 2.0, 200.0, dt=1e-3, diffusion=2)
+    assert lib.ibdns_workspace_size(ctypes.byref(bad), 0, 0, ctypes.byref(out)) == ib.EINVAL

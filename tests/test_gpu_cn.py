@@ -1,0 +1,78 @@
+"""Crank-Nicolson diffusion with approximate factorisation (Sec. II.B) on the
+GPU against the oracle's predictor_cn: coupled steps of a flag case and of the
+grid + flag case, the predictor stage alone, and the mode checks."""
+import numpy as np
+import pytest
+
+import synth
+from tests.gpu_cases import oracle_flag_args, rel_l2
+from tests.test_gpu_parity import small_grid_flag
+
+pytestmark = pytest.mark.gpu
+ib = pytest.importorskip("paper_2103_08246_amd")
+
+
+def _pair(w, bars=True):
+    from oracle.solver import Solver
+    noise = synth.ic_noise(w)
+    pts = synth.bar_points(w) if (bars and w.grid is not None) else None
+    X0 = synth.flag_reference(w) if w.flag is not None else None
+    run = ib.create(ib.domain_from(w, diffusion=ib.DIFFUSION_CN), noise, points=pts,
+                    flag=ib.flag_from(w.flag) if w.flag is not None else None, flag_X0=X0)
+    S = Solver(w, noise, pts, oracle_flag_args(w, X0) if X0 is not None else None, diffusion="cn")
+    return run, S
+
+
+@pytest.mark.parametrize("make", [synth.flag_64_re200, small_grid_flag])
+def test_cn_steps_match_oracle(make):
+    w = make()
+    run, S = _pair(w)
+    try:
+        for _ in range(10):
+            run.step(1)
+            S.step(1)
+        u, v, ww, p, t, k = run.fields()
+        uo, vo, wo, po = S.fields()
+        assert rel_l2([u, v, ww], [uo, vo, wo]) < 1e-12
+        X, V, F = run.flag()
+        assert rel_l2([X], [S.X.reshape(X.shape)]) < 1e-13
+        assert abs(t - S.t) <= 1e-12 * S.t
+    finally:
+        run.close()
+
+
+def test_cn_predictor_stage():
+    """One predictor stage (RHS, outflow, factored solves) against the oracle's
+    provisional velocity before the flux correction."""
+    from oracle import fluid
+    w = small_grid_flag()
+    run, S = _pair(w, bars=False)
+    try:
+        ib.run_stage(run.ctx, ib.STAGE_PREDICT)
+        nx = w.nx
+        ut = ib.get_array(run.ctx, ib.ARR_UT, (w.nz, w.ny, nx + 1))
+        vt = ib.get_array(run.ctx, ib.ARR_VT, (w.nz, w.ny, nx))
+        wt = ib.get_array(run.ctx, ib.ARR_WT, (w.nz, w.ny, nx))
+        f, h = S.f, S.h
+        Hc = fluid.rhs(f, h, 0.0)
+        D = fluid.rhs(f, h, S.nu, advection=False)
+        uo, vo, wo = f.u.copy(), f.v.copy(), f.w.copy()
+        fluid.outlet(f, uo, vo, wo, S.dt, h, S.u_in)
+        fluid.predictor_cn(f, Hc, Hc, D, uo, vo, wo, S.dt, 1.0, h, S.nu)
+        assert rel_l2([ut[..., :nx], vt, wt], [uo[..., :nx], vo[..., :nx], wo[..., :nx]]) < 1e-13
+    finally:
+        run.close()
+
+
+def test_cn_mode_rules():
+    w = small_grid_flag()
+    with pytest.raises(ib.IbdnsError) as e:
+        ib.create(ib.domain_from(w, precision=ib.MIXED, diffusion=ib.DIFFUSION_CN), synth.ic_noise(w))
+    assert e.value.code == ib.EINVAL
+    run = ib.create(ib.domain_from(w, diffusion=ib.DIFFUSION_CN), synth.ic_noise(w))
+    try:
+        with pytest.raises(ib.IbdnsError) as e:
+            ib.Batch([run])
+        assert e.value.code == ib.EINVAL
+    finally:
+        run.close()
