@@ -154,6 +154,7 @@ def main():
     ap.add_argument("--no-mixed", action="store_true")
     ap.add_argument("--no-batch", action="store_true")
     ap.add_argument("--no-eulerian", action="store_true")
+    ap.add_argument("--no-cn", action="store_true")
     ap.add_argument("--batch-steps", type=int, default=20)
     ap.add_argument("--copy-calib", action="store_true",
                     help="also run a plain device copy of 1 GiB (calibrates HBM counters)")
@@ -173,12 +174,12 @@ def main():
     bars = synth.bar_points(w) if w.grid is not None else None
     X0 = synth.flag_reference(w) if w.flag is not None else None
 
-    def measure(precision, breakdown, eulerian=False):
+    def measure(precision, breakdown, eulerian=False, diffusion=0):
         """Timed region: args.steps steps with HIP events around the predictor
         only (two per step).  breakdown: then as many steps again with events
         around every kernel, for the per-kernel table (not the value).
         eulerian: the grid forced at its nodes instead of as points."""
-        run = ib.create(ib.domain_from(w, precision=precision), noise,
+        run = ib.create(ib.domain_from(w, precision=precision, diffusion=diffusion), noise,
                         points=None if eulerian else bars,
                         flag=ib.flag_from(w.flag) if w.flag is not None else None, flag_X0=X0,
                         grid_forcing=w.grid if eulerian else None)
@@ -303,6 +304,28 @@ def main():
                                 "note": "FP64, grid forced at its velocity nodes, flag by delta markers"}
         print(f"# eulerian grid: {wall_e * 1e3 / args.steps:.3f} ms/step", file=sys.stderr, flush=True)
         run_e.close()
+    if not args.no_cn:
+        # the paper's diffusion scheme (Sec. II.B): Crank-Nicolson with approximate
+        # factorisation, same workload and CFL step
+        run_c, wall_c, _, times_c = measure(ib.FP64, True, diffusion=ib.DIFFUSION_CN)
+        a = run.fields()
+        b = run_c.fields()
+        sweeps = times_c["all"].get("cn_sweeps", (0.0, 1))
+        sweep_ms = sweeps[0] / max(sweeps[1], 1)
+        # algorithmic bytes of the sweeps per evolved node (u: (nx-1) ny nz,
+        # v, w: nx ny nz): z and y a read+write forward pass and a read+write
+        # back substitution each, x the same plus the read of u^n
+        sweep_bytes = (32 + 32 + 40) * (3 * w.nx - 1) * w.ny * w.nz
+        out["crank_nicolson"] = {
+            "value": round(w.cells * args.steps / wall_c / 1e6, 1),
+            "ms_per_step": round(wall_c * 1e3 / args.steps, 4),
+            "cn_sweeps_ms": round(sweep_ms, 4),
+            "cn_sweeps_algorithmic_gbs": round(sweep_bytes / (sweep_ms * 1e-3) / 1e9, 1),
+            "vel_rel_l2_vs_explicit": (sum(float(np.sum((x - y) ** 2)) for x, y in zip(b[:3], a[:3]))
+                                       / sum(float(np.sum(y ** 2)) for y in a[:3])) ** 0.5,
+            "note": "FP64; z, y, x factored solves per component (z, y: thread per line; x: LDS tiles of 64 lines)"}
+        print(f"# crank-nicolson: {wall_c * 1e3 / args.steps:.3f} ms/step", file=sys.stderr, flush=True)
+        run_c.close()
     del noise
     run.close()
     if args.copy_calib:

@@ -109,8 +109,9 @@ struct FlagDev {
 // x direction: c' and 1/pivot for u (nx-1 unknowns) and for v, w (nx).
 // sc: r = nu dt / (2 h^2), then per periodic direction (y, z) the ratio
 // (top-right entry / gamma) and 1 / (1 + v.q).
+// Crank-Nicolson factor tables, rebuilt on the device each step.
 struct CnTables {
-  double *y_cp, *y_m, *y_q, *z_cp, *z_m, *z_q, *xu_cp, *xu_m, *xv_cp, *xv_m, *sc;
+  double *y_cp, *y_m, *y_q, *y_w, *z_cp, *z_m, *z_q, *z_w, *xu_cp, *xu_m, *xv_cp, *xv_m, *sc;
 };
 
 // Virtual probes: n probes at X (3n), records of 10 + 2L doubles, rings of

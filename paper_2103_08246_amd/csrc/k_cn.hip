@@ -11,25 +11,29 @@
 // increment; zero-gradient ends under the test hook).
 //
 // The factor tables depend on dt only, which lives on the device: one small
-// kernel rebuilds them each step.  Every sweep is one thread per line, lines
-// of neighbouring x columns in neighbouring lanes for the y and z sweeps
-// (coalesced), one thread per x line for the x sweep.  Constant coefficients:
-// the line loops read c' and 1/pivot from the tables.
+// kernel rebuilds them each step.  Every sweep is one thread per line: for
+// the y and z sweeps lines of neighbouring x columns sit in neighbouring lanes
+// (coalesced); the x sweep stages tiles of 64 lines through LDS.  A periodic
+// sweep reads and writes the field twice (forward, back substitution with the
+// rank-one correction folded in).
+// Constant coefficients: the line loops read c' and 1/pivot from the tables.
 #include "ibdns_internal.h"
 
 namespace ibdns {
 
-size_t cn_table_doubles(int nx, int ny, int nz) { return 3 * (size_t)ny + 3 * (size_t)nz + 4 * (size_t)nx + 8; }
+size_t cn_table_doubles(int nx, int ny, int nz) { return 4 * (size_t)ny + 4 * (size_t)nz + 4 * (size_t)nx + 8; }
 
 CnTables cn_tables_at(double* b, int nx, int ny, int nz) {
   CnTables t;
   t.y_cp = b;
   t.y_m = t.y_cp + ny;
   t.y_q = t.y_m + ny;
-  t.z_cp = t.y_q + ny;
+  t.y_w = t.y_q + ny;
+  t.z_cp = t.y_w + ny;
   t.z_m = t.z_cp + nz;
   t.z_q = t.z_m + nz;
-  t.xu_cp = t.z_q + nz;
+  t.z_w = t.z_q + nz;
+  t.xu_cp = t.z_w + nz;
   t.xu_m = t.xu_cp + nx;
   t.xv_cp = t.xu_m + nx;
   t.xv_m = t.xv_cp + nx;
@@ -41,7 +45,8 @@ namespace {
 
 // Tridiagonal (-r, diag, -r) of n rows with the first and last diagonal
 // entries b0, bn: c'_i and 1/pivot_i of the elimination.
-__device__ void tri_factor(int n, double r, double b0, double bmid, double bn, double* cp, double* m) {
+__device__ void tri_factor(int n, double r, double b0, double bmid, double bn, double* __restrict__ cp,
+                           double* __restrict__ m) {
   double prev = 0.0;
   for (int i = 0; i < n; ++i) {
     const double b = i == 0 ? b0 : (i == n - 1 ? bn : bmid);
@@ -53,31 +58,59 @@ __device__ void tri_factor(int n, double r, double b0, double bmid, double bn, d
 }
 
 // Cyclic (-r, b, -r) of n rows: A = T' + u v^T with u = (g, 0.., 0, -r),
-// v = (1, 0.., 0, -r / g), g = -b; T' is tridiagonal with first and last
-// diagonal entries b - g and b - r^2 / g.  Tables: T' factors, q = T'^{-1} u,
-// the ratio -r / g and 1 / (1 + v.q).
-__device__ void cyclic_factor(int n, double r, double* cp, double* m, double* q, double* sc2) {
-  const double b = 1.0 + 2.0 * r, g = -b;
-  tri_factor(n, r, b - g, b, b - r * r / g, cp, m);
-  // q: forward then backward sweep of u
-  double prev = 0.0;
+// v = (1, 0.., 0, -r / g), g = -b; T' is symmetric tridiagonal with first and
+// last diagonal entries b - g and b - r^2 / g.  Tables: the T' factors,
+// q = T'^{-1} u, w = T'^{-1} e_0 (so that y_0 = w . d for y = T'^{-1} d), the
+// ratio -r / g and 1 / (1 + v.q).  The recurrences carry their values in
+// registers; the back substitution loads its inputs 16 rows at a time.
+__device__ void cyclic_factor(int n, double r, double* __restrict__ cp, double* __restrict__ m,
+                              double* __restrict__ q, double* __restrict__ w, double* __restrict__ sc2) {
+  const double b = 1.0 + 2.0 * r, g = -b, b0 = b - g, bn = b - r * r / g;
+  double c = 0.0, qp = 0.0, wp = 0.0;
   for (int i = 0; i < n; ++i) {
-    const double ui = i == 0 ? g : (i == n - 1 ? -r : 0.0);
-    prev = (ui + r * prev) * m[i];
-    q[i] = prev;
+    const double bi = i == 0 ? b0 : (i == n - 1 ? bn : b);
+    const double inv = 1.0 / (bi - (i == 0 ? 0.0 : -r * c));
+    m[i] = inv;
+    c = -r * inv;
+    cp[i] = c;
+    qp = ((i == 0 ? g : (i == n - 1 ? -r : 0.0)) + r * qp) * inv;
+    q[i] = qp;
+    wp = ((i == 0 ? 1.0 : 0.0) + r * wp) * inv;
+    w[i] = wp;
   }
-  for (int i = n - 2; i >= 0; --i) q[i] = q[i] - cp[i] * q[i + 1];
+  const double qlast = qp;
+  for (int i0 = n - 2; i0 >= 0; i0 -= 16) {
+    double qa[16], wa[16], ca[16];
+#pragma unroll
+    for (int u = 0; u < 16; ++u) {
+      const int i = max(i0 - u, 0);
+      qa[u] = q[i];
+      wa[u] = w[i];
+      ca[u] = cp[i];
+    }
+#pragma unroll
+    for (int u = 0; u < 16; ++u)
+      if (i0 - u >= 0) {
+        qp = qa[u] - ca[u] * qp;
+        q[i0 - u] = qp;
+        wp = wa[u] - ca[u] * wp;
+        w[i0 - u] = wp;
+      }
+  }
   const double vr = -r / g;
   sc2[0] = vr;
-  sc2[1] = 1.0 / (1.0 + q[0] + vr * q[n - 1]);
+  sc2[1] = 1.0 / (1.0 + qp + vr * qlast);   // qp = q_0
 }
 
+// One workgroup per table (the recurrences are sequential; separate
+// workgroups run them side by side), one active thread each.
 __global__ void k_cn_tables(Dims d, const Scalars* __restrict__ s, CnTables t) {
+  if (threadIdx.x != 0) return;
   const double r = 0.5 * d.nu * s->dt / (d.h * d.h);
   const bool neumann = (d.flags & 1u) != 0;
-  switch (threadIdx.x) {
-    case 0: cyclic_factor(d.ny, r, t.y_cp, t.y_m, t.y_q, t.sc + 1); break;
-    case 1: cyclic_factor(d.nz, r, t.z_cp, t.z_m, t.z_q, t.sc + 3); break;
+  switch (blockIdx.x) {
+    case 0: cyclic_factor(d.ny, r, t.y_cp, t.y_m, t.y_q, t.y_w, t.sc + 1); break;
+    case 1: cyclic_factor(d.nz, r, t.z_cp, t.z_m, t.z_q, t.z_w, t.sc + 3); break;
     case 2: tri_factor(d.nx - 1, r, 1.0 + 2.0 * r, 1.0 + 2.0 * r, 1.0 + 2.0 * r, t.xu_cp, t.xu_m); break;
     case 3:
       if (neumann)
@@ -95,78 +128,169 @@ __device__ __forceinline__ double* cn_field(const Fields& f, int comp) {
 }
 
 // Cyclic solve along y (axis 1) or z (axis 2) of every line of component comp
-// over its evolved x range, in place.
+// over its evolved x range, in place.  The forward sweep also forms
+// y_0 = w . d, so the Sherman-Morrison factor is known before the back
+// substitution, which writes the corrected solution y - fac q directly.  The
+// four tables of the axis sit in LDS (4 n doubles; n <= 768, the largest
+// transform size, so at most 24 KiB).
 template <int AXIS>
 __global__ void __launch_bounds__(256) k_cn_periodic(Dims d, Fields f, CnTables t, int comp) {
   const int ilo = comp == 0 ? 1 : 0, nxe = comp == 0 ? d.nx - 1 : d.nx;
   const long long g = (long long)blockIdx.x * 256 + threadIdx.x;
   const int other = AXIS == 1 ? d.nz : d.ny;       // the line index besides x
-  if (g >= (long long)nxe * other) return;
-  const int i = ilo + (int)(g % nxe), o = (int)(g / nxe);
   const int n = AXIS == 1 ? d.ny : d.nz;
+  const long long gl = min(g, (long long)nxe * other - 1);   // threads past the end leave after the sync
+  const int i = ilo + (int)(gl % nxe), o = (int)(gl / nxe);
   const long long stride = AXIS == 1 ? (long long)d.P : d.PS;
   double* a = cn_field(f, comp) + (AXIS == 1 ? fidx(d, i, 0, o) : fidx(d, i, o, 0));
-  const double* cp = AXIS == 1 ? t.y_cp : t.z_cp;
-  const double* m = AXIS == 1 ? t.y_m : t.z_m;
-  const double* q = AXIS == 1 ? t.y_q : t.z_q;
+  extern __shared__ double lt[];   // m, w, c', q
+  {
+    const double* gm = AXIS == 1 ? t.y_m : t.z_m;
+    const double* gw = AXIS == 1 ? t.y_w : t.z_w;
+    const double* gc = AXIS == 1 ? t.y_cp : t.z_cp;
+    const double* gq = AXIS == 1 ? t.y_q : t.z_q;
+    for (int x = threadIdx.x; x < n; x += 256) {
+      lt[x] = gm[x];
+      lt[n + x] = gw[x];
+      lt[2 * n + x] = gc[x];
+      lt[3 * n + x] = gq[x];
+    }
+  }
+  __syncthreads();
+  if (g >= (long long)nxe * other) return;
+  const double* m = lt;
+  const double* w = lt + n;
+  const double* cp = lt + 2 * n;
+  const double* q = lt + 3 * n;
   const double r = t.sc[0], vr = t.sc[AXIS == 1 ? 1 : 3], inv = t.sc[AXIS == 1 ? 2 : 4];
-  double prev = 0.0;
+  double prev = 0.0, y0 = 0.0;
   for (int k = 0; k < n; ++k) {          // forward: d'_k = (d_k + r d'_{k-1}) / pivot_k
-    prev = (a[k * stride] + r * prev) * m[k];
+    const double v = a[k * stride];
+    y0 += w[k] * v;
+    prev = (v + r * prev) * m[k];
     a[k * stride] = prev;
   }
   const double ylast = prev;
+  const double fac = (y0 + vr * ylast) * inv;      // (v.y) / (1 + v.q)
+  a[(n - 1) * stride] = ylast - fac * q[n - 1];
   for (int k = n - 2; k >= 0; --k) {     // backward: y_k = d'_k - c'_k y_{k+1}
     prev = a[k * stride] - cp[k] * prev;
-    a[k * stride] = prev;
+    a[k * stride] = prev - fac * q[k];
   }
-  const double fac = (prev + vr * ylast) * inv;   // (v.y) / (1 + v.q), prev = y_0
-  for (int k = 0; k < n; ++k) a[k * stride] -= fac * q[k];
 }
 
-// x factor with the boundary increments, then u~ = u^n + du.
-__global__ void __launch_bounds__(256) k_cn_x(Dims d, Fields f, CnTables t, int comp) {
-  const long long g = (long long)blockIdx.x * 256 + threadIdx.x;
-  if (g >= (long long)d.ny * d.nz) return;
-  const int j = (int)(g % d.ny), k = (int)(g / d.ny);
+__device__ __forceinline__ void cn_wave_sync() {
+  __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+  __builtin_amdgcn_wave_barrier();
+  __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+}
+
+// x factor with the boundary increments, then u~ = u^n + du.  One wavefront
+// per workgroup takes 64 x lines (line g = j + ny k) and walks x in tiles of
+// XT values: the tile is loaded with 64 / XT lines per load instruction (XT
+// lanes on consecutive values of one line), lane l runs the recurrence along
+// line l in LDS, and the tile is stored the same way.  Loads go in unguarded
+// batches of 16 instructions (line and column indexes clamped into range);
+// only the stores are guarded.
+constexpr int XT = 32;
+__global__ void __launch_bounds__(64) k_cn_x(Dims d, Fields f, CnTables t, int comp) {
+  constexpr int RPL = 64 / XT, NLD = 64 / RPL, B = 16, LD = XT + 1;
+  static_assert(NLD % B == 0, "batch");
+  __shared__ double T[64 * LD];
+  __shared__ long long RB[64];   // field offset of x index ilo on each line
+  const int lane = threadIdx.x;
+  const long long nl = (long long)d.ny * d.nz;
+  const long long g0 = (long long)blockIdx.x * 64;
+  const int nrow = (int)min((long long)64, nl - g0);
   const bool neumann = comp > 0 && (d.flags & 1u) != 0;
   const int ilo = comp == 0 ? 1 : 0, n = comp == 0 ? d.nx - 1 : d.nx;
   const double* st = comp == 0 ? f.u : (comp == 1 ? f.v : f.w);
-  double* a = cn_field(f, comp) + fidx(d, ilo, j, k);
-  const double* s0 = st + fidx(d, ilo, j, k);
+  double* fa = cn_field(f, comp);
   const double* cp = comp == 0 ? t.xu_cp : t.xv_cp;
   const double* m = comp == 0 ? t.xu_m : t.xv_m;
   const double r = t.sc[0];
-  // outlet increment: outflow value (FP64 plane) - state at i = nx
-  const long long nplane = (long long)d.ny * d.nz;
-  const double dout = neumann ? 0.0 : f.bnd[comp * nplane + g] - st[fidx(d, d.nx, j, k)];
-  double prev = 0.0;
-  for (int i = 0; i < n; ++i) {
-    double rhs = a[i];
-    if (i == n - 1) rhs += r * dout;
-    prev = (rhs + r * prev) * m[i];
-    a[i] = prev;
+  double dout = 0.0;   // this lane's line: outlet increment
+  {
+    const long long g = g0 + min(lane, nrow - 1);
+    const int j = (int)(g % d.ny), k = (int)(g / d.ny);
+    RB[lane] = fidx(d, ilo, j, k);
+    if (lane < nrow && !neumann) dout = f.bnd[comp * nl + g] - st[fidx(d, d.nx, j, k)];
   }
-  a[n - 1] = s0[n - 1] + prev;
-  for (int i = n - 2; i >= 0; --i) {
-    prev = a[i] - cp[i] * prev;
-    a[i] = s0[i] + prev;
+  cn_wave_sync();
+  const int sub = lane / XT, col = lane % XT;
+  auto load_tile = [&](int x0, int wt) {
+    const int cc = min(col, wt - 1);
+    for (int b0 = 0; b0 < NLD; b0 += B) {
+      double v[B];
+#pragma unroll
+      for (int q = 0; q < B; ++q) v[q] = fa[RB[(b0 + q) * RPL + sub] + x0 + cc];
+#pragma unroll
+      for (int q = 0; q < B; ++q) T[((b0 + q) * RPL + sub) * LD + col] = v[q];
+    }
+  };
+  const int ntile = (n + XT - 1) / XT;
+  double prev = 0.0;
+  // forward elimination, tiles left to right
+  for (int tt = 0; tt < ntile; ++tt) {
+    const int x0 = tt * XT, wt = min(XT, n - x0);
+    load_tile(x0, wt);
+    cn_wave_sync();
+    if (lane < nrow) {
+      for (int x = 0; x < wt; ++x) {
+        double rhs = T[lane * LD + x];
+        if (x0 + x == n - 1) rhs += r * dout;
+        prev = (rhs + r * prev) * m[x0 + x];
+        T[lane * LD + x] = prev;
+      }
+    }
+    cn_wave_sync();
+    for (int q = 0; q < NLD; ++q) {
+      const int row = q * RPL + sub;
+      if (row < nrow && col < wt) fa[RB[row] + x0 + col] = T[row * LD + col];
+    }
+    cn_wave_sync();
+  }
+  // back substitution, tiles right to left, adding u^n
+  for (int tt = ntile - 1; tt >= 0; --tt) {
+    const int x0 = tt * XT, wt = min(XT, n - x0);
+    load_tile(x0, wt);
+    cn_wave_sync();
+    if (lane < nrow) {
+      for (int x = wt - 1; x >= 0; --x) {
+        const int xi = x0 + x;
+        if (xi < n - 1) prev = T[lane * LD + x] - cp[xi] * prev;   // xi = n-1: prev = d'_{n-1}
+        T[lane * LD + x] = prev;
+      }
+    }
+    cn_wave_sync();
+    const int cc = min(col, wt - 1);
+    for (int b0 = 0; b0 < NLD; b0 += B) {
+      double v[B];
+#pragma unroll
+      for (int q = 0; q < B; ++q) v[q] = st[RB[(b0 + q) * RPL + sub] + x0 + cc];
+#pragma unroll
+      for (int q = 0; q < B; ++q) {
+        const int row = (b0 + q) * RPL + sub;
+        if (row < nrow && col < wt) fa[RB[row] + x0 + col] = v[q] + T[row * LD + col];
+      }
+    }
+    cn_wave_sync();
   }
 }
 
 }  // namespace
 
 void launch_cn(const Dims& d, const Fields& f, const Scalars* s, const CnTables& t, hipStream_t st) {
-  hipLaunchKernelGGL(k_cn_tables, dim3(1), dim3(64), 0, st, d, s, t);
+  hipLaunchKernelGGL(k_cn_tables, dim3(5), dim3(64), 0, st, d, s, t);
   for (int comp = 0; comp < 3; ++comp) {
     const int nxe = comp == 0 ? d.nx - 1 : d.nx;
     const long long nz_lines = (long long)nxe * d.ny, ny_lines = (long long)nxe * d.nz;
-    hipLaunchKernelGGL(k_cn_periodic<2>, dim3((unsigned)((nz_lines + 255) / 256)), dim3(256), 0, st, d, f, t,
-                       comp);
-    hipLaunchKernelGGL(k_cn_periodic<1>, dim3((unsigned)((ny_lines + 255) / 256)), dim3(256), 0, st, d, f, t,
-                       comp);
-    hipLaunchKernelGGL(k_cn_x, dim3((unsigned)(((long long)d.ny * d.nz + 255) / 256)), dim3(256), 0, st, d, f,
-                       t, comp);
+    hipLaunchKernelGGL(k_cn_periodic<2>, dim3((unsigned)((nz_lines + 255) / 256)), dim3(256),
+                       4 * sizeof(double) * d.nz, st, d, f, t, comp);
+    hipLaunchKernelGGL(k_cn_periodic<1>, dim3((unsigned)((ny_lines + 255) / 256)), dim3(256),
+                       4 * sizeof(double) * d.ny, st, d, f, t, comp);
+    const long long nl = (long long)d.ny * d.nz;
+    hipLaunchKernelGGL(k_cn_x, dim3((unsigned)((nl + 63) / 64)), dim3(64), 0, st, d, f, t, comp);
   }
 }
 
