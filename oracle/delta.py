@@ -101,15 +101,9 @@ def spread(field, idx, wt, amount):
     np.add.at(field, (flat_k, flat_j, flat_i), vals)
 
 
-def ibm_force(ut, vt, wt_, X, Ud, dV, h, dt, nx):
-    """Single-pass direct forcing on the provisional velocity (in place).
-
-    ut, vt, wt_: provisional velocity components (arrays [k, j, i]); X (K, 3),
-    Ud (K, 3) target velocities, dV (K,) point volumes.  All points first
-    interpolate the unforced u~, then all spread.  Returns F (K, 3), the force
-    density applied to the fluid at each point.
-    """
-    fields = (ut, vt, wt_)
+def ibm_interp(fields, X, Ud, h, dt, nx):
+    """Interpolation and force density of every point (fields not modified).
+    Returns (F (K, 3), maps [(idx, wt)] per component)."""
     K = X.shape[0]
     F = np.zeros((K, 3))
     maps = []
@@ -120,9 +114,27 @@ def ibm_force(ut, vt, wt_, X, Ud, dV, h, dt, nx):
         U = interpolate(fields[c], idx, wgt) if K else np.zeros(0)
         F[:, c] = (Ud[:, c] - U) / dt
         maps.append((idx, wgt))
+    return F, maps
+
+
+def ibm_spread(fields, maps, F, dV, h, dt):
+    """Spreading of every point's forcing, in increasing point order (in place)."""
     h3 = h * h * h
     for c in range(3):
         idx, wgt = maps[c]
-        if K:
+        if idx.shape[0]:
             spread(fields[c], idx, wgt, dt * F[:, c] * dV / h3)
+
+
+def ibm_force(ut, vt, wt_, X, Ud, dV, h, dt, nx):
+    """Single-pass direct forcing on the provisional velocity (in place).
+
+    ut, vt, wt_: provisional velocity components (arrays [k, j, i]); X (K, 3),
+    Ud (K, 3) target velocities, dV (K,) point volumes.  All points first
+    interpolate the unforced u~, then all spread.  Returns F (K, 3), the force
+    density applied to the fluid at each point.
+    """
+    fields = (ut, vt, wt_)
+    F, maps = ibm_interp(fields, X, Ud, h, dt, nx)
+    ibm_spread(fields, maps, F, dV, h, dt)
     return F

@@ -11,6 +11,7 @@ advanced by its own solver.  Steps, per time step n:
   S4  outflow flux correction                             (fluid.flux_correct)
   S5  direct forcing on u~: passive-grid points (target 0) then flag nodes
       (target V^n)                                        (delta.ibm_force)
+      or, with MLS coupling, the flag's tiling markers    (mls)
   S6  r = D u~ / dt
   S7  L phi = r                                           (poisson.solve_poisson)
   S8  u^{n+1} = u~ - dt G phi,  p^{n+1} = p^n + phi        (fluid.project)
@@ -30,7 +31,8 @@ from __future__ import annotations
 import numpy as np
 
 from . import fluid
-from .delta import ibm_force
+from .delta import ibm_force, ibm_interp, ibm_spread
+from . import mls
 from .flag import FlagModel
 from .poisson import solve_poisson
 from .probes import ProbeStats, probe_positions
@@ -43,7 +45,9 @@ class Solver:
     params: object with nx, ny, nz, lx, ly, lz, re, u_in, dt, cfl, noise_amp.
     noise: (zu, zv, zw) standard normals, shapes (nz, ny, nx+1), (nz, ny, nx) x2.
     bars: (X (K, 3), dV (K,)) static solid points or None.
-    flag: dict(X0=(ns, ns, 3), length, rho, beta, ks, le_bc, h) or None.
+    flag: dict(X0=(ns, ns, 3), length, rho, beta, ks, le_bc, coupling) or None;
+      coupling "nodes" (default): the flag's nodes are its delta markers;
+      "mls": MLS transfer at the markers of the adaptive tiling (oracle.mls).
     """
 
     def __init__(self, params, noise=None, bars=None, flag=None, hooks: int = 0,
@@ -88,6 +92,13 @@ class Solver:
             self.V = np.zeros_like(self.X)
             self.flag_dV = self.flag.dA * self.h
             self.F_flag = np.zeros_like(self.X)
+        self.mls = None
+        if flag is not None and flag.get("coupling", "nodes") == "mls":
+            tri, beta, dVm, _ = mls.build_markers(flag["X0"], self.h)
+            self.mls = dict(tri=tri, beta=beta, dV=dVm)
+            self.F_flag = np.zeros((tri.shape[0], 3))
+        elif flag is not None and flag.get("coupling", "nodes") != "nodes":
+            raise ValueError(flag["coupling"])
         self.F_bar = np.zeros((self.bar_X.shape[0], 3))
         self.nsub = 0
         # Eulerian forcing of the passive grid (dict x_plane, mesh, bar) instead of points
@@ -160,6 +171,18 @@ class Solver:
         Eulerian grid forcing the grid is forced first, at its nodes."""
         if self.grid_lists is not None:
             grid_forcing_apply(ut, vt, wt, self.grid_lists)
+        if self.mls is not None:
+            # grid points (delta) and flag markers (MLS) all read the unforced
+            # field, then spread in that order
+            fields = (ut, vt, wt)
+            M = self.mls
+            Xm, Vm = mls.marker_state(M["tri"], M["beta"], self.X, self.V)
+            Fb, maps_b = ibm_interp(fields, self.bar_X, np.zeros_like(self.bar_X), self.h, self.dt, self.nx)
+            Fm, maps_m = mls.mls_interp(fields, Xm, Vm, self.h, self.dt, self.nx)
+            ibm_spread(fields, maps_b, Fb, self.bar_dV, self.h, self.dt)
+            mls.mls_spread(fields, maps_m, Fm, M["dV"], self.h, self.dt)
+            self.F_bar, self.F_flag = Fb, Fm
+            return np.concatenate([Fb, Fm])
         X, Ud, dV = self.markers()
         F = ibm_force(ut, vt, wt, X, Ud, dV, self.h, self.dt, self.nx)
         nb = self.bar_X.shape[0]
@@ -179,7 +202,11 @@ class Solver:
         """S10 with the forcing of this step."""
         if self.flag is None:
             return
-        f_h = -self.F_flag * self.flag_dV[:, None]
+        if self.mls is not None:
+            M = self.mls
+            f_h = mls.node_load(M["tri"], M["beta"], self.F_flag, M["dV"], self.X.shape[0])
+        else:
+            f_h = -self.F_flag * self.flag_dV[:, None]
         self.X, self.V, self.nsub = self.flag.advance(self.X, self.V, f_h, self.dt)
 
     def step(self, n: int = 1):
