@@ -126,7 +126,8 @@ int ibdns_init_domain(const ibdns_domain* d, const double* zu, const double* zv,
  * with positions X (host, n_points*3, point-major) and volumes dV (host,
  * n_points), forced to zero velocity (the passive grid).  flag (may be NULL)
  * with its reference lattice X0 (host, ns*ns*3, layout above); its nodes are
- * forced to the flag velocity.  Every point's 3x3x3 delta support must stay
+ * forced to the flag velocity (or, after ibdns_set_flag_mls, the markers of its
+ * tiling).  Every point's 3x3x3 delta support must stay
  * on evolved velocity nodes in x (else EINVAL).  May be called once, before
  * the first ibdns_step. */
 int ibdns_set_geometry(ibdns_ctx* ctx, int64_t n_points, const double* X, const double* dV,
@@ -191,6 +192,55 @@ int ibdns_set_grid_forcing(ibdns_ctx* ctx, double x_plane, double mesh, double b
  * weight the weights, in increasing node order.  ESTATE without grid forcing. */
 int ibdns_get_grid_forcing(ibdns_ctx* ctx, int32_t comp, int64_t* count, int64_t* node, int64_t* src,
                            double* weight);
+
+/* ------------------------------------------------------------------------
+ * MLS transfer at the markers of an adaptive Lagrangian tiling of the flag
+ * (Sec. II.B (ii): the moving flag by a Lagrangian direct forcing with a
+ * moving-least-squares interpolation; the tiling paragraph of Sec. II.B: each
+ * triangle refined to the local Eulerian resolution by quadratic and
+ * barycentric tiling rules).  Replaces the flag's node markers and their
+ * delta transfer; the grid's points keep theirs.
+ *
+ * Tiling, once, on the reference lattice (the sheet is essentially
+ * inextensible): every cell (a, b) of the ns x ns lattice has the triangles
+ * (p00, p10, p11) and (p00, p11, p01) (p10 = node (a+1, b) ...), cells in
+ * increasing id, the lower one first.  A triangle is split L times into four
+ * at its edge midpoints (children (v0, m01, m20), (m01, v1, m12),
+ * (m20, m12, v2), (m01, m12, m20)), L the smallest level with
+ * longest rest edge / 2^L <= h (L <= 6, else EINVAL).  Each tile carries one
+ * marker at its barycentre: fixed barycentric coordinates beta of the parent
+ * triangle (tile corners summed, divided by 3), volume
+ * dV = (parent area at rest / 4^L) h.  Each step: X_m = sum beta_v X_v,
+ * U^d_m = sum beta_v V_v.
+ *
+ * MLS (per component, on its staggered lattice): support the 3x3x3 nodes
+ * around the centre node (as the delta); weight W_k = w(|xi_x|/1.5)
+ * w(|xi_y|/1.5) w(|xi_z|/1.5), xi = (x_k - X_m)/h, w the cubic spline
+ * 2/3 - 4q^2 + 4q^3 (q <= 1/2), 4/3 - 4q + 4q^2 - 4q^3/3 (q <= 1), 0 beyond;
+ * linear basis (1, xi); shape functions phi_k = W_k (A^{-1} e_0) . (1, xi_k),
+ * A = sum_k W_k (1, xi_k)(1, xi_k)^T.  U~_m = sum phi_k u~_k,
+ * F_m = (U^d_m - U~_m)/dt, spreading u~_k += dt F_m dV_m phi_k / h^3 (all
+ * markers read the unforced field; spreading after the grid's points, in
+ * increasing marker order).  The flag's load: node v takes
+ * -sum_m beta_mv F_m dV_m.  FP64 only; batches refuse such runs.
+ * ------------------------------------------------------------------------ */
+
+/* Marker count and device workspace bytes for the MLS coupling of the
+ * context's flag.  ESTATE without a flag; EINVAL if a triangle needs more
+ * than 6 splits. */
+int ibdns_flag_mls_workspace_size(ibdns_ctx* ctx, int64_t* n_markers, size_t* bytes);
+
+/* Switch the flag to MLS markers.  dev_ws: caller-owned device memory of at
+ * least the bytes above, 256-byte aligned, kept alive until ibdns_destroy.
+ * After ibdns_set_geometry with a flag and before the first step (ESTATE
+ * otherwise, or if already set); EINVAL in mixed precision. */
+int ibdns_set_flag_mls(ibdns_ctx* ctx, void* dev_ws, size_t ws_bytes);
+
+/* The markers (any pointer may be NULL): parent vertex ids tri (3m), beta
+ * (3m), dV (m), the positions X (3m) and force densities F (3m) of the last
+ * interpolation.  ESTATE without MLS markers.  With MLS markers the F of
+ * ibdns_get_flag is the node load sum_m beta_mv F_m dV_m (a force). */
+int ibdns_get_flag_markers(ibdns_ctx* ctx, int32_t* tri, double* beta, double* dV, double* X, double* F);
 
 /* ------------------------------------------------------------------------
  * Virtual probes (Sec. III: a stencil of probes around the centreline, from

@@ -33,7 +33,8 @@ EXPORTED = ("ibdns_workspace_size", "ibdns_init_domain", "ibdns_set_geometry", "
             "ibdns_batch_step", "ibdns_batch_use_graph", "ibdns_batch_autotune", "ibdns_autotune",
             "ibdns_batch_destroy", "ibdns_probe_workspace_size", "ibdns_set_probes",
             "ibdns_get_probe_stats", "ibdns_grid_forcing_workspace_size", "ibdns_set_grid_forcing",
-            "ibdns_get_grid_forcing")
+            "ibdns_get_grid_forcing", "ibdns_flag_mls_workspace_size", "ibdns_set_flag_mls",
+            "ibdns_get_flag_markers")
 
 
 class Domain(ctypes.Structure):
@@ -111,6 +112,9 @@ def _load():
     lib.ibdns_set_grid_forcing.argtypes = [P, dd, dd, dd, P, ctypes.c_size_t]
     I64 = ctypes.POINTER(ctypes.c_int64)
     lib.ibdns_get_grid_forcing.argtypes = [P, ctypes.c_int32, I64, I64, I64, D]
+    lib.ibdns_flag_mls_workspace_size.argtypes = [P, I64, ctypes.POINTER(ctypes.c_size_t)]
+    lib.ibdns_set_flag_mls.argtypes = [P, P, ctypes.c_size_t]
+    lib.ibdns_get_flag_markers.argtypes = [P, ctypes.POINTER(ctypes.c_int32), D, D, D, D]
     return lib
 
 
@@ -334,6 +338,31 @@ class Run:
                                            src.ctypes.data_as(I64), _dptr(wgt)), "get_grid_forcing")
         return node, src, wgt
 
+    def set_flag_mls(self, device="cuda:0"):
+        """Couple the flag at the markers of its adaptive tiling by MLS (rule in
+        include/ibdns.h); the workspace tensor is kept on this object."""
+        import torch
+        m = ctypes.c_int64(0)
+        size = ctypes.c_size_t(0)
+        _check(_lib.ibdns_flag_mls_workspace_size(self.ctx, ctypes.byref(m), ctypes.byref(size)),
+               "flag_mls_workspace_size")
+        self.mls_ws = torch.empty(max(size.value, 256), dtype=torch.uint8, device=device)
+        _check(_lib.ibdns_set_flag_mls(self.ctx, ctypes.c_void_p(self.mls_ws.data_ptr()), self.mls_ws.numel()),
+               "set_flag_mls")
+        self.n_markers = m.value
+
+    def flag_markers(self, check=True):
+        """(tri (m, 3) int32, beta (m, 3), dV (m,), X (m, 3), F (m, 3)) of the MLS markers."""
+        m = getattr(self, "n_markers", 0)
+        tri = np.empty((max(m, 1), 3), dtype=np.int32)
+        beta, X, F = (np.empty((max(m, 1), 3)) for _ in range(3))
+        dV = np.empty(max(m, 1))
+        code = _lib.ibdns_get_flag_markers(self.ctx, tri.ctypes.data_as(ctypes.POINTER(ctypes.c_int32)),
+                                           _dptr(beta), _dptr(dV), _dptr(X), _dptr(F))
+        if check:
+            _check(code, "get_flag_markers")
+        return tri[:m], beta[:m], dV[:m], X[:m], F[:m]
+
     def close(self):
         if self.ctx is not None:
             destroy(self.ctx)
@@ -341,10 +370,11 @@ class Run:
 
 
 def create(dom: Domain, noise=None, points=None, flag: FlagParams | None = None, flag_X0=None,
-           device="cuda:0", stream=None, grid_forcing=None) -> Run:
+           device="cuda:0", stream=None, grid_forcing=None, flag_mls=False) -> Run:
     """Allocate the workspace with torch on ``device`` and build a context.
     grid_forcing: an object with x_plane, mesh, bar for Eulerian forcing of the
-    passive grid (then points must be None)."""
+    passive grid (then points must be None).  flag_mls: couple the flag at its
+    tiling markers by MLS instead of at its nodes by the delta."""
     import torch
     n_points = 0 if points is None else int(np.asarray(points[1]).size)
     ns = 0 if flag is None else flag.ns
@@ -357,6 +387,8 @@ def create(dom: Domain, noise=None, points=None, flag: FlagParams | None = None,
         run.set_grid_forcing(dom, grid_forcing.x_plane, grid_forcing.mesh, grid_forcing.bar, device)
     if points is not None or flag is not None:
         set_geometry(ctx, points, flag, flag_X0)
+    if flag_mls:
+        run.set_flag_mls(device)
     return run
 
 

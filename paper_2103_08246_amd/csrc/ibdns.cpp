@@ -76,6 +76,8 @@ struct ibdns_ctx {
   // of the lists: host-layout node, source (-1: solid) and weight
   GridForceDev gforce{};
   bool has_gforce = false;
+  MlsDev mlsd{};            // flag coupled at its tiling markers by MLS
+  bool has_mls = false;
   std::vector<long long> g_node[3], g_src[3];
   std::vector<double> g_w[3];
   // timing: IBDNS_TIMING_*
@@ -222,7 +224,14 @@ void stage_ibm_interp(ibdns_ctx* c) {
   if (c->has_gforce) TIMED(c, "grid_force", launch_grid_force(c->d, c->f, c->gforce, c->st));
   if (c->nbars) TIMED(c, "bars_interp", launch_point_interp(c->d, c->f, c->bars, c->s, false, c->st));
   // the flag's maps move with it: computed in the same launch as its interpolation
-  if (c->has_flag) TIMED(c, "flag_interp", launch_point_interp(c->d, c->f, c->flagpts, c->s, true, c->st));
+  if (c->has_flag && c->has_mls) {
+    // tiling markers: positions from the nodes, MLS forcing, then the node loads the flag needs
+    TIMED(c, "flag_markers", launch_mls_markers(c->mlsd, c->fl.X, c->fl.V, c->flagpts, c->st));
+    TIMED(c, "flag_interp", launch_mls_interp(c->d, c->f, c->flagpts, c->s, c->st));
+    TIMED(c, "flag_node_load", launch_mls_node_load(c->mlsd, c->flagpts, c->st));
+  } else if (c->has_flag) {
+    TIMED(c, "flag_interp", launch_point_interp(c->d, c->f, c->flagpts, c->s, true, c->st));
+  }
 }
 // Second half: spreading onto the grid (from the maps and amounts of the
 // first half; the flag positions are not read again).
@@ -822,7 +831,8 @@ int ibdns_get_flag(ibdns_ctx* c, double* X, double* V, double* F) {
   const size_t bytes = 3 * (size_t)c->fl.ns * c->fl.ns * sizeof(double);
   if (X && hipMemcpy(X, c->fl.X, bytes, hipMemcpyDeviceToHost) != hipSuccess) return IBDNS_EHIP;
   if (V && hipMemcpy(V, c->fl.V, bytes, hipMemcpyDeviceToHost) != hipSuccess) return IBDNS_EHIP;
-  if (F && hipMemcpy(F, c->fl.Fh, bytes, hipMemcpyDeviceToHost) != hipSuccess) return IBDNS_EHIP;
+  if (F && hipMemcpy(F, c->has_mls ? c->mlsd.fnode : c->fl.Fh, bytes, hipMemcpyDeviceToHost) != hipSuccess)
+    return IBDNS_EHIP;
   return read_status(c);
 }
 
@@ -1034,6 +1044,190 @@ int ibdns_probe_workspace_size(int32_t n_x, int32_t n_lags, size_t* bytes) {
   *bytes = up(3 * n * sizeof(double)) + up(n * (10 + 2 * (size_t)n_lags) * sizeof(double)) +
            up(n * 2 * (size_t)n_lags * sizeof(double));
   return IBDNS_OK;
+}
+
+}  // extern "C"
+
+namespace {
+
+// Adaptive Lagrangian tiling of the flag (the rule stated with the
+// declarations): triangles (p00, p10, p11), (p00, p11, p01) per cell in
+// increasing cell id, quadratic splits to the mesh spacing, one marker per
+// tile at its barycentre.
+struct Tiling {
+  std::vector<int> tri;
+  std::vector<double> beta, dV;
+};
+
+void emit_tiles(const double (&c)[3][3], int L, const int (&v)[3], double dv, Tiling& t) {
+  if (L == 0) {
+    for (int a = 0; a < 3; ++a) {
+      t.tri.push_back(v[a]);
+      t.beta.push_back((c[0][a] + c[1][a] + c[2][a]) / 3.0);
+    }
+    t.dV.push_back(dv);
+    return;
+  }
+  double m01[3], m12[3], m20[3];
+  for (int a = 0; a < 3; ++a) {
+    m01[a] = (c[0][a] + c[1][a]) / 2.0;
+    m12[a] = (c[1][a] + c[2][a]) / 2.0;
+    m20[a] = (c[2][a] + c[0][a]) / 2.0;
+  }
+  const double* kids[4][3] = {{c[0], m01, m20}, {m01, c[1], m12}, {m20, m12, c[2]}, {m01, m12, m20}};
+  for (auto& k : kids) {
+    double cc[3][3];
+    for (int r = 0; r < 3; ++r)
+      for (int a = 0; a < 3; ++a) cc[r][a] = k[r][a];
+    emit_tiles(cc, L - 1, v, dv, t);
+  }
+}
+
+constexpr int MLS_MAX_LEVEL = 6;   // at most 4^6 tiles per triangle
+
+int build_tiling(const double* X0, int ns, double h, Tiling& t) {
+  auto len = [&](int p, int q) {
+    const double dx = X0[3 * p] - X0[3 * q], dy = X0[3 * p + 1] - X0[3 * q + 1], dz = X0[3 * p + 2] - X0[3 * q + 2];
+    return std::sqrt(dx * dx + dy * dy + dz * dz);
+  };
+  for (int b = 0; b + 1 < ns; ++b)
+    for (int a = 0; a + 1 < ns; ++a) {
+      const int p00 = a + ns * b, p10 = a + 1 + ns * b, p01 = a + ns * (b + 1), p11 = a + 1 + ns * (b + 1);
+      const int tris[2][3] = {{p00, p10, p11}, {p00, p11, p01}};
+      for (auto& tr : tris) {
+        const double emax = std::max({len(tr[0], tr[1]), len(tr[1], tr[2]), len(tr[2], tr[0])});
+        int L = 0;
+        while (std::ldexp(emax, -L) > h) {
+          if (++L > MLS_MAX_LEVEL) return IBDNS_EINVAL;
+        }
+        const double* P0 = X0 + 3 * tr[0];
+        const double* P1 = X0 + 3 * tr[1];
+        const double* P2 = X0 + 3 * tr[2];
+        const double e1[3] = {P1[0] - P0[0], P1[1] - P0[1], P1[2] - P0[2]};
+        const double e2[3] = {P2[0] - P0[0], P2[1] - P0[1], P2[2] - P0[2]};
+        const double cx = e1[1] * e2[2] - e1[2] * e2[1], cy = e1[2] * e2[0] - e1[0] * e2[2],
+                     cz = e1[0] * e2[1] - e1[1] * e2[0];
+        const double area = 0.5 * std::sqrt(cx * cx + cy * cy + cz * cz);
+        const double corners[3][3] = {{1.0, 0.0, 0.0}, {0.0, 1.0, 0.0}, {0.0, 0.0, 1.0}};
+        emit_tiles(corners, L, tr, area / std::ldexp(1.0, 2 * L) * h, t);
+      }
+    }
+  return IBDNS_OK;
+}
+
+size_t mls_bytes(size_t m, size_t n) {
+  return up(3 * m * sizeof(int)) + up(3 * m * sizeof(double)) + up(m * sizeof(double)) +
+         3 * up(3 * m * sizeof(double)) + up(3 * m * sizeof(double)) + up(9 * m * sizeof(int)) +
+         up(27 * m * sizeof(double)) + up(21 * m * sizeof(double)) + up((18 + 18 * ((m + 63) / 64)) * sizeof(int)) +
+         up((n + 1) * sizeof(int)) + up(3 * m * sizeof(int)) + up(3 * n * sizeof(double));
+}
+
+int flag_reference(ibdns_ctx* c, std::vector<double>& X0) {
+  const size_t n = (size_t)c->fl.ns * c->fl.ns;
+  X0.resize(3 * n);
+  if (hipStreamSynchronize(c->st) != hipSuccess ||
+      hipMemcpy(X0.data(), c->fl.X0, 3 * n * sizeof(double), hipMemcpyDeviceToHost) != hipSuccess)
+    return IBDNS_EHIP;
+  return IBDNS_OK;
+}
+
+}  // namespace
+
+extern "C" {
+
+int ibdns_flag_mls_workspace_size(ibdns_ctx* c, int64_t* n_markers, size_t* bytes) {
+  if (!c || !n_markers || !bytes) return IBDNS_EINVAL;
+  if (!c->has_flag) return IBDNS_ESTATE;
+  std::vector<double> X0;
+  int r = flag_reference(c, X0);
+  if (r) return r;
+  Tiling t;
+  if ((r = build_tiling(X0.data(), c->fl.ns, c->d.h, t))) return r;
+  *n_markers = (int64_t)t.dV.size();
+  *bytes = mls_bytes(t.dV.size(), (size_t)c->fl.ns * c->fl.ns);
+  return IBDNS_OK;
+}
+
+int ibdns_set_flag_mls(ibdns_ctx* c, void* dev_ws, size_t ws_bytes) {
+  if (!c) return IBDNS_EINVAL;
+  if (!c->has_flag || c->stepped || c->has_mls) return IBDNS_ESTATE;
+  if (c->d.mixed) return IBDNS_EINVAL;   // the MLS path is FP64
+  if (!dev_ws || (reinterpret_cast<uintptr_t>(dev_ws) % ALIGN) != 0) return IBDNS_EINVAL;
+  std::vector<double> X0;
+  int r = flag_reference(c, X0);
+  if (r) return r;
+  Tiling t;
+  if ((r = build_tiling(X0.data(), c->fl.ns, c->d.h, t))) return r;
+  const size_t m = t.dV.size(), n = (size_t)c->fl.ns * c->fl.ns;
+  if (m >= (size_t)1 << 26) return IBDNS_EINVAL;
+  if (ws_bytes < mls_bytes(m, n)) return IBDNS_ENOMEM;
+  // node -> (marker, slot) lists in increasing marker order
+  std::vector<int> ptr(n + 1, 0), ent(3 * m);
+  for (size_t e = 0; e < 3 * m; ++e) ++ptr[t.tri[e] + 1];
+  for (size_t v = 0; v < n; ++v) ptr[v + 1] += ptr[v];
+  {
+    std::vector<int> fill(ptr.begin(), ptr.end() - 1);
+    for (size_t e = 0; e < 3 * m; ++e) ent[fill[t.tri[e]]++] = (int)e;   // e = marker * 3 + slot
+  }
+  char* ws = static_cast<char*>(dev_ws);
+  size_t used = 0;
+  auto carve = [&](size_t bytes) {
+    char* p = ws + used;
+    used += up(bytes);
+    return p;
+  };
+  int* tri = reinterpret_cast<int*>(carve(3 * m * sizeof(int)));
+  double* beta = reinterpret_cast<double*>(carve(3 * m * sizeof(double)));
+  double* dV = reinterpret_cast<double*>(carve(m * sizeof(double)));
+  double* mX = reinterpret_cast<double*>(carve(3 * m * sizeof(double)));
+  double* mU = reinterpret_cast<double*>(carve(3 * m * sizeof(double)));
+  double* mF = reinterpret_cast<double*>(carve(3 * m * sizeof(double)));
+  double* amount = reinterpret_cast<double*>(carve(3 * m * sizeof(double)));
+  int* centre = reinterpret_cast<int*>(carve(9 * m * sizeof(int)));
+  double* wts = reinterpret_cast<double*>(carve(27 * m * sizeof(double)));
+  double* mls = reinterpret_cast<double*>(carve(21 * m * sizeof(double)));
+  int* bbox = reinterpret_cast<int*>(carve((18 + 18 * ((m + 63) / 64)) * sizeof(int)));
+  int* dptr = reinterpret_cast<int*>(carve((n + 1) * sizeof(int)));
+  int* dent = reinterpret_cast<int*>(carve(3 * m * sizeof(int)));
+  double* fnode = reinterpret_cast<double*>(carve(3 * n * sizeof(double)));
+  if (hipMemcpy(tri, t.tri.data(), 3 * m * sizeof(int), hipMemcpyHostToDevice) != hipSuccess ||
+      hipMemcpy(beta, t.beta.data(), 3 * m * sizeof(double), hipMemcpyHostToDevice) != hipSuccess ||
+      hipMemcpy(dV, t.dV.data(), m * sizeof(double), hipMemcpyHostToDevice) != hipSuccess ||
+      hipMemcpy(dptr, ptr.data(), (n + 1) * sizeof(int), hipMemcpyHostToDevice) != hipSuccess ||
+      hipMemcpy(dent, ent.data(), 3 * m * sizeof(int), hipMemcpyHostToDevice) != hipSuccess ||
+      hipMemset(mF, 0, 3 * m * sizeof(double)) != hipSuccess ||
+      hipMemset(fnode, 0, 3 * n * sizeof(double)) != hipSuccess || hipDeviceSynchronize() != hipSuccess)
+    return IBDNS_EHIP;
+  PointSet& ps = c->flagpts;
+  ps.n = (int)m;
+  ps.X = mX;
+  ps.Ud = mU;
+  ps.dV = dV;
+  ps.F = mF;
+  ps.amount = amount;
+  ps.centre = centre;
+  ps.wts = wts;
+  ps.mls = mls;
+  c->bbox = bbox;
+  c->mlsd = MlsDev{(int)m, (int)n, tri, beta, dptr, dent, fnode};
+  c->fl.fnode = fnode;
+  c->has_mls = true;
+  return IBDNS_OK;
+}
+
+int ibdns_get_flag_markers(ibdns_ctx* c, int32_t* tri, double* beta, double* dV, double* X, double* F) {
+  if (!c) return IBDNS_EINVAL;
+  if (!c->has_mls) return IBDNS_ESTATE;
+  if (hipStreamSynchronize(c->st) != hipSuccess) return IBDNS_EHIP;
+  const size_t m = (size_t)c->mlsd.m;
+  const PointSet& ps = c->flagpts;
+  if ((tri && hipMemcpy(tri, c->mlsd.tri, 3 * m * sizeof(int), hipMemcpyDeviceToHost) != hipSuccess) ||
+      (beta && hipMemcpy(beta, c->mlsd.beta, 3 * m * sizeof(double), hipMemcpyDeviceToHost) != hipSuccess) ||
+      (dV && hipMemcpy(dV, ps.dV, m * sizeof(double), hipMemcpyDeviceToHost) != hipSuccess) ||
+      (X && hipMemcpy(X, ps.X, 3 * m * sizeof(double), hipMemcpyDeviceToHost) != hipSuccess) ||
+      (F && hipMemcpy(F, ps.F, 3 * m * sizeof(double), hipMemcpyDeviceToHost) != hipSuccess))
+    return IBDNS_EHIP;
+  return read_status(c);
 }
 
 int ibdns_set_probes(ibdns_ctx* c, int32_t n_x, double x0, double dx, double yc, double zc, double dyz,
@@ -1432,6 +1626,7 @@ int ibdns_batch_create(ibdns_ctx* const* runs, int32_t n_runs, void* dev_ws, siz
     if (runs[r]->st != runs[0]->st || runs[r]->d.mixed != runs[0]->d.mixed) return IBDNS_EINVAL;
     if (runs[r]->has_flag && flag_bands(runs[r]->fl.ns) > 64) return IBDNS_EINVAL;
     if (runs[r]->has_gforce) return IBDNS_EINVAL;   // batches force grids as points only
+    if (runs[r]->has_mls) return IBDNS_EINVAL;      // and flags at their nodes
     if (runs[r]->d.cn) return IBDNS_EINVAL;         // and diffuse explicitly
   }
   ibdns_batch* b = new ibdns_batch();

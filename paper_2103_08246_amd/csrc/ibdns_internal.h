@@ -78,6 +78,22 @@ struct PointSet {
   double* amount;          // 3*n: dt F dV / h^3 per component
   int* centre;             // 3*n*3: centre node per component
   double* wts;             // 3*n*9: 1-D delta factors per component (x, y, z taps)
+  double* mls = nullptr;   // 3*n*7 with MLS transfer: per component the offsets (x_k - X)/h of
+                           // tap 0 in x, y, z, then the coefficients a0, g of the shape functions
+                           // phi = W (a0 + g . xi); nullptr: delta transfer (wts are delta factors)
+};
+
+// Flag markers of the adaptive tiling: m markers, each at fixed barycentric
+// coordinates beta of a parent triangle (tri), volume dV; node_ptr/node_ent
+// list for every node the (marker * 3 + slot) entries that touch it, in
+// increasing marker order; fnode (3 per node) receives sum beta F dV.
+struct MlsDev {
+  int m = 0, n = 0;
+  const int* tri = nullptr;
+  const double* beta = nullptr;
+  const int* node_ptr = nullptr;
+  const int* node_ent = nullptr;
+  double* fnode = nullptr;
 };
 
 // Static point-to-grid transposed map for atomic-free spreading (per component).
@@ -95,6 +111,7 @@ struct FlagDev {
   double* X;               // ns*ns*3
   double* V;
   double* Fh;              // ns*ns*3 hydrodynamic force density (from the IBM)
+  const double* fnode = nullptr;  // ns*ns*3 node loads sum beta F dV (MLS markers), else nullptr
   const double* X0;        // reference lattice (clamp tangent)
   const double* mass;      // ns*ns
   const double* dV;        // ns*ns IBM volumes
@@ -217,6 +234,11 @@ void launch_point_interp(const Dims& d, const Fields& f, const PointSet& ps, Sca
 void launch_spread_csr(const Dims& d, const Fields& f, const PointSet& ps,
                        const SpreadCSR* csr3, hipStream_t st);
 void launch_point_bbox(const PointSet& ps, int* bbox, hipStream_t st);
+// MLS markers: positions and target velocities from the flag's nodes, the MLS
+// interpolation and forcing, and the node loads from the markers' forcing
+void launch_mls_markers(const MlsDev& m, const double* X, const double* V, const PointSet& ps, hipStream_t st);
+void launch_mls_interp(const Dims& d, const Fields& f, const PointSet& ps, Scalars* s, hipStream_t st);
+void launch_mls_node_load(const MlsDev& m, const PointSet& ps, hipStream_t st);
 void launch_spread_tiles(const Dims& d, const Fields& f, const PointSet& ps, const int* bbox,
                          int ntx, int nty, int ntz, Scalars* s, hipStream_t st);
 

@@ -11,7 +11,8 @@
 //   cell; a clamped edge adds the a = 0 term with the ghost X_1 - 2 ds t0);
 //   springs k_s/2 (|X_p - X_q| - l0)^2 on a-edges, b-edges and the
 //   (a,b)-(a+1,b+1) diagonals, rest lengths of the reference lattice;
-//   load -F dV from the immersed-boundary forcing of the step;
+//   load -F dV from the immersed-boundary forcing of the step (with MLS
+//   markers, the node loads gathered through the barycentric weights);
 //   velocity-Verlet sub-steps, n_sub = ceil(dt / dts_max); a = 0 nodes fixed.
 //
 // Parallel layout: the lattice is cut into bands of spanwise rows, one
@@ -165,7 +166,7 @@ __device__ __forceinline__ void flag_body(const FlagDev& fl, Scalars* s, const i
       const double dV = fl.dV[p];
       for (int c = 0; c < 3; ++c) {
         V[k][c] = fl.V[3 * p + c];
-        fe[k][c] = -fl.Fh[3 * p + c] * dV;
+        fe[k][c] = fl.fnode ? -fl.fnode[3 * p + c] : -fl.Fh[3 * p + c] * dV;
       }
     }
   }

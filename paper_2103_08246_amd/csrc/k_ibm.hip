@@ -1,5 +1,6 @@
 // Direct-forcing immersed boundary (paper Sec. II.B) with the 3-point
-// regularised delta of Roma, Peskin & Berger (1999):
+// regularised delta of Roma, Peskin & Berger (1999) (grid points, flag nodes;
+// the moving-least-squares transfer of the flag's tiling markers further down):
 //   phi(r) = (1 + sqrt(1 - 3 r^2)) / 3                  |r| <= 1/2
 //   phi(r) = (5 - 3|r| - sqrt(1 - 3 (1 - |r|)^2)) / 6   1/2 <= |r| <= 3/2
 // Single pass on the provisional velocity: every point interpolates
@@ -91,6 +92,102 @@ __device__ __forceinline__ void point_interp_body(const Dims& d, const Fields& f
   const double dt = s->dt;
   const double ud = ps.Ud ? ps.Ud[3 * q + comp] : 0.0;
   const double F = (ud - U) / dt;
+  ps.F[3 * q + comp] = F;
+  const double h3 = d.h * d.h * d.h;
+  ps.amount[(size_t)comp * ps.n + q] = dt * F * ps.dV[q] / h3;
+}
+
+// Moving-least-squares transfer (paper Sec. II.B (ii)) at the flag's tiling
+// markers.  Support: the same 3x3x3 nodes around the centre node; weight
+// W_k = w(|xi_x| / R) w(|xi_y| / R) w(|xi_z| / R), xi = (x_k - X) / h, R = 1.5,
+// with the cubic spline w(q) = 2/3 - 4q^2 + 4q^3 (q <= 1/2),
+// 4/3 - 4q + 4q^2 - 4/3 q^3 (q <= 1), 0 beyond; linear basis (1, xi).  The
+// weight is a product over the axes, so the moment matrix is that of three
+// independent coordinates: with per-axis weight sums S_a, means mu_a and
+// variances var_a (S = S_x S_y S_z), the shape functions are
+// phi_k = W_k (a0 + g . xi_k), a0 = (1 + sum mu_a^2 / var_a) / S,
+// g_a = -mu_a / (var_a S): the same A^{-1} e_0 as the general 4 x 4 solve.
+constexpr double MLS_R = 1.5;
+
+__device__ __forceinline__ double mls_spline(double q) {
+  if (q <= 0.5) return 2.0 / 3.0 - 4.0 * q * q + 4.0 * q * q * q;
+  if (q <= 1.0) return 4.0 / 3.0 - 4.0 * q + 4.0 * q * q - (4.0 / 3.0) * q * q * q;
+  return 0.0;
+}
+
+// Centre node, spline factors and tap-0 offsets of every marker for one
+// component, then the shape-function coefficients, the interpolation and the
+// forcing.  Also flags a support that leaves the evolved x range.
+__device__ __forceinline__ void mls_interp_body(const Dims& d, const Fields& f, const PointSet& ps, Scalars* s,
+                                                int bx, int comp) {
+  const int q = bx * 256 + threadIdx.x;
+  if (q >= ps.n) return;
+  int* cen = ps.centre + ((size_t)comp * ps.n + q) * 3;
+  double* wt = ps.wts + ((size_t)comp * ps.n + q) * 9;
+  double* ml = ps.mls + ((size_t)comp * ps.n + q) * 7;
+  double xi0[3], S[3], mu[3], var[3];
+  for (int dir = 0; dir < 3; ++dir) {
+    const double t = (ps.X[3 * q + dir] - origin(comp, dir, d.h)) / d.h;
+    if (!(fabs(t) < 1.0e8)) {  // non-finite or absurd position: park the support off-grid
+      atomicOr(&s->status, (int)ST_NONFINITE);
+      for (int a = 0; a < 3; ++a) cen[a] = -(1 << 28);
+      for (int a = 0; a < 9; ++a) wt[a] = 0.0;
+      for (int a = 0; a < 7; ++a) ml[a] = 0.0;
+      ps.F[3 * q + comp] = 0.0;
+      ps.amount[(size_t)comp * ps.n + q] = 0.0;
+      return;
+    }
+    const int n = (int)floor(t + 0.5);
+    cen[dir] = n;
+    xi0[dir] = (double)(n - 1) - t;
+    double s0 = 0.0, s1 = 0.0;
+    for (int tap = 0; tap < 3; ++tap) {
+      const double xi = xi0[dir] + tap;
+      const double w = mls_spline(fabs(xi) / MLS_R);
+      wt[3 * dir + tap] = w;
+      s0 += w;
+      s1 += w * xi;
+    }
+    S[dir] = s0;
+    mu[dir] = s1 / s0;
+    double s2 = 0.0;
+    for (int tap = 0; tap < 3; ++tap) {
+      const double e = xi0[dir] + tap - mu[dir];
+      s2 += wt[3 * dir + tap] * e * e;
+    }
+    var[dir] = s2 / s0;
+  }
+  const int lo = comp == 0 ? 1 : 0;
+  if (cen[0] - 1 < lo || cen[0] + 1 > d.nx - 1) {
+    atomicOr(&s->status, (int)ST_RANGE);
+    ps.F[3 * q + comp] = 0.0;
+    ps.amount[(size_t)comp * ps.n + q] = 0.0;
+    for (int a = 0; a < 7; ++a) ml[a] = 0.0;
+    return;
+  }
+  const double St = S[0] * S[1] * S[2];
+  const double a0 = (1.0 + mu[0] * mu[0] / var[0] + mu[1] * mu[1] / var[1] + mu[2] * mu[2] / var[2]) / St;
+  const double g[3] = {-mu[0] / (var[0] * St), -mu[1] / (var[1] * St), -mu[2] / (var[2] * St)};
+  for (int a = 0; a < 3; ++a) ml[a] = xi0[a];
+  ml[3] = a0;
+  ml[4] = g[0];
+  ml[5] = g[1];
+  ml[6] = g[2];
+  const double* fld = comp_field<double>(f, comp);
+  double U = 0.0;
+  for (int dk = 0; dk < 3; ++dk) {
+    const int kk = wrap(cen[2] + dk - 1, d.nz);
+    for (int dj = 0; dj < 3; ++dj) {
+      const int jj = wrap(cen[1] + dj - 1, d.ny);
+      for (int di = 0; di < 3; ++di) {
+        const double W = wt[di] * wt[3 + dj] * wt[6 + dk];
+        const double lin = a0 + g[0] * (xi0[0] + di) + g[1] * (xi0[1] + dj) + g[2] * (xi0[2] + dk);
+        U += fld[fidx(d, cen[0] + di - 1, jj, kk)] * (W * lin);
+      }
+    }
+  }
+  const double dt = s->dt;
+  const double F = (ps.Ud[3 * q + comp] - U) / dt;
   ps.F[3 * q + comp] = F;
   const double h3 = d.h * d.h * d.h;
   ps.amount[(size_t)comp * ps.n + q] = dt * F * ps.dV[q] / h3;
@@ -194,7 +291,10 @@ constexpr int TN = TS * TS * TS;    // threads per tile
 // order; eight groups at a time, the points whose support meets the tile are
 // compacted (in increasing order) into LDS, and every thread gathers the
 // contributions to its node in increasing point order.
-template <class T>
+// With MLS (FP64 only) a staged marker carries its spline factors and, folded
+// with its amount, the coefficients of phi = W (a0 + g . xi) in the tap index:
+// amount phi = W (c0 + c . (di, dj, dk)), c0 = amount (a0 + g . xi_tap0), c = amount g.
+template <class T, bool MLS = false>
 __device__ __forceinline__ void spread_tiles_body(const Dims& d, const Fields& f, const PointSet& ps,
                                                   const int* bbox, int ntx, int nty, int ntz, int comp,
                                                   Scalars* s, int bx) {
@@ -219,9 +319,18 @@ __device__ __forceinline__ void spread_tiles_body(const Dims& d, const Fields& f
   __shared__ int4 sc[TN];            // centre node of each staged point
   __shared__ double sw[TN][9];       // its 1-D factors (x, y, z taps)
   __shared__ double sa[TN];          // its amount
+  __shared__ double sg[MLS ? TN : 1][3];   // MLS: amount g
   const int* cenb = ps.centre + (size_t)comp * ps.n * 3;
   const double* wts = ps.wts + (size_t)comp * ps.n * 9;
   const double* amt = ps.amount + (size_t)comp * ps.n;
+  // contribution of staged point e to the node at tap (di, dj, dk)
+  auto contrib = [&](int e, int di, int dj, int dk) -> T {
+    const double W = sw[e][di] * sw[e][3 + dj] * sw[e][6 + dk];
+    if constexpr (MLS)
+      return (T)(W * (sa[e] + sg[e][0] * di + sg[e][1] * dj + sg[e][2] * dk));
+    else
+      return (T)sa[e] * (T)W;
+  };
   T acc = 0;
   for (int gbase = 0; gbase < ng; gbase += TN) {
     // list the groups of this chunk whose support box meets the tile
@@ -269,7 +378,16 @@ __device__ __forceinline__ void spread_tiles_body(const Dims& d, const Fields& f
         sc[e] = make_int4(cx, cy, cz, 0);
         const double* wt = wts + (size_t)q * 9;
         for (int t = 0; t < 9; ++t) sw[e][t] = wt[t];
-        sa[e] = amt[q];
+        if constexpr (MLS) {
+          const double* ml = ps.mls + ((size_t)comp * ps.n + q) * 7;
+          const double am = amt[q];
+          sa[e] = am * (ml[3] + ml[4] * ml[0] + ml[5] * ml[1] + ml[6] * ml[2]);
+          sg[e][0] = am * ml[4];
+          sg[e][1] = am * ml[5];
+          sg[e][2] = am * ml[6];
+        } else {
+          sa[e] = amt[q];
+        }
       }
       __syncthreads();
       int e = 0;
@@ -280,15 +398,13 @@ __device__ __forceinline__ void spread_tiles_body(const Dims& d, const Fields& f
 #pragma unroll
         for (int u = 0; u < 4; ++u) {
           const int di = ni - c[u].x + 1, dj = nj - c[u].y + 1, dk = nk - c[u].z + 1;
-          if ((unsigned)di < 3u && (unsigned)dj < 3u && (unsigned)dk < 3u)
-            acc += (T)sa[e + u] * (T)(sw[e + u][di] * sw[e + u][3 + dj] * sw[e + u][6 + dk]);
+          if ((unsigned)di < 3u && (unsigned)dj < 3u && (unsigned)dk < 3u) acc += contrib(e + u, di, dj, dk);
         }
       }
       for (; e < np; ++e) {
         const int4 c = sc[e];
         const int di = ni - c.x + 1, dj = nj - c.y + 1, dk = nk - c.z + 1;
-        if ((unsigned)di < 3u && (unsigned)dj < 3u && (unsigned)dk < 3u)
-          acc += (T)sa[e] * (T)(sw[e][di] * sw[e][3 + dj] * sw[e][6 + dk]);
+        if ((unsigned)di < 3u && (unsigned)dj < 3u && (unsigned)dk < 3u) acc += contrib(e, di, dj, dk);
       }
       __syncthreads();
     }
@@ -325,6 +441,40 @@ __global__ void __launch_bounds__(TN) k_spread_tiles(Dims d, Fields f, PointSet 
                                                      int nty, int ntz, Scalars* s) {
   const int nt = ntx * nty * ntz;  // one launch for the three components
   spread_tiles_body<T>(d, f, ps, bbox, ntx, nty, ntz, blockIdx.x / nt, s, blockIdx.x % nt);
+}
+
+__global__ void __launch_bounds__(256) k_mls_interp(Dims d, Fields f, PointSet ps, Scalars* s) {
+  mls_interp_body(d, f, ps, s, xcd_remap(blockIdx.x, gridDim.x), blockIdx.y);
+}
+__global__ void __launch_bounds__(TN) k_spread_tiles_mls(Dims d, Fields f, PointSet ps, const int* bbox, int ntx,
+                                                         int nty, int ntz, Scalars* s) {
+  const int nt = ntx * nty * ntz;
+  spread_tiles_body<double, true>(d, f, ps, bbox, ntx, nty, ntz, blockIdx.x / nt, s, blockIdx.x % nt);
+}
+// Marker positions and target velocities: X_m = sum_v beta_v X_v, U^d_m likewise.
+__global__ void __launch_bounds__(256) k_mls_markers(MlsDev m, const double* X, const double* V, PointSet ps) {
+  const int q = blockIdx.x * 256 + threadIdx.x;
+  if (q >= m.m) return;
+  const int v0 = m.tri[3 * q], v1 = m.tri[3 * q + 1], v2 = m.tri[3 * q + 2];
+  const double b0 = m.beta[3 * q], b1 = m.beta[3 * q + 1], b2 = m.beta[3 * q + 2];
+  double* Xm = const_cast<double*>(ps.X);
+  double* Um = const_cast<double*>(ps.Ud);
+  for (int c = 0; c < 3; ++c) {
+    Xm[3 * q + c] = b0 * X[3 * v0 + c] + b1 * X[3 * v1 + c] + b2 * X[3 * v2 + c];
+    Um[3 * q + c] = b0 * V[3 * v0 + c] + b1 * V[3 * v1 + c] + b2 * V[3 * v2 + c];
+  }
+}
+// Node loads: fnode_v = sum over the markers touching v (increasing) of beta (F dV).
+__global__ void __launch_bounds__(256) k_mls_node_load(MlsDev m, PointSet ps) {
+  const int v = blockIdx.x * 256 + threadIdx.x;
+  if (v >= m.n) return;
+  double acc[3] = {0.0, 0.0, 0.0};
+  for (int e = m.node_ptr[v]; e < m.node_ptr[v + 1]; ++e) {
+    const int code = m.node_ent[e], q = code / 3, slot = code % 3;
+    const double b = m.beta[3 * q + slot], dv = ps.dV[q];
+    for (int c = 0; c < 3; ++c) acc[c] += b * (ps.F[3 * q + c] * dv);
+  }
+  for (int c = 0; c < 3; ++c) m.fnode[3 * v + c] = acc[c];
 }
 
 // ---- batched forms: run r owns [off[r], off[r+1]) blocks ----
@@ -439,11 +589,26 @@ void launch_point_bbox(const PointSet& ps, int* bbox, hipStream_t st) {
   hipLaunchKernelGGL(k_point_bbox, dim3(3), dim3(BBT), 0, st, ps, bbox);
 }
 
+void launch_mls_markers(const MlsDev& m, const double* X, const double* V, const PointSet& ps, hipStream_t st) {
+  if (m.m == 0) return;
+  hipLaunchKernelGGL(k_mls_markers, dim3((m.m + 255) / 256), dim3(256), 0, st, m, X, V, ps);
+}
+void launch_mls_interp(const Dims& d, const Fields& f, const PointSet& ps, Scalars* s, hipStream_t st) {
+  if (ps.n == 0) return;
+  hipLaunchKernelGGL(k_mls_interp, dim3((ps.n + 255) / 256, 3), dim3(256), 0, st, d, f, ps, s);
+}
+void launch_mls_node_load(const MlsDev& m, const PointSet& ps, hipStream_t st) {
+  if (m.n == 0) return;
+  hipLaunchKernelGGL(k_mls_node_load, dim3((m.n + 255) / 256), dim3(256), 0, st, m, ps);
+}
+
 void launch_spread_tiles(const Dims& d, const Fields& f, const PointSet& ps, const int* bbox,
                          int ntx, int nty, int ntz, Scalars* s, hipStream_t st) {
   if (ps.n == 0) return;
   const dim3 grid(3 * ntx * nty * ntz);
-  if (d.mixed)
+  if (ps.mls)
+    hipLaunchKernelGGL(k_spread_tiles_mls, grid, dim3(TN), 0, st, d, f, ps, bbox, ntx, nty, ntz, s);
+  else if (d.mixed)
     hipLaunchKernelGGL(k_spread_tiles<float>, grid, dim3(TN), 0, st, d, f, ps, bbox, ntx, nty, ntz, s);
   else
     hipLaunchKernelGGL(k_spread_tiles<double>, grid, dim3(TN), 0, st, d, f, ps, bbox, ntx, nty, ntz, s);

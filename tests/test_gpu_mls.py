@@ -1,0 +1,126 @@
+"""MLS transfer at the flag's tiling markers (Sec. II.B (ii) and the tiling
+paragraph of Sec. II.B) on the GPU against the oracle (oracle/mls.py): the
+marker table, one immersed-boundary stage, coupled steps, the node loads,
+and the state and mode rules."""
+import numpy as np
+import pytest
+
+import synth
+from tests.gpu_cases import oracle_flag_args, rel_l2
+from tests.test_gpu_parity import small_grid_flag
+
+pytestmark = pytest.mark.gpu
+ib = pytest.importorskip("paper_2103_08246_amd")
+
+
+def _pair(w, bars=True):
+    from oracle.solver import Solver
+    noise = synth.ic_noise(w)
+    pts = synth.bar_points(w) if (bars and w.grid is not None) else None
+    X0 = synth.flag_reference(w)
+    run = ib.create(ib.domain_from(w), noise, points=pts, flag=ib.flag_from(w.flag), flag_X0=X0,
+                    flag_mls=True)
+    S = Solver(w, noise, pts, dict(oracle_flag_args(w, X0), coupling="mls"))
+    return run, S
+
+
+@pytest.mark.parametrize("make,level", [(synth.flag_64_re200, 1), (small_grid_flag, 1)])
+def test_marker_table_matches_oracle(make, level):
+    from oracle import mls
+    w = make()
+    run, S = _pair(w, bars=False)
+    try:
+        tri, beta, dV, X, F = run.flag_markers()
+        otri, obeta, odV, olev = mls.build_markers(synth.flag_reference(w), w.lx / w.nx)
+        assert np.all(olev == level)
+        assert tri.shape == otri.shape and np.array_equal(tri, otri)
+        assert np.array_equal(beta, obeta)                       # dyadic sums / 3 on both sides
+        assert np.max(np.abs(dV - odV)) <= 1e-15 * np.max(odV)
+    finally:
+        run.close()
+
+
+def test_ibm_stage_matches_oracle():
+    w = small_grid_flag()
+    run, S = _pair(w)
+    try:
+        for st in (ib.STAGE_PREDICT, ib.STAGE_FLUX, ib.STAGE_IBM):
+            ib.run_stage(run.ctx, st)
+        ut, vt, wt, _ = S.stage_predict()
+        S.stage_ibm(ut, vt, wt)
+        nx = w.nx
+        gu = ib.get_array(run.ctx, ib.ARR_UT, (w.nz, w.ny, nx + 1))
+        gv = ib.get_array(run.ctx, ib.ARR_VT, (w.nz, w.ny, nx))
+        gw = ib.get_array(run.ctx, ib.ARR_WT, (w.nz, w.ny, nx))
+        assert rel_l2([gu[..., 1:nx], gv, gw], [ut[..., 1:nx], vt[..., :nx], wt[..., :nx]]) < 1e-13
+        _, _, _, Xm, Fm = run.flag_markers()
+        from oracle import mls
+        oXm, _ = mls.marker_state(S.mls["tri"], S.mls["beta"], S.X, S.V)
+        assert np.max(np.abs(Xm - oXm)) < 1e-14
+        assert np.max(np.abs(Fm - S.F_flag)) <= 1e-11 * np.max(np.abs(S.F_flag))
+        assert np.max(np.abs(S.F_flag)) > 1.0                     # the markers are really forced
+    finally:
+        run.close()
+
+
+@pytest.mark.parametrize("make", [synth.flag_64_re200, small_grid_flag])
+def test_mls_steps_match_oracle(make):
+    from oracle import mls
+    w = make()
+    run, S = _pair(w)
+    try:
+        for _ in range(10):
+            run.step(1)
+            S.step(1)
+        u, v, ww, p, t, k = run.fields()
+        uo, vo, wo, po = S.fields()
+        assert rel_l2([u, v, ww], [uo, vo, wo]) < 1e-12
+        X, V, Fn = run.flag()
+        assert rel_l2([X], [S.X.reshape(X.shape)]) < 1e-13
+        assert ib.get_scalars(run.ctx)["nsub"] == S.nsub
+        # node loads of the last step: sum beta F dV through the same markers.  F =
+        # (U^d - U~)/dt is a small difference of O(1) velocities: the 1e-13 agreement
+        # of the fields after 10 steps becomes ~1e-13/dt in F, 1e-10 of its scale
+        M = S.mls
+        want = -mls.node_load(M["tri"], M["beta"], S.F_flag, M["dV"], S.X.shape[0])
+        assert np.max(np.abs(Fn.reshape(-1, 3) - want)) <= 1e-10 * np.max(np.abs(want))
+    finally:
+        run.close()
+
+
+def test_mls_rules():
+    w = small_grid_flag()
+    noise = synth.ic_noise(w)
+    X0 = synth.flag_reference(w)
+    with pytest.raises(ib.IbdnsError) as e:        # FP64 only
+        ib.create(ib.domain_from(w, precision=ib.MIXED), noise, flag=ib.flag_from(w.flag), flag_X0=X0,
+                  flag_mls=True)
+    assert e.value.code == ib.EINVAL
+    plain = ib.create(ib.domain_from(w), noise)
+    try:
+        with pytest.raises(ib.IbdnsError) as e:    # no flag
+            plain.set_flag_mls()
+        assert e.value.code == ib.ESTATE
+        with pytest.raises(ib.IbdnsError) as e:
+            plain.flag_markers()
+        assert e.value.code == ib.ESTATE
+    finally:
+        plain.close()
+    run = ib.create(ib.domain_from(w), noise, flag=ib.flag_from(w.flag), flag_X0=X0, flag_mls=True)
+    try:
+        with pytest.raises(ib.IbdnsError) as e:    # once
+            run.set_flag_mls()
+        assert e.value.code == ib.ESTATE
+        with pytest.raises(ib.IbdnsError) as e:    # batches couple flags at their nodes
+            ib.Batch([run])
+        assert e.value.code == ib.EINVAL
+    finally:
+        run.close()
+    late = ib.create(ib.domain_from(w), noise, flag=ib.flag_from(w.flag), flag_X0=X0)
+    try:
+        late.step(1)
+        with pytest.raises(ib.IbdnsError) as e:    # before the first step only
+            late.set_flag_mls()
+        assert e.value.code == ib.ESTATE
+    finally:
+        late.close()
