@@ -155,6 +155,8 @@ def main():
     ap.add_argument("--no-batch", action="store_true")
     ap.add_argument("--no-eulerian", action="store_true")
     ap.add_argument("--no-cn", action="store_true")
+    ap.add_argument("--no-mls", action="store_true")
+    ap.add_argument("--no-paper-scheme", action="store_true")
     ap.add_argument("--batch-steps", type=int, default=20)
     ap.add_argument("--copy-calib", action="store_true",
                     help="also run a plain device copy of 1 GiB (calibrates HBM counters)")
@@ -174,15 +176,16 @@ def main():
     bars = synth.bar_points(w) if w.grid is not None else None
     X0 = synth.flag_reference(w) if w.flag is not None else None
 
-    def measure(precision, breakdown, eulerian=False, diffusion=0):
+    def measure(precision, breakdown, eulerian=False, diffusion=0, mls=False):
         """Timed region: args.steps steps with HIP events around the predictor
         only (two per step).  breakdown: then as many steps again with events
         around every kernel, for the per-kernel table (not the value).
-        eulerian: the grid forced at its nodes instead of as points."""
+        eulerian: the grid forced at its nodes instead of as points; mls: the
+        flag coupled at its tiling markers by MLS instead of at its nodes."""
         run = ib.create(ib.domain_from(w, precision=precision, diffusion=diffusion), noise,
                         points=None if eulerian else bars,
                         flag=ib.flag_from(w.flag) if w.flag is not None else None, flag_X0=X0,
-                        grid_forcing=w.grid if eulerian else None)
+                        grid_forcing=w.grid if eulerian else None, flag_mls=mls and w.flag is not None)
         run.variant = ib.autotune(run.ctx)   # predictor tile shape, picked by timing
         run.step(args.warmup)
         ib.sync(run.ctx)
@@ -304,6 +307,37 @@ def main():
                                 "note": "FP64, grid forced at its velocity nodes, flag by delta markers"}
         print(f"# eulerian grid: {wall_e * 1e3 / args.steps:.3f} ms/step", file=sys.stderr, flush=True)
         run_e.close()
+    flag_keys = ("flag_markers", "flag_interp", "flag_node_load", "flag_bbox", "flag_spread", "flag_step")
+    if w.flag is not None and not args.no_mls:
+        # the paper's flag coupling (Sec. II.B (ii)): MLS transfer at the markers of
+        # the adaptive tiling instead of the delta at the nodes
+        run_l, wall_l, _, times_l = measure(ib.FP64, True, mls=True)
+        a = run.fields()
+        b = run_l.fields()
+        out["flag_mls"] = {"value": round(w.cells * args.steps / wall_l / 1e6, 1),
+                           "ms_per_step": round(wall_l * 1e3 / args.steps, 4),
+                           "markers": int(run_l.n_markers), "nodes": int(w.flag.ns ** 2),
+                           "kernel_avg_ms": {k: round(v[0] / max(v[1], 1), 4) for k, v in
+                                             sorted(times_l["all"].items(), key=lambda kv: -kv[1][0])
+                                             if k in flag_keys},
+                           "node_coupling_kernel_avg_ms": {k: round(v[0] / max(v[1], 1), 4) for k, v in
+                                                           sorted(times["all"].items(), key=lambda kv: -kv[1][0])
+                                                           if k in flag_keys},
+                           "vel_rel_l2_vs_nodes": (sum(float(np.sum((x - y) ** 2)) for x, y in zip(b[:3], a[:3]))
+                                                   / sum(float(np.sum(y ** 2)) for y in a[:3])) ** 0.5,
+                           "note": "FP64; grid by delta points, flag by MLS at its tiling markers"}
+        print(f"# flag mls: {wall_l * 1e3 / args.steps:.3f} ms/step", file=sys.stderr, flush=True)
+        run_l.close()
+    if w.flag is not None and w.grid is not None and not args.no_paper_scheme:
+        # all three of the paper's choices together (Sec. II.B): Eulerian grid
+        # forcing, MLS flag markers, Crank-Nicolson with approximate factorisation
+        run_p, wall_p, _, times_p = measure(ib.FP64, False, eulerian=True, diffusion=ib.DIFFUSION_CN, mls=True)
+        out["paper_scheme"] = {"value": round(w.cells * args.steps / wall_p / 1e6, 1),
+                               "ms_per_step": round(wall_p * 1e3 / args.steps, 4),
+                               "note": "FP64; Eulerian grid forcing + MLS flag markers + Crank-Nicolson "
+                                       "with approximate factorisation"}
+        print(f"# paper scheme: {wall_p * 1e3 / args.steps:.3f} ms/step", file=sys.stderr, flush=True)
+        run_p.close()
     if not args.no_cn:
         # the paper's diffusion scheme (Sec. II.B): Crank-Nicolson with approximate
         # factorisation, same workload and CFL step
