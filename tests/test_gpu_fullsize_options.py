@@ -1,0 +1,144 @@
+"""The paper's own scheme options at the full size (768 x 384 x 384, grid bars
+and a 96 x 96 flag) in the launch configuration bench.py times: Crank-Nicolson
+with approximate factorisation (Sec. II.B) and MLS at the flag's tiling
+markers (Sec. II.B (ii)).
+
+The oracle cannot step this size in test time, so:
+* CN: on x-slabs, the factored operator (1 - b Dx)(1 - b Dy)(1 - b Dz)
+  applied to the GPU's increment gives back the oracle's right-hand side
+  (a local identity that holds at any size);
+* MLS: the marker table bit for bit, every marker's forcing against the
+  oracle's MLS interpolation of the GPU's provisional field, and after whole
+  steps the force balance between markers and nodes;
+* both: divergence at machine level, outflow = inflow, finite fields.
+"""
+import numpy as np
+import pytest
+
+import synth
+from tests.gpu_cases import rel_l2
+
+pytestmark = pytest.mark.gpu
+ib = pytest.importorskip("paper_2103_08246_amd")
+
+
+def _create(**kw):
+    w = synth.grid_flag_768_re1000()
+    X0 = synth.flag_reference(w)
+    bars = synth.bar_points(w)
+    diffusion = kw.pop("diffusion", ib.DIFFUSION_EXPLICIT)
+    run = ib.create(ib.domain_from(w, diffusion=diffusion), synth.ic_noise(w), points=bars,
+                    flag=ib.flag_from(w.flag), flag_X0=X0, **kw)
+    return w, run, X0
+
+
+def _step_properties(w, run):
+    from oracle import fluid
+    run.step(3)
+    u, v, ww, p, t, k = run.fields()
+    assert np.all(np.isfinite(u)) and np.all(np.isfinite(v)) and np.all(np.isfinite(ww))
+    vg = ib.get_array(run.ctx, ib.ARR_V_GHOST, (w.nz, w.ny))
+    wg = ib.get_array(run.ctx, ib.ARR_W_GHOST, (w.nz, w.ny))
+    div = fluid.divergence(u, np.concatenate([v, vg[..., None]], 2),
+                           np.concatenate([ww, wg[..., None]], 2), w.h)
+    assert np.max(np.abs(div)) < 1e-10
+    assert abs(np.sum(u[..., -1]) - np.sum(u[..., 0])) < 1e-12 * u[..., 0].size
+
+
+@pytest.fixture(scope="module")
+def cn_full():
+    w, run, X0 = _create(diffusion=ib.DIFFUSION_CN)
+    yield w, run
+    run.close()
+
+
+def test_cn_factored_operator_on_slabs(cn_full):
+    from oracle import fluid
+    w, run = cn_full
+    nx, ny, nz, h = w.nx, w.ny, w.nz, w.h
+    nu = 1.0 / w.re
+    u, v, ww, p, _, _ = run.fields()
+    vg = ib.get_array(run.ctx, ib.ARR_V_GHOST, (nz, ny))
+    wg = ib.get_array(run.ctx, ib.ARR_W_GHOST, (nz, ny))
+    dt = ib.get_scalars(run.ctx)["dt"]
+    ib.run_stage(run.ctx, ib.STAGE_PREDICT)       # first step: Euler, H^{n-1} := H^n
+    ut = ib.get_array(run.ctx, ib.ARR_UT, (nz, ny, nx + 1))
+    vt = ib.get_array(run.ctx, ib.ARR_VT, (nz, ny, nx))
+    wt = ib.get_array(run.ctx, ib.ARR_WT, (nz, ny, nx))
+    r = 0.5 * nu * dt / h ** 2
+
+    def yz(a):
+        for ax in (1, 0):
+            a = (1 + 2 * r) * a - r * (np.roll(a, 1, ax) + np.roll(a, -1, ax))
+        return a
+
+    for i0, n in ((4, 24), (200, 20), (500, 20)):   # bars, flag, mid-domain
+        hi = i0 + n
+        F = fluid.Fields(u=u[..., i0:hi + 1], v=v[..., i0:hi + 1], w=ww[..., i0:hi + 1], p=p[..., i0:hi])
+        Hc = fluid.rhs(F, h, 0.0)
+        D = fluid.rhs(F, h, nu, advection=False)
+        pp = p[..., i0 - 1:hi]                       # one more cell for the u-face gradient
+        gp = ((pp[..., 1:] - pp[..., :-1]) / h,
+              (p[..., i0:hi] - np.roll(p[..., i0:hi], 1, 1)) / h,
+              (p[..., i0:hi] - np.roll(p[..., i0:hi], 1, 0)) / h)
+        for c, (st, tl) in enumerate(((u, ut), (v, vt), (ww, wt))):
+            du = tl[..., i0:hi] - st[..., i0:hi]
+            a = (1 + 2 * r) * du[..., 1:-1] - r * (du[..., 2:] + du[..., :-2])   # x factor, interior
+            a = yz(a)
+            rhs = dt * (Hc[c][..., 1:n - 1] - gp[c][..., 1:n - 1] + D[c][..., 1:n - 1])
+            assert rel_l2([a[..., 1:-1]], [rhs[..., 1:-1]]) < 1e-12, (i0, c)
+
+
+def test_cn_steps_properties(cn_full):
+    w, run = cn_full
+    _step_properties(w, run)
+
+
+@pytest.fixture(scope="module")
+def mls_full():
+    w, run, X0 = _create(flag_mls=True)
+    yield w, run, X0
+    run.close()
+
+
+def test_mls_marker_table(mls_full):
+    from oracle import mls
+    w, run, X0 = mls_full
+    tri, beta, dV, _, _ = run.flag_markers()
+    otri, obeta, odV, olev = mls.build_markers(X0, w.h)
+    assert tri.shape[0] == 2 * (w.flag.ns - 1) ** 2 and np.all(olev == 0)
+    assert np.array_equal(tri, otri) and np.array_equal(beta, obeta)
+    assert np.max(np.abs(dV - odV)) <= 1e-15 * np.max(odV)
+
+
+def test_mls_forcing_matches_oracle(mls_full):
+    from oracle import mls
+    w, run, X0 = mls_full
+    nx, ny, nz = w.nx, w.ny, w.nz
+    for st in (ib.STAGE_PREDICT, ib.STAGE_FLUX):
+        ib.run_stage(run.ctx, st)
+    ut = ib.get_array(run.ctx, ib.ARR_UT, (nz, ny, nx + 1))
+    vt = ib.get_array(run.ctx, ib.ARR_VT, (nz, ny, nx))
+    wt = ib.get_array(run.ctx, ib.ARR_WT, (nz, ny, nx))
+    X, V, _ = run.flag()
+    ib.run_stage(run.ctx, ib.STAGE_IBM)
+    tri, beta, dV, Xm, Fm = run.flag_markers()
+    oXm, oVm = mls.marker_state(tri.astype(np.int64), beta, X.reshape(-1, 3), V.reshape(-1, 3))
+    assert np.max(np.abs(Xm - oXm)) < 1e-14
+    dt = ib.get_scalars(run.ctx)["dt"]
+    F, _ = mls.mls_interp((ut, vt, wt), oXm, oVm, w.h, dt, nx)
+    assert np.max(np.abs(Fm - F)) <= 1e-12 * np.max(np.abs(F))
+
+
+def test_mls_steps_properties(mls_full):
+    w, run, X0 = mls_full
+    _step_properties(w, run)
+    _, _, dV, _, Fm = run.flag_markers()
+    X, V, Fn = run.flag()
+    assert np.all(np.isfinite(Fm)) and np.all(np.isfinite(X))
+    # the nodes carry exactly the markers' force (sum_v beta_mv = 1)
+    tot = np.sum(Fm * dV[:, None], axis=0)
+    assert np.max(np.abs(Fn.reshape(-1, 3).sum(axis=0) - tot)) <= 1e-12 * np.sum(np.abs(Fm * dV[:, None]))
+    d = X[:, 1:] - X[:, :-1]
+    strain = np.abs(np.sqrt(np.sum(d * d, -1)) / (w.flag.length / (w.flag.ns - 1)) - 1)
+    assert np.max(strain) < 5e-3
