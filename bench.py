@@ -359,6 +359,21 @@ def main():
                                        / sum(float(np.sum(y ** 2)) for y in a[:3])) ** 0.5,
             "note": "FP64; z, y, x factored solves per component (z, y: thread per line; x: LDS tiles of 64 lines)"}
         print(f"# crank-nicolson: {wall_c * 1e3 / args.steps:.3f} ms/step", file=sys.stderr, flush=True)
+        if not args.no_mixed:
+            # mixed form: FP32 right-hand side and increments between the sweeps
+            run_cm, wall_cm, _, times_cm = measure(ib.MIXED, True, diffusion=ib.DIFFUSION_CN)
+            bm = run_cm.fields()
+            sw = times_cm["all"].get("cn_sweeps", (0.0, 1))
+            sw_ms = sw[0] / max(sw[1], 1)
+            out["crank_nicolson"]["mixed"] = {
+                "value": round(w.cells * args.steps / wall_cm / 1e6, 1),
+                "ms_per_step": round(wall_cm * 1e3 / args.steps, 4),
+                "speedup_vs_fp64_cn": round(wall_c / wall_cm, 3),
+                "cn_sweeps_ms": round(sw_ms, 4),
+                "vel_rel_l2_vs_fp64_cn": (sum(float(np.sum((x - y) ** 2)) for x, y in zip(bm[:3], b[:3]))
+                                          / sum(float(np.sum(y ** 2)) for y in b[:3])) ** 0.5}
+            print(f"# crank-nicolson mixed: {wall_cm * 1e3 / args.steps:.3f} ms/step", file=sys.stderr, flush=True)
+            run_cm.close()
         run_c.close()
     del noise
     run.close()

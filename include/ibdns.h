@@ -87,7 +87,10 @@ typedef struct {
  * then x), the x factor carrying the boundary increments: u: du_0 = 0,
  * du_nx = outflow value - u^n_nx; v, w: inlet ghost du_{-1} = -du_0, outlet
  * ghost increment outflow value - u^n_nx (zero-gradient at both ends under
- * the test hook).  FP64 only (EINVAL with IBDNS_MIXED); batches refuse it. */
+ * the test hook).  With IBDNS_MIXED the right-hand side comes from the FP32
+ * predictor and the increment is stored in FP32 between the sweeps (the
+ * provisional-velocity arrays); every recurrence runs in FP64.  Batches
+ * refuse it. */
 enum { IBDNS_DIFFUSION_EXPLICIT = 0, IBDNS_DIFFUSION_CN = 1 };
 
 /* Flag (Sec. II.A: square of side L, mass ratio rho, bending coefficient beta,

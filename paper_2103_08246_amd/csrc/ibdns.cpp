@@ -173,7 +173,6 @@ int validate(const ibdns_domain* d) {
   if (d->dt <= 0 && !(d->cfl > 0 && d->cfl < 1)) return IBDNS_EINVAL;
   if (d->precision != IBDNS_FP64 && d->precision != IBDNS_MIXED) return IBDNS_EINVAL;
   if (d->diffusion != IBDNS_DIFFUSION_EXPLICIT && d->diffusion != IBDNS_DIFFUSION_CN) return IBDNS_EINVAL;
-  if (d->diffusion == IBDNS_DIFFUSION_CN && d->precision != IBDNS_FP64) return IBDNS_EINVAL;
   if ((long long)row_pitch(*d) * d->ny * d->nz >= (1LL << 31)) return IBDNS_EINVAL;
   return IBDNS_OK;
 }

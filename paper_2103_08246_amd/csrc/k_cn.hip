@@ -123,8 +123,11 @@ __global__ void k_cn_tables(Dims d, const Scalars* __restrict__ s, CnTables t) {
   }
 }
 
-__device__ __forceinline__ double* cn_field(const Fields& f, int comp) {
-  return comp == 0 ? f.ut : (comp == 1 ? f.vt : f.wt);
+// The increment lives in the provisional-velocity arrays, stored as T (FP32
+// in mixed precision); every recurrence runs in FP64.
+template <class T>
+__device__ __forceinline__ T* cn_field(const Fields& f, int comp) {
+  return reinterpret_cast<T*>(comp == 0 ? f.ut : (comp == 1 ? f.vt : f.wt));
 }
 
 // Cyclic solve along y (axis 1) or z (axis 2) of every line of component comp
@@ -133,7 +136,7 @@ __device__ __forceinline__ double* cn_field(const Fields& f, int comp) {
 // substitution, which writes the corrected solution y - fac q directly.  The
 // four tables of the axis sit in LDS (4 n doubles; n <= 768, the largest
 // transform size, so at most 24 KiB).
-template <int AXIS>
+template <int AXIS, class T>
 __global__ void __launch_bounds__(256) k_cn_periodic(Dims d, Fields f, CnTables t, int comp) {
   const int ilo = comp == 0 ? 1 : 0, nxe = comp == 0 ? d.nx - 1 : d.nx;
   const long long g = (long long)blockIdx.x * 256 + threadIdx.x;
@@ -142,7 +145,7 @@ __global__ void __launch_bounds__(256) k_cn_periodic(Dims d, Fields f, CnTables 
   const long long gl = min(g, (long long)nxe * other - 1);   // threads past the end leave after the sync
   const int i = ilo + (int)(gl % nxe), o = (int)(gl / nxe);
   const long long stride = AXIS == 1 ? (long long)d.P : d.PS;
-  double* a = cn_field(f, comp) + (AXIS == 1 ? fidx(d, i, 0, o) : fidx(d, i, o, 0));
+  T* a = cn_field<T>(f, comp) + (AXIS == 1 ? fidx(d, i, 0, o) : fidx(d, i, o, 0));
   extern __shared__ double lt[];   // m, w, c', q
   {
     const double* gm = AXIS == 1 ? t.y_m : t.z_m;
@@ -165,17 +168,17 @@ __global__ void __launch_bounds__(256) k_cn_periodic(Dims d, Fields f, CnTables 
   const double r = t.sc[0], vr = t.sc[AXIS == 1 ? 1 : 3], inv = t.sc[AXIS == 1 ? 2 : 4];
   double prev = 0.0, y0 = 0.0;
   for (int k = 0; k < n; ++k) {          // forward: d'_k = (d_k + r d'_{k-1}) / pivot_k
-    const double v = a[k * stride];
+    const double v = (double)a[k * stride];
     y0 += w[k] * v;
     prev = (v + r * prev) * m[k];
-    a[k * stride] = prev;
+    a[k * stride] = (T)prev;
   }
   const double ylast = prev;
   const double fac = (y0 + vr * ylast) * inv;      // (v.y) / (1 + v.q)
-  a[(n - 1) * stride] = ylast - fac * q[n - 1];
+  a[(n - 1) * stride] = (T)(ylast - fac * q[n - 1]);
   for (int k = n - 2; k >= 0; --k) {     // backward: y_k = d'_k - c'_k y_{k+1}
-    prev = a[k * stride] - cp[k] * prev;
-    a[k * stride] = prev - fac * q[k];
+    prev = (double)a[k * stride] - cp[k] * prev;
+    a[k * stride] = (T)(prev - fac * q[k]);
   }
 }
 
@@ -193,10 +196,11 @@ __device__ __forceinline__ void cn_wave_sync() {
 // batches of 16 instructions (line and column indexes clamped into range);
 // only the stores are guarded.
 constexpr int XT = 32;
+template <class T>
 __global__ void __launch_bounds__(64) k_cn_x(Dims d, Fields f, CnTables t, int comp) {
   constexpr int RPL = 64 / XT, NLD = 64 / RPL, B = 16, LD = XT + 1;
   static_assert(NLD % B == 0, "batch");
-  __shared__ double T[64 * LD];
+  __shared__ double tl[64 * LD];
   __shared__ long long RB[64];   // field offset of x index ilo on each line
   const int lane = threadIdx.x;
   const long long nl = (long long)d.ny * d.nz;
@@ -205,7 +209,7 @@ __global__ void __launch_bounds__(64) k_cn_x(Dims d, Fields f, CnTables t, int c
   const bool neumann = comp > 0 && (d.flags & 1u) != 0;
   const int ilo = comp == 0 ? 1 : 0, n = comp == 0 ? d.nx - 1 : d.nx;
   const double* st = comp == 0 ? f.u : (comp == 1 ? f.v : f.w);
-  double* fa = cn_field(f, comp);
+  T* fa = cn_field<T>(f, comp);
   const double* cp = comp == 0 ? t.xu_cp : t.xv_cp;
   const double* m = comp == 0 ? t.xu_m : t.xv_m;
   const double r = t.sc[0];
@@ -223,9 +227,9 @@ __global__ void __launch_bounds__(64) k_cn_x(Dims d, Fields f, CnTables t, int c
     for (int b0 = 0; b0 < NLD; b0 += B) {
       double v[B];
 #pragma unroll
-      for (int q = 0; q < B; ++q) v[q] = fa[RB[(b0 + q) * RPL + sub] + x0 + cc];
+      for (int q = 0; q < B; ++q) v[q] = (double)fa[RB[(b0 + q) * RPL + sub] + x0 + cc];
 #pragma unroll
-      for (int q = 0; q < B; ++q) T[((b0 + q) * RPL + sub) * LD + col] = v[q];
+      for (int q = 0; q < B; ++q) tl[((b0 + q) * RPL + sub) * LD + col] = v[q];
     }
   };
   const int ntile = (n + XT - 1) / XT;
@@ -237,16 +241,16 @@ __global__ void __launch_bounds__(64) k_cn_x(Dims d, Fields f, CnTables t, int c
     cn_wave_sync();
     if (lane < nrow) {
       for (int x = 0; x < wt; ++x) {
-        double rhs = T[lane * LD + x];
+        double rhs = tl[lane * LD + x];
         if (x0 + x == n - 1) rhs += r * dout;
         prev = (rhs + r * prev) * m[x0 + x];
-        T[lane * LD + x] = prev;
+        tl[lane * LD + x] = prev;
       }
     }
     cn_wave_sync();
     for (int q = 0; q < NLD; ++q) {
       const int row = q * RPL + sub;
-      if (row < nrow && col < wt) fa[RB[row] + x0 + col] = T[row * LD + col];
+      if (row < nrow && col < wt) fa[RB[row] + x0 + col] = (T)tl[row * LD + col];
     }
     cn_wave_sync();
   }
@@ -258,8 +262,8 @@ __global__ void __launch_bounds__(64) k_cn_x(Dims d, Fields f, CnTables t, int c
     if (lane < nrow) {
       for (int x = wt - 1; x >= 0; --x) {
         const int xi = x0 + x;
-        if (xi < n - 1) prev = T[lane * LD + x] - cp[xi] * prev;   // xi = n-1: prev = d'_{n-1}
-        T[lane * LD + x] = prev;
+        if (xi < n - 1) prev = tl[lane * LD + x] - cp[xi] * prev;   // xi = n-1: prev = d'_{n-1}
+        tl[lane * LD + x] = prev;
       }
     }
     cn_wave_sync();
@@ -271,27 +275,35 @@ __global__ void __launch_bounds__(64) k_cn_x(Dims d, Fields f, CnTables t, int c
 #pragma unroll
       for (int q = 0; q < B; ++q) {
         const int row = (b0 + q) * RPL + sub;
-        if (row < nrow && col < wt) fa[RB[row] + x0 + col] = v[q] + T[row * LD + col];
+        if (row < nrow && col < wt) fa[RB[row] + x0 + col] = (T)(v[q] + tl[row * LD + col]);
       }
     }
     cn_wave_sync();
   }
 }
 
-}  // namespace
-
-void launch_cn(const Dims& d, const Fields& f, const Scalars* s, const CnTables& t, hipStream_t st) {
+template <class T>
+void launch_cn_t(const Dims& d, const Fields& f, const Scalars* s, const CnTables& t, hipStream_t st) {
   hipLaunchKernelGGL(k_cn_tables, dim3(5), dim3(64), 0, st, d, s, t);
   for (int comp = 0; comp < 3; ++comp) {
     const int nxe = comp == 0 ? d.nx - 1 : d.nx;
     const long long nz_lines = (long long)nxe * d.ny, ny_lines = (long long)nxe * d.nz;
-    hipLaunchKernelGGL(k_cn_periodic<2>, dim3((unsigned)((nz_lines + 255) / 256)), dim3(256),
+    hipLaunchKernelGGL((k_cn_periodic<2, T>), dim3((unsigned)((nz_lines + 255) / 256)), dim3(256),
                        4 * sizeof(double) * d.nz, st, d, f, t, comp);
-    hipLaunchKernelGGL(k_cn_periodic<1>, dim3((unsigned)((ny_lines + 255) / 256)), dim3(256),
+    hipLaunchKernelGGL((k_cn_periodic<1, T>), dim3((unsigned)((ny_lines + 255) / 256)), dim3(256),
                        4 * sizeof(double) * d.ny, st, d, f, t, comp);
     const long long nl = (long long)d.ny * d.nz;
-    hipLaunchKernelGGL(k_cn_x, dim3((unsigned)((nl + 63) / 64)), dim3(64), 0, st, d, f, t, comp);
+    hipLaunchKernelGGL(k_cn_x<T>, dim3((unsigned)((nl + 63) / 64)), dim3(64), 0, st, d, f, t, comp);
   }
+}
+
+}  // namespace
+
+void launch_cn(const Dims& d, const Fields& f, const Scalars* s, const CnTables& t, hipStream_t st) {
+  if (d.mixed)
+    launch_cn_t<float>(d, f, s, t, st);
+  else
+    launch_cn_t<double>(d, f, s, t, st);
 }
 
 }  // namespace ibdns
