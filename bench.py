@@ -338,6 +338,13 @@ def main():
                                        "with approximate factorisation"}
         print(f"# paper scheme: {wall_p * 1e3 / args.steps:.3f} ms/step", file=sys.stderr, flush=True)
         run_p.close()
+        if not args.no_mixed:
+            run_pm, wall_pm, _, _ = measure(ib.MIXED, False, eulerian=True, diffusion=ib.DIFFUSION_CN, mls=True)
+            out["paper_scheme"]["mixed"] = {"value": round(w.cells * args.steps / wall_pm / 1e6, 1),
+                                            "ms_per_step": round(wall_pm * 1e3 / args.steps, 4),
+                                            "speedup_vs_fp64": round(wall_p / wall_pm, 3)}
+            print(f"# paper scheme mixed: {wall_pm * 1e3 / args.steps:.3f} ms/step", file=sys.stderr, flush=True)
+            run_pm.close()
     if not args.no_cn:
         # the paper's diffusion scheme (Sec. II.B): Crank-Nicolson with approximate
         # factorisation, same workload and CFL step

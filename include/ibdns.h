@@ -225,7 +225,9 @@ int ibdns_get_grid_forcing(ibdns_ctx* ctx, int32_t comp, int64_t* count, int64_t
  * F_m = (U^d_m - U~_m)/dt, spreading u~_k += dt F_m dV_m phi_k / h^3 (all
  * markers read the unforced field; spreading after the grid's points, in
  * increasing marker order).  The flag's load: node v takes
- * -sum_m beta_mv F_m dV_m.  FP64 only; batches refuse such runs.
+ * -sum_m beta_mv F_m dV_m.  In IBDNS_MIXED the interpolation sums and the
+ * spreading run in FP32 on the FP32 provisional velocity (weights FP64);
+ * batches refuse such runs.
  * ------------------------------------------------------------------------ */
 
 /* Marker count and device workspace bytes for the MLS coupling of the
@@ -236,7 +238,7 @@ int ibdns_flag_mls_workspace_size(ibdns_ctx* ctx, int64_t* n_markers, size_t* by
 /* Switch the flag to MLS markers.  dev_ws: caller-owned device memory of at
  * least the bytes above, 256-byte aligned, kept alive until ibdns_destroy.
  * After ibdns_set_geometry with a flag and before the first step (ESTATE
- * otherwise, or if already set); EINVAL in mixed precision. */
+ * otherwise, or if already set). */
 int ibdns_set_flag_mls(ibdns_ctx* ctx, void* dev_ws, size_t ws_bytes);
 
 /* The markers (any pointer may be NULL): parent vertex ids tri (3m), beta

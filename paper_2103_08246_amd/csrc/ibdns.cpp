@@ -1150,7 +1150,6 @@ int ibdns_flag_mls_workspace_size(ibdns_ctx* c, int64_t* n_markers, size_t* byte
 int ibdns_set_flag_mls(ibdns_ctx* c, void* dev_ws, size_t ws_bytes) {
   if (!c) return IBDNS_EINVAL;
   if (!c->has_flag || c->stepped || c->has_mls) return IBDNS_ESTATE;
-  if (c->d.mixed) return IBDNS_EINVAL;   // the MLS path is FP64
   if (!dev_ws || (reinterpret_cast<uintptr_t>(dev_ws) % ALIGN) != 0) return IBDNS_EINVAL;
   std::vector<double> X0;
   int r = flag_reference(c, X0);

@@ -117,7 +117,9 @@ __device__ __forceinline__ double mls_spline(double q) {
 
 // Centre node, spline factors and tap-0 offsets of every marker for one
 // component, then the shape-function coefficients, the interpolation and the
-// forcing.  Also flags a support that leaves the evolved x range.
+// forcing.  Also flags a support that leaves the evolved x range.  The sum
+// runs in the field type T (FP32 in mixed precision), the weights in FP64.
+template <class T>
 __device__ __forceinline__ void mls_interp_body(const Dims& d, const Fields& f, const PointSet& ps, Scalars* s,
                                                 int bx, int comp) {
   const int q = bx * 256 + threadIdx.x;
@@ -173,8 +175,8 @@ __device__ __forceinline__ void mls_interp_body(const Dims& d, const Fields& f, 
   ml[4] = g[0];
   ml[5] = g[1];
   ml[6] = g[2];
-  const double* fld = comp_field<double>(f, comp);
-  double U = 0.0;
+  const T* fld = comp_field<T>(f, comp);
+  T U = 0;
   for (int dk = 0; dk < 3; ++dk) {
     const int kk = wrap(cen[2] + dk - 1, d.nz);
     for (int dj = 0; dj < 3; ++dj) {
@@ -182,7 +184,7 @@ __device__ __forceinline__ void mls_interp_body(const Dims& d, const Fields& f, 
       for (int di = 0; di < 3; ++di) {
         const double W = wt[di] * wt[3 + dj] * wt[6 + dk];
         const double lin = a0 + g[0] * (xi0[0] + di) + g[1] * (xi0[1] + dj) + g[2] * (xi0[2] + dk);
-        U += fld[fidx(d, cen[0] + di - 1, jj, kk)] * (W * lin);
+        U += fld[fidx(d, cen[0] + di - 1, jj, kk)] * (T)(W * lin);
       }
     }
   }
@@ -291,7 +293,7 @@ constexpr int TN = TS * TS * TS;    // threads per tile
 // order; eight groups at a time, the points whose support meets the tile are
 // compacted (in increasing order) into LDS, and every thread gathers the
 // contributions to its node in increasing point order.
-// With MLS (FP64 only) a staged marker carries its spline factors and, folded
+// With MLS a staged marker carries its spline factors and, folded
 // with its amount, the coefficients of phi = W (a0 + g . xi) in the tap index:
 // amount phi = W (c0 + c . (di, dj, dk)), c0 = amount (a0 + g . xi_tap0), c = amount g.
 template <class T, bool MLS = false>
@@ -443,13 +445,15 @@ __global__ void __launch_bounds__(TN) k_spread_tiles(Dims d, Fields f, PointSet 
   spread_tiles_body<T>(d, f, ps, bbox, ntx, nty, ntz, blockIdx.x / nt, s, blockIdx.x % nt);
 }
 
+template <class T>
 __global__ void __launch_bounds__(256) k_mls_interp(Dims d, Fields f, PointSet ps, Scalars* s) {
-  mls_interp_body(d, f, ps, s, xcd_remap(blockIdx.x, gridDim.x), blockIdx.y);
+  mls_interp_body<T>(d, f, ps, s, xcd_remap(blockIdx.x, gridDim.x), blockIdx.y);
 }
+template <class T>
 __global__ void __launch_bounds__(TN) k_spread_tiles_mls(Dims d, Fields f, PointSet ps, const int* bbox, int ntx,
                                                          int nty, int ntz, Scalars* s) {
   const int nt = ntx * nty * ntz;
-  spread_tiles_body<double, true>(d, f, ps, bbox, ntx, nty, ntz, blockIdx.x / nt, s, blockIdx.x % nt);
+  spread_tiles_body<T, true>(d, f, ps, bbox, ntx, nty, ntz, blockIdx.x / nt, s, blockIdx.x % nt);
 }
 // Marker positions and target velocities: X_m = sum_v beta_v X_v, U^d_m likewise.
 __global__ void __launch_bounds__(256) k_mls_markers(MlsDev m, const double* X, const double* V, PointSet ps) {
@@ -595,7 +599,10 @@ void launch_mls_markers(const MlsDev& m, const double* X, const double* V, const
 }
 void launch_mls_interp(const Dims& d, const Fields& f, const PointSet& ps, Scalars* s, hipStream_t st) {
   if (ps.n == 0) return;
-  hipLaunchKernelGGL(k_mls_interp, dim3((ps.n + 255) / 256, 3), dim3(256), 0, st, d, f, ps, s);
+  if (d.mixed)
+    hipLaunchKernelGGL(k_mls_interp<float>, dim3((ps.n + 255) / 256, 3), dim3(256), 0, st, d, f, ps, s);
+  else
+    hipLaunchKernelGGL(k_mls_interp<double>, dim3((ps.n + 255) / 256, 3), dim3(256), 0, st, d, f, ps, s);
 }
 void launch_mls_node_load(const MlsDev& m, const PointSet& ps, hipStream_t st) {
   if (m.n == 0) return;
@@ -606,8 +613,10 @@ void launch_spread_tiles(const Dims& d, const Fields& f, const PointSet& ps, con
                          int ntx, int nty, int ntz, Scalars* s, hipStream_t st) {
   if (ps.n == 0) return;
   const dim3 grid(3 * ntx * nty * ntz);
-  if (ps.mls)
-    hipLaunchKernelGGL(k_spread_tiles_mls, grid, dim3(TN), 0, st, d, f, ps, bbox, ntx, nty, ntz, s);
+  if (ps.mls && d.mixed)
+    hipLaunchKernelGGL(k_spread_tiles_mls<float>, grid, dim3(TN), 0, st, d, f, ps, bbox, ntx, nty, ntz, s);
+  else if (ps.mls)
+    hipLaunchKernelGGL(k_spread_tiles_mls<double>, grid, dim3(TN), 0, st, d, f, ps, bbox, ntx, nty, ntz, s);
   else if (d.mixed)
     hipLaunchKernelGGL(k_spread_tiles<float>, grid, dim3(TN), 0, st, d, f, ps, bbox, ntx, nty, ntz, s);
   else

@@ -1,7 +1,7 @@
 """MLS transfer at the flag's tiling markers (Sec. II.B (ii) and the tiling
 paragraph of Sec. II.B) on the GPU against the oracle (oracle/mls.py): the
 marker table, one immersed-boundary stage, coupled steps, the node loads,
-and the state and mode rules."""
+the mixed form against the FP64 oracle, and the state and mode rules."""
 import numpy as np
 import pytest
 
@@ -88,14 +88,41 @@ def test_mls_steps_match_oracle(make):
         run.close()
 
 
+@pytest.mark.parametrize("make", [synth.flag_64_re200, small_grid_flag])
+def test_mls_mixed_vs_fp64_oracle(make):
+    """FP32 interpolation sums and spreading on the FP32 provisional velocity:
+    the mixed form's accuracy target after 30 steps."""
+    from oracle import fluid
+    from oracle.solver import Solver
+    w = make()
+    noise = synth.ic_noise(w)
+    pts = synth.bar_points(w) if w.grid is not None else None
+    X0 = synth.flag_reference(w)
+    run = ib.create(ib.domain_from(w, precision=ib.MIXED), noise, points=pts, flag=ib.flag_from(w.flag),
+                    flag_X0=X0, flag_mls=True)
+    S = Solver(w, noise, pts, dict(oracle_flag_args(w, X0), coupling="mls"))
+    try:
+        run.step(30)
+        S.step(30)
+        u, v, ww, p, t, k = run.fields()
+        uo, vo, wo, po = S.fields()
+        err = rel_l2([u, v, ww], [uo, vo, wo])
+        assert 1e-12 < err < 1e-5, err
+        vg = ib.get_array(run.ctx, ib.ARR_V_GHOST, (w.nz, w.ny))
+        wg = ib.get_array(run.ctx, ib.ARR_W_GHOST, (w.nz, w.ny))
+        div = fluid.divergence(u, np.concatenate([v, vg[..., None]], 2),
+                               np.concatenate([ww, wg[..., None]], 2), w.h)
+        assert np.max(np.abs(div)) < 1e-10
+        X, V, F = run.flag()
+        assert rel_l2([X], [S.X.reshape(X.shape)]) < 1e-6
+    finally:
+        run.close()
+
+
 def test_mls_rules():
     w = small_grid_flag()
     noise = synth.ic_noise(w)
     X0 = synth.flag_reference(w)
-    with pytest.raises(ib.IbdnsError) as e:        # FP64 only
-        ib.create(ib.domain_from(w, precision=ib.MIXED), noise, flag=ib.flag_from(w.flag), flag_X0=X0,
-                  flag_mls=True)
-    assert e.value.code == ib.EINVAL
     plain = ib.create(ib.domain_from(w), noise)
     try:
         with pytest.raises(ib.IbdnsError) as e:    # no flag
