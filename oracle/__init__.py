@@ -3,9 +3,12 @@
 Plain, slow, FP64 numpy implementation of one fractional-step time step of
 the paper's method (Sec. II.B): incompressible Navier-Stokes (Eqs. 2-3) on a
 staggered Cartesian mesh with second-order centred differences, Adams-Bashforth
-nonlinear terms, direct-forcing immersed boundaries for the passive grid and
-the flag, a pressure-Poisson projection, and the flag's spring-network
-structural update.
+nonlinear terms (diffusion explicit, or Crank-Nicolson with approximate
+factorisation), direct-forcing immersed boundaries for the passive grid (delta
+points, or Eulerian forcing at the nodes) and the flag (delta at the nodes, or
+MLS at the markers of an adaptive tiling), a pressure-Poisson projection, and
+the flag's spring-network structural update; virtual probes for the in-situ
+statistics.
 
 Only ``tests/``, ``__graft_entry__.smoke()`` and the ``cpu_baseline`` leg of
 ``bench.py`` may import this package.  The GPU library never imports it and
@@ -24,4 +27,6 @@ from .fluid import (Fields, rhs, predictor, outlet, flux_correct, divergence,  #
 from .poisson import solve_poisson, apply_laplacian  # noqa: F401
 from .flag import FlagModel  # noqa: F401
 from .probes import ProbeStats, probe_positions, station_statistics  # noqa: F401
+from .grid_forcing import GridGeometry, forcing_list  # noqa: F401
+from .mls import mls_stencil, build_markers, node_load  # noqa: F401
 from .solver import Solver  # noqa: F401
