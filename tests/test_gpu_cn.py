@@ -32,7 +32,15 @@ def ragged_box():
                           lz=48 * h, re=300.0, dt=0.0, cfl=0.4, steps=10)
 
 
-@pytest.mark.parametrize("make", [synth.flag_64_re200, small_grid_flag, ragged_box])
+def viscous_box():
+    """Re 2 with a fixed dt at nu dt / h^2 = 0.32, about four times the explicit
+    diffusion limit 1/12 (the case Crank-Nicolson is for); CFL 0.08."""
+    h = 0.125
+    return synth.Workload(name="cn_viscous_96x24x48", nx=96, ny=24, nz=48, lx=96 * h, ly=24 * h,
+                          lz=48 * h, re=2.0, dt=0.01, cfl=0.4, steps=20)
+
+
+@pytest.mark.parametrize("make", [synth.flag_64_re200, small_grid_flag, ragged_box, viscous_box])
 def test_cn_steps_match_oracle(make):
     w = make()
     run, S = _pair(w)
