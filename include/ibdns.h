@@ -366,7 +366,8 @@ int ibdns_set_time(ibdns_ctx* ctx, double dt, double dt_prev, int32_t first_step
 /* Index maps of the immersed points: centre node (i, j, k) of the 3x3x3
  * support of every point (static points first, then flag nodes a-fastest) for
  * velocity component comp (0 u, 1 v, 2 w), computed on the device from the
- * current positions as floor((X - o_comp)/h + 1/2).  out: n_total*3 int32. */
+ * current positions as floor((X - o_comp)/h + 1/2).  out: n_total*3 int32.
+ * ESTATE once the flag is coupled at MLS markers (ibdns_set_flag_mls). */
 int ibdns_get_maps(ibdns_ctx* ctx, int32_t comp, int32_t* out);
 
 /* Per-kernel timing with HIP events recorded on the stream each kernel runs on.

@@ -1380,6 +1380,7 @@ int ibdns_set_time(ibdns_ctx* c, double dt, double dt_prev, int32_t first_step) 
 
 int ibdns_get_maps(ibdns_ctx* c, int32_t comp, int32_t* out) {
   if (!c || !out || comp < 0 || comp > 2) return IBDNS_EINVAL;
+  if (c->has_mls) return IBDNS_ESTATE;   // the flag's points are its markers, not its nodes
   if (c->has_flag) launch_point_stencil(c->d, c->flagpts, c->s, c->st);
   if (hipStreamSynchronize(c->st) != hipSuccess) return IBDNS_EHIP;
   size_t off = 0;

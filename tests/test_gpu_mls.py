@@ -138,6 +138,9 @@ def test_mls_rules():
         with pytest.raises(ib.IbdnsError) as e:    # once
             run.set_flag_mls()
         assert e.value.code == ib.ESTATE
+        with pytest.raises(ib.IbdnsError) as e:    # node maps: the flag's points are its markers now
+            ib.get_maps(run.ctx, 0, w.flag.ns ** 2)
+        assert e.value.code == ib.ESTATE
         with pytest.raises(ib.IbdnsError) as e:    # batches couple flags at their nodes
             ib.Batch([run])
         assert e.value.code == ib.EINVAL
