@@ -136,6 +136,10 @@ __device__ __forceinline__ T* cn_field(const Fields& f, int comp) {
 // substitution, which writes the corrected solution y - fac q directly.  The
 // four tables of the axis sit in LDS (4 n doubles; n <= 768, the largest
 // transform size, so at most 24 KiB).
+// FP32 storage moves half the bytes per row access, so those sweeps load
+// PUF rows ahead (indexes clamped into range) to keep enough bytes in flight;
+// FP64 sweeps measured fastest one row at a time.
+constexpr int PUF = 8;
 template <int AXIS, class T>
 __global__ void __launch_bounds__(256) k_cn_periodic(Dims d, Fields f, CnTables t, int comp) {
   const int ilo = comp == 0 ? 1 : 0, nxe = comp == 0 ? d.nx - 1 : d.nx;
@@ -166,19 +170,35 @@ __global__ void __launch_bounds__(256) k_cn_periodic(Dims d, Fields f, CnTables 
   const double* cp = lt + 2 * n;
   const double* q = lt + 3 * n;
   const double r = t.sc[0], vr = t.sc[AXIS == 1 ? 1 : 3], inv = t.sc[AXIS == 1 ? 2 : 4];
+  constexpr int PU = sizeof(T) == 4 ? PUF : 1;
   double prev = 0.0, y0 = 0.0;
-  for (int k = 0; k < n; ++k) {          // forward: d'_k = (d_k + r d'_{k-1}) / pivot_k
-    const double v = (double)a[k * stride];
-    y0 += w[k] * v;
-    prev = (v + r * prev) * m[k];
-    a[k * stride] = (T)prev;
+  for (int k0 = 0; k0 < n; k0 += PU) {
+    double v[PU];
+#pragma unroll
+    for (int u = 0; u < PU; ++u) v[u] = (double)a[min(k0 + u, n - 1) * stride];
+#pragma unroll
+    for (int u = 0; u < PU; ++u)
+      if (k0 + u < n) {
+        const int k = k0 + u;
+        y0 += w[k] * v[u];
+        prev = (v[u] + r * prev) * m[k];
+        a[k * stride] = (T)prev;
+      }
   }
   const double ylast = prev;
   const double fac = (y0 + vr * ylast) * inv;      // (v.y) / (1 + v.q)
   a[(n - 1) * stride] = (T)(ylast - fac * q[n - 1]);
-  for (int k = n - 2; k >= 0; --k) {     // backward: y_k = d'_k - c'_k y_{k+1}
-    prev = (double)a[k * stride] - cp[k] * prev;
-    a[k * stride] = (T)(prev - fac * q[k]);
+  for (int k0 = n - 2; k0 >= 0; k0 -= PU) {
+    double v[PU];
+#pragma unroll
+    for (int u = 0; u < PU; ++u) v[u] = (double)a[max(k0 - u, 0) * stride];
+#pragma unroll
+    for (int u = 0; u < PU; ++u)
+      if (k0 - u >= 0) {
+        const int k = k0 - u;
+        prev = v[u] - cp[k] * prev;
+        a[k * stride] = (T)(prev - fac * q[k]);
+      }
   }
 }
 
