@@ -213,12 +213,13 @@ __device__ __forceinline__ void cn_wave_sync() {
 // XT values: the tile is loaded with 64 / XT lines per load instruction (XT
 // lanes on consecutive values of one line), lane l runs the recurrence along
 // line l in LDS, and the tile is stored the same way.  Loads go in unguarded
-// batches of 16 instructions (line and column indexes clamped into range);
-// only the stores are guarded.
+// batches (line and column indexes clamped into range); only the stores are
+// guarded.
 constexpr int XT = 32;
 template <class T>
 __global__ void __launch_bounds__(64) k_cn_x(Dims d, Fields f, CnTables t, int comp) {
-  constexpr int RPL = 64 / XT, NLD = 64 / RPL, B = 16, LD = XT + 1;
+  // loads per batch: 32 for FP64 storage, 16 for FP32 (each measured best)
+  constexpr int RPL = 64 / XT, NLD = 64 / RPL, B = sizeof(T) == 8 ? 32 : 16, LD = XT + 1;
   static_assert(NLD % B == 0, "batch");
   __shared__ double tl[64 * LD];
   __shared__ long long RB[64];   // field offset of x index ilo on each line
