@@ -106,3 +106,25 @@ def test_solver_forces_grid_nodes():
         solid = [(k, j, i) for (k, j, i, kq, jq, iq, w) in lst if iq < 0]
         assert len(solid) > 0
         assert all(arr[k, j, i] == 0.0 for (k, j, i) in solid)
+
+
+def test_y_face_source_and_tie_order():
+    """h = 1, rods of side 2 at x = 10.3, one rod each way at y = 0 and z = 0.
+    u node (i, j, k) = (10, 1, 3): its only solid neighbour is -y (the wall at
+    y = 1), so it copies the node opposite, j = 2, with weight 0.5/1.5.  Node
+    (10, 1, 1) has solid neighbours at -y and -z at the same distance 0.5: the
+    tie goes to -y (the stated order), source (j, k) = (2, 1)."""
+    geom = gf.GridGeometry(10.3, 8.0, 2.0, 8.0, 8.0)
+    lst = {(e[0], e[1], e[2]): e for e in gf.forcing_list(geom, 0, 24, 8, 8, 1.0)}
+    e = lst[(3, 1, 10)]
+    assert (e[3], e[4], e[5]) == (3, 2, 10) and abs(e[6] - 0.5 / 1.5) < 1e-15
+    e = lst[(1, 1, 10)]
+    assert (e[3], e[4], e[5]) == (1, 2, 10) and abs(e[6] - 0.5 / 1.5) < 1e-15
+
+
+def test_rods_are_closed():
+    """A node exactly on a rod face is solid (closed rods): faces at x = 9 and 11."""
+    geom = gf.GridGeometry(10.0, 8.0, 2.0, 8.0, 8.0)
+    lst = {(e[0], e[1], e[2]): e for e in gf.forcing_list(geom, 0, 24, 8, 8, 1.0)}
+    assert lst[(0, 3, 9)][5] == -1 and lst[(0, 3, 11)][5] == -1
+    assert lst[(0, 3, 8)][5] == 7          # the fluid node next to the face copies its opposite

@@ -117,3 +117,27 @@ def test_solver_samples_after_each_projection():
     assert np.max(np.abs(r[:, 1] - 5.0)) < 1e-12
     assert np.max(np.abs(r[:, 2:4])) < 1e-12
     assert np.max(np.abs(r[:, 10:14] - np.array([5.0, 4.0, 3.0, 2.0]))) < 1e-12
+
+
+def test_probe_index_layout():
+    """Probe (p, a, b) at (x0 + p dx, yc + a dyz, zc + b dyz) has index
+    q = (b+1) + 3 ((a+1) + 3 p): spot values of that stated layout."""
+    from oracle.probes import probe_positions
+    pos = probe_positions(2, 1.0, 0.5, 3.0, 4.0, 0.25)
+    assert np.allclose(pos[0], (1.0, 2.75, 3.75))     # p 0, a -1, b -1
+    assert np.allclose(pos[1], (1.0, 2.75, 4.0))      # p 0, a -1, b 0
+    assert np.allclose(pos[3], (1.0, 3.0, 3.75))      # p 0, a 0, b -1
+    assert np.allclose(pos[17], (1.5, 3.25, 4.25))    # p 1, a 1, b 1
+
+
+def test_lagged_means_count_only_pairs():
+    """Series 1, 2, 3, 4 at every probe of a station: the lag-1 mean product is
+    (2*1 + 3*2 + 4*3)/3 = 20/3 (three pairs), mean 2.5, variance 1.25, so
+    f(1) = (20/3 - 6.25)/1.25 = 1/3 and f(0) = 1."""
+    from oracle.probes import ProbeStats, station_statistics
+    S = ProbeStats(np.zeros((9, 3)), 3)
+    for x in (1.0, 2.0, 3.0, 4.0):
+        S.add(np.full(9, x), np.full(9, x), np.full(9, 0.5 * x))
+    st = station_statistics(S.rec, 3)[0]
+    assert abs(st["f"][0] - 1.0) < 1e-14 and abs(st["f"][1] - 1.0 / 3.0) < 1e-14
+    assert abs(st["f"][2] - ((3 * 1 + 4 * 2) / 2 - 6.25) / 1.25) < 1e-14
