@@ -232,7 +232,7 @@ int ibdns_get_grid_forcing(ibdns_ctx* ctx, int32_t comp, int64_t* count, int64_t
 
 /* Marker count and device workspace bytes for the MLS coupling of the
  * context's flag.  ESTATE without a flag; EINVAL if a triangle needs more
- * than 6 splits. */
+ * than 6 splits or the tiling has 2^26 markers or more. */
 int ibdns_flag_mls_workspace_size(ibdns_ctx* ctx, int64_t* n_markers, size_t* bytes);
 
 /* Switch the flag to MLS markers.  dev_ws: caller-owned device memory of at

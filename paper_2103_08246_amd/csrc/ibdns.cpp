@@ -1082,23 +1082,43 @@ void emit_tiles(const double (&c)[3][3], int L, const int (&v)[3], double dv, Ti
   }
 }
 
-constexpr int MLS_MAX_LEVEL = 6;   // at most 4^6 tiles per triangle
+constexpr int MLS_MAX_LEVEL = 6;                  // at most 4^6 tiles per triangle
+constexpr long long MLS_MAX_MARKERS = 1LL << 26;  // markers per flag
 
 int build_tiling(const double* X0, int ns, double h, Tiling& t) {
   auto len = [&](int p, int q) {
     const double dx = X0[3 * p] - X0[3 * q], dy = X0[3 * p + 1] - X0[3 * q + 1], dz = X0[3 * p + 2] - X0[3 * q + 2];
     return std::sqrt(dx * dx + dy * dy + dz * dz);
   };
+  auto level = [&](const int (&tr)[3]) {   // -1: beyond the maximum level
+    const double emax = std::max({len(tr[0], tr[1]), len(tr[1], tr[2]), len(tr[2], tr[0])});
+    int L = 0;
+    while (std::ldexp(emax, -L) > h)
+      if (++L > MLS_MAX_LEVEL) return -1;
+    return L;
+  };
+  // count first: refuse a tiling too large to hold before building it
+  long long total = 0;
   for (int b = 0; b + 1 < ns; ++b)
     for (int a = 0; a + 1 < ns; ++a) {
       const int p00 = a + ns * b, p10 = a + 1 + ns * b, p01 = a + ns * (b + 1), p11 = a + 1 + ns * (b + 1);
       const int tris[2][3] = {{p00, p10, p11}, {p00, p11, p01}};
       for (auto& tr : tris) {
-        const double emax = std::max({len(tr[0], tr[1]), len(tr[1], tr[2]), len(tr[2], tr[0])});
-        int L = 0;
-        while (std::ldexp(emax, -L) > h) {
-          if (++L > MLS_MAX_LEVEL) return IBDNS_EINVAL;
-        }
+        const int L = level(tr);
+        if (L < 0) return IBDNS_EINVAL;
+        total += 1LL << (2 * L);
+      }
+    }
+  if (total >= MLS_MAX_MARKERS) return IBDNS_EINVAL;
+  t.tri.reserve(3 * (size_t)total);
+  t.beta.reserve(3 * (size_t)total);
+  t.dV.reserve((size_t)total);
+  for (int b = 0; b + 1 < ns; ++b)
+    for (int a = 0; a + 1 < ns; ++a) {
+      const int p00 = a + ns * b, p10 = a + 1 + ns * b, p01 = a + ns * (b + 1), p11 = a + 1 + ns * (b + 1);
+      const int tris[2][3] = {{p00, p10, p11}, {p00, p11, p01}};
+      for (auto& tr : tris) {
+        const int L = level(tr);
         const double* P0 = X0 + 3 * tr[0];
         const double* P1 = X0 + 3 * tr[1];
         const double* P2 = X0 + 3 * tr[2];
@@ -1157,7 +1177,6 @@ int ibdns_set_flag_mls(ibdns_ctx* c, void* dev_ws, size_t ws_bytes) {
   Tiling t;
   if ((r = build_tiling(X0.data(), c->fl.ns, c->d.h, t))) return r;
   const size_t m = t.dV.size(), n = (size_t)c->fl.ns * c->fl.ns;
-  if (m >= (size_t)1 << 26) return IBDNS_EINVAL;
   if (ws_bytes < mls_bytes(m, n)) return IBDNS_ENOMEM;
   // node -> (marker, slot) lists in increasing marker order
   std::vector<int> ptr(n + 1, 0), ent(3 * m);

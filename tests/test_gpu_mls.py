@@ -154,3 +154,26 @@ def test_mls_rules():
         assert e.value.code == ib.ESTATE
     finally:
         late.close()
+
+
+def test_mls_refuses_too_fine_a_tiling():
+    """A 3 x 3 flag of side 1.5 on h = 1/64: the cell diagonal 1.06 needs 7
+    quadratic splits to reach h, beyond the limit of 6: EINVAL, and the run
+    keeps its node coupling (no markers; the node maps are still served)."""
+    h = 1.0 / 64
+    w = synth.Workload(name="coarse_flag", nx=192, ny=128, nz=128, lx=192 * h, ly=128 * h, lz=128 * h,
+                       re=200.0, dt=1e-3, steps=1,
+                       flag=synth.Flag(ns=3, length=1.5, x_le=0.5, y_c=1.0, z_c=1.0, bending=0.01))
+    run = ib.create(ib.domain_from(w), None, flag=ib.flag_from(w.flag), flag_X0=synth.flag_reference(w))
+    try:
+        with pytest.raises(ib.IbdnsError) as e:
+            run.set_flag_mls()
+        assert e.value.code == ib.EINVAL
+        with pytest.raises(ib.IbdnsError) as e:
+            run.flag_markers()
+        assert e.value.code == ib.ESTATE
+        maps = ib.get_maps(run.ctx, 0, w.flag.ns ** 2)
+        X0 = synth.flag_reference(w).reshape(-1, 3)
+        assert np.array_equal(maps[:, 0], np.floor(X0[:, 0] / h + 0.5).astype(np.int32))
+    finally:
+        run.close()
