@@ -225,7 +225,7 @@ void stage_ibm_interp(ibdns_ctx* c) {
   // the flag's maps move with it: computed in the same launch as its interpolation
   if (c->has_flag && c->has_mls) {
     // tiling markers: positions from the nodes, MLS forcing, then the node loads the flag needs
-    TIMED(c, "flag_markers", launch_mls_markers(c->mlsd, c->fl.X, c->fl.V, c->flagpts, c->st));
+    TIMED(c, "flag_markers", launch_mls_markers(c->mlsd, c->fl.X, c->fl.V, c->st));
     TIMED(c, "flag_interp", launch_mls_interp(c->d, c->f, c->flagpts, c->s, c->st));
     TIMED(c, "flag_node_load", launch_mls_node_load(c->mlsd, c->flagpts, c->st));
   } else if (c->has_flag) {
@@ -1226,7 +1226,7 @@ int ibdns_set_flag_mls(ibdns_ctx* c, void* dev_ws, size_t ws_bytes) {
   ps.wts = wts;
   ps.mls = mls;
   c->bbox = bbox;
-  c->mlsd = MlsDev{(int)m, (int)n, tri, beta, dptr, dent, fnode};
+  c->mlsd = MlsDev{(int)m, (int)n, tri, beta, dptr, dent, fnode, mX, mU};
   c->fl.fnode = fnode;
   c->has_mls = true;
   return IBDNS_OK;

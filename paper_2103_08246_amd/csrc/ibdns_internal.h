@@ -86,7 +86,9 @@ struct PointSet {
 // Flag markers of the adaptive tiling: m markers, each at fixed barycentric
 // coordinates beta of a parent triangle (tri), volume dV; node_ptr/node_ent
 // list for every node the (marker * 3 + slot) entries that touch it, in
-// increasing marker order; fnode (3 per node) receives sum beta F dV.
+// increasing marker order; fnode (3 per node) receives sum beta F dV; X and
+// U (3 per marker) receive the marker positions and target velocities (the
+// flag's point set reads them).
 struct MlsDev {
   int m = 0, n = 0;
   const int* tri = nullptr;
@@ -94,6 +96,8 @@ struct MlsDev {
   const int* node_ptr = nullptr;
   const int* node_ent = nullptr;
   double* fnode = nullptr;
+  double* X = nullptr;
+  double* U = nullptr;
 };
 
 // Static point-to-grid transposed map for atomic-free spreading (per component).
@@ -236,7 +240,7 @@ void launch_spread_csr(const Dims& d, const Fields& f, const PointSet& ps,
 void launch_point_bbox(const PointSet& ps, int* bbox, hipStream_t st);
 // MLS markers: positions and target velocities from the flag's nodes, the MLS
 // interpolation and forcing, and the node loads from the markers' forcing
-void launch_mls_markers(const MlsDev& m, const double* X, const double* V, const PointSet& ps, hipStream_t st);
+void launch_mls_markers(const MlsDev& m, const double* X, const double* V, hipStream_t st);
 void launch_mls_interp(const Dims& d, const Fields& f, const PointSet& ps, Scalars* s, hipStream_t st);
 void launch_mls_node_load(const MlsDev& m, const PointSet& ps, hipStream_t st);
 void launch_spread_tiles(const Dims& d, const Fields& f, const PointSet& ps, const int* bbox,

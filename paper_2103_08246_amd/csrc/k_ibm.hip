@@ -456,16 +456,14 @@ __global__ void __launch_bounds__(TN) k_spread_tiles_mls(Dims d, Fields f, Point
   spread_tiles_body<T, true>(d, f, ps, bbox, ntx, nty, ntz, blockIdx.x / nt, s, blockIdx.x % nt);
 }
 // Marker positions and target velocities: X_m = sum_v beta_v X_v, U^d_m likewise.
-__global__ void __launch_bounds__(256) k_mls_markers(MlsDev m, const double* X, const double* V, PointSet ps) {
+__global__ void __launch_bounds__(256) k_mls_markers(MlsDev m, const double* X, const double* V) {
   const int q = blockIdx.x * 256 + threadIdx.x;
   if (q >= m.m) return;
   const int v0 = m.tri[3 * q], v1 = m.tri[3 * q + 1], v2 = m.tri[3 * q + 2];
   const double b0 = m.beta[3 * q], b1 = m.beta[3 * q + 1], b2 = m.beta[3 * q + 2];
-  double* Xm = const_cast<double*>(ps.X);
-  double* Um = const_cast<double*>(ps.Ud);
   for (int c = 0; c < 3; ++c) {
-    Xm[3 * q + c] = b0 * X[3 * v0 + c] + b1 * X[3 * v1 + c] + b2 * X[3 * v2 + c];
-    Um[3 * q + c] = b0 * V[3 * v0 + c] + b1 * V[3 * v1 + c] + b2 * V[3 * v2 + c];
+    m.X[3 * q + c] = b0 * X[3 * v0 + c] + b1 * X[3 * v1 + c] + b2 * X[3 * v2 + c];
+    m.U[3 * q + c] = b0 * V[3 * v0 + c] + b1 * V[3 * v1 + c] + b2 * V[3 * v2 + c];
   }
 }
 // Node loads: fnode_v = sum over the markers touching v (increasing) of beta (F dV).
@@ -593,9 +591,9 @@ void launch_point_bbox(const PointSet& ps, int* bbox, hipStream_t st) {
   hipLaunchKernelGGL(k_point_bbox, dim3(3), dim3(BBT), 0, st, ps, bbox);
 }
 
-void launch_mls_markers(const MlsDev& m, const double* X, const double* V, const PointSet& ps, hipStream_t st) {
+void launch_mls_markers(const MlsDev& m, const double* X, const double* V, hipStream_t st) {
   if (m.m == 0) return;
-  hipLaunchKernelGGL(k_mls_markers, dim3((m.m + 255) / 256), dim3(256), 0, st, m, X, V, ps);
+  hipLaunchKernelGGL(k_mls_markers, dim3((m.m + 255) / 256), dim3(256), 0, st, m, X, V);
 }
 void launch_mls_interp(const Dims& d, const Fields& f, const PointSet& ps, Scalars* s, hipStream_t st) {
   if (ps.n == 0) return;
