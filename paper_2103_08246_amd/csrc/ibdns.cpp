@@ -68,6 +68,7 @@ struct ibdns_ctx {
   // after the immersed-boundary stage and joined before the time advance
   hipStream_t side = nullptr;
   hipEvent_t ev_fork = nullptr, ev_join = nullptr;
+  hipEvent_t ev_cn_fork = nullptr, ev_cn_join = nullptr;   // CN tables beside the predictor
   // Crank-Nicolson factor tables (used when d.cn)
   CnTables cnt{};
   // virtual probes (caller-owned workspace), sampled after each projection
@@ -208,11 +209,28 @@ void rec_end(ibdns_ctx* c, const char* name, hipEvent_t a, hipStream_t st) {
 #define TIMED(ctx, name, call) TIMED_ON(ctx, (ctx)->st, name, call)
 
 void stage_predict(ibdns_ctx* c) {
+  // Crank-Nicolson: the factor tables need only this step's dt, already on the
+  // device: they are rebuilt on the second stream while the predictor runs
+  const bool cn_side = c->d.cn && c->side && c->ev_cn_fork;
+  if (cn_side) {
+    if (hipEventRecord(c->ev_cn_fork, c->st) != hipSuccess ||
+        hipStreamWaitEvent(c->side, c->ev_cn_fork, 0) != hipSuccess)
+      c->launch_failed = true;
+    TIMED_ON(c, c->side, "cn_tables", launch_cn_tables(c->d, c->s, c->cnt, c->side));
+    if (hipEventRecord(c->ev_cn_join, c->side) != hipSuccess) c->launch_failed = true;
+  }
   TIMED(c, "predict", launch_predict(c->d, c->f, c->s, c->variant, c->st));
   TIMED(c, "outlet", launch_outlet(c->d, c->f, c->s, c->nparts, 1, c->st));
-  // Crank-Nicolson: the predictor wrote the increment's right-hand side; the
-  // factored solves need the outflow values of the outlet kernel
-  if (c->d.cn) TIMED(c, "cn_sweeps", launch_cn(c->d, c->f, c->s, c->cnt, c->st));
+  // the predictor wrote the increment's right-hand side; the factored solves
+  // need the outflow values of the outlet kernel and the tables
+  if (c->d.cn) {
+    if (cn_side) {
+      if (hipStreamWaitEvent(c->st, c->ev_cn_join, 0) != hipSuccess) c->launch_failed = true;
+    } else {
+      TIMED(c, "cn_tables", launch_cn_tables(c->d, c->s, c->cnt, c->st));
+    }
+    TIMED(c, "cn_sweeps", launch_cn_sweeps(c->d, c->f, c->cnt, c->st));
+  }
 }
 void stage_flux(ibdns_ctx* c) { TIMED(c, "flux_apply", launch_flux_apply(c->d, c->f, c->s, c->nparts, c->st)); }
 
@@ -270,6 +288,19 @@ void stage_flag(ibdns_ctx* c) {
 // before the join.  Plain launch: its bands are co-resident once dispatched
 // alongside the fluid kernels, and a band that waits for a neighbour not
 // yet dispatched only spins (bounded) until the dispatcher places it.
+// The second stream (default priority, non-blocking: ordered with the main
+// stream by events only) and its events, created once.
+int ensure_side(ibdns_ctx* c) {
+  if (!c->side &&
+      (hipStreamCreateWithFlags(&c->side, hipStreamNonBlocking) != hipSuccess ||
+       hipEventCreateWithFlags(&c->ev_fork, hipEventDisableTiming) != hipSuccess ||
+       hipEventCreateWithFlags(&c->ev_join, hipEventDisableTiming) != hipSuccess ||
+       hipEventCreateWithFlags(&c->ev_cn_fork, hipEventDisableTiming) != hipSuccess ||
+       hipEventCreateWithFlags(&c->ev_cn_join, hipEventDisableTiming) != hipSuccess))
+    return IBDNS_EHIP;
+  return IBDNS_OK;
+}
+
 bool fork_flag(ibdns_ctx* c) {
   if (!c->has_flag || !c->side) return false;
   if (hipEventRecord(c->ev_fork, c->st) != hipSuccess || hipStreamWaitEvent(c->side, c->ev_fork, 0) != hipSuccess) {
@@ -534,6 +565,10 @@ int ibdns_init_domain(const ibdns_domain* dm, const double* zu, const double* zv
     delete c;
     return IBDNS_EHIP;
   }
+  if (c->d.cn && ensure_side(c) != IBDNS_OK) {   // the CN tables run beside the predictor
+    ibdns_destroy(c);
+    return IBDNS_EHIP;
+  }
   *out = c;
   return IBDNS_OK;
 }
@@ -754,12 +789,7 @@ int ibdns_set_geometry(ibdns_ctx* c, int64_t n_points, const double* X, const do
     const int ext = (int)std::ceil(std::sqrt(2.0) * 1.01 * L / h) + 4;
     c->ntx = c->nty = c->ntz = (ext + 7) / 8 + 1;
     c->has_flag = true;
-    // default-priority, non-blocking: ordered with the main stream by events only
-    if (!c->side &&
-        (hipStreamCreateWithFlags(&c->side, hipStreamNonBlocking) != hipSuccess ||
-         hipEventCreateWithFlags(&c->ev_fork, hipEventDisableTiming) != hipSuccess ||
-         hipEventCreateWithFlags(&c->ev_join, hipEventDisableTiming) != hipSuccess))
-      return IBDNS_EHIP;
+    if (ensure_side(c) != IBDNS_OK) return IBDNS_EHIP;
   }
   c->geometry_set = true;
   if (check_launch() != IBDNS_OK || hipStreamSynchronize(c->st) != hipSuccess) return IBDNS_EHIP;
@@ -1306,6 +1336,8 @@ int ibdns_destroy(ibdns_ctx* c) {
     hipStreamDestroy(c->side);
     hipEventDestroy(c->ev_fork);
     hipEventDestroy(c->ev_join);
+    if (c->ev_cn_fork) hipEventDestroy(c->ev_cn_fork);
+    if (c->ev_cn_join) hipEventDestroy(c->ev_cn_join);
   }
   for (auto& r : c->recs) {
     hipEventDestroy(r.a);

@@ -263,7 +263,8 @@ void launch_advance(Scalars* s, const double* partial, int nparts, double h, hip
 void launch_probes(const Dims& d, const Fields& f, const ProbeDev& pr, hipStream_t st);
 size_t cn_table_doubles(int nx, int ny, int nz);
 CnTables cn_tables_at(double* base, int nx, int ny, int nz);
-void launch_cn(const Dims& d, const Fields& f, const Scalars* s, const CnTables& t, hipStream_t st);
+void launch_cn_tables(const Dims& d, const Scalars* s, const CnTables& t, hipStream_t st);
+void launch_cn_sweeps(const Dims& d, const Fields& f, const CnTables& t, hipStream_t st);
 void launch_grid_force(const Dims& d, const Fields& f, const GridForceDev& g, hipStream_t st);
 void launch_set_dt0(Scalars* s, const double* partial, int nparts, double h, hipStream_t st);
 

@@ -11,7 +11,7 @@
 // increment; zero-gradient ends under the test hook).
 //
 // The factor tables depend on dt only, which lives on the device: one small
-// kernel rebuilds them each step.  Every sweep is one thread per line: for
+// kernel rebuilds them each step (on a second stream, beside the predictor).  Every sweep is one thread per line: for
 // the y and z sweeps lines of neighbouring x columns sit in neighbouring lanes
 // (coalesced); the x sweep stages tiles of 64 lines through LDS.  A periodic
 // sweep reads and writes the field twice (forward, back substitution with the
@@ -304,8 +304,7 @@ __global__ void __launch_bounds__(64) k_cn_x(Dims d, Fields f, CnTables t, int c
 }
 
 template <class T>
-void launch_cn_t(const Dims& d, const Fields& f, const Scalars* s, const CnTables& t, hipStream_t st) {
-  hipLaunchKernelGGL(k_cn_tables, dim3(5), dim3(64), 0, st, d, s, t);
+void launch_cn_t(const Dims& d, const Fields& f, const CnTables& t, hipStream_t st) {
   for (int comp = 0; comp < 3; ++comp) {
     const int nxe = comp == 0 ? d.nx - 1 : d.nx;
     const long long nz_lines = (long long)nxe * d.ny, ny_lines = (long long)nxe * d.nz;
@@ -320,11 +319,15 @@ void launch_cn_t(const Dims& d, const Fields& f, const Scalars* s, const CnTable
 
 }  // namespace
 
-void launch_cn(const Dims& d, const Fields& f, const Scalars* s, const CnTables& t, hipStream_t st) {
+void launch_cn_tables(const Dims& d, const Scalars* s, const CnTables& t, hipStream_t st) {
+  hipLaunchKernelGGL(k_cn_tables, dim3(5), dim3(64), 0, st, d, s, t);
+}
+
+void launch_cn_sweeps(const Dims& d, const Fields& f, const CnTables& t, hipStream_t st) {
   if (d.mixed)
-    launch_cn_t<float>(d, f, s, t, st);
+    launch_cn_t<float>(d, f, t, st);
   else
-    launch_cn_t<double>(d, f, s, t, st);
+    launch_cn_t<double>(d, f, t, st);
 }
 
 }  // namespace ibdns
