@@ -1,7 +1,7 @@
 """The paper's own scheme options at the full size (768 x 384 x 384, grid bars
 and a 96 x 96 flag) in the launch configuration bench.py times: Crank-Nicolson
-with approximate factorisation (Sec. II.B) and MLS at the flag's tiling
-markers (Sec. II.B (ii)).
+with approximate factorisation (Sec. II.B), MLS at the flag's tiling markers
+(Sec. II.B (ii)) and the Eulerian forcing of the grid (Sec. II.B (i)).
 
 The oracle cannot step this size in test time, so:
 * CN: on x-slabs, the factored operator (1 - b Dx)(1 - b Dy)(1 - b Dz)
@@ -10,7 +10,9 @@ The oracle cannot step this size in test time, so:
 * MLS: the marker table bit for bit, every marker's forcing against the
   oracle's MLS interpolation of the GPU's provisional field, and after whole
   steps the force balance between markers and nodes;
-* both: divergence at machine level, outflow = inflow, finite fields.
+* both: divergence at machine level, outflow = inflow, finite fields;
+* Eulerian grid forcing: per component the solid nodes against their
+  closed-form count, and well-formed interface entries.
 """
 import numpy as np
 import pytest
@@ -142,3 +144,33 @@ def test_mls_steps_properties(mls_full):
     d = X[:, 1:] - X[:, :-1]
     strain = np.abs(np.sqrt(np.sum(d * d, -1)) / (w.flag.length / (w.flag.ns - 1)) - 1)
     assert np.max(strain) < 5e-3
+
+
+def test_grid_forcing_full_size_counts():
+    """Eulerian grid forcing at full size (12 rods each way, d = 6.4 h): per
+    component the solid nodes equal the closed-form count of mesh positions
+    inside the closed rods, every other entry is an interface node with a
+    weight in (0, 1) and a source inside the domain."""
+    from oracle import grid_forcing as gf
+    from tests.test_oracle_grid_forcing import _count_in
+    w = synth.grid_flag_768_re1000()
+    g = w.grid
+    run = ib.create(ib.domain_from(w), synth.ic_noise(w), grid_forcing=g)
+    try:
+        geom = gf.GridGeometry(g.x_plane, g.mesh, g.bar, w.ly, w.lz)
+        assert len(geom.yc) == len(geom.zc) == 12
+        for comp in range(3):
+            node, src, wgt = run.grid_forcing(comp)
+            o = gf._ORIGIN[comp]
+            cx = _count_in(g.x_plane - g.bar / 2, g.x_plane + g.bar / 2, o[0], w.h)
+            cy = sum(_count_in(c - g.bar / 2, c + g.bar / 2, o[1], w.h, w.ny) for c in geom.yc)
+            cz = sum(_count_in(c - g.bar / 2, c + g.bar / 2, o[2], w.h, w.nz) for c in geom.zc)
+            assert np.sum(src < 0) == cx * (w.ny * cz + w.nz * cy - cy * cz), comp
+            inter = src >= 0
+            assert np.sum(inter) > 0
+            assert np.all((wgt[inter] > 0) & (wgt[inter] < 1))
+            NX = w.nx + 1 if comp == 0 else w.nx
+            assert np.all(node < NX * w.ny * w.nz) and np.all(src[inter] < NX * w.ny * w.nz)
+            assert np.all(np.diff(node) > 0)                  # increasing, no node twice
+    finally:
+        run.close()
