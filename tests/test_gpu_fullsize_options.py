@@ -12,7 +12,9 @@ The oracle cannot step this size in test time, so:
   steps the force balance between markers and nodes;
 * both: divergence at machine level, outflow = inflow, finite fields;
 * Eulerian grid forcing: per component the solid nodes against their
-  closed-form count, and well-formed interface entries.
+  closed-form count, and well-formed interface entries;
+* probes: the records after one step against the oracle's samples of the
+  GPU's fields.
 """
 import numpy as np
 import pytest
@@ -174,3 +176,23 @@ def test_grid_forcing_full_size_counts():
             assert np.all(np.diff(node) > 0)                  # increasing, no node twice
     finally:
         run.close()
+
+
+def test_probes_full_size(mls_full):
+    """The 423 probes of the bench's layout after one more step: each record's
+    latest sample, recovered from its running sums, equals the oracle's
+    trilinear interpolation of the GPU's own fields at the probe."""
+    from oracle.probes import probe_positions, sample
+    w, run, X0 = mls_full
+    pr = synth.probe_layout(w, 4)
+    run.set_probes(pr["n_x"], pr["x0"], pr["dx"], pr["yc"], pr["zc"], pr["dyz"], pr["n_lags"])
+    run.step(1)
+    rec = run.probe_stats()
+    u, v, ww, p, t, k = run.fields()
+    X = probe_positions(pr["n_x"], pr["x0"], pr["dx"], pr["yc"], pr["zc"], pr["dyz"])
+    assert X.shape[0] == 423 and np.all(rec[:, 0] == 1.0)
+    su = sample(u, 0, X, w.h, w.nx)
+    sv = sample(v, 1, X, w.h, w.nx - 1)
+    sw = sample(ww, 2, X, w.h, w.nx - 1)
+    for col, want in ((1, su), (2, sv), (3, sw), (4, su * su), (7, su * sv), (10, su * su), (14, sv * sv)):
+        assert np.max(np.abs(rec[:, col] - want)) <= 1e-13 * max(1.0, np.max(np.abs(want))), col
