@@ -128,3 +128,23 @@ def test_rods_are_closed():
     lst = {(e[0], e[1], e[2]): e for e in gf.forcing_list(geom, 0, 24, 8, 8, 1.0)}
     assert lst[(0, 3, 9)][5] == -1 and lst[(0, 3, 11)][5] == -1
     assert lst[(0, 3, 8)][5] == 7          # the fluid node next to the face copies its opposite
+
+
+def test_grid_solidity_matches_the_paper():
+    """tests/golden/grid_solidity.json: at M/d = 4 the paper's grid blocks 44%
+    of the cross-section.  The oracle's solid mask, sampled at cell midpoints
+    of a fine lattice over the grid plane (400 samples per mesh M), covers
+    exactly 1 - (1 - d/M)^2 = 0.4375 of it."""
+    import json
+    import os
+    g = json.load(open(os.path.join(os.path.dirname(__file__), "golden", "grid_solidity.json")))
+    M = 1.0
+    d = M / g["M_over_d"]
+    L = 4 * M
+    geom = gf.GridGeometry(2.0, M, d, L, L)
+    n = 1600
+    s = (np.arange(n) + 0.5) * (L / n)
+    Y, Z = np.meshgrid(s, s, indexing="ij")
+    frac = np.mean(geom.solid(np.full_like(Y, 2.0), Y, Z))
+    assert frac == 1.0 - (1.0 - d / M) ** 2
+    assert abs(100.0 * frac - g["solidity_percent_printed"]) < 0.5
