@@ -238,7 +238,9 @@ int ibdns_flag_mls_workspace_size(ibdns_ctx* ctx, int64_t* n_markers, size_t* by
 /* Switch the flag to MLS markers.  dev_ws: caller-owned device memory of at
  * least the bytes above, 256-byte aligned, kept alive until ibdns_destroy.
  * After ibdns_set_geometry with a flag and before the first step (ESTATE
- * otherwise, or if already set). */
+ * otherwise, or if already set); EINVAL for a misaligned workspace or a
+ * refused tiling, ENOMEM if ws_bytes is short.  On error the flag keeps its
+ * node coupling.  Once set, ibdns_get_maps answers ESTATE. */
 int ibdns_set_flag_mls(ibdns_ctx* ctx, void* dev_ws, size_t ws_bytes);
 
 /* The markers (any pointer may be NULL): parent vertex ids tri (3m), beta
