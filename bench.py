@@ -50,6 +50,19 @@ def max_divergence(u, v, w, h):
     return float(np.max(np.abs(d))) / h
 
 
+def max_edge_strain(X, X0):
+    """max |l/l0 - 1| over the flag's a-edges, b-edges and cell diagonals
+    (X, X0: (ns, ns, 3) indexed [b, a]); the spring network's inextensibility."""
+    out = 0.0
+    for sl_p, sl_q in (((slice(None), slice(1, None)), (slice(None), slice(None, -1))),
+                       ((slice(1, None), slice(None)), (slice(None, -1), slice(None))),
+                       ((slice(1, None), slice(1, None)), (slice(None, -1), slice(None, -1)))):
+        ln = np.linalg.norm(X[sl_p] - X[sl_q], axis=-1)
+        l0 = np.linalg.norm(X0[sl_p] - X0[sl_q], axis=-1)
+        out = max(out, float(np.max(np.abs(ln / l0 - 1.0))))
+    return out
+
+
 def make_workload(name: str):
     import synth
     if name in ("grid_flag_768x384x384_re1000", "default"):
@@ -65,11 +78,7 @@ def batch_leg(ib, torch, ws_list, precision, steps, warmup, keep=False):
     runs = []
     for w in ws_list:
         noise = synth.ic_noise(w)
-        bars = synth.bar_points(w) if w.grid is not None else None
-        X0 = synth.flag_reference(w) if w.flag is not None else None
-        runs.append(ib.create(ib.domain_from(w, precision=precision), noise, points=bars,
-                              flag=ib.flag_from(w.flag) if w.flag is not None else None,
-                              flag_X0=X0))
+        runs.append(ib.create(ib.domain_from(w, precision=precision), noise, grid=w.grid, flag=w.flag))
     b = ib.Batch(runs)
     variant = b.autotune()
     b.use_graph(True)
@@ -103,13 +112,14 @@ def cpu_baseline(w, budget_s: float = 20.0) -> dict:
     t = cells / (sub-box cell rate) + t_flag.
     """
     import synth
+    from oracle import geometry
     from oracle.flag import FlagModel
     from oracle.solver import Solver
     import dataclasses
     sub = dataclasses.replace(w, nx=128, ny=96, nz=96, lx=128 * w.h, ly=96 * w.h,
                               lz=96 * w.h, flag=None)
     noise = synth.ic_noise(sub)
-    bars = synth.bar_points(sub) if sub.grid is not None else None
+    bars = geometry.grid_points_of(sub) if sub.grid is not None else None
     S = Solver(sub, noise, bars, None)
     S.step(1)   # warm-up
     t0 = time.perf_counter()
@@ -122,7 +132,7 @@ def cpu_baseline(w, budget_s: float = 20.0) -> dict:
     t_flag = 0.0
     if w.flag is not None:
         f = w.flag
-        X0 = synth.flag_reference(w)
+        X0 = geometry.flag_lattice(f)
         F = FlagModel(X0, f.length, f.mass_ratio, f.bending, f.stretch, f.le_bc)
         X = X0.reshape(-1, 3).copy()
         V = np.zeros_like(X)
@@ -173,8 +183,6 @@ def main():
     w = make_workload(args.workload)
     print(f"# workload {w.name}: {w.nx}x{w.ny}x{w.nz} = {w.cells} cells", file=sys.stderr, flush=True)
     noise = synth.ic_noise(w)
-    bars = synth.bar_points(w) if w.grid is not None else None
-    X0 = synth.flag_reference(w) if w.flag is not None else None
 
     def measure(precision, breakdown, eulerian=False, diffusion=0, mls=False):
         """Timed region: args.steps steps with HIP events around the predictor
@@ -183,9 +191,10 @@ def main():
         eulerian: the grid forced at its nodes instead of as points; mls: the
         flag coupled at its tiling markers by MLS instead of at its nodes."""
         run = ib.create(ib.domain_from(w, precision=precision, diffusion=diffusion), noise,
-                        points=None if eulerian else bars,
-                        flag=ib.flag_from(w.flag) if w.flag is not None else None, flag_X0=X0,
+                        grid=None if eulerian else w.grid, flag=w.flag,
                         grid_forcing=w.grid if eulerian else None, flag_mls=mls and w.flag is not None)
+        # the flag's reference lattice as the library built it (rest lengths of the strain)
+        run.X_ref = run.flag()[0] if w.flag is not None else None
         run.variant = ib.autotune(run.ctx)   # predictor tile shape, picked by timing
         run.step(args.warmup)
         ib.sync(run.ctx)
@@ -258,7 +267,7 @@ def main():
            "higher_is_better": True, "scaling": "weak", "vs_baseline": None, "dtype": "f64",
            "data": "synthetic",
            "config": {"workload": w.name, "cells": w.cells, "grid": [w.nx, w.ny, w.nz],
-                      "re": w.re, "cfl": w.cfl, "solid_points": 0 if bars is None else len(bars[1]),
+                      "re": w.re, "cfl": w.cfl, "solid_points": int(ib.get_grid_points(run.ctx)[1].size),
                       "flag_nodes": 0 if w.flag is None else w.flag.ns ** 2,
                       "precision": "fp64", "flag_substeps": sc["nsub"], "dt": sc["dt"],
                       "predict_variant": run.variant},
@@ -267,6 +276,9 @@ def main():
            "gpu_event_ms_per_step": round(gpu_ms / args.steps, 4),
            "kernel_avg_ms": breakdown,
            "kernel_avg_ms_note": "separate pass of the same length with events around every kernel"}
+    if w.flag is not None:
+        out["flag_max_edge_strain"] = max_edge_strain(run.flag()[0], run.X_ref)
+        out["flag_max_edge_strain_after_steps"] = args.warmup + 2 * args.steps
     rec = run.probe_stats()
     out["probes"] = {"probes": int(rec.shape[0]), "stations": run.probe_layout["n_x"],
                      "lags": run.probe_layout["n_lags"], "samples": int(rec[0, 0]),

@@ -26,10 +26,12 @@
  *
  * Errors
  *   Every entry point returns an int status (IBDNS_OK = 0 or a negative code);
- *   nothing throws across the ABI.  EUNSTABLE is sticky: it is raised on the
- *   device (non-finite velocity, CFL number above 1, or an immersed point whose
- *   support leaves the evolved x range) and reported by the next call that
- *   synchronises (ibdns_get_fields, ibdns_get_flag, ibdns_sync).
+ *   nothing throws across the ABI.  EUNSTABLE and ETIMEOUT are sticky: they
+ *   are raised on the device (EUNSTABLE: non-finite velocity, CFL number above
+ *   1, or an immersed point whose support leaves the evolved x range;
+ *   ETIMEOUT: the flag's bands gave up waiting for each other) and reported by
+ *   the next call that synchronises (ibdns_get_fields, ibdns_get_flag,
+ *   ibdns_sync, ibdns_get_scalars).
  *   Calls on one context must not overlap; use one context per host thread.
  */
 #ifndef IBDNS_H
@@ -50,7 +52,12 @@ enum {
   IBDNS_ENOMEM = -2,    /* workspace too small                             */
   IBDNS_EHIP = -3,      /* a HIP runtime call failed                       */
   IBDNS_EUNSTABLE = -4, /* device status: non-finite / CFL > 1 / point left range */
-  IBDNS_ESTATE = -5     /* call out of order (e.g. step before init)       */
+  IBDNS_ESTATE = -5,    /* call out of order (e.g. step before init)       */
+  IBDNS_ETIMEOUT = -6   /* device status: the flag's bands did not finish a   */
+                        /* sub-step exchange within their bounded wait; the    */
+                        /* flag state of that step is partly advanced (some    */
+                        /* rows at the new step, others at the old one) and    */
+                        /* the run is to be discarded                          */
 };
 
 enum { IBDNS_FP64 = 0, IBDNS_MIXED = 1 };
@@ -93,25 +100,55 @@ typedef struct {
  * refuse it. */
 enum { IBDNS_DIFFUSION_EXPLICIT = 0, IBDNS_DIFFUSION_CN = 1 };
 
+/* Passive grid (Sec. II.A: a monoplane grid of square rods of side d, mesh
+ * size M, in the plane x = x_plane normal to the stream, M/2 from the inlet
+ * in the paper; the coordinates are centred on the grid).  With
+ * ibdns_set_geometry the library samples the rods with solid points, forced
+ * to zero velocity by the delta transfer of the flag (the paper forces the
+ * grid at the Eulerian nodes instead; ibdns_set_grid_forcing below does that):
+ *   nc = max(1, floor(d/h + 1/2)) points per rod side, at streamwise and
+ *   transverse offsets (q + 1/2) d/nc - d/2 (q < nc) from the plane and the
+ *   rod axis, one cross-section every h along the rod at (m + 1/2) h; rods
+ *   along y at z = lz/2 + (b + 1/2) M (mod lz), b < round(lz/M), rods along z
+ *   at y = ly/2 + (b + 1/2) M (mod ly), b < round(ly/M); a z-rod
+ *   cross-section strictly within d/2 of a y-rod axis (periodic distance) is
+ *   left out; every point has the volume (d/nc)^2 h.  Order: the y-rods,
+ *   then the z-rods; along the rod, then the streamwise offset, then the
+ *   transverse offset.  Requires 0 < d < M <= min(ly, lz). */
+typedef struct {
+  double x_plane;      /* streamwise position of the grid's plane               */
+  double mesh;         /* M: rod spacing                                         */
+  double bar;          /* d: rod side                                            */
+} ibdns_grid;
+
 /* Flag (Sec. II.A: square of side L, mass ratio rho, bending coefficient beta,
- * hinged at its leading edge; Sec. II.B: spring network, essentially
- * inextensible). */
+ * hinged at its leading edge, centred transversely, initially straight and
+ * pitched by theta = 0.1 pi; Sec. II.B: spring network, essentially
+ * inextensible).  Reference lattice built by the library: node (a, b),
+ * a streamwise from the leading edge, b spanwise, at
+ *   (x_le, y_c, z_c - L/2) + a ds (cos pitch, sin pitch, 0) + b ds (0, 0, 1),
+ * ds = L/(ns - 1): the hinge runs along z through (x_le, y_c). */
 typedef struct {
   int32_t ns;          /* nodes per side, 3 <= ns <= 128                         */
   double length;       /* L                                                      */
+  double x_le, y_c, z_c; /* leading-edge x, transverse centre of the flag        */
+  double pitch;        /* theta: initial angle to the stream in the x-y plane    */
   double mass_ratio;   /* rho: mass per unit area                                */
   double bending;      /* beta                                                   */
   double stretch;      /* in-plane spring stiffness per unit width (large)       */
   int32_t le_bc;       /* IBDNS_LE_HINGED or IBDNS_LE_CLAMPED                    */
 } ibdns_flag;
 
-/* Bytes of device workspace needed for a domain with up to n_points static
- * solid points and a flag of flag_ns nodes per side (0: no flag).
- * Returns EINVAL for an unsupported domain. */
-int ibdns_workspace_size(const ibdns_domain* d, int64_t n_points, int32_t flag_ns,
+/* Bytes of device workspace for the fluid state of a domain (Sec. II.A-B:
+ * staggered fields, half spectrum, step scalars) plus the immersed bodies of
+ * ibdns_set_geometry: the grid's solid points (grid may be NULL) and the flag
+ * (flag may be NULL).  EINVAL for an unsupported domain or invalid body
+ * parameters. */
+int ibdns_workspace_size(const ibdns_domain* d, const ibdns_grid* grid, const ibdns_flag* flag,
                          size_t* bytes);
 
-/* Create a context over the caller's device workspace (dev_ws, ws_bytes; at
+/* Create a context for the problem of Sec. II.A (box, Re, inflow U) over the
+ * caller's device workspace (dev_ws, ws_bytes; at
  * least ibdns_workspace_size bytes, 256-byte aligned) on the caller's HIP
  * stream (hipStream_t passed as void*; NULL = default stream) of the current
  * device, and set the initial condition (reading of the paper's uniform
@@ -125,48 +162,63 @@ int ibdns_init_domain(const ibdns_domain* d, const double* zu, const double* zv,
                       const double* zw, void* dev_ws, size_t ws_bytes, void* hip_stream,
                       ibdns_ctx** out);
 
-/* Immersed bodies (Sec. II.B direct forcing).  n_points static solid points
- * with positions X (host, n_points*3, point-major) and volumes dV (host,
- * n_points), forced to zero velocity (the passive grid).  flag (may be NULL)
- * with its reference lattice X0 (host, ns*ns*3, layout above); its nodes are
- * forced to the flag velocity (or, after ibdns_set_flag_mls, the markers of its
- * tiling).  Every point's 3x3x3 delta support must stay
- * on evolved velocity nodes in x (else EINVAL).  May be called once, before
- * the first ibdns_step. */
-int ibdns_set_geometry(ibdns_ctx* ctx, int64_t n_points, const double* X, const double* dV,
-                       const ibdns_flag* flag, const double* flag_X0);
+/* Immersed bodies of Sec. II.A, built by the library from their parameters
+ * (direct forcing, Sec. II.B): the passive grid's solid points (grid may be
+ * NULL; the rule with ibdns_grid) forced to zero velocity, and the flag (may
+ * be NULL) on its reference lattice (the rule with ibdns_flag), its nodes
+ * forced to the flag velocity (or, after ibdns_set_flag_mls, the markers of
+ * its tiling).  Every point's 3x3x3 delta support must stay on evolved
+ * velocity nodes in x (else EINVAL); EINVAL for invalid parameters or a grid
+ * when the context forces its grid at the nodes (ibdns_set_grid_forcing);
+ * ENOMEM if the workspace was sized for other bodies.  May be called once,
+ * before the first ibdns_step (ESTATE otherwise). */
+int ibdns_set_geometry(ibdns_ctx* ctx, const ibdns_grid* grid, const ibdns_flag* flag);
 
-/* Advance n_steps time steps, asynchronously on the context's stream. */
+/* The grid's solid points as built by ibdns_set_geometry: *count points and,
+ * when not NULL, their positions X (host, count*3, point-major) and volumes
+ * dV (host, count).  *count = 0 without a grid.  Synchronises. */
+int ibdns_get_grid_points(ibdns_ctx* ctx, int64_t* count, double* X, double* dV);
+
+/* Advance n_steps fractional time steps (Sec. II.B: provisional velocity,
+ * direct forcing of the bodies, pressure projection, the flag's own
+ * structural update), asynchronously on the context's stream.  EINVAL for
+ * n_steps < 0; EHIP if a launch failed.  Device-side failures are sticky
+ * and reported by the next synchronising call. */
 int ibdns_step(ibdns_ctx* ctx, int32_t n_steps);
 
-/* Wait for the stream and report the sticky device status. */
+/* Wait for the stream and report the sticky device status (EUNSTABLE,
+ * ETIMEOUT) of the steps so far. */
 int ibdns_sync(ibdns_ctx* ctx);
 
-/* Copy the current state to host arrays (any may be NULL): u, v, w, p in the
- * layouts above, the time t and the step count.  Synchronises. */
+/* Copy the state of Eqs. (2)-(3) to host arrays (any may be NULL): the
+ * staggered velocity u, v, w and the pressure p in the layouts above, the
+ * time t and the step count.  Synchronises; returns the sticky status. */
 int ibdns_get_fields(ibdns_ctx* ctx, double* u, double* v, double* w, double* p, double* t,
                      int64_t* step);
 
-/* Copy the flag's node positions X, velocities V and the hydrodynamic force
- * density F applied to the fluid at each node in the last step (host arrays of
- * ns*ns*3, any may be NULL).  Synchronises.  EINVAL if there is no flag. */
+/* Copy the flag's (Sec. II.A) node positions X, velocities V and the
+ * hydrodynamic force density F applied to the fluid at each node in the last
+ * step (host arrays of ns*ns*3, any may be NULL).  Synchronises; returns the
+ * sticky status.  EINVAL if there is no flag. */
 int ibdns_get_flag(ibdns_ctx* ctx, double* X, double* V, double* F);
 
-/* Release the context (not the workspace). */
+/* Release the context (not the workspace).  Waits for its streams; no call
+ * on the context may follow. */
 int ibdns_destroy(ibdns_ctx* ctx);
 
+/* Text of a status code. */
 const char* ibdns_strerror(int status);
 
 /* ------------------------------------------------------------------------
  * Eulerian direct forcing of the passive grid (Sec. II.B (i): the fixed grid
  * is imposed at the Eulerian velocity nodes, Fadlun et al. 2000), an
- * alternative to passing the grid as static points to ibdns_set_geometry.
+ * alternative to the grid's solid points of ibdns_set_geometry.
  *
- * Geometry (Sec. II.A): square rods of side bar at x = x_plane, rods along y
- * at z = lz/2 + (b + 1/2) mesh (mod lz), b < round(lz/mesh), rods along z at
- * y = ly/2 + (b + 1/2) mesh (mod ly), b < round(ly/mesh); a point is solid
- * when |x - x_plane| <= bar/2 and its periodic transverse distance to a rod's
- * centre line is <= bar/2.  Each step, before the flag's forcing, every
+ * Geometry (Sec. II.A): square rods of side d = bar at x = x_plane, rods
+ * along y at z = lz/2 + (b + 1/2) M (mod lz), b < round(lz/M), rods along z
+ * at y = ly/2 + (b + 1/2) M (mod ly), b < round(ly/M) (M = mesh); a point is
+ * solid when |x - x_plane| <= d/2 and its periodic transverse distance to a
+ * rod's centre line is <= d/2.  Each step, before the flag's forcing, every
  * evolved velocity node (u faces 1..nx-1, v and w cells 0..nx-1) that is
  * solid is set to 0; a fluid node with a solid neighbour among its six grid
  * neighbours takes u~(Q) delta/(delta + h), where the wall lies at distance
@@ -176,18 +228,16 @@ const char* ibdns_strerror(int status);
  * ---------------------------------------------------------------------- */
 
 /* Device bytes of the forcing lists of this domain and grid.  EINVAL for an
- * unsupported domain, non-positive mesh or bar, or a grid that reaches the
- * x ends. */
-int ibdns_grid_forcing_workspace_size(const ibdns_domain* d, double x_plane, double mesh, double bar,
-                                      size_t* bytes);
+ * unsupported domain, invalid grid parameters (as for ibdns_grid), or a grid
+ * that reaches the x ends. */
+int ibdns_grid_forcing_workspace_size(const ibdns_domain* d, const ibdns_grid* grid, size_t* bytes);
 
 /* Build the lists on the host and upload them into dev_ws (caller-owned, at
  * least ibdns_grid_forcing_workspace_size bytes, 256-byte aligned, kept alive
  * until ibdns_destroy).  Before the first ibdns_step, once; EINVAL if static
  * points were set (or are set later: ibdns_set_geometry then refuses them),
  * ESTATE after a step, ENOMEM if ws_bytes is short. */
-int ibdns_set_grid_forcing(ibdns_ctx* ctx, double x_plane, double mesh, double bar, void* dev_ws,
-                           size_t ws_bytes);
+int ibdns_set_grid_forcing(ibdns_ctx* ctx, const ibdns_grid* grid, void* dev_ws, size_t ws_bytes);
 
 /* The forcing list of component comp (0 u, 1 v, 2 w): *count entries; when
  * the arrays are not NULL, node and src receive host-layout indices

@@ -12,7 +12,10 @@ statistics.
 
 Only ``tests/``, ``__graft_entry__.smoke()`` and the ``cpu_baseline`` leg of
 ``bench.py`` may import this package.  The GPU library never imports it and
-shares no code with it; the only common module is ``synth`` (seeded inputs).
+shares no code with it; the only common module is ``synth`` (seeded inputs
+and workload parameters).  The immersed bodies are built here from the
+problem statement's parameters (``geometry``), independently of the
+library's own construction.
 
 Readings of passages the paper leaves open are stated where they are used,
 and collected in the design notes of the repository.
@@ -29,4 +32,5 @@ from .flag import FlagModel  # noqa: F401
 from .probes import ProbeStats, probe_positions, station_statistics  # noqa: F401
 from .grid_forcing import GridGeometry, forcing_list  # noqa: F401
 from .mls import mls_stencil, build_markers, node_load  # noqa: F401
+from .geometry import grid_points, grid_points_of, flag_lattice  # noqa: F401
 from .solver import Solver  # noqa: F401

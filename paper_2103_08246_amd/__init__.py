@@ -16,7 +16,7 @@ import numpy as np
 HERE = os.path.dirname(os.path.abspath(__file__))
 LIB_PATH = os.path.join(HERE, "libibdns.so")
 
-OK, EINVAL, ENOMEM, EHIP, EUNSTABLE, ESTATE = 0, -1, -2, -3, -4, -5
+OK, EINVAL, ENOMEM, EHIP, EUNSTABLE, ESTATE, ETIMEOUT = 0, -1, -2, -3, -4, -5, -6
 FP64, MIXED = 0, 1
 DIFFUSION_EXPLICIT, DIFFUSION_CN = 0, 1
 LE_HINGED, LE_CLAMPED = 0, 1
@@ -25,7 +25,8 @@ STAGE_PREDICT, STAGE_FLUX, STAGE_IBM, STAGE_PROJECT, STAGE_FLAG, STAGE_ADVANCE =
 (ARR_U, ARR_V, ARR_W, ARR_P, ARR_UT, ARR_VT, ARR_WT, ARR_HU, ARR_HV, ARR_HW, ARR_PHI,
  ARR_POINT_F, ARR_V_GHOST, ARR_W_GHOST) = range(14)
 
-EXPORTED = ("ibdns_workspace_size", "ibdns_init_domain", "ibdns_set_geometry", "ibdns_step",
+EXPORTED = ("ibdns_workspace_size", "ibdns_init_domain", "ibdns_set_geometry",
+            "ibdns_get_grid_points", "ibdns_step",
             "ibdns_sync", "ibdns_get_fields", "ibdns_get_flag", "ibdns_destroy",
             "ibdns_strerror", "ibdns_run_stage", "ibdns_get_array", "ibdns_set_array",
             "ibdns_get_scalars", "ibdns_set_time", "ibdns_get_maps", "ibdns_enable_timing",
@@ -46,10 +47,16 @@ class Domain(ctypes.Structure):
                 ("diffusion", ctypes.c_int32)]
 
 
+class GridParams(ctypes.Structure):
+    _fields_ = [("x_plane", ctypes.c_double), ("mesh", ctypes.c_double), ("bar", ctypes.c_double)]
+
+
 class FlagParams(ctypes.Structure):
     _fields_ = [("ns", ctypes.c_int32), ("length", ctypes.c_double),
-                ("mass_ratio", ctypes.c_double), ("bending", ctypes.c_double),
-                ("stretch", ctypes.c_double), ("le_bc", ctypes.c_int32)]
+                ("x_le", ctypes.c_double), ("y_c", ctypes.c_double), ("z_c", ctypes.c_double),
+                ("pitch", ctypes.c_double), ("mass_ratio", ctypes.c_double),
+                ("bending", ctypes.c_double), ("stretch", ctypes.c_double),
+                ("le_bc", ctypes.c_int32)]
 
 
 class IbdnsError(RuntimeError):
@@ -72,11 +79,12 @@ def _load():
     lib = ctypes.CDLL(LIB_PATH)
     P = ctypes.c_void_p
     D = ctypes.POINTER(ctypes.c_double)
-    lib.ibdns_workspace_size.argtypes = [ctypes.POINTER(Domain), ctypes.c_int64, ctypes.c_int32,
-                                         ctypes.POINTER(ctypes.c_size_t)]
+    lib.ibdns_workspace_size.argtypes = [ctypes.POINTER(Domain), ctypes.POINTER(GridParams),
+                                         ctypes.POINTER(FlagParams), ctypes.POINTER(ctypes.c_size_t)]
     lib.ibdns_init_domain.argtypes = [ctypes.POINTER(Domain), D, D, D, P, ctypes.c_size_t, P,
                                       ctypes.POINTER(P)]
-    lib.ibdns_set_geometry.argtypes = [P, ctypes.c_int64, D, D, ctypes.POINTER(FlagParams), D]
+    lib.ibdns_set_geometry.argtypes = [P, ctypes.POINTER(GridParams), ctypes.POINTER(FlagParams)]
+    lib.ibdns_get_grid_points.argtypes = [P, ctypes.POINTER(ctypes.c_int64), D, D]
     lib.ibdns_step.argtypes = [P, ctypes.c_int32]
     lib.ibdns_sync.argtypes = [P]
     lib.ibdns_get_fields.argtypes = [P, D, D, D, D, D, ctypes.POINTER(ctypes.c_int64)]
@@ -107,9 +115,9 @@ def _load():
     lib.ibdns_set_probes.argtypes = [P, ctypes.c_int32, dd, dd, dd, dd, dd, ctypes.c_int32, P,
                                      ctypes.c_size_t]
     lib.ibdns_get_probe_stats.argtypes = [P, D]
-    lib.ibdns_grid_forcing_workspace_size.argtypes = [ctypes.POINTER(Domain), dd, dd, dd,
+    lib.ibdns_grid_forcing_workspace_size.argtypes = [ctypes.POINTER(Domain), ctypes.POINTER(GridParams),
                                                       ctypes.POINTER(ctypes.c_size_t)]
-    lib.ibdns_set_grid_forcing.argtypes = [P, dd, dd, dd, P, ctypes.c_size_t]
+    lib.ibdns_set_grid_forcing.argtypes = [P, ctypes.POINTER(GridParams), P, ctypes.c_size_t]
     I64 = ctypes.POINTER(ctypes.c_int64)
     lib.ibdns_get_grid_forcing.argtypes = [P, ctypes.c_int32, I64, I64, I64, D]
     lib.ibdns_flag_mls_workspace_size.argtypes = [P, I64, ctypes.POINTER(ctypes.c_size_t)]
@@ -147,9 +155,13 @@ def make_domain(nx, ny, nz, lx, ly, lz, re, u_in=1.0, dt=0.0, cfl=0.5, noise_amp
     return Domain(nx, ny, nz, lx, ly, lz, re, u_in, dt, cfl, noise_amp, precision, flags, diffusion)
 
 
-def workspace_size(dom: Domain, n_points: int = 0, flag_ns: int = 0) -> int:
+def _ref(x):
+    return ctypes.byref(x) if x is not None else None
+
+
+def workspace_size(dom: Domain, grid: GridParams | None = None, flag: FlagParams | None = None) -> int:
     out = ctypes.c_size_t(0)
-    _check(_lib.ibdns_workspace_size(ctypes.byref(dom), n_points, flag_ns, ctypes.byref(out)),
+    _check(_lib.ibdns_workspace_size(ctypes.byref(dom), _ref(grid), _ref(flag), ctypes.byref(out)),
            "workspace_size")
     return out.value
 
@@ -166,17 +178,19 @@ def init_domain(dom: Domain, noise, ws_ptr: int, ws_bytes: int, stream_ptr: int)
     return ctx
 
 
-def set_geometry(ctx, points=None, flag: FlagParams | None = None, flag_X0=None):
-    n = 0
-    X = dV = None
-    if points is not None:
-        X = np.ascontiguousarray(points[0], dtype=np.float64).reshape(-1)
-        dV = np.ascontiguousarray(points[1], dtype=np.float64).reshape(-1)
-        n = dV.size
-    X0 = None if flag_X0 is None else np.ascontiguousarray(flag_X0, dtype=np.float64).reshape(-1)
-    _check(_lib.ibdns_set_geometry(ctx, n, _dptr(X), _dptr(dV),
-                                   ctypes.byref(flag) if flag is not None else None, _dptr(X0)),
-           "set_geometry")
+def set_geometry(ctx, grid: GridParams | None = None, flag: FlagParams | None = None):
+    _check(_lib.ibdns_set_geometry(ctx, _ref(grid), _ref(flag)), "set_geometry")
+
+
+def get_grid_points(ctx):
+    """(X (K, 3), dV (K,)) of the grid's solid points built by the library."""
+    n = ctypes.c_int64(0)
+    _check(_lib.ibdns_get_grid_points(ctx, ctypes.byref(n), None, None), "get_grid_points")
+    X = np.empty((n.value, 3))
+    dV = np.empty(n.value)
+    if n.value:
+        _check(_lib.ibdns_get_grid_points(ctx, ctypes.byref(n), _dptr(X), _dptr(dV)), "get_grid_points")
+    return X, dV
 
 
 def step(ctx, n: int = 1):
@@ -313,15 +327,15 @@ class Run:
             _check(code, "get_probe_stats")
         return out
 
-    def set_grid_forcing(self, dom: Domain, x_plane, mesh, bar, device="cuda:0"):
+    def set_grid_forcing(self, dom: Domain, grid: GridParams, device="cuda:0"):
         """Eulerian forcing of the passive grid (rule in include/ibdns.h); the
         workspace tensor is kept on this object."""
         import torch
         size = ctypes.c_size_t(0)
-        _check(_lib.ibdns_grid_forcing_workspace_size(ctypes.byref(dom), x_plane, mesh, bar,
+        _check(_lib.ibdns_grid_forcing_workspace_size(ctypes.byref(dom), ctypes.byref(grid),
                                                       ctypes.byref(size)), "grid_forcing_workspace_size")
         self.grid_ws = torch.empty(max(size.value, 256), dtype=torch.uint8, device=device)
-        _check(_lib.ibdns_set_grid_forcing(self.ctx, x_plane, mesh, bar,
+        _check(_lib.ibdns_set_grid_forcing(self.ctx, ctypes.byref(grid),
                                            ctypes.c_void_p(self.grid_ws.data_ptr()), self.grid_ws.numel()),
                "set_grid_forcing")
 
@@ -369,26 +383,37 @@ class Run:
             self.ctx = None
 
 
-def create(dom: Domain, noise=None, points=None, flag: FlagParams | None = None, flag_X0=None,
-           device="cuda:0", stream=None, grid_forcing=None, flag_mls=False) -> Run:
+def create(dom: Domain, noise=None, grid=None, flag=None, device="cuda:0", stream=None,
+           grid_forcing=None, flag_mls=False) -> Run:
     """Allocate the workspace with torch on ``device`` and build a context.
-    grid_forcing: an object with x_plane, mesh, bar for Eulerian forcing of the
-    passive grid (then points must be None).  flag_mls: couple the flag at its
-    tiling markers by MLS instead of at its nodes by the delta."""
+    grid: the passive grid as solid points; grid_forcing: the passive grid
+    forced at the Eulerian nodes instead (then grid must be None); both
+    GridParams or any object with x_plane, mesh, bar.  flag: FlagParams or any
+    object with its fields.  flag_mls: couple the flag at its tiling markers
+    by MLS instead of at its nodes by the delta."""
     import torch
-    n_points = 0 if points is None else int(np.asarray(points[1]).size)
+    if grid is not None and not isinstance(grid, GridParams):
+        grid = grid_from(grid)
+    if grid_forcing is not None and not isinstance(grid_forcing, GridParams):
+        grid_forcing = grid_from(grid_forcing)
+    if flag is not None and not isinstance(flag, FlagParams):
+        flag = flag_from(flag)
     ns = 0 if flag is None else flag.ns
-    nbytes = workspace_size(dom, n_points, ns)
+    nbytes = workspace_size(dom, grid, flag)
     ws = torch.empty(nbytes, dtype=torch.uint8, device=device)
     st = stream if stream is not None else torch.cuda.current_stream(device)
     ctx = init_domain(dom, noise, ws.data_ptr(), nbytes, st.cuda_stream)
     run = Run(ctx, ws, dom.nx, dom.ny, dom.nz, ns)
-    if grid_forcing is not None:
-        run.set_grid_forcing(dom, grid_forcing.x_plane, grid_forcing.mesh, grid_forcing.bar, device)
-    if points is not None or flag is not None:
-        set_geometry(ctx, points, flag, flag_X0)
-    if flag_mls:
-        run.set_flag_mls(device)
+    try:
+        if grid_forcing is not None:
+            run.set_grid_forcing(dom, grid_forcing, device)
+        if grid is not None or flag is not None:
+            set_geometry(ctx, grid, flag)
+        if flag_mls:
+            run.set_flag_mls(device)
+    except Exception:
+        run.close()
+        raise
     return run
 
 
@@ -398,9 +423,20 @@ def domain_from(w, precision=FP64, flags=0, diffusion=DIFFUSION_EXPLICIT) -> Dom
                        w.noise_amp, precision, flags, diffusion)
 
 
-def flag_from(f) -> FlagParams:
-    """FlagParams from any object with ns, length, mass_ratio, bending, stretch, le_bc."""
-    return FlagParams(f.ns, f.length, f.mass_ratio, f.bending, f.stretch, f.le_bc)
+def flag_from(f) -> FlagParams | None:
+    """FlagParams from any object with ns, length, x_le, y_c, z_c, pitch,
+    mass_ratio, bending, stretch, le_bc (None passes through)."""
+    if f is None:
+        return None
+    return FlagParams(f.ns, f.length, f.x_le, f.y_c, f.z_c, f.pitch, f.mass_ratio, f.bending,
+                      f.stretch, f.le_bc)
+
+
+def grid_from(g) -> GridParams | None:
+    """GridParams from any object with x_plane, mesh, bar (None passes through)."""
+    if g is None:
+        return None
+    return GridParams(g.x_plane, g.mesh, g.bar)
 
 
 def autotune(ctx) -> int:

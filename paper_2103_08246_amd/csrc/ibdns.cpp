@@ -178,6 +178,104 @@ int validate(const ibdns_domain* d) {
   return IBDNS_OK;
 }
 
+// ---- immersed bodies from the problem statement (Sec. II.A) ----
+// Written without contraction into fused multiply-adds, so that positions are
+// the plain double expressions stated with the declarations.
+#pragma clang fp contract(off)
+
+// Rod axis positions lc/2 + (b + 1/2) M, wrapped into [0, lc), b < round(lc/M).
+std::vector<double> rod_axes(double lc, double M) {
+  std::vector<double> c;
+  const long n = (long)std::floor(lc / M + 0.5);
+  for (long b = 0; b < n; ++b) {
+    double x = 0.5 * lc + ((double)b + 0.5) * M;
+    if (x >= lc) x = x - lc;
+    c.push_back(x);
+  }
+  return c;
+}
+
+double wrap_into(double a, double lc) {
+  if (a < 0.0) return a + lc;
+  if (a >= lc) return a - lc;
+  return a;
+}
+
+bool grid_params_ok(const ibdns_domain& dm, const ibdns_grid& g) {
+  return std::isfinite(g.x_plane) && g.mesh > 0.0 && g.bar > 0.0 && g.bar < g.mesh &&
+         g.mesh <= std::min(dm.ly, dm.lz) && std::isfinite(g.mesh) && std::isfinite(g.bar);
+}
+
+// Solid points of the passive grid: nc x nc points per rod cross-section
+// (nc = max(1, floor(d/h + 1/2)), offsets (q + 1/2) d/nc - d/2 about the rod
+// axis and the plane), one cross-section every h along the rod at (m + 1/2) h;
+// rods along y at z = lz/2 + (b + 1/2) M, rods along z at y = ly/2 + (b + 1/2) M
+// (mod the box); a z-rod cross-section strictly within d/2 of a y-rod axis is
+// left out.  Volume (d/nc)^2 h each.  Order: y-rods, then z-rods; position
+// along the rod, streamwise offset, transverse offset.
+int build_grid_points(const ibdns_domain& dm, const ibdns_grid& g, std::vector<double>& X,
+                      std::vector<double>& dV) {
+  if (!grid_params_ok(dm, g)) return IBDNS_EINVAL;
+  const double h = dm.lx / dm.nx, d = g.bar;
+  const int nc = std::max(1, (int)std::floor(d / h + 0.5));
+  std::vector<double> offs(nc);
+  for (int q = 0; q < nc; ++q) offs[q] = ((double)q + 0.5) * (d / nc) - 0.5 * d;
+  const std::vector<double> zax = rod_axes(dm.lz, g.mesh), yax = rod_axes(dm.ly, g.mesh);
+  const double vol = (d / nc) * (d / nc) * h;
+  auto put = [&](double x, double y, double z) {
+    X.push_back(x);
+    X.push_back(y);
+    X.push_back(z);
+    dV.push_back(vol);
+  };
+  for (double zc : zax)
+    for (int m = 0; m < dm.ny; ++m) {
+      const double y = ((double)m + 0.5) * h;
+      for (double ox : offs)
+        for (double ot : offs) put(g.x_plane + ox, y, wrap_into(zc + ot, dm.lz));
+    }
+  for (double yc : yax)
+    for (int m = 0; m < dm.nz; ++m) {
+      const double z = ((double)m + 0.5) * h;
+      bool covered = false;
+      for (double zc : zax) {
+        const double dz = std::fabs(z - zc);
+        if (std::min(dz, dm.lz - dz) < 0.5 * d) covered = true;
+      }
+      if (covered) continue;
+      for (double ox : offs)
+        for (double ot : offs) put(g.x_plane + ox, wrap_into(yc + ot, dm.ly), z);
+    }
+  return IBDNS_OK;
+}
+
+bool flag_params_ok(const ibdns_flag& f) {
+  if (f.ns < 3 || f.ns > 128) return false;
+  if (!(f.length > 0 && f.mass_ratio > 0 && f.bending >= 0 && f.stretch >= 0)) return false;
+  if (f.bending == 0 && f.stretch == 0) return false;
+  if (!std::isfinite(f.x_le) || !std::isfinite(f.y_c) || !std::isfinite(f.z_c) || !std::isfinite(f.pitch))
+    return false;
+  return f.le_bc == IBDNS_LE_HINGED || f.le_bc == IBDNS_LE_CLAMPED;
+}
+
+// Reference lattice: node (a, b) at (x_le, y_c, z_c - L/2) + a ds (cos t, sin t, 0)
+// + b ds (0, 0, 1), ds = L/(ns - 1); X0[(a + ns b) * 3 + c].
+void build_flag_lattice(const ibdns_flag& f, std::vector<double>& X0) {
+  const int ns = f.ns;
+  const double ds = f.length / (ns - 1), ct = std::cos(f.pitch), st = std::sin(f.pitch);
+  const double z0 = f.z_c - 0.5 * f.length;
+  X0.assign(3 * (size_t)ns * ns, 0.0);
+  for (int b = 0; b < ns; ++b)
+    for (int a = 0; a < ns; ++a) {
+      double* x = &X0[3 * ((size_t)a + (size_t)ns * b)];
+      x[0] = f.x_le + ((double)a * ds) * ct;
+      x[1] = f.y_c + ((double)a * ds) * st;
+      x[2] = z0 + (double)b * ds;
+    }
+}
+
+#pragma clang fp contract(on)
+
 #define HIPCHK(x)                        \
   do {                                   \
     if ((x) != hipSuccess) return IBDNS_EHIP; \
@@ -327,11 +425,18 @@ int check_launch(ibdns_ctx* c = nullptr) {
   return bad ? IBDNS_EHIP : IBDNS_OK;
 }
 
+// Status code of the sticky device bits: a flag band that timed out leaves an
+// inconsistent flag and takes precedence over the instability bits.
+int status_code(int bits) {
+  if (bits & ST_FLAG_WAIT) return IBDNS_ETIMEOUT;
+  return bits ? IBDNS_EUNSTABLE : IBDNS_OK;
+}
+
 int read_status(ibdns_ctx* c) {
   if (hipStreamSynchronize(c->st) != hipSuccess) return IBDNS_EHIP;
   Scalars hs;
   if (hipMemcpy(&hs, c->s, sizeof(Scalars), hipMemcpyDeviceToHost) != hipSuccess) return IBDNS_EHIP;
-  return hs.status ? IBDNS_EUNSTABLE : IBDNS_OK;
+  return status_code(hs.status);
 }
 
 // Host array dimensions of a field id: x extent (nx+1 or nx) and device pointer.
@@ -425,16 +530,25 @@ const char* ibdns_strerror(int status) {
     case IBDNS_ENOMEM: return "workspace too small";
     case IBDNS_EHIP: return "HIP runtime error";
     case IBDNS_EUNSTABLE: return "unstable: non-finite velocity, CFL > 1 or immersed point out of range";
+    case IBDNS_ETIMEOUT: return "flag sub-step exchange between bands timed out: the flag state of that step is partly advanced";
     case IBDNS_ESTATE: return "call out of order";
     default: return "unknown status";
   }
 }
 
-int ibdns_workspace_size(const ibdns_domain* d, int64_t n_points, int32_t flag_ns, size_t* bytes) {
+int ibdns_workspace_size(const ibdns_domain* d, const ibdns_grid* grid, const ibdns_flag* flag,
+                         size_t* bytes) {
   int v = validate(d);
   if (v) return v;
-  if (!bytes || n_points < 0 || flag_ns < 0) return IBDNS_EINVAL;
-  *bytes = fluid_bytes(*d) + points_bytes(n_points) + flag_bytes(flag_ns) + ALIGN;
+  if (!bytes) return IBDNS_EINVAL;
+  if (flag && !flag_params_ok(*flag)) return IBDNS_EINVAL;
+  int64_t n_points = 0;
+  if (grid) {
+    std::vector<double> X, dV;
+    if ((v = build_grid_points(*d, *grid, X, dV))) return v;
+    n_points = (int64_t)dV.size();
+  }
+  *bytes = fluid_bytes(*d) + points_bytes(n_points) + flag_bytes(flag ? flag->ns : 0) + ALIGN;
   return IBDNS_OK;
 }
 
@@ -573,18 +687,18 @@ int ibdns_init_domain(const ibdns_domain* dm, const double* zu, const double* zv
   return IBDNS_OK;
 }
 
-int ibdns_set_geometry(ibdns_ctx* c, int64_t n_points, const double* X, const double* dV,
-                       const ibdns_flag* flag, const double* flag_X0) {
-  if (!c) return IBDNS_EINVAL;
-  if (c->geometry_set || c->stepped) return IBDNS_ESTATE;
-  if (n_points < 0 || (n_points > 0 && (!X || !dV))) return IBDNS_EINVAL;
+}  // extern "C"
+
+namespace {
+
+// Static solid points (host arrays X: n*3, dV: n): stencil centres on the
+// host for the transposed spreading map, then the device point set.
+int set_points(ibdns_ctx* c, int64_t n_points, const double* X, const double* dV) {
   if (27 * n_points >= (1LL << 31)) return IBDNS_EINVAL;
-  if (n_points > 0 && c->has_gforce) return IBDNS_EINVAL;   // the grid is forced at its nodes
   const Dims& d = c->d;
   const double h = d.h;
   const int nx = d.nx;
-  // ---- static points: stencil centres on the host for the transposed map ----
-  if (n_points > 0) {
+  {
     const int64_t n = n_points;
     std::vector<std::vector<std::pair<int, int>>> pairs(3);
     for (int comp = 0; comp < 3; ++comp) {
@@ -654,13 +768,17 @@ int ibdns_set_geometry(ibdns_ctx* c, int64_t n_points, const double* X, const do
     c->nbars = n;
     launch_point_stencil(d, ps, c->s, c->st);
   }
-  // ---- flag ----
-  if (flag) {
+  return IBDNS_OK;
+}
+
+// The flag (parameters checked by flag_params_ok) on its reference lattice
+// flag_X0 (host, ns*ns*3).
+int set_flag(ibdns_ctx* c, const ibdns_flag* flag, const double* flag_X0) {
+  const Dims& d = c->d;
+  const double h = d.h;
+  const int nx = d.nx;
+  {
     const int ns = flag->ns;
-    if (ns < 3 || ns > 128 || !flag_X0) return IBDNS_EINVAL;
-    if (!(flag->length > 0 && flag->mass_ratio > 0 && flag->bending >= 0 && flag->stretch >= 0))
-      return IBDNS_EINVAL;
-    if (flag->bending == 0 && flag->stretch == 0) return IBDNS_EINVAL;
     const double L = flag->length;
     if (L > std::min(c->dom.ly, c->dom.lz) - 4 * h) return IBDNS_EINVAL;
     const int n = ns * ns;
@@ -791,8 +909,46 @@ int ibdns_set_geometry(ibdns_ctx* c, int64_t n_points, const double* X, const do
     c->has_flag = true;
     if (ensure_side(c) != IBDNS_OK) return IBDNS_EHIP;
   }
+  return IBDNS_OK;
+}
+
+}  // namespace
+
+extern "C" {
+
+int ibdns_set_geometry(ibdns_ctx* c, const ibdns_grid* grid, const ibdns_flag* flag) {
+  if (!c) return IBDNS_EINVAL;
+  if (c->geometry_set || c->stepped) return IBDNS_ESTATE;
+  if (grid && c->has_gforce) return IBDNS_EINVAL;   // the grid is forced at its nodes
+  if (flag && !flag_params_ok(*flag)) return IBDNS_EINVAL;
+  std::vector<double> X, dV;
+  if (grid) {
+    int r = build_grid_points(c->dom, *grid, X, dV);
+    if (r) return r;
+  }
+  if (!X.empty()) {
+    int r = set_points(c, (int64_t)dV.size(), X.data(), dV.data());
+    if (r) return r;
+  }
+  if (flag) {
+    std::vector<double> X0;
+    build_flag_lattice(*flag, X0);
+    int r = set_flag(c, flag, X0.data());
+    if (r) return r;
+  }
   c->geometry_set = true;
   if (check_launch() != IBDNS_OK || hipStreamSynchronize(c->st) != hipSuccess) return IBDNS_EHIP;
+  return IBDNS_OK;
+}
+
+int ibdns_get_grid_points(ibdns_ctx* c, int64_t* count, double* X, double* dV) {
+  if (!c || !count) return IBDNS_EINVAL;
+  *count = c->nbars;
+  if (hipStreamSynchronize(c->st) != hipSuccess) return IBDNS_EHIP;
+  if (c->nbars == 0) return IBDNS_OK;
+  if ((X && hipMemcpy(X, c->bars.X, 3 * c->nbars * sizeof(double), hipMemcpyDeviceToHost) != hipSuccess) ||
+      (dV && hipMemcpy(dV, c->bars.dV, c->nbars * sizeof(double), hipMemcpyDeviceToHost) != hipSuccess))
+    return IBDNS_EHIP;
   return IBDNS_OK;
 }
 
@@ -850,7 +1006,7 @@ int ibdns_get_fields(ibdns_ctx* c, double* u, double* v, double* w, double* p, d
   if (hipMemcpy(&hs, c->s, sizeof(Scalars), hipMemcpyDeviceToHost) != hipSuccess) return IBDNS_EHIP;
   if (t) *t = hs.t;
   if (step) *step = hs.step;
-  return hs.status ? IBDNS_EUNSTABLE : IBDNS_OK;
+  return status_code(hs.status);
 }
 
 int ibdns_get_flag(ibdns_ctx* c, double* X, double* V, double* F) {
@@ -870,16 +1026,6 @@ int ibdns_get_flag(ibdns_ctx* c, double* X, double* V, double* F) {
 namespace {
 
 // Eulerian grid forcing lists (the rule stated with the declarations).
-std::vector<double> rod_centres(double L, double M) {
-  std::vector<double> c;
-  const long n = std::lround(L / M);
-  for (long b = 0; b < n; ++b) {
-    double x = 0.5 * L + (b + 0.5) * M;
-    if (x >= L) x -= L;
-    c.push_back(x);
-  }
-  return c;
-}
 double pdist(double a, double c, double L) {
   const double d = std::fabs(a - c);
   return std::min(d, L - d);
@@ -897,7 +1043,7 @@ int build_grid_lists(const ibdns_domain& dm, int P, double xp, double M, double 
   if (!(M > 0.0) || !(bar > 0.0) || !std::isfinite(xp)) return IBDNS_EINVAL;
   if (!(xp - half - 2 * h > 0.0) || !(xp + half + 2 * h < dm.lx)) return IBDNS_EINVAL;
   if ((long long)P * ny * nz >= (1LL << 31)) return IBDNS_EINVAL;
-  const std::vector<double> zc = rod_centres(dm.lz, M), yc = rod_centres(dm.ly, M);
+  const std::vector<double> zc = rod_axes(dm.lz, M), yc = rod_axes(dm.ly, M);
   for (int comp = 0; comp < 3; ++comp) {
     const double o[3] = {comp == 0 ? 0.0 : 0.5, comp == 1 ? 0.0 : 0.5, comp == 2 ? 0.0 : 0.5};
     const int ilo = comp == 0 ? 1 : 0, ihi = nx - 1;
@@ -998,25 +1144,25 @@ size_t grid_lists_bytes(const GridLists& g) {
 
 extern "C" {
 
-int ibdns_grid_forcing_workspace_size(const ibdns_domain* d, double x_plane, double mesh, double bar,
-                                      size_t* bytes) {
+int ibdns_grid_forcing_workspace_size(const ibdns_domain* d, const ibdns_grid* grid, size_t* bytes) {
   size_t dummy = 0;
-  if (!d || !bytes || ibdns_workspace_size(d, 0, 0, &dummy) != IBDNS_OK) return IBDNS_EINVAL;
+  if (!d || !grid || !bytes || ibdns_workspace_size(d, nullptr, nullptr, &dummy) != IBDNS_OK) return IBDNS_EINVAL;
+  if (!grid_params_ok(*d, *grid)) return IBDNS_EINVAL;
   GridLists g;
-  const int r = build_grid_lists(*d, row_pitch(*d), x_plane, mesh, bar, g);
+  const int r = build_grid_lists(*d, row_pitch(*d), grid->x_plane, grid->mesh, grid->bar, g);
   if (r != IBDNS_OK) return r;
   *bytes = grid_lists_bytes(g);
   return IBDNS_OK;
 }
 
-int ibdns_set_grid_forcing(ibdns_ctx* c, double x_plane, double mesh, double bar, void* dev_ws,
-                           size_t ws_bytes) {
-  if (!c) return IBDNS_EINVAL;
+int ibdns_set_grid_forcing(ibdns_ctx* c, const ibdns_grid* grid, void* dev_ws, size_t ws_bytes) {
+  if (!c || !grid) return IBDNS_EINVAL;
   if (c->stepped || c->has_gforce) return IBDNS_ESTATE;
   if (c->nbars > 0) return IBDNS_EINVAL;
   if (!dev_ws || (reinterpret_cast<uintptr_t>(dev_ws) % ALIGN) != 0) return IBDNS_EINVAL;
+  if (!grid_params_ok(c->dom, *grid)) return IBDNS_EINVAL;
   GridLists g;
-  const int r = build_grid_lists(c->dom, c->d.P, x_plane, mesh, bar, g);
+  const int r = build_grid_lists(c->dom, c->d.P, grid->x_plane, grid->mesh, grid->bar, g);
   if (r != IBDNS_OK) return r;
   if (ws_bytes < grid_lists_bytes(g)) return IBDNS_ENOMEM;
   char* p = static_cast<char*>(dev_ws);
@@ -1415,7 +1561,7 @@ int ibdns_get_scalars(ibdns_ctx* c, double* out6) {
   out6[3] = hs.speed_last;
   out6[4] = hs.corr;
   out6[5] = hs.nsub;
-  return hs.status ? IBDNS_EUNSTABLE : IBDNS_OK;
+  return status_code(hs.status);
 }
 
 int ibdns_set_time(ibdns_ctx* c, double dt, double dt_prev, int32_t first_step) {

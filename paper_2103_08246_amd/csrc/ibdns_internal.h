@@ -55,7 +55,10 @@ struct Scalars {
   int pad1;
 };
 
-enum StatusBits : int { ST_NONFINITE = 1, ST_CFL = 2, ST_RANGE = 4 };
+// ST_FLAG_WAIT: a flag band gave up waiting for a neighbour's sub-step
+// (bounded spin); its rows were not written back, so the flag state of that
+// step is partly advanced.
+enum StatusBits : int { ST_NONFINITE = 1, ST_CFL = 2, ST_RANGE = 4, ST_FLAG_WAIT = 8 };
 
 struct Fields {
   double *u, *v, *w, *p;

@@ -234,7 +234,7 @@ __device__ __forceinline__ void flag_body(const FlagDev& fl, Scalars* s, const i
         __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "agent");
         if (!ok) {
           abort_flag = 1;
-          atomicOr(&s->status, (int)ST_RANGE);
+          atomicOr(&s->status, (int)ST_FLAG_WAIT);
         }
       }
       __syncthreads();

@@ -1,11 +1,11 @@
 """Seeded synthetic inputs shared by the oracle and the GPU library.
 
-This module holds only *inputs*: the workload parameters, the Gaussian noise
-of the initial condition, and the geometry of the immersed bodies (solid
-points of the passive grid, reference lattice of the flag).  It contains none
-of the time step's arithmetic.  The oracle (``oracle/``) and the HIP library
-(``paper_2103_08246_amd``) both receive these arrays and never import each
-other.
+This module holds only *inputs*: the workload parameters (box, Re, the
+passive grid's and the flag's parameters) and the Gaussian noise of the
+initial condition.  It contains none of the time step's arithmetic and builds
+no geometry: the library builds its bodies from the parameters, and the
+oracle builds its own (``oracle/geometry.py``).  The oracle (``oracle/``) and
+the HIP library (``paper_2103_08246_amd``) never import each other.
 
 Problem statement (paper, Sec. II.A and Fig. 1): a box with uniform inflow
 (U, 0, 0), convective outflow, periodic y and z; a monoplane passive grid of
@@ -16,7 +16,7 @@ pitched by theta = 0.1 pi.
 from __future__ import annotations
 
 import math
-from dataclasses import dataclass, field, replace
+from dataclasses import dataclass, replace
 from typing import Optional
 
 import numpy as np
@@ -155,96 +155,3 @@ def ic_noise(w: Workload):
     zv = rng.standard_normal((w.nz, w.ny, w.nx))
     zw = rng.standard_normal((w.nz, w.ny, w.nx))
     return zu, zv, zw
-
-
-# --------------------------------------------------------------------------------------
-# Body geometry
-# --------------------------------------------------------------------------------------
-
-def bar_points(w: Workload):
-    """Solid points of the passive grid (monoplane, square rods; Sec. II.A).
-
-    Each rod carries an nc x nc lattice of points per cross-section,
-    nc = max(1, round(d/h)), at offsets (q + 1/2) d/nc - d/2, repeated every h
-    along the rod at (m + 1/2) h.  Rods running along y sit at
-    z = Lz/2 + (b + 1/2) M (mod Lz); rods running along z sit at
-    y = Ly/2 + (b + 1/2) M (mod Ly), so the box centre faces an opening.
-    Points of a z-rod that fall strictly inside a y-rod's cross-section are
-    dropped.  Each point carries the volume (d/nc)^2 h and target velocity 0.
-
-    Order: y-rods then z-rods; rod, then position along the rod, then the
-    streamwise offset, then the transverse offset.
-    Returns X (K, 3) and dV (K,).
-    """
-    g = w.grid
-    if g is None:
-        return np.zeros((0, 3)), np.zeros(0)
-    h = w.h
-    d = g.bar
-    nc = max(1, int(round(d / h)))
-    nby = int(round(w.lz / g.mesh))   # rods along y, indexed by z position
-    nbz = int(round(w.ly / g.mesh))   # rods along z, indexed by y position
-    offs = [(q + 0.5) * (d / nc) - 0.5 * d for q in range(nc)]
-    zc_list = []
-    for b in range(nby):
-        zc = 0.5 * w.lz + (b + 0.5) * g.mesh
-        if zc >= w.lz:
-            zc -= w.lz
-        zc_list.append(zc)
-    yc_list = []
-    for b in range(nbz):
-        yc = 0.5 * w.ly + (b + 0.5) * g.mesh
-        if yc >= w.ly:
-            yc -= w.ly
-        yc_list.append(yc)
-    pts = []
-    for zc in zc_list:                      # rods along y
-        for m in range(w.ny):
-            y = (m + 0.5) * h
-            for ox in offs:
-                for ot in offs:
-                    pts.append((g.x_plane + ox, y, zc + ot))
-    for yc in yc_list:                      # rods along z
-        for m in range(w.nz):
-            z = (m + 0.5) * h
-            inside = False
-            for zc in zc_list:
-                dz = abs(z - zc)
-                dz = min(dz, w.lz - dz)
-                if dz < 0.5 * d:
-                    inside = True
-                    break
-            if inside:
-                continue
-            for ox in offs:
-                for ot in offs:
-                    pts.append((g.x_plane + ox, yc + ot, z))
-    X = np.array(pts, dtype=np.float64).reshape(-1, 3)
-    # positions may fall outside [0, L) by less than d/2 near the periodic seam
-    X[:, 1] = np.where(X[:, 1] < 0.0, X[:, 1] + w.ly, X[:, 1])
-    X[:, 1] = np.where(X[:, 1] >= w.ly, X[:, 1] - w.ly, X[:, 1])
-    X[:, 2] = np.where(X[:, 2] < 0.0, X[:, 2] + w.lz, X[:, 2])
-    X[:, 2] = np.where(X[:, 2] >= w.lz, X[:, 2] - w.lz, X[:, 2])
-    dV = np.full(X.shape[0], (d / nc) * (d / nc) * h)
-    return X, dV
-
-
-def flag_reference(w: Workload):
-    """Initial (reference) flag lattice, straight and pitched (Sec. II.A).
-
-    Node (a, b), a streamwise from the leading edge, b spanwise:
-    X = (x_le, y_c, z_c - L/2) + a ds (cos theta, sin theta, 0) + b ds (0, 0, 1),
-    ds = L / (ns - 1).  Returned with shape (ns, ns, 3) indexed [b, a, component].
-    """
-    f = w.flag
-    ns = f.ns
-    ds = f.length / (ns - 1)
-    ct, st = math.cos(f.pitch), math.sin(f.pitch)
-    X = np.empty((ns, ns, 3))
-    z0 = f.z_c - 0.5 * f.length
-    for b in range(ns):
-        for a in range(ns):
-            X[b, a, 0] = f.x_le + (a * ds) * ct
-            X[b, a, 1] = f.y_c + (a * ds) * st
-            X[b, a, 2] = z0 + b * ds
-    return X

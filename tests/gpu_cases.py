@@ -3,6 +3,7 @@ the HIP library (through the C ABI binding) and to the oracle."""
 import numpy as np
 
 import synth
+from oracle import geometry
 
 
 def oracle_flag_args(w, X0):
@@ -16,10 +17,10 @@ def build_pair(w, hooks=0, with_noise=True):
     import paper_2103_08246_amd as ib
     from oracle.solver import Solver
     noise = synth.ic_noise(w) if with_noise else None
-    bars = synth.bar_points(w) if w.grid is not None else None
-    X0 = synth.flag_reference(w) if w.flag is not None else None
-    run = ib.create(ib.domain_from(w, flags=hooks), noise, points=bars,
-                    flag=ib.flag_from(w.flag) if w.flag is not None else None, flag_X0=X0)
+    bars = geometry.grid_points_of(w) if w.grid is not None else None
+    X0 = geometry.flag_lattice(w.flag) if w.flag is not None else None
+    run = ib.create(ib.domain_from(w, flags=hooks), noise, grid=w.grid if bars is not None else None,
+                    flag=ib.flag_from(w.flag) if w.flag is not None else None)
     S = Solver(w, noise, bars, oracle_flag_args(w, X0) if X0 is not None else None, hooks=hooks)
     return run, S
 

@@ -28,7 +28,8 @@ def test_library_exports_every_declared_symbol():
 def test_workspace_size_validation():
     import paper_2103_08246_amd as ib
     good = ib.make_domain(64, 32, 32, 4.0, 2.0, 2.0, 200.0, dt=1e-3)
-    n = ib.workspace_size(good, 0, 16)
+    flag = ib.FlagParams(16, 1.0, 1.0, 1.0, 1.0, 0.1, 1.0, 0.01, 1e4, ib.LE_HINGED)
+    n = ib.workspace_size(good, None, flag)
     P = 80  # pitch of nx+1 = 65 rounded to 16
     assert n > 11 * P * 32 * 32 * 8
     bad = [ib.make_domain(64, 30, 32, 4.0, 1.875, 2.0, 200.0, dt=1e-3),   # 30 = 2*3*5
@@ -38,7 +39,7 @@ def test_workspace_size_validation():
            ib.make_domain(64, 32, 32, 4.0, 2.0, 2.0, 200.0, dt=1e-3, precision=7)]
     # mixed precision pads rows to 32 elements (FP32 rows on 128-byte lines): 96, not 80
     m = ib.workspace_size(ib.make_domain(64, 32, 32, 4.0, 2.0, 2.0, 200.0, dt=1e-3,
-                                         precision=ib.MIXED), 0, 16)
+                                         precision=ib.MIXED), None, flag)
     assert m > 11 * 96 * 32 * 32 * 8 and m > n
     for d in bad:
         with pytest.raises(ib.IbdnsError) as e:
@@ -69,9 +70,34 @@ def test_diffusion_mode_validation():
     out = ctypes.c_size_t(0)
     lib = ib.lib()
     cn = ib.make_domain(64, 32, 32, 4.0, 2.0, 2.0, 200.0, dt=1e-3, diffusion=ib.DIFFUSION_CN)
-    assert lib.ibdns_workspace_size(ctypes.byref(cn), 0, 0, ctypes.byref(out)) == ib.OK
+    assert lib.ibdns_workspace_size(ctypes.byref(cn), None, None, ctypes.byref(out)) == ib.OK
     cn_mixed = ib.make_domain(64, 32, 32, 4.0, 2.0, 2.0, 200.0, dt=1e-3, precision=ib.MIXED,
                               diffusion=ib.DIFFUSION_CN)
-    assert lib.ibdns_workspace_size(ctypes.byref(cn_mixed), 0, 0, ctypes.byref(out)) == ib.OK
+    assert lib.ibdns_workspace_size(ctypes.byref(cn_mixed), None, None, ctypes.byref(out)) == ib.OK
     bad = ib.make_domain(64, 32, 32, 4.0, 2.0, 2.0, 200.0, dt=1e-3, diffusion=2)
-    assert lib.ibdns_workspace_size(ctypes.byref(bad), 0, 0, ctypes.byref(out)) == ib.EINVAL
+    assert lib.ibdns_workspace_size(ctypes.byref(bad), None, None, ctypes.byref(out)) == ib.EINVAL
+
+
+def test_body_parameter_validation():
+    """Invalid grid and flag parameters are refused on the host (Sec. II.A:
+    rods thinner than their spacing; a flag of 3..128 nodes per side with
+    positive length and mass)."""
+    import paper_2103_08246_amd as ib
+    dom = ib.make_domain(64, 32, 32, 4.0, 2.0, 2.0, 200.0, dt=1e-3)
+    base = ib.workspace_size(dom)
+    with_grid = ib.workspace_size(dom, ib.GridParams(1.0, 0.5, 0.1))
+    assert with_grid > base
+    for g in (ib.GridParams(1.0, 0.5, 0.5), ib.GridParams(1.0, 0.0, 0.1), ib.GridParams(1.0, 0.5, -0.1),
+              ib.GridParams(float("nan"), 0.5, 0.1), ib.GridParams(1.0, 3.0, 0.1)):
+        with pytest.raises(ib.IbdnsError) as e:
+            ib.workspace_size(dom, g)
+        assert e.value.code == ib.EINVAL
+    ok = dict(ns=8, length=1.0, x_le=1.0, y_c=1.0, z_c=1.0, pitch=0.3, mass_ratio=1.0, bending=0.01,
+              stretch=1e4, le_bc=ib.LE_HINGED)
+    assert ib.workspace_size(dom, None, ib.FlagParams(**ok)) > base
+    for bad in (dict(ns=2), dict(ns=129), dict(length=0.0), dict(mass_ratio=0.0),
+                dict(bending=0.0, stretch=0.0), dict(le_bc=5), dict(pitch=float("inf"))):
+        with pytest.raises(ib.IbdnsError) as e:
+            ib.workspace_size(dom, None, ib.FlagParams(**dict(ok, **bad)))
+        assert e.value.code == ib.EINVAL
+    assert ib.strerror(ib.ETIMEOUT).startswith("flag sub-step exchange")

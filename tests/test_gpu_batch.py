@@ -7,6 +7,7 @@ import numpy as np
 import pytest
 
 import synth
+from oracle import geometry
 from tests.test_gpu_parity import small_grid_flag
 
 pytestmark = pytest.mark.gpu
@@ -21,10 +22,10 @@ def members():
 
 def make(w, precision=ib.FP64):
     noise = synth.ic_noise(w)
-    bars = synth.bar_points(w) if w.grid is not None else None
-    X0 = synth.flag_reference(w) if w.flag is not None else None
-    return ib.create(ib.domain_from(w, precision=precision), noise, points=bars,
-                     flag=ib.flag_from(w.flag) if w.flag is not None else None, flag_X0=X0)
+    bars = geometry.grid_points_of(w) if w.grid is not None else None
+    X0 = geometry.flag_lattice(w.flag) if w.flag is not None else None
+    return ib.create(ib.domain_from(w, precision=precision), noise, grid=w.grid if bars is not None else None,
+                     flag=ib.flag_from(w.flag) if w.flag is not None else None)
 
 
 @pytest.mark.parametrize("graph,tune,precision", [(False, False, ib.FP64), (True, False, ib.FP64),

@@ -6,6 +6,7 @@ import numpy as np
 import pytest
 
 import synth
+from oracle import geometry
 from tests.gpu_cases import oracle_flag_args, rel_l2
 from tests.test_gpu_parity import small_grid_flag
 
@@ -16,10 +17,10 @@ ib = pytest.importorskip("paper_2103_08246_amd")
 def _pair(w, bars=True):
     from oracle.solver import Solver
     noise = synth.ic_noise(w)
-    pts = synth.bar_points(w) if (bars and w.grid is not None) else None
-    X0 = synth.flag_reference(w) if w.flag is not None else None
-    run = ib.create(ib.domain_from(w, diffusion=ib.DIFFUSION_CN), noise, points=pts,
-                    flag=ib.flag_from(w.flag) if w.flag is not None else None, flag_X0=X0)
+    pts = geometry.grid_points_of(w) if (bars and w.grid is not None) else None
+    X0 = geometry.flag_lattice(w.flag) if w.flag is not None else None
+    run = ib.create(ib.domain_from(w, diffusion=ib.DIFFUSION_CN), noise, grid=w.grid if pts is not None else None,
+                    flag=ib.flag_from(w.flag) if w.flag is not None else None)
     S = Solver(w, noise, pts, oracle_flag_args(w, X0) if X0 is not None else None, diffusion="cn")
     return run, S
 
@@ -91,10 +92,10 @@ def test_cn_mixed_vs_fp64_oracle(make):
     from oracle import fluid
     w = make()
     noise = synth.ic_noise(w)
-    pts = synth.bar_points(w) if w.grid is not None else None
-    X0 = synth.flag_reference(w)
-    run = ib.create(ib.domain_from(w, precision=ib.MIXED, diffusion=ib.DIFFUSION_CN), noise, points=pts,
-                    flag=ib.flag_from(w.flag), flag_X0=X0)
+    pts = geometry.grid_points_of(w) if w.grid is not None else None
+    X0 = geometry.flag_lattice(w.flag)
+    run = ib.create(ib.domain_from(w, precision=ib.MIXED, diffusion=ib.DIFFUSION_CN), noise, grid=w.grid if pts is not None else None,
+                    flag=ib.flag_from(w.flag))
     from oracle.solver import Solver
     S = Solver(w, noise, pts, oracle_flag_args(w, X0), diffusion="cn")
     try:

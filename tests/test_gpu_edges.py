@@ -13,6 +13,7 @@ import numpy as np
 import pytest
 
 import synth
+from oracle import geometry
 from tests.gpu_cases import build_pair, rel_l2
 
 pytestmark = pytest.mark.gpu
@@ -21,10 +22,10 @@ ib = pytest.importorskip("paper_2103_08246_amd")
 
 def _make(w):
     noise = synth.ic_noise(w)
-    bars = synth.bar_points(w) if w.grid is not None else None
-    X0 = synth.flag_reference(w) if w.flag is not None else None
-    return ib.create(ib.domain_from(w), noise, points=bars,
-                     flag=ib.flag_from(w.flag) if w.flag is not None else None, flag_X0=X0)
+    bars = geometry.grid_points_of(w) if w.grid is not None else None
+    X0 = geometry.flag_lattice(w.flag) if w.flag is not None else None
+    return ib.create(ib.domain_from(w), noise, grid=w.grid if bars is not None else None,
+                     flag=ib.flag_from(w.flag) if w.flag is not None else None)
 
 
 def _grid_flag():

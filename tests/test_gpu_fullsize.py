@@ -11,6 +11,7 @@ import numpy as np
 import pytest
 
 import synth
+from oracle import geometry
 from tests.gpu_cases import rel_l2
 
 pytestmark = pytest.mark.gpu
@@ -21,10 +22,9 @@ ib = pytest.importorskip("paper_2103_08246_amd")
 def full():
     w = synth.grid_flag_768_re1000()
     noise = synth.ic_noise(w)
-    bars = synth.bar_points(w)
-    X0 = synth.flag_reference(w)
-    run = ib.create(ib.domain_from(w), noise, points=bars, flag=ib.flag_from(w.flag),
-                    flag_X0=X0)
+    bars = geometry.grid_points_of(w)
+    X0 = geometry.flag_lattice(w.flag)
+    run = ib.create(ib.domain_from(w), noise, grid=w.grid if bars is not None else None, flag=ib.flag_from(w.flag))
     yield w, run, bars, X0
     run.close()
 

@@ -20,6 +20,7 @@ import numpy as np
 import pytest
 
 import synth
+from oracle import geometry
 from tests.gpu_cases import rel_l2
 
 pytestmark = pytest.mark.gpu
@@ -28,11 +29,11 @@ ib = pytest.importorskip("paper_2103_08246_amd")
 
 def _create(**kw):
     w = synth.grid_flag_768_re1000()
-    X0 = synth.flag_reference(w)
-    bars = synth.bar_points(w)
+    X0 = geometry.flag_lattice(w.flag)
+    bars = geometry.grid_points_of(w)
     diffusion = kw.pop("diffusion", ib.DIFFUSION_EXPLICIT)
-    run = ib.create(ib.domain_from(w, diffusion=diffusion), synth.ic_noise(w), points=bars,
-                    flag=ib.flag_from(w.flag), flag_X0=X0, **kw)
+    run = ib.create(ib.domain_from(w, diffusion=diffusion), synth.ic_noise(w), grid=w.grid if bars is not None else None,
+                    flag=ib.flag_from(w.flag), **kw)
     return w, run, X0
 
 

@@ -5,6 +5,7 @@ import numpy as np
 import pytest
 
 import synth
+from oracle import geometry
 from tests.gpu_cases import oracle_flag_args, rel_l2
 from tests.test_gpu_parity import small_grid_flag
 
@@ -29,9 +30,8 @@ def _oracle_lists(w):
 
 
 def _make(w, flag=True):
-    X0 = synth.flag_reference(w) if flag else None
-    return ib.create(ib.domain_from(w), synth.ic_noise(w), flag=ib.flag_from(w.flag) if flag else None,
-                     flag_X0=X0, grid_forcing=w.grid)
+    X0 = geometry.flag_lattice(w.flag) if flag else None
+    return ib.create(ib.domain_from(w), synth.ic_noise(w), flag=ib.flag_from(w.flag) if flag else None, grid_forcing=w.grid)
 
 
 def test_lists_match_oracle():
@@ -51,7 +51,7 @@ def test_lists_match_oracle():
 def test_steps_match_oracle():
     from oracle.solver import Solver
     w = small_grid_flag()
-    X0 = synth.flag_reference(w)
+    X0 = geometry.flag_lattice(w.flag)
     g = w.grid
     S = Solver(w, synth.ic_noise(w), None, oracle_flag_args(w, X0),
                grid_forcing=dict(x_plane=g.x_plane, mesh=g.mesh, bar=g.bar))
@@ -75,10 +75,10 @@ def test_grid_forcing_state_rules():
     run = ib.create(ib.domain_from(w), synth.ic_noise(w), grid_forcing=w.grid)
     try:
         with pytest.raises(ib.IbdnsError) as e:      # points and node forcing exclude each other
-            ib.set_geometry(run.ctx, synth.bar_points(w))
+            ib.set_geometry(run.ctx, ib.grid_from(w.grid))
         assert e.value.code == ib.EINVAL
         with pytest.raises(ib.IbdnsError) as e:      # once
-            run.set_grid_forcing(ib.domain_from(w), w.grid.x_plane, w.grid.mesh, w.grid.bar)
+            run.set_grid_forcing(ib.domain_from(w), ib.grid_from(w.grid))
         assert e.value.code == ib.ESTATE
         with pytest.raises(ib.IbdnsError) as e:      # batches take grids as points only
             ib.Batch([run])
@@ -91,7 +91,7 @@ def test_grid_forcing_state_rules():
             plain.grid_forcing(0)
         assert e.value.code == ib.ESTATE
         with pytest.raises(ib.IbdnsError) as e:      # rods reaching the inlet
-            plain.set_grid_forcing(ib.domain_from(w), 0.1, w.grid.mesh, w.grid.bar)
+            plain.set_grid_forcing(ib.domain_from(w), ib.GridParams(0.1, w.grid.mesh, w.grid.bar))
         assert e.value.code == ib.EINVAL
     finally:
         plain.close()

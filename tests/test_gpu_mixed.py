@@ -10,6 +10,7 @@ import numpy as np
 import pytest
 
 import synth
+from oracle import geometry
 from oracle import fluid
 from tests.gpu_cases import build_pair, rel_l2
 from tests.test_gpu_parity import small_grid_flag
@@ -33,10 +34,10 @@ def test_mixed_100_steps_vs_fp64_oracle(make):
     from oracle.solver import Solver
     from tests.gpu_cases import oracle_flag_args
     noise = synth.ic_noise(w)
-    bars = synth.bar_points(w) if w.grid is not None else None
-    X0 = synth.flag_reference(w)
-    run = ibm.create(ibm.domain_from(w, precision=ibm.MIXED), noise, points=bars,
-                     flag=ibm.flag_from(w.flag), flag_X0=X0)
+    bars = geometry.grid_points_of(w) if w.grid is not None else None
+    X0 = geometry.flag_lattice(w.flag)
+    run = ibm.create(ibm.domain_from(w, precision=ibm.MIXED), noise, grid=w.grid if bars is not None else None,
+                     flag=ibm.flag_from(w.flag))
     S = Solver(w, noise, bars, oracle_flag_args(w, X0))
     try:
         run.step(100)
@@ -56,13 +57,13 @@ def test_mixed_100_steps_vs_fp64_oracle(make):
 def test_mixed_full_size_vs_fp64_path():
     w = synth.grid_flag_768_re1000()
     noise = synth.ic_noise(w)
-    bars = synth.bar_points(w)
-    X0 = synth.flag_reference(w)
+    bars = geometry.grid_points_of(w)
+    X0 = geometry.flag_lattice(w.flag)
     runs = {}
     try:
         for prec in (ib.FP64, ib.MIXED):
-            runs[prec] = ib.create(ib.domain_from(w, precision=prec), noise, points=bars,
-                                   flag=ib.flag_from(w.flag), flag_X0=X0)
+            runs[prec] = ib.create(ib.domain_from(w, precision=prec), noise, grid=w.grid if bars is not None else None,
+                                   flag=ib.flag_from(w.flag))
             runs[prec].step(20)
         a = runs[ib.FP64].fields()
         b = runs[ib.MIXED].fields()

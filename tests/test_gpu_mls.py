@@ -6,6 +6,7 @@ import numpy as np
 import pytest
 
 import synth
+from oracle import geometry
 from tests.gpu_cases import oracle_flag_args, rel_l2
 from tests.test_gpu_parity import small_grid_flag
 
@@ -16,9 +17,9 @@ ib = pytest.importorskip("paper_2103_08246_amd")
 def _pair(w, bars=True):
     from oracle.solver import Solver
     noise = synth.ic_noise(w)
-    pts = synth.bar_points(w) if (bars and w.grid is not None) else None
-    X0 = synth.flag_reference(w)
-    run = ib.create(ib.domain_from(w), noise, points=pts, flag=ib.flag_from(w.flag), flag_X0=X0,
+    pts = geometry.grid_points_of(w) if (bars and w.grid is not None) else None
+    X0 = geometry.flag_lattice(w.flag)
+    run = ib.create(ib.domain_from(w), noise, grid=w.grid if pts is not None else None, flag=ib.flag_from(w.flag),
                     flag_mls=True)
     S = Solver(w, noise, pts, dict(oracle_flag_args(w, X0), coupling="mls"))
     return run, S
@@ -31,7 +32,7 @@ def test_marker_table_matches_oracle(make, level):
     run, S = _pair(w, bars=False)
     try:
         tri, beta, dV, X, F = run.flag_markers()
-        otri, obeta, odV, olev = mls.build_markers(synth.flag_reference(w), w.lx / w.nx)
+        otri, obeta, odV, olev = mls.build_markers(geometry.flag_lattice(w.flag), w.lx / w.nx)
         assert np.all(olev == level)
         assert tri.shape == otri.shape and np.array_equal(tri, otri)
         assert np.array_equal(beta, obeta)                       # dyadic sums / 3 on both sides
@@ -96,10 +97,9 @@ def test_mls_mixed_vs_fp64_oracle(make):
     from oracle.solver import Solver
     w = make()
     noise = synth.ic_noise(w)
-    pts = synth.bar_points(w) if w.grid is not None else None
-    X0 = synth.flag_reference(w)
-    run = ib.create(ib.domain_from(w, precision=ib.MIXED), noise, points=pts, flag=ib.flag_from(w.flag),
-                    flag_X0=X0, flag_mls=True)
+    pts = geometry.grid_points_of(w) if w.grid is not None else None
+    X0 = geometry.flag_lattice(w.flag)
+    run = ib.create(ib.domain_from(w, precision=ib.MIXED), noise, grid=w.grid if pts is not None else None, flag=ib.flag_from(w.flag), flag_mls=True)
     S = Solver(w, noise, pts, dict(oracle_flag_args(w, X0), coupling="mls"))
     try:
         run.step(30)
@@ -122,7 +122,7 @@ def test_mls_mixed_vs_fp64_oracle(make):
 def test_mls_rules():
     w = small_grid_flag()
     noise = synth.ic_noise(w)
-    X0 = synth.flag_reference(w)
+    X0 = geometry.flag_lattice(w.flag)
     plain = ib.create(ib.domain_from(w), noise)
     try:
         with pytest.raises(ib.IbdnsError) as e:    # no flag
@@ -133,7 +133,7 @@ def test_mls_rules():
         assert e.value.code == ib.ESTATE
     finally:
         plain.close()
-    run = ib.create(ib.domain_from(w), noise, flag=ib.flag_from(w.flag), flag_X0=X0, flag_mls=True)
+    run = ib.create(ib.domain_from(w), noise, flag=ib.flag_from(w.flag), flag_mls=True)
     try:
         with pytest.raises(ib.IbdnsError) as e:    # once
             run.set_flag_mls()
@@ -146,7 +146,7 @@ def test_mls_rules():
         assert e.value.code == ib.EINVAL
     finally:
         run.close()
-    late = ib.create(ib.domain_from(w), noise, flag=ib.flag_from(w.flag), flag_X0=X0)
+    late = ib.create(ib.domain_from(w), noise, flag=ib.flag_from(w.flag))
     try:
         late.step(1)
         with pytest.raises(ib.IbdnsError) as e:    # before the first step only
@@ -164,7 +164,7 @@ def test_mls_refuses_too_fine_a_tiling():
     w = synth.Workload(name="coarse_flag", nx=192, ny=128, nz=128, lx=192 * h, ly=128 * h, lz=128 * h,
                        re=200.0, dt=1e-3, steps=1,
                        flag=synth.Flag(ns=3, length=1.5, x_le=0.5, y_c=1.0, z_c=1.0, bending=0.01))
-    run = ib.create(ib.domain_from(w), None, flag=ib.flag_from(w.flag), flag_X0=synth.flag_reference(w))
+    run = ib.create(ib.domain_from(w), None, flag=ib.flag_from(w.flag))
     try:
         with pytest.raises(ib.IbdnsError) as e:
             run.set_flag_mls()
@@ -173,7 +173,7 @@ def test_mls_refuses_too_fine_a_tiling():
             run.flag_markers()
         assert e.value.code == ib.ESTATE
         maps = ib.get_maps(run.ctx, 0, w.flag.ns ** 2)
-        X0 = synth.flag_reference(w).reshape(-1, 3)
+        X0 = geometry.flag_lattice(w.flag).reshape(-1, 3)
         assert np.array_equal(maps[:, 0], np.floor(X0[:, 0] / h + 0.5).astype(np.int32))
     finally:
         run.close()

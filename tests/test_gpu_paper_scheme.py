@@ -7,6 +7,7 @@ import numpy as np
 import pytest
 
 import synth
+from oracle import geometry
 from tests.gpu_cases import oracle_flag_args, rel_l2
 from tests.test_gpu_parity import small_grid_flag
 
@@ -20,10 +21,10 @@ def test_paper_scheme_matches_oracle(precision, steps, tol):
     from oracle.solver import Solver
     w = small_grid_flag()
     noise = synth.ic_noise(w)
-    X0 = synth.flag_reference(w)
+    X0 = geometry.flag_lattice(w.flag)
     prec = ib.FP64 if precision == "fp64" else ib.MIXED
     run = ib.create(ib.domain_from(w, precision=prec, diffusion=ib.DIFFUSION_CN), noise,
-                    flag=ib.flag_from(w.flag), flag_X0=X0, grid_forcing=w.grid, flag_mls=True)
+                    flag=ib.flag_from(w.flag), grid_forcing=w.grid, flag_mls=True)
     g = w.grid
     S = Solver(w, noise, None, dict(oracle_flag_args(w, X0), coupling="mls"),
                grid_forcing=dict(x_plane=g.x_plane, mesh=g.mesh, bar=g.bar), diffusion="cn")

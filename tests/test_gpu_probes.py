@@ -5,6 +5,7 @@ import numpy as np
 import pytest
 
 import synth
+from oracle import geometry
 from tests.gpu_cases import oracle_flag_args
 from tests.test_gpu_parity import small_grid_flag
 
@@ -23,10 +24,10 @@ def test_probe_records_match_oracle(n_lags, steps):
     w = small_grid_flag()
     pr = synth.probe_layout(w, n_lags)
     noise = synth.ic_noise(w)
-    X0 = synth.flag_reference(w)
-    S = Solver(w, noise, synth.bar_points(w), oracle_flag_args(w, X0), probes=pr)
-    run = ib.create(ib.domain_from(w), noise, points=synth.bar_points(w),
-                    flag=ib.flag_from(w.flag), flag_X0=X0)
+    X0 = geometry.flag_lattice(w.flag)
+    S = Solver(w, noise, geometry.grid_points_of(w), oracle_flag_args(w, X0), probes=pr)
+    run = ib.create(ib.domain_from(w), noise, grid=w.grid,
+                    flag=ib.flag_from(w.flag))
     try:
         run.set_probes(pr["n_x"], pr["x0"], pr["dx"], pr["yc"], pr["zc"], pr["dyz"], n_lags)
         for _ in range(steps):

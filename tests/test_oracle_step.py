@@ -11,6 +11,7 @@ import numpy as np
 import pytest
 
 import synth
+from oracle import geometry
 from oracle import fluid
 from oracle.solver import Solver
 
@@ -33,8 +34,8 @@ def _small_with_bars():
 def test_shift_symmetry(axis, shift):
     w = _small_with_bars()
     noise = synth.ic_noise(w)
-    bars = synth.bar_points(w)
-    X0 = synth.flag_reference(w)
+    bars = geometry.grid_points_of(w)
+    X0 = geometry.flag_lattice(w.flag)
     S1 = Solver(w, noise, bars, _flag_args(w, X0))
     S1.step(4)
     h = w.h
@@ -56,7 +57,7 @@ def test_shift_symmetry(axis, shift):
 
 def test_small_flag_workload_invariants():
     w = synth.flag_64_re200()
-    X0 = synth.flag_reference(w)
+    X0 = geometry.flag_lattice(w.flag)
     S = Solver(w, synth.ic_noise(w), None, _flag_args(w, X0))
     for _ in range(w.steps):
         S.step()
