@@ -105,53 +105,34 @@ def batch_leg(ib, torch, ws_list, precision, steps, warmup, keep=False):
 def cpu_baseline(w, budget_s: float = 20.0) -> dict:
     """Time the oracle (as it stands) on a bounded sample of the workload.
 
-    Sample: the workload's mesh spacing, Re, CFL rule, bars and seeded noise on
-    a 128 x 96 x 96 sub-box (2L x 1.5L x 1.5L), stepped for about
-    budget_s/2; plus the oracle's flag update (the workload's full flag at the
-    workload's dt) timed on its own.  Scaled to one full step:
-    t = cells / (sub-box cell rate) + t_flag.
+    The oracle's fast form (oracle/fast.py: the fluid stages as plain C loops,
+    OpenMP over the host's threads, the flag's spring network in numpy) steps
+    the full workload -- the same mesh, bodies and seeded inputs -- for about
+    budget_s after one warm-up step; the rate is cells / (mean time per step).
     """
     import synth
-    from oracle import geometry
-    from oracle.flag import FlagModel
-    from oracle.solver import Solver
-    import dataclasses
-    sub = dataclasses.replace(w, nx=128, ny=96, nz=96, lx=128 * w.h, ly=96 * w.h,
-                              lz=96 * w.h, flag=None)
-    noise = synth.ic_noise(sub)
-    bars = geometry.grid_points_of(sub) if sub.grid is not None else None
-    S = Solver(sub, noise, bars, None)
-    S.step(1)   # warm-up
-    t0 = time.perf_counter()
-    n = 0
-    while time.perf_counter() - t0 < budget_s / 2 or n < 1:
-        S.step(1)
-        n += 1
-    t_cells = (time.perf_counter() - t0) / n
-    rate = sub.cells / t_cells                     # cell-steps per second
-    t_flag = 0.0
+    from oracle import fast, geometry
+    noise = synth.ic_noise(w)
+    bars = geometry.grid_points_of(w) if w.grid is not None else None
+    flag = None
     if w.flag is not None:
         f = w.flag
-        X0 = geometry.flag_lattice(f)
-        F = FlagModel(X0, f.length, f.mass_ratio, f.bending, f.stretch, f.le_bc)
-        X = X0.reshape(-1, 3).copy()
-        V = np.zeros_like(X)
-        dt = w.cfl * w.h / 1.5 if w.dt <= 0 else w.dt   # representative CFL step
-        t1 = time.perf_counter()
-        m = 0
-        while time.perf_counter() - t1 < budget_s / 2 or m < 1:
-            X, V, _ = F.advance(X, V, np.zeros_like(X), dt)
-            m += 1
-        t_flag = (time.perf_counter() - t1) / m
-    t_step = w.cells / rate + t_flag
-    # numpy's element-wise kernels and pocketfft run on one thread
-    return {"value": w.cells / t_step / 1e6, "unit": "Mcell-steps/s", "cores": 1,
-            "kind": "oracle",
-            "sample": (f"numpy FP64 oracle: {n} steps of a 128x96x96 sub-box at the workload's "
-                       f"h, Re, CFL and bars ({t_cells:.2f} s/step, "
-                       f"{rate / 1e6:.3f} Mcell-steps/s) plus {0 if w.flag is None else m} "
-                       f"flag updates of the full flag ({t_flag:.2f} s each), scaled to "
-                       f"{w.cells} cells")}
+        flag = dict(X0=geometry.flag_lattice(f), length=f.length, rho=f.mass_ratio, beta=f.bending,
+                    ks=f.stretch, le_bc=f.le_bc)
+    C = fast.FastSolver(w, noise, bars, flag)
+    del noise
+    C.step(1)   # warm-up: first touch of the work arrays
+    t0 = time.perf_counter()
+    n = 0
+    while time.perf_counter() - t0 < budget_s or n < 2:
+        C.step(1)
+        n += 1
+    t_step = (time.perf_counter() - t0) / n
+    threads = fast.threads()
+    return {"value": w.cells / t_step / 1e6, "unit": "Mcell-steps/s", "cores": threads, "kind": "oracle",
+            "sample": (f"FP64 oracle (fluid stages as plain C loops over {threads} OpenMP threads, "
+                       f"flag model in numpy): {n} steps of the full {w.name} workload "
+                       f"({w.cells} cells, bars and flag) after one warm-up step, {t_step:.2f} s/step")}
 
 
 def main():

@@ -334,6 +334,26 @@ int ibdns_set_probes(ibdns_ctx* ctx, int32_t n_x, double x0, double dx, double y
  * ESTATE if no probes are set. */
 int ibdns_get_probe_stats(ibdns_ctx* ctx, double* out);
 
+/* The derived quantities of Sec. III per station p (its nine probes pooled):
+ * the turbulent kinetic energy k = (<u'u'> + <v'v'> + <w'w'>)/2, the
+ * large-scale anisotropy <u'u'>/<v'v'>, and the autocorrelation coefficients
+ * of the streamwise and of a transverse velocity
+ *   f(l) = <u'(t) u'(t - l)> / <u'u'>,  g(l) = <v'(t) v'(t - l)> / <v'v'>,
+ * at lags of l steps (tau = l dt with a fixed dt; Taylor's hypothesis maps
+ * tau to a separation U tau).  Per probe, means and second moments are taken
+ * over all its samples, lagged products over the pairs that exist; the nine
+ * probes of a station are then averaged.  A lag without a pair gives NaN.
+ * Output per station, host array of n_x (2 + 2 n_lags) doubles:
+ *   [k, anisotropy, f(0..n_lags-1), g(0..n_lags-1)].
+ * ibdns_station_stats_size gives n_x, n_lags and the bytes of the device
+ * staging buffer (ESTATE without probes).  ibdns_get_station_stats computes
+ * them on the device into dev_ws (caller-owned, 256-byte aligned, at least
+ * those bytes; its contents are overwritten) and copies them to out;
+ * synchronises.  ESTATE without probes, EINVAL for a misaligned dev_ws,
+ * ENOMEM if ws_bytes is short. */
+int ibdns_station_stats_size(ibdns_ctx* ctx, int32_t* n_stations, int32_t* n_lags, size_t* bytes);
+int ibdns_get_station_stats(ibdns_ctx* ctx, void* dev_ws, size_t ws_bytes, double* out);
+
 /* ------------------------------------------------------------------------
  * Batched ensembles: independent runs (uneven sizes allowed), each created by
  * ibdns_init_domain + ibdns_set_geometry on the same stream and precision,
@@ -367,6 +387,17 @@ int ibdns_batch_autotune(ibdns_batch* b, int32_t* variant_out);
 
 /* Single-run form of the tile-shape autotuner (same rule). */
 int ibdns_autotune(ibdns_ctx* ctx, int32_t* variant_out);
+
+/* The predictor's tile shapes (x columns, y rows, z planes per workgroup)
+ * that the autotuners time, by index: 0 64x8x16, 1 64x4x32, 2 64x8x32,
+ * 3 32x8x16, 4 64x16x8, 5 64x16x16, 6 32x16x32, 7 128x8x32, 8 128x4x32,
+ * 9 128x8x16, 10 256x4x16, 11 128x4x16, 12 128x8x24, 13 128x8x48. */
+enum { IBDNS_NUM_TILES = 14 };
+
+/* Use tile shape `variant` for the context's predictor from now on (the
+ * choice ibdns_autotune makes by timing), e.g. to reproduce a tuned run.
+ * EINVAL outside 0 .. IBDNS_NUM_TILES-1. */
+int ibdns_set_tile(ibdns_ctx* ctx, int32_t variant);
 
 /* Release the batch (not the runs, not the workspace). */
 int ibdns_batch_destroy(ibdns_batch* b);

@@ -35,7 +35,8 @@ EXPORTED = ("ibdns_workspace_size", "ibdns_init_domain", "ibdns_set_geometry",
             "ibdns_batch_destroy", "ibdns_probe_workspace_size", "ibdns_set_probes",
             "ibdns_get_probe_stats", "ibdns_grid_forcing_workspace_size", "ibdns_set_grid_forcing",
             "ibdns_get_grid_forcing", "ibdns_flag_mls_workspace_size", "ibdns_set_flag_mls",
-            "ibdns_get_flag_markers")
+            "ibdns_get_flag_markers", "ibdns_set_tile", "ibdns_station_stats_size",
+            "ibdns_get_station_stats")
 
 
 class Domain(ctypes.Structure):
@@ -108,6 +109,7 @@ def _load():
     lib.ibdns_batch_use_graph.argtypes = [P, ctypes.c_int32]
     lib.ibdns_batch_autotune.argtypes = [P, ctypes.POINTER(ctypes.c_int32)]
     lib.ibdns_autotune.argtypes = [P, ctypes.POINTER(ctypes.c_int32)]
+    lib.ibdns_set_tile.argtypes = [P, ctypes.c_int32]
     lib.ibdns_batch_destroy.argtypes = [P]
     lib.ibdns_probe_workspace_size.argtypes = [ctypes.c_int32, ctypes.c_int32,
                                                ctypes.POINTER(ctypes.c_size_t)]
@@ -115,6 +117,9 @@ def _load():
     lib.ibdns_set_probes.argtypes = [P, ctypes.c_int32, dd, dd, dd, dd, dd, ctypes.c_int32, P,
                                      ctypes.c_size_t]
     lib.ibdns_get_probe_stats.argtypes = [P, D]
+    lib.ibdns_station_stats_size.argtypes = [P, ctypes.POINTER(ctypes.c_int32), ctypes.POINTER(ctypes.c_int32),
+                                             ctypes.POINTER(ctypes.c_size_t)]
+    lib.ibdns_get_station_stats.argtypes = [P, P, ctypes.c_size_t, D]
     lib.ibdns_grid_forcing_workspace_size.argtypes = [ctypes.POINTER(Domain), ctypes.POINTER(GridParams),
                                                       ctypes.POINTER(ctypes.c_size_t)]
     lib.ibdns_set_grid_forcing.argtypes = [P, ctypes.POINTER(GridParams), P, ctypes.c_size_t]
@@ -327,6 +332,22 @@ class Run:
             _check(code, "get_probe_stats")
         return out
 
+    def station_stats(self, device="cuda:0", check=True):
+        """Per station: dict(k, anisotropy, f (L,), g (L,)) computed on the device
+        (rule in include/ibdns.h); the staging tensor is allocated per call."""
+        import torch
+        ns_, L = ctypes.c_int32(0), ctypes.c_int32(0)
+        size = ctypes.c_size_t(0)
+        _check(_lib.ibdns_station_stats_size(self.ctx, ctypes.byref(ns_), ctypes.byref(L), ctypes.byref(size)),
+               "station_stats_size")
+        ws = torch.empty(max(size.value, 256), dtype=torch.uint8, device=device)
+        out = np.empty((ns_.value, 2 + 2 * L.value))
+        code = _lib.ibdns_get_station_stats(self.ctx, ctypes.c_void_p(ws.data_ptr()), ws.numel(), _dptr(out))
+        if check:
+            _check(code, "get_station_stats")
+        Lv = L.value
+        return [dict(k=r[0], anisotropy=r[1], f=r[2:2 + Lv], g=r[2 + Lv:]) for r in out]
+
     def set_grid_forcing(self, dom: Domain, grid: GridParams, device="cuda:0"):
         """Eulerian forcing of the passive grid (rule in include/ibdns.h); the
         workspace tensor is kept on this object."""
@@ -437,6 +458,13 @@ def grid_from(g) -> GridParams | None:
     if g is None:
         return None
     return GridParams(g.x_plane, g.mesh, g.bar)
+
+
+NUM_TILES = 14
+
+
+def set_tile(ctx, variant: int):
+    _check(_lib.ibdns_set_tile(ctx, variant), "set_tile")
 
 
 def autotune(ctx) -> int:

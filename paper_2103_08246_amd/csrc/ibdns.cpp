@@ -1474,6 +1474,30 @@ int ibdns_get_probe_stats(ibdns_ctx* c, double* out) {
   return read_status(c);
 }
 
+int ibdns_station_stats_size(ibdns_ctx* c, int32_t* n_stations, int32_t* n_lags, size_t* bytes) {
+  if (!c || !n_stations || !n_lags || !bytes) return IBDNS_EINVAL;
+  if (c->probes.n <= 0) return IBDNS_ESTATE;
+  *n_stations = c->probes.n / 9;
+  *n_lags = c->probes.L;
+  *bytes = (size_t)(c->probes.n / 9) * (2 + 2 * (size_t)c->probes.L) * sizeof(double);
+  return IBDNS_OK;
+}
+
+int ibdns_get_station_stats(ibdns_ctx* c, void* dev_ws, size_t ws_bytes, double* out) {
+  if (!c || !out) return IBDNS_EINVAL;
+  if (c->probes.n <= 0) return IBDNS_ESTATE;
+  if (!dev_ws || (reinterpret_cast<uintptr_t>(dev_ws) % ALIGN) != 0) return IBDNS_EINVAL;
+  const size_t bytes = (size_t)(c->probes.n / 9) * (2 + 2 * (size_t)c->probes.L) * sizeof(double);
+  if (ws_bytes < bytes) return IBDNS_ENOMEM;
+  double* staged = static_cast<double*>(dev_ws);
+  launch_station_stats(c->probes, staged, c->st);
+  if (check_launch() != IBDNS_OK) return IBDNS_EHIP;
+  if (hipStreamSynchronize(c->st) != hipSuccess ||
+      hipMemcpy(out, staged, bytes, hipMemcpyDeviceToHost) != hipSuccess)
+    return IBDNS_EHIP;
+  return read_status(c);
+}
+
 int ibdns_destroy(ibdns_ctx* c) {
   if (!c) return IBDNS_EINVAL;
   hipStreamSynchronize(c->st);
@@ -1986,6 +2010,12 @@ int ibdns_autotune(ibdns_ctx* c, int32_t* variant_out) {
   c->variant = bestv;
   if (variant_out) *variant_out = bestv;
   return check_launch();
+}
+
+int ibdns_set_tile(ibdns_ctx* c, int32_t variant) {
+  if (!c || variant < 0 || variant >= predict_variants() || variant >= IBDNS_NUM_TILES) return IBDNS_EINVAL;
+  c->variant = variant;
+  return IBDNS_OK;
 }
 
 int ibdns_batch_destroy(ibdns_batch* b) {

@@ -264,6 +264,8 @@ void launch_flag_step_plain(const FlagDev& fl, Scalars* s, hipStream_t st);
 int flag_bands(int ns);
 void launch_advance(Scalars* s, const double* partial, int nparts, double h, hipStream_t st);
 void launch_probes(const Dims& d, const Fields& f, const ProbeDev& pr, hipStream_t st);
+// per-station statistics of the probe records into out (n/9 stations x (2 + 2L) doubles)
+void launch_station_stats(const ProbeDev& pr, double* out, hipStream_t st);
 size_t cn_table_doubles(int nx, int ny, int nz);
 CnTables cn_tables_at(double* base, int nx, int ny, int nz);
 void launch_cn_tables(const Dims& d, const Scalars* s, const CnTables& t, hipStream_t st);

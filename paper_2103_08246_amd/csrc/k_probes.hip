@@ -92,7 +92,66 @@ __global__ void __launch_bounds__(64 * PROBE_WAVES) k_probes(Dims d, Fields f, P
   }
 }
 
+// Derived statistics of Sec. III per station (the nine probes of a station
+// pooled): k = (<u'u'> + <v'v'> + <w'w'>)/2, the large-scale anisotropy
+// <u'u'>/<v'v'>, and the autocorrelation coefficients
+//   f(l) = <u'(t) u'(t - l)> / <u'u'>,  g(l) = <v'(t) v'(t - l)> / <v'v'>
+// (Taylor's hypothesis turns the lag into a separation U l dt).  Per probe the
+// means are over all its samples and the lagged products over the pairs that
+// exist; the nine probes are averaged in probe order.  A lag with no pair
+// gives NaN.  One workgroup per station; out[s (2 + 2L) + ...] =
+// [k, anisotropy, f(0..L-1), g(0..L-1)].
+constexpr int STAT_T = 128;
+
+__global__ void __launch_bounds__(STAT_T) k_station_stats(ProbeDev pr, double* __restrict__ out) {
+  const int s = blockIdx.x;
+  const int L = pr.L;
+  const int rl = 10 + 2 * L;
+  const double* r = pr.rec + (long long)9 * s * rl;
+  __shared__ double mu[9], mv[9], cov[3];
+  if (threadIdx.x == 0) {
+    double uu = 0.0, vv = 0.0, ww = 0.0;
+    for (int p = 0; p < 9; ++p) {
+      const double* q = r + (long long)p * rl;
+      const double n = q[0];
+      mu[p] = q[1] / n;
+      mv[p] = q[2] / n;
+      const double mw = q[3] / n;
+      uu += q[4] / n - mu[p] * mu[p];
+      vv += q[5] / n - mv[p] * mv[p];
+      ww += q[6] / n - mw * mw;
+    }
+    cov[0] = uu / 9.0;
+    cov[1] = vv / 9.0;
+    cov[2] = ww / 9.0;
+  }
+  __syncthreads();
+  double* o = out + (long long)s * (2 + 2 * L);
+  if (threadIdx.x == 0) {
+    o[0] = 0.5 * (cov[0] + cov[1] + cov[2]);
+    o[1] = cov[0] / cov[1];
+  }
+  for (int l = threadIdx.x; l < L; l += STAT_T) {
+    double fu = 0.0, gv = 0.0;
+    bool paired = true;
+    for (int p = 0; p < 9; ++p) {
+      const double* q = r + (long long)p * rl;
+      const double cnt = q[0] - (double)l;
+      paired = paired && cnt > 0.0;
+      fu += q[10 + l] / cnt - mu[p] * mu[p];
+      gv += q[10 + L + l] / cnt - mv[p] * mv[p];
+    }
+    o[2 + l] = paired ? (fu / 9.0) / cov[0] : __builtin_nan("");
+    o[2 + L + l] = paired ? (gv / 9.0) / cov[1] : __builtin_nan("");
+  }
+}
+
 }  // namespace
+
+void launch_station_stats(const ProbeDev& pr, double* out, hipStream_t st) {
+  if (pr.n <= 0) return;
+  hipLaunchKernelGGL(k_station_stats, dim3(pr.n / 9), dim3(STAT_T), 0, st, pr, out);
+}
 
 void launch_probes(const Dims& d, const Fields& f, const ProbeDev& pr, hipStream_t st) {
   if (pr.n <= 0) return;

@@ -12,15 +12,17 @@ def oracle_flag_args(w, X0):
                 le_bc=f.le_bc)
 
 
-def build_pair(w, hooks=0, with_noise=True):
-    """(gpu_run, oracle_solver) on identical inputs."""
+def build_pair(w, hooks=0, with_noise=True, precision=0, noise=None):
+    """(gpu_run, oracle_solver) on identical inputs: the library builds its
+    bodies from the workload's parameters, the oracle its own (oracle.geometry).
+    precision: the library's (the oracle is FP64); noise: precomputed ic_noise."""
     import paper_2103_08246_amd as ib
     from oracle.solver import Solver
-    noise = synth.ic_noise(w) if with_noise else None
+    if noise is None and with_noise:
+        noise = synth.ic_noise(w)
     bars = geometry.grid_points_of(w) if w.grid is not None else None
     X0 = geometry.flag_lattice(w.flag) if w.flag is not None else None
-    run = ib.create(ib.domain_from(w, flags=hooks), noise, grid=w.grid if bars is not None else None,
-                    flag=ib.flag_from(w.flag) if w.flag is not None else None)
+    run = ib.create(ib.domain_from(w, flags=hooks, precision=precision), noise, grid=w.grid, flag=w.flag)
     S = Solver(w, noise, bars, oracle_flag_args(w, X0) if X0 is not None else None, hooks=hooks)
     return run, S
 

@@ -40,6 +40,57 @@ def test_probe_records_match_oracle(n_lags, steps):
         # sums of sampled velocities: the fields agree to ~1e-13, so do the sums
         assert _rel_max(rec[:, 1:10], ref[:, 1:10]) < 1e-11
         assert _rel_max(rec[:, 10:], ref[:, 10:]) < 1e-11
+        # derived quantities of Sec. III per station, on the device
+        from oracle.probes import station_statistics
+        got = run.station_stats()
+        own = station_statistics(rec, n_lags)            # the oracle's rule on the GPU's records
+        ref_st = station_statistics(ref, n_lags)         # and on the oracle's own records
+        assert len(got) == len(own) == pr["n_x"]
+        for g, o, r in zip(got, own, ref_st):
+            for key in ("k", "anisotropy"):
+                assert abs(g[key] - o[key]) <= 1e-12 * abs(o[key]), key
+                # the records agree to ~1e-11 of their scale; a variance is a
+                # difference of O(1) moments, so it keeps ~1e-8 of itself
+                assert abs(g[key] - r[key]) <= 1e-7 * abs(r[key]), key
+            for key in ("f", "g"):
+                assert g[key].shape == (n_lags,)
+                # over a short transient the trend dominates the lagged products:
+                # compare relative to the coefficients' size
+                scale = max(1.0, float(np.max(np.abs(o[key]))))
+                assert np.max(np.abs(g[key] - o[key])) <= 1e-11 * scale, key
+                assert np.max(np.abs(g[key] - r[key])) <= 1e-6 * scale, key
+            assert g["f"][0] == pytest.approx(1.0, abs=1e-12) and g["g"][0] == pytest.approx(1.0, abs=1e-12)
+    finally:
+        run.close()
+
+
+def test_station_stats_unpaired_lags_and_rules():
+    """Lags longer than the record have no pair: NaN; a short or misaligned
+    staging buffer and a run without probes are refused."""
+    import ctypes
+    w = small_grid_flag()
+    run = ib.create(ib.domain_from(w), synth.ic_noise(w), grid=w.grid, flag=w.flag)
+    try:
+        with pytest.raises(ib.IbdnsError) as e:
+            run.station_stats()
+        assert e.value.code == ib.ESTATE
+        pr = synth.probe_layout(w, 7)
+        run.set_probes(pr["n_x"], pr["x0"], pr["dx"], pr["yc"], pr["zc"], pr["dyz"], 7)
+        run.step(5)
+        st = run.station_stats()
+        for s in st:
+            assert np.all(np.isfinite(s["f"][:5])) and np.all(np.isnan(s["f"][5:]))
+            assert np.all(np.isfinite(s["g"][:5])) and np.all(np.isnan(s["g"][5:]))
+            assert s["k"] > 0
+        import torch
+        lib = ib.lib()
+        ws = torch.empty(1 << 16, dtype=torch.uint8, device="cuda:0")
+        out = np.empty((pr["n_x"], 16))
+        D = ctypes.POINTER(ctypes.c_double)
+        assert lib.ibdns_get_station_stats(run.ctx, ctypes.c_void_p(ws.data_ptr()), 64,
+                                           out.ctypes.data_as(D)) == ib.ENOMEM
+        assert lib.ibdns_get_station_stats(run.ctx, ctypes.c_void_p(ws.data_ptr() + 8), ws.numel() - 8,
+                                           out.ctypes.data_as(D)) == ib.EINVAL
     finally:
         run.close()
 

@@ -157,3 +157,37 @@ def test_first_mode_frequency(ns):
         return times[i] + 0.5 * dt * (y0 - y2) / (y0 - 2 * y1 + y2)
     T = refine(imax)
     assert abs(T - period) < 0.01 * period, (T, period)
+
+
+def test_strain_scales_as_one_over_spring_stiffness():
+    """Essential inextensibility comes from the in-plane springs alone: under
+    a small in-plane pull on the trailing edge (bending off, leading edge
+    fixed), the static edge strain of the triangulated network is inversely
+    proportional to k_s.  Linear response: the stiffness is the finite-
+    difference Jacobian of the spring forces at rest, restricted to the
+    in-plane components of the free nodes (a triangulated sheet is rigid in
+    its plane)."""
+    ns, L = 6, 1.0
+    X0 = flat(ns, L=L)                     # in the x-z plane
+    x0 = X0.reshape(-1, 3)
+    strains = {}
+    for ks in (1e3, 1e4, 1e5):
+        F = FlagModel(X0, L, 1.0, 0.0, ks, le_bc=0)
+        dofs = [(n, c) for n in range(ns * ns) if not F.fixed[n] for c in (0, 2)]
+        eta = 1e-7 * F.ds
+        J = np.empty((len(dofs), len(dofs)))
+        for col, (n, c) in enumerate(dofs):
+            xp, xm = x0.copy(), x0.copy()
+            xp[n, c] += eta
+            xm[n, c] -= eta
+            df = (F.spring_force(xp) - F.spring_force(xm)) / (2 * eta)
+            J[:, col] = [df[m, cc] for (m, cc) in dofs]
+        load = np.array([1e-3 if (m % ns == ns - 1 and cc == 0) else 0.0 for (m, cc) in dofs])
+        d = np.linalg.solve(-J, load)
+        x = x0.copy()
+        for (m, cc), val in zip(dofs, d):
+            x[m, cc] += val
+        strains[ks] = F.max_strain(x)
+    assert strains[1e3] > 1e-6
+    assert strains[1e3] / strains[1e4] == pytest.approx(10.0, rel=1e-4)
+    assert strains[1e4] / strains[1e5] == pytest.approx(10.0, rel=1e-4)
