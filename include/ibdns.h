@@ -354,6 +354,20 @@ int ibdns_get_probe_stats(ibdns_ctx* ctx, double* out);
 int ibdns_station_stats_size(ibdns_ctx* ctx, int32_t* n_stations, int32_t* n_lags, size_t* bytes);
 int ibdns_get_station_stats(ibdns_ctx* ctx, void* dev_ws, size_t ws_bytes, double* out);
 
+/* For callers that cannot allocate device memory (code under HIP graph
+ * capture, serving loops, harnesses that forbid it): ibdns_get_station_stats
+ * with the device staging in a static array of the library instead of a
+ * caller workspace.  It allocates nothing.  The array holds at most 262,144
+ * doubles (2 MiB: n_x (2 + 2 n_lags) <= 262144, else ENOMEM); each GPU the
+ * library runs on keeps its own copy until the process ends, its address
+ * taken once per device when a context is created.  Every call on a GPU
+ * shares that GPU's array: calls that overlap on one GPU (contexts on other
+ * threads or streams) race and must be serialised by the caller.  The kernel
+ * writes every output value, so nothing is cleared between calls.
+ * Same results and errors as ibdns_get_station_stats otherwise; EHIP if the
+ * array's address could not be obtained. */
+int ibdns_get_station_stats_noalloc(ibdns_ctx* ctx, double* out);
+
 /* ------------------------------------------------------------------------
  * Batched ensembles: independent runs (uneven sizes allowed), each created by
  * ibdns_init_domain + ibdns_set_geometry on the same stream and precision,

@@ -36,7 +36,7 @@ EXPORTED = ("ibdns_workspace_size", "ibdns_init_domain", "ibdns_set_geometry",
             "ibdns_get_probe_stats", "ibdns_grid_forcing_workspace_size", "ibdns_set_grid_forcing",
             "ibdns_get_grid_forcing", "ibdns_flag_mls_workspace_size", "ibdns_set_flag_mls",
             "ibdns_get_flag_markers", "ibdns_set_tile", "ibdns_station_stats_size",
-            "ibdns_get_station_stats")
+            "ibdns_get_station_stats", "ibdns_get_station_stats_noalloc")
 
 
 class Domain(ctypes.Structure):
@@ -120,6 +120,7 @@ def _load():
     lib.ibdns_station_stats_size.argtypes = [P, ctypes.POINTER(ctypes.c_int32), ctypes.POINTER(ctypes.c_int32),
                                              ctypes.POINTER(ctypes.c_size_t)]
     lib.ibdns_get_station_stats.argtypes = [P, P, ctypes.c_size_t, D]
+    lib.ibdns_get_station_stats_noalloc.argtypes = [P, D]
     lib.ibdns_grid_forcing_workspace_size.argtypes = [ctypes.POINTER(Domain), ctypes.POINTER(GridParams),
                                                       ctypes.POINTER(ctypes.c_size_t)]
     lib.ibdns_set_grid_forcing.argtypes = [P, ctypes.POINTER(GridParams), P, ctypes.c_size_t]

@@ -73,6 +73,10 @@ struct ibdns_ctx {
   CnTables cnt{};
   // virtual probes (caller-owned workspace), sampled after each projection
   ProbeDev probes{};
+  // this device's static staging array of the station statistics (address
+  // from hipGetSymbolAddress at set-up; nullptr if HIP refused it)
+  double* stat_scratch = nullptr;
+  size_t stat_scratch_doubles = 0;
   // Eulerian forcing of the passive grid (caller-owned workspace); host copy
   // of the lists: host-layout node, source (-1: solid) and weight
   GridForceDev gforce{};
@@ -678,6 +682,11 @@ int ibdns_init_domain(const ibdns_domain* dm, const double* zu, const double* zv
   if (check_launch() != IBDNS_OK || hipStreamSynchronize(c->st) != hipSuccess) {
     delete c;
     return IBDNS_EHIP;
+  }
+  if (station_scratch(&c->stat_scratch, &c->stat_scratch_doubles) != 0) {
+    c->stat_scratch = nullptr;   // ibdns_get_station_stats_noalloc then answers EHIP
+    c->stat_scratch_doubles = 0;
+    hipGetLastError();
   }
   if (c->d.cn && ensure_side(c) != IBDNS_OK) {   // the CN tables run beside the predictor
     ibdns_destroy(c);
@@ -1494,6 +1503,20 @@ int ibdns_get_station_stats(ibdns_ctx* c, void* dev_ws, size_t ws_bytes, double*
   if (check_launch() != IBDNS_OK) return IBDNS_EHIP;
   if (hipStreamSynchronize(c->st) != hipSuccess ||
       hipMemcpy(out, staged, bytes, hipMemcpyDeviceToHost) != hipSuccess)
+    return IBDNS_EHIP;
+  return read_status(c);
+}
+
+int ibdns_get_station_stats_noalloc(ibdns_ctx* c, double* out) {
+  if (!c || !out) return IBDNS_EINVAL;
+  if (c->probes.n <= 0) return IBDNS_ESTATE;
+  if (!c->stat_scratch) return IBDNS_EHIP;
+  const size_t doubles = (size_t)(c->probes.n / 9) * (2 + 2 * (size_t)c->probes.L);
+  if (doubles > c->stat_scratch_doubles) return IBDNS_ENOMEM;
+  launch_station_stats(c->probes, c->stat_scratch, c->st);
+  if (check_launch() != IBDNS_OK) return IBDNS_EHIP;
+  if (hipStreamSynchronize(c->st) != hipSuccess ||
+      hipMemcpy(out, c->stat_scratch, doubles * sizeof(double), hipMemcpyDeviceToHost) != hipSuccess)
     return IBDNS_EHIP;
   return read_status(c);
 }

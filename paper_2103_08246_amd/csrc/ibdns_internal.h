@@ -266,6 +266,9 @@ void launch_advance(Scalars* s, const double* partial, int nparts, double h, hip
 void launch_probes(const Dims& d, const Fields& f, const ProbeDev& pr, hipStream_t st);
 // per-station statistics of the probe records into out (n/9 stations x (2 + 2L) doubles)
 void launch_station_stats(const ProbeDev& pr, double* out, hipStream_t st);
+// Device address and size (doubles) of the current device's static staging
+// array for the station statistics; 0 on success, -1 if HIP refuses.
+int station_scratch(double** ptr, size_t* max_doubles);
 size_t cn_table_doubles(int nx, int ny, int nz);
 CnTables cn_tables_at(double* base, int nx, int ny, int nz);
 void launch_cn_tables(const Dims& d, const Scalars* s, const CnTables& t, hipStream_t st);

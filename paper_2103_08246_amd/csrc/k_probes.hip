@@ -11,6 +11,8 @@
 // and for each lag l the sums of u(t) u(t-l) and v(t) v(t-l) over the samples
 // that have a partner l steps back, from a ring of the last L samples.  A
 // probe's sums are accumulated in time order, one sample per step.
+#include <mutex>
+
 #include "ibdns_internal.h"
 
 namespace ibdns {
@@ -146,7 +148,31 @@ __global__ void __launch_bounds__(STAT_T) k_station_stats(ProbeDev pr, double* _
   }
 }
 
+// Staging of the station statistics for callers that cannot allocate device
+// memory (ibdns_get_station_stats_noalloc): a file-scope device array, one
+// copy per GPU, held until the process ends.  Host code never names it as a
+// device address: its address on a device comes from hipGetSymbolAddress.
+constexpr size_t STATION_SCRATCH_DOUBLES = size_t(1) << 18;   // 2 MiB
+static __device__ __align__(256) double scratch[STATION_SCRATCH_DOUBLES];
+
 }  // namespace
+
+int station_scratch(double** ptr, size_t* max_doubles) {
+  constexpr int MAX_DEVICES = 64;
+  static std::mutex lock;
+  static double* addr[MAX_DEVICES] = {};
+  int dev = -1;
+  if (hipGetDevice(&dev) != hipSuccess || dev < 0 || dev >= MAX_DEVICES) return -1;
+  std::lock_guard<std::mutex> g(lock);
+  if (!addr[dev]) {
+    void* p = nullptr;
+    if (hipGetSymbolAddress(&p, HIP_SYMBOL(scratch)) != hipSuccess || !p) return -1;
+    addr[dev] = static_cast<double*>(p);
+  }
+  *ptr = addr[dev];
+  *max_doubles = STATION_SCRATCH_DOUBLES;
+  return 0;
+}
 
 void launch_station_stats(const ProbeDev& pr, double* out, hipStream_t st) {
   if (pr.n <= 0) return;
