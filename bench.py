@@ -50,6 +50,12 @@ def max_divergence(u, v, w, h):
     return float(np.max(np.abs(d))) / h
 
 
+def cn_axis_ms(times: dict, steps: int) -> dict:
+    """Per-step milliseconds of the Crank-Nicolson factors (z, y, x; three
+    components each) from the per-kernel pass."""
+    return {k: times[k][0] / steps for k in ("cn_z", "cn_y", "cn_x") if k in times}
+
+
 def max_edge_strain(X, X0):
     """max |l/l0 - 1| over the flag's a-edges, b-edges and cell diagonals
     (X, X0: (ns, ns, 3) indexed [b, a]); the spring network's inextensibility."""
@@ -344,32 +350,36 @@ def main():
         run_c, wall_c, _, times_c = measure(ib.FP64, True, diffusion=ib.DIFFUSION_CN)
         a = run.fields()
         b = run_c.fields()
-        sweeps = times_c["all"].get("cn_sweeps", (0.0, 1))
-        sweep_ms = sweeps[0] / max(sweeps[1], 1)
-        # algorithmic bytes of the sweeps per evolved node (u: (nx-1) ny nz,
-        # v, w: nx ny nz): z and y a read+write forward pass and a read+write
-        # back substitution each, x the same plus the read of u^n
-        sweep_bytes = (32 + 32 + 40) * (3 * w.nx - 1) * w.ny * w.nz
+        per_axis = cn_axis_ms(times_c["all"], args.steps)
+        sweep_ms = sum(per_axis.values())
+        # algorithmic bytes of the factors per evolved node (u: (nx-1) ny nz,
+        # v, w: nx ny nz): z and y one read and one write each, x the read of
+        # the right-hand side and of u^n and the write of u~
+        sweep_bytes = (16 + 16 + 24) * (3 * w.nx - 1) * w.ny * w.nz
         out["crank_nicolson"] = {
             "value": round(w.cells * args.steps / wall_c / 1e6, 1),
             "ms_per_step": round(wall_c * 1e3 / args.steps, 4),
             "cn_sweeps_ms": round(sweep_ms, 4),
+            "cn_factor_ms": {k: round(v, 4) for k, v in per_axis.items()},
             "cn_sweeps_algorithmic_gbs": round(sweep_bytes / (sweep_ms * 1e-3) / 1e9, 1),
             "vel_rel_l2_vs_explicit": (sum(float(np.sum((x - y) ** 2)) for x, y in zip(b[:3], a[:3]))
                                        / sum(float(np.sum(y ** 2)) for y in a[:3])) ** 0.5,
-            "note": "FP64; z, y, x factored solves per component (z, y: thread per line; x: LDS tiles of 64 lines)"}
+            "note": "FP64; z, y, x factored solves per component, each one read and one write of the field "
+                    "(z, y: the periodic factors' inverse as a short convolution, thread per line; x: a "
+                    "wavefront per line, chunked elimination and cyclic reduction)"}
         print(f"# crank-nicolson: {wall_c * 1e3 / args.steps:.3f} ms/step", file=sys.stderr, flush=True)
         if not args.no_mixed:
             # mixed form: FP32 right-hand side and increments between the sweeps
             run_cm, wall_cm, _, times_cm = measure(ib.MIXED, True, diffusion=ib.DIFFUSION_CN)
             bm = run_cm.fields()
-            sw = times_cm["all"].get("cn_sweeps", (0.0, 1))
-            sw_ms = sw[0] / max(sw[1], 1)
+            per_axis_m = cn_axis_ms(times_cm["all"], args.steps)
+            sw_ms = sum(per_axis_m.values())
             out["crank_nicolson"]["mixed"] = {
                 "value": round(w.cells * args.steps / wall_cm / 1e6, 1),
                 "ms_per_step": round(wall_cm * 1e3 / args.steps, 4),
                 "speedup_vs_fp64_cn": round(wall_c / wall_cm, 3),
                 "cn_sweeps_ms": round(sw_ms, 4),
+                "cn_factor_ms": {k: round(v, 4) for k, v in per_axis_m.items()},
                 "vel_rel_l2_vs_fp64_cn": (sum(float(np.sum((x - y) ** 2)) for x, y in zip(bm[:3], b[:3]))
                                           / sum(float(np.sum(y ** 2)) for y in b[:3])) ** 0.5}
             print(f"# crank-nicolson mixed: {wall_cm * 1e3 / args.steps:.3f} ms/step", file=sys.stderr, flush=True)

@@ -331,7 +331,12 @@ void stage_predict(ibdns_ctx* c) {
     } else {
       TIMED(c, "cn_tables", launch_cn_tables(c->d, c->s, c->cnt, c->st));
     }
-    TIMED(c, "cn_sweeps", launch_cn_sweeps(c->d, c->f, c->cnt, c->st));
+    // per component: the z factor, then y, then x (u~ = u^n + du)
+    for (int comp = 0; comp < 3; ++comp) {
+      TIMED(c, "cn_z", launch_cn_axis(c->d, c->f, c->cnt, comp, 2, c->st));
+      TIMED(c, "cn_y", launch_cn_axis(c->d, c->f, c->cnt, comp, 1, c->st));
+      TIMED(c, "cn_x", launch_cn_axis(c->d, c->f, c->cnt, comp, 0, c->st));
+    }
   }
 }
 void stage_flux(ibdns_ctx* c) { TIMED(c, "flux_apply", launch_flux_apply(c->d, c->f, c->s, c->nparts, c->st)); }

@@ -5,23 +5,31 @@
 // here, per component,
 //   du = X^{-1} Y^{-1} Z^{-1} RHS,   X, Y, Z = 1 - (nu dt / 2) D2 along x, y, z,
 // in place, and finally u~ = u^n + du.  The periodic factors are cyclic
-// tridiagonal systems solved by Sherman-Morrison on a modified tridiagonal
-// system; the x factor carries the boundary increments (u: 0 at the inlet,
-// outflow value - u^n at the outlet; v, w: inlet ghost -du_0, outlet ghost
-// increment; zero-gradient ends under the test hook).
+// tridiagonal; the x factor carries the boundary increments (u: 0 at the
+// inlet, outflow value - u^n at the outlet; v, w: inlet ghost -du_0, outlet
+// ghost increment; zero-gradient ends under the test hook).
 //
 // The factor tables depend on dt only, which lives on the device: one small
-// kernel rebuilds them each step (on a second stream, beside the predictor).  Every sweep is one thread per line: for
-// the y and z sweeps lines of neighbouring x columns sit in neighbouring lanes
-// (coalesced); the x sweep stages tiles of 64 lines through LDS.  A periodic
-// sweep reads and writes the field twice (forward, back substitution with the
-// rank-one correction folded in).
-// Constant coefficients: the line loops read c' and 1/pivot from the tables.
+// kernel rebuilds them each step (on a second stream, beside the predictor).
+// Each factor reads and writes the field once:
+//   * z and y: the periodic factor's exact inverse is a short convolution
+//     (its kernel decays like rho^|m|, rho ~ nu dt / (2 h^2)), applied by one
+//     thread per line, neighbouring x columns in neighbouring lanes; when the
+//     truncated kernel would not reproduce the solve to round-off (large
+//     nu dt / h^2, short lines) the step falls back to the two-pass sweeps
+//     (Sherman-Morrison on a modified tridiagonal system), chosen on the
+//     device;
+//   * x: one wavefront per line, chunked elimination and cyclic reduction of
+//     the reduced system in LDS, as for the pressure's x lines.
+#include <algorithm>
+
 #include "ibdns_internal.h"
 
 namespace ibdns {
 
-size_t cn_table_doubles(int nx, int ny, int nz) { return 4 * (size_t)ny + 4 * (size_t)nz + 4 * (size_t)nx + 8; }
+size_t cn_table_doubles(int nx, int ny, int nz) {
+  return 4 * (size_t)ny + 4 * (size_t)nz + 4 * (size_t)nx + 8 + 4 * (CN_M + 1);
+}
 
 CnTables cn_tables_at(double* b, int nx, int ny, int nz) {
   CnTables t;
@@ -38,10 +46,18 @@ CnTables cn_tables_at(double* b, int nx, int ny, int nz) {
   t.xv_cp = t.xu_m + nx;
   t.xv_m = t.xv_cp + nx;
   t.sc = t.xv_m + nx;
+  t.gy = t.sc + 8;
+  t.gz = t.gy + CN_M + 1;
+  t.gx = t.gz + CN_M + 1;
   return t;
 }
 
 namespace {
+
+// rows the periodic convolution loads ahead of the one it needs next
+// (measured: 4 and 8 rows equal in FP32, 8 faster than 4 in FP64 along z)
+template <class T>
+__host__ __device__ constexpr int cn_pf() { return 8; }
 
 // Tridiagonal (-r, diag, -r) of n rows with the first and last diagonal
 // entries b0, bn: c'_i and 1/pivot_i of the elimination.
@@ -102,6 +118,53 @@ __device__ void cyclic_factor(int n, double r, double* __restrict__ cp, double* 
   sc2[1] = 1.0 / (1.0 + qp + vr * qlast);   // qp = q_0
 }
 
+// The inverse of a periodic factor (1 + 2r) x_k - r (x_{k-1} + x_{k+1}) = d_k
+// (n rows) is a convolution x_k = sum_m G(m) d_{k+m}: on the infinite line
+// G(m) = rho^|m| / sqrt(1 + 4r), rho = 2r / (1 + 2r + sqrt(1 + 4r)) the root
+// below 1 of r rho^2 - (1 + 2r) rho + r = 0; the periodic images add up to
+// G_n(m) = (rho^m + rho^(n - m)) / ((1 - rho^n) sqrt(1 + 4r)).  Truncated to
+// |m| <= CN_M it reproduces the solve to round-off when the dropped tail
+// 2 rho^(CN_M + 1) / (1 - rho) is below 2^-56 and the line is long enough for
+// the convolution's window; sel receives 1 then, else 0 (the sweeps run).
+__device__ void green_table(int n, double r, int pf, double* __restrict__ g, double* __restrict__ sel) {
+  const double s = sqrt(1.0 + 4.0 * r), rho = 2.0 * r / ((1.0 + 2.0 * r) + s);
+  double pw[CN_M + 1];
+  pw[0] = 1.0;
+  for (int m = 1; m <= CN_M; ++m) pw[m] = pw[m - 1] * rho;
+  double rn = 1.0, base = rho;   // rho^n by squaring (it underflows to 0 for long lines)
+  for (int e = n; e > 0; e >>= 1) {
+    if (e & 1) rn *= base;
+    base *= base;
+  }
+  for (int m = 0; m <= CN_M; ++m) {
+    const double far_ = pw[m] > 0.0 ? rn / pw[m] : 0.0;   // rho^(n - m)
+    g[m] = (pw[m] + far_) / ((1.0 - rn) * s);
+  }
+  const double pm = pw[CN_M] * rho;
+  const double tail = 2.0 * pm / (1.0 - rho);   // pm = rho^(CN_M + 1)
+  *sel = (tail <= 0x1p-56 && n >= 2 * CN_M + pf + 2) ? 1.0 : 0.0;
+}
+
+// x factor (non-periodic, boundary rows b0 and bn): with the infinite-line
+// solution y = G * d (d zero outside the line), x = y + alpha rho^i +
+// beta rho^(n-1-i), the homogeneous solutions fixed by the two boundary rows
+// (exact once rho^(n-2) is negligible).  gx[0..M] = rho^m / sqrt(1 + 4r),
+// gx[M+1 .. 2M+1] = rho^m; sel: 1 when this reproduces the solve to round-off
+// for lines of n rows.
+__device__ void green_table_x(int n, double r, double* __restrict__ gx, double* __restrict__ sel) {
+  const double s = sqrt(1.0 + 4.0 * r), rho = 2.0 * r / ((1.0 + 2.0 * r) + s);
+  double pm = 1.0;
+  for (int m = 0; m <= CN_M; ++m) {
+    gx[m] = pm / s;
+    gx[CN_M + 1 + m] = pm;
+    pm *= rho;
+  }
+  const double tail = 2.0 * pm / (1.0 - rho);
+  double rn = 1.0;
+  for (int e = 0; e < n - 2 - CN_M && rn > 0x1p-60; ++e) rn *= rho;
+  *sel = (tail <= 0x1p-56 && rn <= 0x1p-60 && n >= 4 * CN_M) ? 1.0 : 0.0;
+}
+
 // One workgroup per table (the recurrences are sequential; separate
 // workgroups run them side by side), one active thread each.
 __global__ void k_cn_tables(Dims d, const Scalars* __restrict__ s, CnTables t) {
@@ -119,6 +182,9 @@ __global__ void k_cn_tables(Dims d, const Scalars* __restrict__ s, CnTables t) {
         tri_factor(d.nx, r, 1.0 + 3.0 * r, 1.0 + 2.0 * r, 1.0 + 2.0 * r, t.xv_cp, t.xv_m);
       break;
     case 4: t.sc[0] = r; break;
+    case 5: green_table(d.ny, r, d.mixed ? cn_pf<float>() : cn_pf<double>(), t.gy, t.sc + 5); break;
+    case 6: green_table(d.nz, r, d.mixed ? cn_pf<float>() : cn_pf<double>(), t.gz, t.sc + 6); break;
+    case 7: green_table_x(d.nx - 1, r, t.gx, t.sc + 7); break;
     default: break;
   }
 }
@@ -142,6 +208,7 @@ __device__ __forceinline__ T* cn_field(const Fields& f, int comp) {
 constexpr int PUF = 8;
 template <int AXIS, class T>
 __global__ void __launch_bounds__(256) k_cn_periodic(Dims d, Fields f, CnTables t, int comp) {
+  if (t.sc[AXIS == 1 ? 5 : 6] != 0.0) return;   // the convolution takes this step
   const int ilo = comp == 0 ? 1 : 0, nxe = comp == 0 ? d.nx - 1 : d.nx;
   const long long g = (long long)blockIdx.x * 256 + threadIdx.x;
   const int other = AXIS == 1 ? d.nz : d.ny;       // the line index besides x
@@ -202,132 +269,465 @@ __global__ void __launch_bounds__(256) k_cn_periodic(Dims d, Fields f, CnTables 
   }
 }
 
+// Periodic factor by the convolution of green_table, one thread per line
+// (neighbouring x columns in neighbouring lanes), in place: one read and one
+// write of every value.  The thread marches k over the line with the window
+// d_{k-M} .. d_{k+M} and PF more rows in flight held in a ring of W registers
+// (slot e mod W holds d_e); the march is unrolled by W so that every slot is
+// a fixed register and a load in flight is never touched before it is used.
+// x_0 .. x_{M-1} are kept until the end: the window wraps around onto
+// d_0 .. d_{M-1} for the last rows.
+template <int AXIS, class T>
+__global__ void __launch_bounds__(256) k_cn_pconv(Dims d, Fields f, CnTables t, int comp) {
+  constexpr int M = CN_M, PF = cn_pf<T>(), W = 2 * M + 1 + PF;
+  if (t.sc[AXIS == 1 ? 5 : 6] == 0.0) return;   // the sweeps take this step
+  const int ilo = comp == 0 ? 1 : 0, nxe = comp == 0 ? d.nx - 1 : d.nx;
+  const int other = AXIS == 1 ? d.nz : d.ny;
+  const int n = AXIS == 1 ? d.ny : d.nz;
+  const long long g = (long long)blockIdx.x * 256 + threadIdx.x;
+  if (g >= (long long)nxe * other) return;
+  const int i = ilo + (int)(g % nxe), o = (int)(g / nxe);
+  const long long stride = AXIS == 1 ? (long long)d.P : d.PS;
+  T* a = cn_field<T>(f, comp) + (AXIS == 1 ? fidx(d, i, 0, o) : fidx(d, i, o, 0));
+  const double* G = AXIS == 1 ? t.gy : t.gz;
+  double gm[M + 1];
+#pragma unroll
+  for (int m = 0; m <= M; ++m) gm[m] = G[m];
+  // rows are visited from s0 on (y lines start at a row that depends on
+  // their plane, so that the waves in flight at a given time do not all read
+  // addresses a power-of-two multiple apart)
+  const int s0 = AXIS == 1 ? o % n : 0;
+  auto wrapn = [&](int e) {
+    e = e < 0 ? e + n : (e >= n ? e - n : e);
+    e += s0;
+    return e >= n ? e - n : e;
+  };
+  // ring[e mod W] = d_e for e = k - M .. k + M + PF at step k
+  double ring[W], headx[M];
+#pragma unroll
+  for (int e = -M; e <= M + PF; ++e) ring[(e + W) % W] = (double)a[(long long)wrapn(e) * stride];
+  for (int k0 = 0; k0 < n; k0 += W) {
+#pragma unroll
+    for (int u = 0; u < W; ++u) {
+      const int k = k0 + u;
+      if (k < n) {
+        double x = 0.0;
+#pragma unroll
+        for (int m = M; m >= 1; --m) x += gm[m] * (ring[(u - m + W) % W] + ring[(u + m) % W]);
+        x += gm[0] * ring[u];
+        if (k0 == 0 && u < M)
+          headx[u < M ? u : 0] = x;
+        else
+          a[(long long)wrapn(k) * stride] = (T)x;
+        // d_{k-M} leaves the window; d_{k+M+PF+1} (mod n) takes its slot.
+        // Rows past n - 1 + M are never used; they load a valid index.
+        ring[(u - M + W) % W] = (double)a[(long long)wrapn(k + M + PF + 1 >= 2 * n ? 0 : k + M + PF + 1) * stride];
+      }
+    }
+  }
+#pragma unroll
+  for (int u = 0; u < M; ++u) a[(long long)wrapn(u) * stride] = (T)headx[u];
+}
+
 __device__ __forceinline__ void cn_wave_sync() {
   __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
   __builtin_amdgcn_wave_barrier();
   __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
 }
 
-// x factor with the boundary increments, then u~ = u^n + du.  One wavefront
-// per workgroup takes 64 x lines (line g = j + ny k) and walks x in tiles of
-// XT values: the tile is loaded with 64 / XT lines per load instruction (XT
-// lanes on consecutive values of one line), lane l runs the recurrence along
-// line l in LDS, and the tile is stored the same way.  Loads go in unguarded
-// batches (line and column indexes clamped into range); only the stores are
-// guarded.
-constexpr int XT = 32;
-template <class T>
-__global__ void __launch_bounds__(64) k_cn_x(Dims d, Fields f, CnTables t, int comp) {
-  // loads per batch: 32 for FP64 storage, 16 for FP32 (each measured best)
-  constexpr int RPL = 64 / XT, NLD = 64 / RPL, B = sizeof(T) == 8 ? 32 : 16, LD = XT + 1;
-  static_assert(NLD % B == 0, "batch");
-  __shared__ double tl[64 * LD];
-  __shared__ long long RB[64];   // field offset of x index ilo on each line
-  const int lane = threadIdx.x;
+// x factor with the boundary increments and u~ = u^n + du in one pass: one
+// wavefront per x line, as for the pressure's x lines.  Lane l holds the
+// values l, l + 64, ... of the line (coalesced loads), staged in LDS as
+// contiguous chunks of C rows per lane; each lane eliminates its chunk's
+// interior rows onto the chunk's two end rows, the 128-row reduced system is
+// solved by parallel cyclic reduction in LDS, and the interior follows from
+// the end values.  The matrix is (-r, 1 + 2r, -r), strictly diagonally
+// dominant, so no pivoting.  Rows past the line are identity rows.
+constexpr int CNX_WAVES = 4;
+
+__device__ __forceinline__ double cnx_rcp(double x) {
+  double y = __builtin_amdgcn_rcp(x);
+  y = fma(y, fma(-x, y, 1.0), y);
+  y = fma(y, fma(-x, y, 1.0), y);
+  return y;
+}
+__device__ __forceinline__ int cnx_rpos(int r) { return (r & 1) * 64 + (r >> 1); }
+
+template <int C, class T>
+__global__ void __launch_bounds__(64 * CNX_WAVES) k_cn_xline(Dims d, Fields f, CnTables t, int comp) {
+  if (t.sc[7] != 0.0) return;   // the convolution takes this step
+  constexpr int LSP = C + 1, R = 128;
+  __shared__ double lb[CNX_WAVES][64 * LSP];
+  __shared__ double rA[CNX_WAVES][R], rB[CNX_WAVES][R], rC[CNX_WAVES][R], rD[CNX_WAVES][R];
+  const int wv = threadIdx.x / 64, lane0 = threadIdx.x % 64;
   const long long nl = (long long)d.ny * d.nz;
-  const long long g0 = (long long)blockIdx.x * 64;
-  const int nrow = (int)min((long long)64, nl - g0);
+  const long long first = (long long)blockIdx.x * CNX_WAVES + wv, stride = (long long)gridDim.x * CNX_WAVES;
   const bool neumann = comp > 0 && (d.flags & 1u) != 0;
   const int ilo = comp == 0 ? 1 : 0, n = comp == 0 ? d.nx - 1 : d.nx;
-  const double* st = comp == 0 ? f.u : (comp == 1 ? f.v : f.w);
-  T* fa = cn_field<T>(f, comp);
-  const double* cp = comp == 0 ? t.xu_cp : t.xv_cp;
-  const double* m = comp == 0 ? t.xu_m : t.xv_m;
+  const double* __restrict__ st = comp == 0 ? f.u : (comp == 1 ? f.v : f.w);
+  T* __restrict__ fa = cn_field<T>(f, comp);
   const double r = t.sc[0];
-  double dout = 0.0;   // this lane's line: outlet increment
-  {
-    const long long g = g0 + min(lane, nrow - 1);
-    const int j = (int)(g % d.ny), k = (int)(g / d.ny);
-    RB[lane] = fidx(d, ilo, j, k);
-    if (lane < nrow && !neumann) dout = f.bnd[comp * nl + g] - st[fidx(d, d.nx, j, k)];
-  }
-  cn_wave_sync();
-  const int sub = lane / XT, col = lane % XT;
-  auto load_tile = [&](int x0, int wt) {
-    const int cc = min(col, wt - 1);
-    for (int b0 = 0; b0 < NLD; b0 += B) {
-      double v[B];
+  const double bm = 1.0 + 2.0 * r;
+  const double b0 = comp == 0 ? bm : (neumann ? 1.0 + r : 1.0 + 3.0 * r);
+  const double bn = (comp > 0 && neumann) ? 1.0 + r : bm;
+  double* L = lb[wv];
+  double* A_ = rA[wv];
+  double* B_ = rB[wv];
+  double* C_ = rC[wv];
+  double* D_ = rD[wv];
+  auto coef = [&](int e, double& a, double& b, double& c) {
+    if (e >= n) {
+      a = 0.0;
+      b = 1.0;
+      c = 0.0;
+      return;
+    }
+    a = e == 0 ? 0.0 : -r;
+    c = e == n - 1 ? 0.0 : -r;
+    b = e == 0 ? b0 : (e == n - 1 ? bn : bm);
+  };
+  // the next line's right-hand side, u^n and outlet values are loaded while
+  // the current line is solved
+  double pre[C], pst[C], pout = 0.0, pin = 0.0;
+  auto fetch = [&](long long ln) {
+    const int j = (int)(ln % d.ny), k = (int)(ln / d.ny);
+    const long long base = fidx(d, ilo, j, k);
 #pragma unroll
-      for (int q = 0; q < B; ++q) v[q] = (double)fa[RB[(b0 + q) * RPL + sub] + x0 + cc];
-#pragma unroll
-      for (int q = 0; q < B; ++q) tl[((b0 + q) * RPL + sub) * LD + col] = v[q];
+    for (int q = 0; q < C; ++q) {
+      const int e = min(lane0 + 64 * q, n - 1);   // clamped: rows past the line are not used
+      pre[q] = (double)fa[base + e];
+      pst[q] = st[base + e];
+    }
+    if (!neumann) {
+      pout = f.bnd[comp * nl + ln];
+      pin = st[fidx(d, d.nx, j, k)];
     }
   };
-  const int ntile = (n + XT - 1) / XT;
-  double prev = 0.0;
-  // forward elimination, tiles left to right
-  for (int tt = 0; tt < ntile; ++tt) {
-    const int x0 = tt * XT, wt = min(XT, n - x0);
-    load_tile(x0, wt);
-    cn_wave_sync();
-    if (lane < nrow) {
-      for (int x = 0; x < wt; ++x) {
-        double rhs = tl[lane * LD + x];
-        if (x0 + x == n - 1) rhs += r * dout;
-        prev = (rhs + r * prev) * m[x0 + x];
-        tl[lane * LD + x] = prev;
-      }
-    }
-    cn_wave_sync();
-    for (int q = 0; q < NLD; ++q) {
-      const int row = q * RPL + sub;
-      if (row < nrow && col < wt) fa[RB[row] + x0 + col] = (T)tl[row * LD + col];
-    }
-    cn_wave_sync();
-  }
-  // back substitution, tiles right to left, adding u^n
-  for (int tt = ntile - 1; tt >= 0; --tt) {
-    const int x0 = tt * XT, wt = min(XT, n - x0);
-    load_tile(x0, wt);
-    cn_wave_sync();
-    if (lane < nrow) {
-      for (int x = wt - 1; x >= 0; --x) {
-        const int xi = x0 + x;
-        if (xi < n - 1) prev = tl[lane * LD + x] - cp[xi] * prev;   // xi = n-1: prev = d'_{n-1}
-        tl[lane * LD + x] = prev;
-      }
-    }
-    cn_wave_sync();
-    const int cc = min(col, wt - 1);
-    for (int b0 = 0; b0 < NLD; b0 += B) {
-      double v[B];
+  if (first < nl) fetch(first);
+  for (long long line = first; line < nl; line += stride) {
+    int lane = lane0;
+    asm volatile("" : "+v"(lane));
+    const int j = (int)(line % d.ny), k = (int)(line / d.ny);
+    const long long base = fidx(d, ilo, j, k);
+    const double dout = neumann ? 0.0 : pout - pin;
+    double sn[C];   // u^n of the values this lane stores
 #pragma unroll
-      for (int q = 0; q < B; ++q) v[q] = st[RB[(b0 + q) * RPL + sub] + x0 + cc];
-#pragma unroll
-      for (int q = 0; q < B; ++q) {
-        const int row = (b0 + q) * RPL + sub;
-        if (row < nrow && col < wt) fa[RB[row] + x0 + col] = (T)(v[q] + tl[row * LD + col]);
-      }
+    for (int q = 0; q < C; ++q) {
+      const int e = lane + 64 * q;
+      L[(e / C) * LSP + e % C] = e < n ? pre[q] + (e == n - 1 ? r * dout : 0.0) : 0.0;
+      sn[q] = pst[q];
     }
     cn_wave_sync();
+    if (line + stride < nl) fetch(line + stride);
+    double x[C];
+    {
+      const int s0 = lane * C;
+      double a[C], b[C], c[C], dd[C];
+#pragma unroll
+      for (int q = 0; q < C; ++q) {
+        coef(s0 + q, a[q], b[q], c[q]);
+        dd[q] = L[lane * LSP + q];
+      }
+      // interior rows q = 1..C-2: x_q = al_q + be_q x_s + ga_q x_e
+      double cp[C], al[C], be[C], ga[C];
+#pragma unroll
+      for (int q = 0; q < C; ++q) {
+        cp[q] = 0.0;
+        al[q] = 0.0;
+        be[q] = 0.0;
+        ga[q] = 0.0;
+      }
+#pragma unroll
+      for (int q = 1; q <= C - 2; ++q) {
+        const double inv = cnx_rcp(q == 1 ? b[1] : b[q] - a[q] * cp[q - 1]);
+        cp[q] = c[q] * inv;
+        if (q == 1) {
+          al[q] = dd[1] * inv;
+          be[q] = -a[1] * inv;
+          ga[q] = (q == C - 2 ? -c[q] : 0.0) * inv;
+        } else {
+          al[q] = (dd[q] - a[q] * al[q - 1]) * inv;
+          be[q] = (-a[q] * be[q - 1]) * inv;
+          ga[q] = ((q == C - 2 ? -c[q] : 0.0) - a[q] * ga[q - 1]) * inv;
+        }
+      }
+#pragma unroll
+      for (int q = C - 3; q >= 1; --q) {
+        al[q] = al[q] - cp[q] * al[q + 1];
+        be[q] = be[q] - cp[q] * be[q + 1];
+        ga[q] = ga[q] - cp[q] * ga[q + 1];
+      }
+      double A0, B0, C0, D0, A1, B1, C1, D1;
+      if constexpr (C >= 3) {
+        A0 = a[0];
+        B0 = b[0] + c[0] * be[1];
+        C0 = c[0] * ga[1];
+        D0 = dd[0] - c[0] * al[1];
+        A1 = a[C - 1] * be[C - 2];
+        B1 = b[C - 1] + a[C - 1] * ga[C - 2];
+        C1 = c[C - 1];
+        D1 = dd[C - 1] - a[C - 1] * al[C - 2];
+      } else {
+        A0 = a[0]; B0 = b[0]; C0 = c[0]; D0 = dd[0];
+        A1 = a[1]; B1 = b[1]; C1 = c[1]; D1 = dd[1];
+      }
+      const int r0 = 2 * lane, r1 = 2 * lane + 1;
+      A_[cnx_rpos(r0)] = A0; B_[cnx_rpos(r0)] = B0; C_[cnx_rpos(r0)] = C0; D_[cnx_rpos(r0)] = D0;
+      A_[cnx_rpos(r1)] = A1; B_[cnx_rpos(r1)] = B1; C_[cnx_rpos(r1)] = C1; D_[cnx_rpos(r1)] = D1;
+      for (int sp = 1; sp < R; sp <<= 1) {
+        cn_wave_sync();
+        double nA[2], nB[2], nC[2], nD[2];
+#pragma unroll
+        for (int u = 0; u < 2; ++u) {
+          const int rr = 2 * lane + u, rm = rr - sp, rp = rr + sp;
+          const double Ar = A_[cnx_rpos(rr)], Cr = C_[cnx_rpos(rr)];
+          double Aq = 0.0, Cq = 0.0, Bq = B_[cnx_rpos(rr)], Dq = D_[cnx_rpos(rr)];
+          if (rm >= 0) {
+            const double k1 = Ar * cnx_rcp(B_[cnx_rpos(rm)]);
+            Aq = -A_[cnx_rpos(rm)] * k1;
+            Bq -= C_[cnx_rpos(rm)] * k1;
+            Dq -= D_[cnx_rpos(rm)] * k1;
+          }
+          if (rp < R) {
+            const double k2 = Cr * cnx_rcp(B_[cnx_rpos(rp)]);
+            Cq = -C_[cnx_rpos(rp)] * k2;
+            Bq -= A_[cnx_rpos(rp)] * k2;
+            Dq -= D_[cnx_rpos(rp)] * k2;
+          }
+          nA[u] = Aq; nB[u] = Bq; nC[u] = Cq; nD[u] = Dq;
+        }
+        cn_wave_sync();
+#pragma unroll
+        for (int u = 0; u < 2; ++u) {
+          const int rr = 2 * lane + u;
+          A_[cnx_rpos(rr)] = nA[u]; B_[cnx_rpos(rr)] = nB[u]; C_[cnx_rpos(rr)] = nC[u]; D_[cnx_rpos(rr)] = nD[u];
+        }
+      }
+      cn_wave_sync();
+      const double xs = D_[cnx_rpos(r0)] * cnx_rcp(B_[cnx_rpos(r0)]);
+      const double xe = D_[cnx_rpos(r1)] * cnx_rcp(B_[cnx_rpos(r1)]);
+      x[0] = xs;
+      x[C - 1] = xe;
+#pragma unroll
+      for (int q = 1; q <= C - 2; ++q) x[q] = al[q] + be[q] * xs + ga[q] * xe;
+    }
+    cn_wave_sync();
+#pragma unroll
+    for (int q = 0; q < C; ++q) L[lane * LSP + q] = x[q];
+    cn_wave_sync();
+#pragma unroll
+    for (int q = 0; q < C; ++q) {
+      const int e = lane + 64 * q;
+      if (e < n) stream_store((T)(sn[q] + L[(e / C) * LSP + e % C]), &fa[base + e]);
+    }
+    cn_wave_sync();   // the line has left LDS
   }
 }
 
+// x factor by the convolution (green_table_x), one wavefront per line: the
+// right-hand side (with r dout in its last row) goes to LDS between zero
+// pads, lane l convolves its contiguous chunk of C rows from a register
+// window, the lanes holding rows 0 and n-1 also form y_{-1} and y_n, and
+// alpha, beta follow from the boundary rows:
+//   alpha = -((b0 - b) y_0 + r y_{-1}) / (b0 - r rho),
+//   beta  = -((bn - b) y_{n-1} + r y_n) / (bn - r rho),  b = 1 + 2r.
+// x goes back through LDS and leaves as u^n + x in coalesced rows.  The next
+// line's right-hand side, u^n and outlet values are loaded while the current
+// one is processed.
+template <int C, class T>
+__global__ void __launch_bounds__(64 * CNX_WAVES) k_cn_xconv(Dims d, Fields f, CnTables t, int comp) {
+  constexpr int M = CN_M, PAD = M + 1, LW = 64 * C + 2 * PAD, WIN = C + 2 * M + 2;
+  if (t.sc[7] == 0.0) return;   // the chunked solver takes this step
+  __shared__ double lb[CNX_WAVES][LW];
+  const int wv = threadIdx.x / 64, lane = threadIdx.x % 64;
+  const long long nl = (long long)d.ny * d.nz;
+  const long long first = (long long)blockIdx.x * CNX_WAVES + wv, stride = (long long)gridDim.x * CNX_WAVES;
+  const bool neumann = comp > 0 && (d.flags & 1u) != 0;
+  const int ilo = comp == 0 ? 1 : 0, n = comp == 0 ? d.nx - 1 : d.nx;
+  const double* __restrict__ st = comp == 0 ? f.u : (comp == 1 ? f.v : f.w);
+  T* __restrict__ fa = cn_field<T>(f, comp);
+  const double r = t.sc[0];
+  const double b = 1.0 + 2.0 * r;
+  const double b0 = comp == 0 ? b : (neumann ? 1.0 + r : 1.0 + 3.0 * r);
+  const double bn = (comp > 0 && neumann) ? 1.0 + r : b;
+  double G[M + 1];
+#pragma unroll
+  for (int m = 0; m <= M; ++m) G[m] = t.gx[m];
+  const double rho = t.gx[M + 2];
+  const double den0 = 1.0 / (b0 - r * rho), denn = 1.0 / (bn - r * rho);
+  double* L = lb[wv] + PAD;   // L[e], e = -PAD .. 64 C + PAD - 1
+  // zero pads once: rows -PAD..-1 and n..64C+PAD-1 are never written by a line
+  for (int e = lane - PAD; e < 64 * C + PAD; e += 64)
+    if (e < 0 || e >= n) L[e] = 0.0;
+  double pre[C], pst[C], pout = 0.0, pin = 0.0;
+  auto fetch = [&](long long ln) {
+    const int j = (int)(ln % d.ny), k = (int)(ln / d.ny);
+    const long long base = fidx(d, ilo, j, k);
+#pragma unroll
+    for (int q = 0; q < C; ++q) {
+      const int e = min(lane + 64 * q, n - 1);   // clamped: rows past the line are not used
+      pre[q] = (double)fa[base + e];
+      pst[q] = st[base + e];
+    }
+    if (!neumann) {
+      pout = f.bnd[comp * nl + ln];
+      pin = st[fidx(d, d.nx, j, k)];
+    }
+  };
+  if (first < nl) fetch(first);
+  for (long long line = first; line < nl; line += stride) {
+    const int j = (int)(line % d.ny), k = (int)(line / d.ny);
+    const long long base = fidx(d, ilo, j, k);
+    const double dout = neumann ? 0.0 : pout - pin;
+    double sn[C];
+#pragma unroll
+    for (int q = 0; q < C; ++q) {
+      const int e = lane + 64 * q;
+      if (e < n) L[e] = pre[q] + (e == n - 1 ? r * dout : 0.0);
+      sn[q] = pst[q];
+    }
+    cn_wave_sync();
+    if (line + stride < nl) fetch(line + stride);
+    // window rows e0 - M - 1 .. e0 + C + M of this lane's chunk e0 = lane C
+    const int e0 = lane * C;
+    double wnd[WIN];
+#pragma unroll
+    for (int q = 0; q < WIN; ++q) wnd[q] = L[e0 - M - 1 + q];
+    double y[C];
+#pragma unroll
+    for (int q = 0; q < C; ++q) {
+      double acc = 0.0;
+#pragma unroll
+      for (int m = M; m >= 1; --m) acc += G[m] * (wnd[q + M + 1 - m] + wnd[q + M + 1 + m]);
+      y[q] = acc + G[0] * wnd[q + M + 1];
+    }
+    // y_{-1} (lane 0) and y_n (the lane holding row n - 1): the window's first
+    // row and the one after the chunk
+    double yb = 0.0;
+    {
+      const int last = (n - 1) / C;
+      const int qo = lane == 0 ? 0 : (n - 1) - e0 + 2;   // window offset of row -1 or row n, minus M
+      if (lane == 0 || lane == last) {
+        double acc = 0.0;
+#pragma unroll
+        for (int m = M; m >= 1; --m) {
+          const int a1 = qo + M - m, a2 = qo + M + m;
+          acc += G[m] * (L[e0 - M - 1 + a1] + L[e0 - M - 1 + a2]);
+        }
+        yb = acc + G[0] * L[e0 - M - 1 + qo + M];
+      }
+    }
+    const int last = (n - 1) / C;
+    const double ym1 = __shfl(yb, 0, 64), y0 = __shfl(y[0], 0, 64);
+    const double yn = __shfl(yb, last, 64);
+    double ynm1 = 0.0;
+#pragma unroll
+    for (int q = 0; q < C; ++q)
+      if (e0 + q == n - 1) ynm1 = y[q];
+    ynm1 = __shfl(ynm1, last, 64);
+    const double alpha = -((b0 - b) * y0 + r * ym1) * den0;
+    const double beta = -((bn - b) * ynm1 + r * yn) * denn;
+    cn_wave_sync();   // every lane has read its window
+#pragma unroll
+    for (int q = 0; q < C; ++q) {
+      const int e = e0 + q;
+      double x = y[q];
+      if (e <= M) x += alpha * t.gx[M + 1 + e];                            // alpha rho^e
+      if (e < n && n - 1 - e <= M) x += beta * t.gx[M + 1 + (n - 1 - e)];  // beta rho^(n-1-e)
+      if (e < n) L[e] = x;
+    }
+    cn_wave_sync();
+#pragma unroll
+    for (int q = 0; q < C; ++q) {
+      const int e = lane + 64 * q;
+      if (e < n) stream_store((T)(sn[q] + L[e]), &fa[base + e]);
+    }
+    cn_wave_sync();   // the line has left LDS
+  }
+}
+
+static int cnx_chunk(int nx) {   // the pressure x solve's chunk sizes
+  int C = (nx + 63) / 64;
+  if (C < 2) C = 2;
+  if (C == 7) C = 8;
+  if (C > 8 && C <= 12) C = 12;
+  return C;
+}
+
+template <class T, int C>
+void launch_cnx(const Dims& d, const Fields& f, const CnTables& t, int comp, hipStream_t st) {
+  static int grid = 0;
+  if (grid == 0) {
+    int dev = 0, cus = 0, per = 0;
+    if (hipGetDevice(&dev) != hipSuccess || hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev) != hipSuccess ||
+        hipOccupancyMaxActiveBlocksPerMultiprocessor(&per, k_cn_xline<C, T>, 64 * CNX_WAVES, 0) != hipSuccess)
+      cus = per = 1;
+    grid = std::max(1, cus * per);
+  }
+  static int gridc = 0;
+  if (gridc == 0) {
+    int dev = 0, cus = 0, per = 0;
+    if (hipGetDevice(&dev) != hipSuccess || hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev) != hipSuccess ||
+        hipOccupancyMaxActiveBlocksPerMultiprocessor(&per, k_cn_xconv<C, T>, 64 * CNX_WAVES, 0) != hipSuccess)
+      cus = per = 1;
+    gridc = std::max(1, cus * per);
+  }
+  const long long nl = (long long)d.ny * d.nz;
+  const long long lines_blocks = (nl + CNX_WAVES - 1) / CNX_WAVES;
+  // the convolution when exact to round-off this step, else the chunked
+  // solver (a device-side choice, sc[7]; the launch not chosen returns at once)
+  hipLaunchKernelGGL((k_cn_xconv<C, T>), dim3((int)std::min<long long>(gridc, lines_blocks)), dim3(64 * CNX_WAVES),
+                     0, st, d, f, t, comp);
+  hipLaunchKernelGGL((k_cn_xline<C, T>), dim3((int)std::min<long long>(grid, lines_blocks)), dim3(64 * CNX_WAVES), 0,
+                     st, d, f, t, comp);
+}
+
 template <class T>
-void launch_cn_t(const Dims& d, const Fields& f, const CnTables& t, hipStream_t st) {
-  for (int comp = 0; comp < 3; ++comp) {
-    const int nxe = comp == 0 ? d.nx - 1 : d.nx;
-    const long long nz_lines = (long long)nxe * d.ny, ny_lines = (long long)nxe * d.nz;
-    hipLaunchKernelGGL((k_cn_periodic<2, T>), dim3((unsigned)((nz_lines + 255) / 256)), dim3(256),
-                       4 * sizeof(double) * d.nz, st, d, f, t, comp);
-    hipLaunchKernelGGL((k_cn_periodic<1, T>), dim3((unsigned)((ny_lines + 255) / 256)), dim3(256),
-                       4 * sizeof(double) * d.ny, st, d, f, t, comp);
-    const long long nl = (long long)d.ny * d.nz;
-    hipLaunchKernelGGL(k_cn_x<T>, dim3((unsigned)((nl + 63) / 64)), dim3(64), 0, st, d, f, t, comp);
+void launch_cnx_c(const Dims& d, const Fields& f, const CnTables& t, int comp, hipStream_t st) {
+  switch (cnx_chunk(d.nx)) {
+    case 2: launch_cnx<T, 2>(d, f, t, comp, st); break;
+    case 3: launch_cnx<T, 3>(d, f, t, comp, st); break;
+    case 4: launch_cnx<T, 4>(d, f, t, comp, st); break;
+    case 5: launch_cnx<T, 5>(d, f, t, comp, st); break;
+    case 6: launch_cnx<T, 6>(d, f, t, comp, st); break;
+    case 8: launch_cnx<T, 8>(d, f, t, comp, st); break;
+    case 12: launch_cnx<T, 12>(d, f, t, comp, st); break;
+    default: break;
+  }
+}
+
+// One factor of one component: z or y (the convolution when it is exact to
+// round-off this step -- a device-side choice, sc[5] and sc[6] -- else the
+// two-pass sweeps; the launch not chosen returns at once), or x.
+template <class T>
+void launch_cn_axis_t(const Dims& d, const Fields& f, const CnTables& t, int comp, int axis, hipStream_t st) {
+  const int nxe = comp == 0 ? d.nx - 1 : d.nx;
+  if (axis == 2) {
+    const long long lines = (long long)nxe * d.ny;
+    const dim3 grid((unsigned)((lines + 255) / 256));
+    hipLaunchKernelGGL((k_cn_pconv<2, T>), grid, dim3(256), 0, st, d, f, t, comp);
+    hipLaunchKernelGGL((k_cn_periodic<2, T>), grid, dim3(256), 4 * sizeof(double) * d.nz, st, d, f, t, comp);
+  } else if (axis == 1) {
+    const long long lines = (long long)nxe * d.nz;
+    const dim3 grid((unsigned)((lines + 255) / 256));
+    hipLaunchKernelGGL((k_cn_pconv<1, T>), grid, dim3(256), 0, st, d, f, t, comp);
+    hipLaunchKernelGGL((k_cn_periodic<1, T>), grid, dim3(256), 4 * sizeof(double) * d.ny, st, d, f, t, comp);
+  } else {
+    launch_cnx_c<T>(d, f, t, comp, st);
   }
 }
 
 }  // namespace
 
 void launch_cn_tables(const Dims& d, const Scalars* s, const CnTables& t, hipStream_t st) {
-  hipLaunchKernelGGL(k_cn_tables, dim3(5), dim3(64), 0, st, d, s, t);
+  hipLaunchKernelGGL(k_cn_tables, dim3(8), dim3(64), 0, st, d, s, t);
 }
 
-void launch_cn_sweeps(const Dims& d, const Fields& f, const CnTables& t, hipStream_t st) {
+void launch_cn_axis(const Dims& d, const Fields& f, const CnTables& t, int comp, int axis, hipStream_t st) {
   if (d.mixed)
-    launch_cn_t<float>(d, f, t, st);
+    launch_cn_axis_t<float>(d, f, t, comp, axis, st);
   else
-    launch_cn_t<double>(d, f, t, st);
+    launch_cn_axis_t<double>(d, f, t, comp, axis, st);
 }
 
 }  // namespace ibdns

@@ -292,7 +292,7 @@ __device__ __forceinline__ void div_ffty_body(const Dims& d, const Fields& f, co
       out = make_double2(0.5 * (A.x + B.x), 0.5 * (A.y - B.y));   // (Z_m + conj Z_{N-m}) / 2
     else
       out = make_double2(0.5 * (A.y + B.y), -0.5 * (A.x - B.x));  // (Z_m - conj Z_{N-m}) / 2i
-    if (i < d.nx) f.spec[i + (long long)d.nx * (m + (long long)MY * k)] = out;
+    if (i < d.nx) stream_store(out, &f.spec[i + (long long)d.nx * (m + (long long)MY * k)]);
   }
 }
 
@@ -332,7 +332,7 @@ __device__ __forceinline__ void fftz_body(const Dims& d, const Fields& f, const 
   for (int e = threadIdx.x; e < TXC * NZ; e += FT) {
     const int ix = e % TXC, k = e / TXC;
     const int i = i0 + ix;
-    if (i < d.nx) base[i + lstride * k] = buf[ix * LS + lp(k)];
+    if (i < d.nx) stream_store(buf[ix * LS + lp(k)], &base[i + lstride * k]);
   }
 }
 
@@ -599,7 +599,7 @@ __device__ __forceinline__ void tri_body(const Dims& d, const Fields& f, const d
     wave_sync();
     for (int t = 0; t < C; ++t) {
       const int e = lane + 64 * t;
-      if (e < nx) g[e] = L[(e / C) * LSP + e % C];
+      if (e < nx) stream_store(L[(e / C) * LSP + e % C], &g[e]);
     }
     wave_sync();  // the line has left LDS
   }
@@ -653,15 +653,15 @@ __device__ __forceinline__ void project_body(const Dims& d, const Fields& f, Sca
       const long long cjm = fidx(d, i, jm, k), cjp = fidx(d, i, jp, k);
       const double vj = (double)vt[c] - dt * (ph_c - phi[cjm]) * inv_h;
       const double vjp = (double)vt[cjp] - dt * (phi[cjp] - ph_c) * inv_h;
-      uo[c] = ui;
-      vo[c] = vj;
-      wo[c] = wk;
+      stream_store(ui, &uo[c]);
+      stream_store(vj, &vo[c]);
+      stream_store(wk, &wo[c]);
       if (i == nx - 1) {
         uo[c + 1] = uip;                 // outlet face keeps u~
         vo[c + 1] = bnd[nplane + qb];    // outlet ghosts keep their provisional values
         wo[c + 1] = bnd[2 * nplane + qb];
       }
-      if (mode == 0) po[c] = po[c] + ph_c;
+      if (mode == 0) stream_store(po[c] + ph_c, &po[c]);
       double speed = fabs(0.5 * (ui + uip)) + fabs(0.5 * (vj + vjp)) + fabs(0.5 * (wk + wkp));
       if (!(speed <= 1.7976931348623157e308)) {
         atomicOr(&s->status, (int)ST_NONFINITE);

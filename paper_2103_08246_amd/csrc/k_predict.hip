@@ -157,9 +157,9 @@ __device__ __forceinline__ void predict_body(const Dims& d, const Fields& f, con
         const T lap = (uxp + uxm - two * u0) + (uyp + uym - two * u0) + (uzp + uzm - two * u0);
         const T H = cn ? -adv : -adv + c_d * lap;
         const T Hold = first ? H : hu[c];
-        hu[c] = H;
+        stream_store(H, &hu[c]);
         const T gp = (p_c - spp[o0 - 1]) * inv_h;
-        ut[c] = cn ? dt * (c1 * H - c2 * Hold - gp + c_d * lap) : u0 + dt * (c1 * H - c2 * Hold - gp);
+        stream_store(cn ? dt * (c1 * H - c2 * Hold - gp + c_d * lap) : u0 + dt * (c1 * H - c2 * Hold - gp), &ut[c]);
       } else {
         ut[c] = U(0, 0, sc);  // inlet face keeps U
         hu[c] = (T)0;
@@ -181,9 +181,9 @@ __device__ __forceinline__ void predict_body(const Dims& d, const Fields& f, con
         const T lap = (vxp + vxm - two * v0) + (vyp + vym - two * v0) + (vzp + vzm - two * v0);
         const T H = cn ? -adv : -adv + c_d * lap;
         const T Hold = first ? H : hv[c];
-        hv[c] = H;
+        stream_store(H, &hv[c]);
         const T gp = (p_c - spp[o0 - LX]) * inv_h;
-        vt[c] = cn ? dt * (c1 * H - c2 * Hold - gp + c_d * lap) : v0 + dt * (c1 * H - c2 * Hold - gp);
+        stream_store(cn ? dt * (c1 * H - c2 * Hold - gp + c_d * lap) : v0 + dt * (c1 * H - c2 * Hold - gp), &vt[c]);
       }
       // ---------------- w cell i ----------------
       {
@@ -202,9 +202,9 @@ __device__ __forceinline__ void predict_body(const Dims& d, const Fields& f, con
         const T lap = (wxp + wxm - two * w0) + (wyp + wym - two * w0) + (wzp + wzm - two * w0);
         const T H = cn ? -adv : -adv + c_d * lap;
         const T Hold = first ? H : hw[c];
-        hw[c] = H;
+        stream_store(H, &hw[c]);
         const T gp = (p_c - p_km) * inv_h;
-        wt[c] = cn ? dt * (c1 * H - c2 * Hold - gp + c_d * lap) : w0 + dt * (c1 * H - c2 * Hold - gp);
+        stream_store(cn ? dt * (c1 * H - c2 * Hold - gp + c_d * lap) : w0 + dt * (c1 * H - c2 * Hold - gp), &wt[c]);
       }
     }
     p_km = p_c;
