@@ -241,7 +241,7 @@ __device__ __forceinline__ void div_ffty_body(const Dims& d, const Fields& f, co
   // j = tid / TXC + RP n; the loads of U rows are issued before any is used.
   // Columns past nx read the last column and store 0.
   static_assert(FT % TXC == 0, "one column per thread");
-  constexpr int RP = FT / TXC, NIT = (NY + RP - 1) / RP, U = load_batch(NIT, 4);
+  constexpr int RP = FT / TXC, NIT = (NY + RP - 1) / RP, U = load_batch(NIT, sizeof(T) == 4 ? 8 : 4);
   const int ix = threadIdx.x % TXC, i = bx * TXC + ix;
   const bool live = i < d.nx;
   const int ic = live ? i : d.nx - 1;
@@ -685,23 +685,21 @@ __device__ __forceinline__ void project_body(const Dims& d, const Fields& f, Sca
 }
 
 // Single-run kernels: 1-D grids; the z FFT takes its tiles in XCD-aware order.
-// FP32 provisional rows: a 16-column tile reads half of each 128-byte line, so
-// a workgroup takes the two tiles that share those lines, one after the other.
-template <class T>
-__host__ __device__ constexpr int div_tiles_per_block() { return sizeof(T) == 4 ? 2 : 1; }
+// FP32 provisional rows: a 16-column tile reads half of each 128-byte line.
+// In every full group of 16 dispatches, dispatches b and b + 8 (which the
+// round-robin dispatcher sends to the same XCD, one after the other) take the
+// two neighbouring tiles that share those lines, so the second finds them in
+// that XCD's L2.  Bijective on [0, n).
+__device__ inline int pair_remap(int b, int n) {
+  const int g = b & ~15, r = b & 15;
+  return g + 16 <= n ? g + 2 * (r & 7) + (r >> 3) : b;
+}
 template <int NY, class T>
 __global__ void __launch_bounds__(FT) k_div_ffty(Dims d, Fields f, const Scalars* __restrict__ s,
                                                  const double2* __restrict__ tw) {
-  constexpr int TPB = div_tiles_per_block<T>();
-  const int gx = (d.nx + 15) / 16, gp = (gx + TPB - 1) / TPB;
-  const int bp = blockIdx.x % gp, k = blockIdx.x / gp;
-  div_ffty_body<NY, T>(d, f, s, tw, TPB * bp, k);
-  if constexpr (TPB == 2) {
-    if (2 * bp + 1 < gx) {
-      __syncthreads();  // the first tile has left LDS
-      div_ffty_body<NY, T>(d, f, s, tw, 2 * bp + 1, k);
-    }
-  }
+  const int gx = (d.nx + 15) / 16;
+  const int b = sizeof(T) == 4 ? pair_remap(blockIdx.x, gridDim.x) : (int)blockIdx.x;
+  div_ffty_body<NY, T>(d, f, s, tw, b % gx, b / gx);
 }
 template <int NZ, int SIGN>
 __global__ void __launch_bounds__(FT) k_fftz(Dims d, Fields f, const double2* __restrict__ tw) {
@@ -816,14 +814,12 @@ bool fft_size_supported(int n) {
 
 void launch_div_ffty(const Dims& d, const Fields& f, const Scalars* s, const double2* tw_y,
                      hipStream_t st) {
-  const int gx = (d.nx + 15) / 16;
+  const dim3 grid(((d.nx + 15) / 16) * d.nz);
   if (d.mixed) {
-    const dim3 grid(((gx + 1) / 2) * d.nz);
 #define CALL(NY) hipLaunchKernelGGL((k_div_ffty<NY, float>), grid, dim3(FT), 0, st, d, f, s, tw_y)
     IBDNS_FFT_SWITCH(d.ny, CALL)
 #undef CALL
   } else {
-    const dim3 grid(gx * d.nz);
 #define CALL(NY) hipLaunchKernelGGL((k_div_ffty<NY, double>), grid, dim3(FT), 0, st, d, f, s, tw_y)
     IBDNS_FFT_SWITCH(d.ny, CALL)
 #undef CALL
