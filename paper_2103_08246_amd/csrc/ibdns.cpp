@@ -124,7 +124,7 @@ size_t fluid_bytes(const ibdns_domain& dm) {
   dd.nx = dm.nx;
   dd.ny = dm.ny;
   dd.nz = dm.nz;
-  b += up(project_blocks(dd) * sizeof(double));
+  b += up(project_part_slots(dd) * sizeof(double));
   b += up(3 * (size_t)dm.ny * dm.nz * sizeof(double));  // outlet planes
   b += up(dm.ny * sizeof(double2)) + up(dm.nz * sizeof(double2));
   b += up(MY * sizeof(double)) + up(dm.nz * sizeof(double));
@@ -597,7 +597,7 @@ int ibdns_init_domain(const ibdns_domain* dm, const double* zu, const double* zv
   for (auto p : fl) *p = c->carve<double>(d.FS);
   c->f.spec = c->carve<double2>((size_t)d.nx * d.MY * d.nz);
   c->f.partial = c->carve<double>(2 * (size_t)c->nparts);
-  c->f.speed_part = c->carve<double>(project_blocks(d));
+  c->f.speed_part = c->carve<double>(project_part_slots(d));
   c->f.bnd = c->carve<double>(3 * (size_t)d.ny * d.nz);
   c->tw_y = c->carve<double2>(d.ny);
   c->tw_z = c->carve<double2>(d.nz);
@@ -1756,7 +1756,7 @@ RunDesc make_desc(ibdns_ctx* c) {
   r.lam_y = c->lam_y;
   r.lam_z = c->lam_z;
   r.nparts = c->nparts;
-  r.nspeed = project_blocks(c->d);
+  r.nspeed = project_batch_blocks(c->d);
   r.has_flag = c->has_flag ? 1 : 0;
   return r;
 }
@@ -1911,7 +1911,7 @@ int ibdns_batch_create(ibdns_ctx* const* runs, int32_t n_runs, void* dev_ws, siz
   ok = ok && make_groups(b, b->fftz_g, [&](int r) { return R(r)->d.nz; }, [&](int r) { return fftz_blocks(R(r)->d); });
   ok = ok && make_groups(b, b->tri_g, [&](int r) { return tri_chunk(R(r)->d.nx); }, [&](int r) { return tri_blocks(R(r)->d); });
   ok = ok && make_groups(b, b->iffty_g, [&](int r) { return R(r)->d.ny; }, [&](int r) { return iffty_blocks(R(r)->d); });
-  ok = ok && make_launch(b, b->project, all, [&](int r) { return project_blocks(R(r)->d); });
+  ok = ok && make_launch(b, b->project, all, [&](int r) { return project_batch_blocks(R(r)->d); });
   ok = ok && make_launch(b, b->flag_prep, hasf, [&](int) { return 1; });
   ok = ok && make_launch(b, b->flag_bands, hasf, [&](int r) { return flag_bands(R(r)->fl.ns); });
   ok = ok && make_launch(b, b->advance, all, [&](int) { return 1; });

@@ -18,7 +18,7 @@
 //   k_iffty     complex-to-real inverse y FFT to phi;
 //   k_project   projection, pressure update and the CFL maximum (max of the
 //               cell speed per block, written to a per-block slot).
-// FFTs: mixed-radix (8, 4, 2, 3) Stockham passes over lines held in LDS, one
+// FFTs: mixed-radix (8, 4, 6, 2, 3) Stockham passes over lines held in LDS, one
 // register-staged butterfly set per thread and pass, twiddles from a table
 // exp(-2 pi i m / N) built on the host.
 #include <algorithm>
@@ -82,6 +82,27 @@ struct DFT<4, SIGN> {
     v[1] = cadd(t1, t3);
     v[2] = csub(t0, t2);
     v[3] = csub(t1, t3);
+  }
+};
+
+// Two 3-point DFTs of the even and odd samples, then one radix-2 stage with
+// the twiddles exp(SIGN i pi k / 3).
+template <int SIGN>
+struct DFT<6, SIGN> {
+  static __device__ __forceinline__ void run(double2* v) {
+    double2 e[3] = {v[0], v[2], v[4]};
+    double2 o[3] = {v[1], v[3], v[5]};
+    DFT<3, SIGN>::run(e);
+    DFT<3, SIGN>::run(o);
+    const double h = 0.86602540378443864676;  // sin(pi / 3)
+    const double2 o1 = cadd(cscale(o[1], 0.5), cscale(mul_si<SIGN>(o[1]), h));
+    const double2 o2 = csub(cscale(mul_si<SIGN>(o[2]), h), cscale(o[2], 0.5));
+    v[0] = cadd(e[0], o[0]);
+    v[3] = csub(e[0], o[0]);
+    v[1] = cadd(e[1], o1);
+    v[4] = csub(e[1], o1);
+    v[2] = cadd(e[2], o2);
+    v[5] = csub(e[2], o2);
   }
 };
 
@@ -205,7 +226,7 @@ struct FFTPasses {
                                              const int tid = threadIdx.x) {
     constexpr int REM = N / P;
     if constexpr (REM > 1) {
-      constexpr int R = (REM % 8 == 0) ? 8 : (REM % 4 == 0) ? 4 : (REM % 2 == 0) ? 2 : 3;
+      constexpr int R = (REM % 8 == 0) ? 8 : (REM % 4 == 0) ? 4 : (REM == 6) ? 6 : (REM % 2 == 0) ? 2 : 3;
       static_assert(REM % R == 0, "FFT length must be 2^a 3^b");
       stockham_pass<N, R, P, SIGN, NL, NT, LS>(buf, tw, tid);
       FFTPasses<N, P * R, SIGN, NL, NT, LS>::run(buf, tw, tid);
@@ -220,7 +241,7 @@ __device__ __forceinline__ double2 cfms(double2 d, double2 a, double s) {
   return make_double2(d.x - a.x * s, d.y - a.y * s);
 }
 
-constexpr int FT = 256;  // threads per FFT workgroup
+constexpr int FT = 256;  // threads per FFT workgroup (512 measured no faster)
 
 // r = D u~ / dt for a 16-column x tile of one z plane, then the y FFT of the
 // 16 real columns as 8 complex lines, unpacked into the half spectrum.
@@ -606,19 +627,36 @@ __device__ __forceinline__ void tri_body(const Dims& d, const Fields& f, const d
 }
 
 // ---------------------------------------------------------------------------
-constexpr int PBX = 64, PBY = 4, PKZ = 16;
+// Projection tiles (x, y, z-march).  A single run whose nx is a multiple of
+// 256 takes rows of 256 cells (each wavefront set reads 2 KB row segments of
+// every field); other runs and batches take 64 x 4 columns.  Both march
+// 8 planes.  Measured on the 768 x 384 x 384 step (FP64 / mixed):
+// 64 x 4 x 16 1.744 / 1.519 ms, 64 x 4 x 8 1.692 / 1.459, 256 x 1 x 8
+// 1.675 / 1.431; 16 or 32 planes, or 128 x 4, 64 x 8, 32 x 8, 384 x 1 tiles
+// were slower.
+struct ProjWide {
+  static constexpr int X = 256, Y = 1, Z = 8;
+};
+struct ProjSquare {
+  static constexpr int X = 64, Y = 4, Z = 8;
+};
+template <class S>
+__host__ __device__ inline int proj_tiles(const Dims& d) {
+  return ((d.nx + S::X - 1) / S::X) * ((d.ny + S::Y - 1) / S::Y) * ((d.nz + S::Z - 1) / S::Z);
+}
+inline bool proj_wide(const Dims& d) { return d.nx % ProjWide::X == 0; }
 
-// Projection of the faces of a column of cells (z-march over PKZ planes: phi
+// Projection of the faces of a column of cells (z-march over KZ planes: phi
 // and the projected w of plane k+1 are reused by plane k+1), pressure update,
 // and the per-block maximum of the cell speed |u_c| + |v_c| + |w_c| (face
 // means of the projected field).  mode 1 (initial projection) leaves p.
-template <class T>
+template <class T, class S>
 __device__ __forceinline__ void project_body(const Dims& d, const Fields& f, Scalars* s, int mode, const Blk bk) {
-  const int tx = threadIdx.x % PBX, ty = threadIdx.x / PBX;
-  const int i = bk.x * PBX + tx;
-  const int j = bk.y * PBY + ty;
-  const int kb = bk.z * PKZ;
-  const int ke = min(kb + PKZ, d.nz);
+  const int tx = threadIdx.x % S::X, ty = threadIdx.x / S::X;
+  const int i = bk.x * S::X + tx;
+  const int j = bk.y * S::Y + ty;
+  const int kb = bk.z * S::Z;
+  const int ke = min(kb + S::Z, d.nz);
   const T* __restrict__ ut = reinterpret_cast<const T*>(f.ut);
   const T* __restrict__ vt = reinterpret_cast<const T*>(f.vt);
   const T* __restrict__ wt = reinterpret_cast<const T*>(f.wt);
@@ -673,33 +711,33 @@ __device__ __forceinline__ void project_body(const Dims& d, const Fields& f, Sca
     }
   }
   for (int off = 32; off > 0; off >>= 1) smax = fmax(smax, __shfl_xor(smax, off, 64));
-  __shared__ double wmax[PBX * PBY / 64];
+  constexpr int NW = S::X * S::Y / 64;
+  __shared__ double wmax[NW];
   const int tid = threadIdx.x;
   if ((tid & 63) == 0) wmax[tid >> 6] = smax;
   __syncthreads();
   if (tid == 0) {
     double mx = wmax[0];
-    for (int q = 1; q < PBX * PBY / 64; ++q) mx = fmax(mx, wmax[q]);
+    for (int q = 1; q < NW; ++q) mx = fmax(mx, wmax[q]);
     f.speed_part[bk.x + bk.gx * (bk.y + bk.gy * bk.z)] = mx;
   }
 }
 
 // Single-run kernels: 1-D grids; the z FFT takes its tiles in XCD-aware order.
-// FP32 provisional rows: a 16-column tile reads half of each 128-byte line.
-// In every full group of 16 dispatches, dispatches b and b + 8 (which the
-// round-robin dispatcher sends to the same XCD, one after the other) take the
-// two neighbouring tiles that share those lines, so the second finds them in
-// that XCD's L2.  Bijective on [0, n).
-__device__ inline int pair_remap(int b, int n) {
-  const int g = b & ~15, r = b & 15;
-  return g + 16 <= n ? g + 2 * (r & 7) + (r >> 3) : b;
-}
+// FP32 divergence tiles: a 16-column tile reads half of each 128-byte line of
+// u~, so x-neighbours share lines; they go in XCD patches of 8 (consecutive
+// dispatches on one XCD: 0.687 -> 0.658 ms on the 768 x 384 x 384 step, and
+// 0.685 with patches of 2).  FP64 tiles keep the plain order (patches cut the
+// halo fetches of the x+1 line and the plane above by 12 % without changing
+// the time).
+constexpr int DIV_PATCH_F32 = 8;
 template <int NY, class T>
 __global__ void __launch_bounds__(FT) k_div_ffty(Dims d, Fields f, const Scalars* __restrict__ s,
                                                  const double2* __restrict__ tw) {
   const int gx = (d.nx + 15) / 16;
-  const int b = sizeof(T) == 4 ? pair_remap(blockIdx.x, gridDim.x) : (int)blockIdx.x;
-  div_ffty_body<NY, T>(d, f, s, tw, b % gx, b / gx);
+  const Blk b = sizeof(T) == 4 ? blk_patch(blockIdx.x, gx, d.nz, 1, DIV_PATCH_F32, 1)
+                               : blk_linear(blockIdx.x, gx, d.nz, 1);
+  div_ffty_body<NY, T>(d, f, s, tw, b.x, b.y);
 }
 template <int NZ, int SIGN>
 __global__ void __launch_bounds__(FT) k_fftz(Dims d, Fields f, const double2* __restrict__ tw) {
@@ -717,10 +755,10 @@ __global__ void __launch_bounds__(64 * TRI_WAVES) k_tri(Dims d, Fields f, const 
   tri_body<C>(d, f, lam_y, lam_z, scale, (long long)blockIdx.x * TRI_WAVES + threadIdx.x / 64,
               (long long)gridDim.x * TRI_WAVES);
 }
-template <class T>
-__global__ void __launch_bounds__(PBX* PBY) k_project(Dims d, Fields f, Scalars* s, int mode) {
-  const int gx = (d.nx + PBX - 1) / PBX, gy = (d.ny + PBY - 1) / PBY, gz = (d.nz + PKZ - 1) / PKZ;
-  project_body<T>(d, f, s, mode, blk_linear(blockIdx.x, gx, gy, gz));
+template <class T, class S>
+__global__ void __launch_bounds__(S::X* S::Y) k_project(Dims d, Fields f, Scalars* s, int mode) {
+  const int gx = (d.nx + S::X - 1) / S::X, gy = (d.ny + S::Y - 1) / S::Y, gz = (d.nz + S::Z - 1) / S::Z;
+  project_body<T, S>(d, f, s, mode, blk_linear(blockIdx.x, gx, gy, gz));
 }
 
 // ---- batched forms (all runs of the launch share the template size) ----
@@ -754,12 +792,13 @@ __global__ void __launch_bounds__(64 * TRI_WAVES) kb_tri(BatchLaunch bl) {
   tri_body<C>(R.d, R.f, R.lam_y, R.lam_z, scale, (long long)lb * TRI_WAVES + threadIdx.x / 64, nl);
 }
 template <class T>
-__global__ void __launch_bounds__(PBX* PBY) kb_project(BatchLaunch bl, int mode) {
+__global__ void __launch_bounds__(ProjSquare::X* ProjSquare::Y) kb_project(BatchLaunch bl, int mode) {
+  using S = ProjSquare;
   int lb;
   const RunDesc& R = bl.runs[batch_run(bl, blockIdx.x, &lb)];
   const Dims& d = R.d;
-  project_body<T>(d, R.f, R.s, mode,
-                  blk_linear(lb, (d.nx + PBX - 1) / PBX, (d.ny + PBY - 1) / PBY, (d.nz + PKZ - 1) / PKZ));
+  project_body<T, S>(d, R.f, R.s, mode,
+                     blk_linear(lb, (d.nx + S::X - 1) / S::X, (d.ny + S::Y - 1) / S::Y, (d.nz + S::Z - 1) / S::Z));
 }
 
 // u~ := u (in the storage type of u~), used before the initial projection.
@@ -894,16 +933,25 @@ void launch_tri(const Dims& d, const Fields& f, const double* lam_y, const doubl
 #undef CALL
 }
 
-int project_blocks(const Dims& d) {
-  return ((d.nx + PBX - 1) / PBX) * ((d.ny + PBY - 1) / PBY) * ((d.nz + PKZ - 1) / PKZ);
-}
+int project_blocks(const Dims& d) { return proj_wide(d) ? proj_tiles<ProjWide>(d) : proj_tiles<ProjSquare>(d); }
+int project_batch_blocks(const Dims& d) { return proj_tiles<ProjSquare>(d); }
+int project_part_slots(const Dims& d) { return std::max(project_blocks(d), project_batch_blocks(d)); }
 
 void launch_project(const Dims& d, const Fields& f, Scalars* s, int mode, hipStream_t st) {
-  dim3 grid(((d.nx + PBX - 1) / PBX) * ((d.ny + PBY - 1) / PBY) * ((d.nz + PKZ - 1) / PKZ));
-  if (d.mixed)
-    hipLaunchKernelGGL(k_project<float>, grid, dim3(PBX * PBY), 0, st, d, f, s, mode);
-  else
-    hipLaunchKernelGGL(k_project<double>, grid, dim3(PBX * PBY), 0, st, d, f, s, mode);
+  const dim3 grid(project_blocks(d));
+  if (proj_wide(d)) {
+    using S = ProjWide;
+    if (d.mixed)
+      hipLaunchKernelGGL((k_project<float, S>), grid, dim3(S::X * S::Y), 0, st, d, f, s, mode);
+    else
+      hipLaunchKernelGGL((k_project<double, S>), grid, dim3(S::X * S::Y), 0, st, d, f, s, mode);
+  } else {
+    using S = ProjSquare;
+    if (d.mixed)
+      hipLaunchKernelGGL((k_project<float, S>), grid, dim3(S::X * S::Y), 0, st, d, f, s, mode);
+    else
+      hipLaunchKernelGGL((k_project<double, S>), grid, dim3(S::X * S::Y), 0, st, d, f, s, mode);
+  }
 }
 
 }  // namespace ibdns
@@ -965,9 +1013,9 @@ void launch_tri_batch(const BatchLaunch& bl, int nblocks, int C, hipStream_t st)
 
 void launch_project_batch(const BatchLaunch& bl, int nblocks, int mixed, hipStream_t st) {
   if (mixed)
-    hipLaunchKernelGGL(kb_project<float>, dim3(nblocks), dim3(PBX * PBY), 0, st, bl, 0);
+    hipLaunchKernelGGL(kb_project<float>, dim3(nblocks), dim3(ProjSquare::X * ProjSquare::Y), 0, st, bl, 0);
   else
-    hipLaunchKernelGGL(kb_project<double>, dim3(nblocks), dim3(PBX * PBY), 0, st, bl, 0);
+    hipLaunchKernelGGL(kb_project<double>, dim3(nblocks), dim3(ProjSquare::X * ProjSquare::Y), 0, st, bl, 0);
 }
 
 }  // namespace ibdns

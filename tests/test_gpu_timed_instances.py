@@ -6,7 +6,7 @@
   Adams-Bashforth history H^{n-1} differs from H^n.
 * The projection stage (divergence + y FFT, z FFT, x tridiagonal solve,
   inverse FFTs, projection) with the transform lengths and x-line lengths of
-  the 768 x 384 x 384 workload: y and z FFTs of 384 and 192 (radix 8 8 2 3
+  the 768 x 384 x 384 workload: y and z FFTs of 384 and 192 (radix 8 8 6
   and 8 8 3) and x lines of 768, 384 and 192, in FP64 and with the FP32
   provisional velocity of the mixed form.
 
