@@ -19,8 +19,10 @@
 //     nu dt / h^2, short lines) the step falls back to the two-pass sweeps
 //     (Sherman-Morrison on a modified tridiagonal system), chosen on the
 //     device;
-//   * x: one wavefront per line, chunked elimination and cyclic reduction of
-//     the reduced system in LDS, as for the pressure's x lines.
+//   * x: the infinite-line convolution plus the two homogeneous solutions
+//     that the boundary rows fix, one wavefront per line; the same device
+//     check falls back to chunked elimination and cyclic reduction of the
+//     reduced system in LDS, as for the pressure's x lines.
 #include <algorithm>
 
 #include "ibdns_internal.h"
