@@ -320,7 +320,7 @@ __global__ void __launch_bounds__(256) k_cn_pconv(Dims d, Fields f, CnTables t, 
         if (k0 == 0 && u < M)
           headx[u < M ? u : 0] = x;
         else
-          a[(long long)wrapn(k) * stride] = (T)x;
+          stream_store((T)x, &a[(long long)wrapn(k) * stride]);
         // d_{k-M} leaves the window; d_{k+M+PF+1} (mod n) takes its slot.
         // Rows past n - 1 + M are never used; they load a valid index.
         ring[(u - M + W) % W] = (double)a[(long long)wrapn(k + M + PF + 1 >= 2 * n ? 0 : k + M + PF + 1) * stride];
@@ -328,7 +328,7 @@ __global__ void __launch_bounds__(256) k_cn_pconv(Dims d, Fields f, CnTables t, 
     }
   }
 #pragma unroll
-  for (int u = 0; u < M; ++u) a[(long long)wrapn(u) * stride] = (T)headx[u];
+  for (int u = 0; u < M; ++u) stream_store((T)headx[u], &a[(long long)wrapn(u) * stride]);
 }
 
 __device__ __forceinline__ void cn_wave_sync() {

@@ -241,7 +241,16 @@ __device__ __forceinline__ double2 cfms(double2 d, double2 a, double s) {
   return make_double2(d.x - a.x * s, d.y - a.y * s);
 }
 
-constexpr int FT = 256;  // threads per FFT workgroup (512 measured no faster)
+// Threads per workgroup of the FFT kernels (the same 50 KB of LDS for the
+// 384-point lines; three workgroups per CU), and the rows or elements each
+// thread loads per batch in the divergence.  Measured on the 768 x 384 x 384
+// step: the divergence 0.77 ms with 256 threads (batches of 2 rows) and 0.72
+// ms with 512 (1 row; 1024: 0.72), FP32 u~ 0.66 -> 0.58 ms; the z FFT 0.353
+// -> 0.347 ms with 512; the inverse y FFT 0.383 ms with 256, 0.388 with 512.
+constexpr int DT = 512;   // divergence + y FFT
+constexpr int DIV_BATCH = 1;
+constexpr int ZT = 512;   // z FFT
+constexpr int YT = 256;   // inverse y FFT
 
 // r = D u~ / dt for a 16-column x tile of one z plane, then the y FFT of the
 // 16 real columns as 8 complex lines, unpacked into the half spectrum.
@@ -251,7 +260,7 @@ __device__ __forceinline__ void div_ffty_body(const Dims& d, const Fields& f, co
   constexpr int TXC = 16, NL = 8, LS = line_stride(NY), MY = NY / 2 + 1;
   __shared__ double2 buf[NL * LS];
   __shared__ double2 oc[NY / 8 + 1];
-  load_octant<NY>(oc, tw, threadIdx.x, FT);
+  load_octant<NY>(oc, tw, threadIdx.x, DT);
   const T* __restrict__ ut = reinterpret_cast<const T*>(f.ut);
   const T* __restrict__ vt = reinterpret_cast<const T*>(f.vt);
   const T* __restrict__ wt = reinterpret_cast<const T*>(f.wt);
@@ -265,13 +274,14 @@ __device__ __forceinline__ void div_ffty_body(const Dims& d, const Fields& f, co
   // w~ at planes k, k + 1 (pair loads: the pitch and the pair's first column
   // are even), the loads of U rows issued before any is used.  Pairs past nx
   // read the last full pair and store 0.  Measured on the 768 x 384 x 384
-  // step: one column per thread 0.80 / 0.64 ms (FP64 / FP32 u~), column pairs
-  // 0.77 / 0.65 ms; batches of 2 (FP64) and 3 (FP32) rows.  The kernel waits
-  // on these loads: running the first radix-12 FFT pass in registers (each
-  // thread's rows are one butterfly of it) measured no faster.
-  static_assert(FT % (TXC / 2) == 0, "one column pair per thread");
+  // step with 256 threads: one column per thread 0.80 / 0.64 ms (FP64 / FP32
+  // u~), column pairs 0.77 / 0.65 ms.  The kernel waits on these loads:
+  // running the first radix-12 FFT pass in registers (each thread's rows are
+  // one butterfly of it) measured no faster; more threads per workgroup, each
+  // with one row in flight, did (above).
+  static_assert(DT % (TXC / 2) == 0, "one column pair per thread");
   typedef T T2 __attribute__((ext_vector_type(2)));
-  constexpr int TP = TXC / 2, RP = FT / TP, NIT = (NY + RP - 1) / RP, U = load_batch(NIT, sizeof(T) == 4 ? 3 : 2);
+  constexpr int TP = TXC / 2, RP = DT / TP, NIT = (NY + RP - 1) / RP, U = load_batch(NIT, DIV_BATCH);
   const int cx = threadIdx.x % TP, ie = bx * TXC + 2 * cx;
   const bool live0 = ie < d.nx, live1 = ie + 1 < d.nx;
   const int ic = live0 ? ie : ((d.nx - 1) & ~1);     // an even column inside the box
@@ -312,9 +322,9 @@ __device__ __forceinline__ void div_ffty_body(const Dims& d, const Fields& f, co
     }
   }
   __syncthreads();
-  FFTPasses<NY, 1, -1, NL, FT, LS>::run(buf, oc);
+  FFTPasses<NY, 1, -1, NL, DT, LS>::run(buf, oc);
   const int i0 = bx * TXC;
-  for (int e = threadIdx.x; e < TXC * MY; e += FT) {
+  for (int e = threadIdx.x; e < TXC * MY; e += DT) {
     const int ix = e % TXC, m = e / TXC;
     const int i = i0 + ix;
     const int L = ix >> 1;
@@ -336,24 +346,24 @@ __device__ __forceinline__ void fftz_body(const Dims& d, const Fields& f, const 
   constexpr int TXC = 8, NL = 8, LS = line_stride(NZ);
   __shared__ double2 buf[NL * LS];
   __shared__ double2 oc[NZ / 8 + 1];
-  load_octant<NZ>(oc, tw, threadIdx.x, FT);
+  load_octant<NZ>(oc, tw, threadIdx.x, ZT);
   const int i0 = bx * TXC;
   const int m = by;
   const long long lstride = (long long)d.nx * d.MY;
   double2* base = f.spec + (long long)d.nx * m;
   // loads of U elements per thread issued before any is used; out-of-range
   // elements read a clamped address and store 0
-  constexpr int TOT = TXC * NZ, NIT = (TOT + FT - 1) / FT, U = load_batch(NIT);
+  constexpr int TOT = TXC * NZ, NIT = (TOT + ZT - 1) / ZT, U = load_batch(NIT);
   for (int n0 = 0; n0 < NIT; n0 += U) {
     double2 v[U];
 #pragma unroll
     for (int q = 0; q < U; ++q) {
-      const int e = min((int)threadIdx.x + (n0 + q) * FT, TOT - 1);
+      const int e = min((int)threadIdx.x + (n0 + q) * ZT, TOT - 1);
       v[q] = base[min(i0 + e % TXC, d.nx - 1) + lstride * (e / TXC)];
     }
 #pragma unroll
     for (int q = 0; q < U; ++q) {
-      const int e = threadIdx.x + (n0 + q) * FT;
+      const int e = threadIdx.x + (n0 + q) * ZT;
       if (e < TOT) {
         const int ix = e % TXC, k = e / TXC;
         buf[ix * LS + lp(k)] = (i0 + ix < d.nx) ? v[q] : make_double2(0.0, 0.0);
@@ -361,8 +371,8 @@ __device__ __forceinline__ void fftz_body(const Dims& d, const Fields& f, const 
     }
   }
   __syncthreads();
-  FFTPasses<NZ, 1, SIGN, NL, FT, LS>::run(buf, oc);
-  for (int e = threadIdx.x; e < TXC * NZ; e += FT) {
+  FFTPasses<NZ, 1, SIGN, NL, ZT, LS>::run(buf, oc);
+  for (int e = threadIdx.x; e < TXC * NZ; e += ZT) {
     const int ix = e % TXC, k = e / TXC;
     const int i = i0 + ix;
     if (i < d.nx) stream_store(buf[ix * LS + lp(k)], &base[i + lstride * k]);
@@ -377,16 +387,16 @@ __device__ __forceinline__ void iffty_body(const Dims& d, const Fields& f, const
   constexpr int TXC = 16, NL = 8, LS = line_stride(NY), MY = NY / 2 + 1;
   __shared__ double2 buf[NL * LS];
   __shared__ double2 oc[NY / 8 + 1];
-  load_octant<NY>(oc, tw, threadIdx.x, FT);
+  load_octant<NY>(oc, tw, threadIdx.x, YT);
   const int i0 = bx * TXC;
   const int k = by;
   // loads of U element pairs per thread issued before any is used
-  constexpr int TOT = NL * MY, NIT = (TOT + FT - 1) / FT, U = load_batch(NIT);
+  constexpr int TOT = NL * MY, NIT = (TOT + YT - 1) / YT, U = load_batch(NIT);
   for (int n0 = 0; n0 < NIT; n0 += U) {
     double2 ve[U], vo[U];
 #pragma unroll
     for (int q = 0; q < U; ++q) {
-      const int e = min((int)threadIdx.x + (n0 + q) * FT, TOT - 1);
+      const int e = min((int)threadIdx.x + (n0 + q) * YT, TOT - 1);
       const int ie = i0 + 2 * (e % NL);
       const long long off = (long long)d.nx * (e / NL + (long long)MY * k);
       ve[q] = f.spec[min(ie, d.nx - 1) + off];
@@ -394,7 +404,7 @@ __device__ __forceinline__ void iffty_body(const Dims& d, const Fields& f, const
     }
 #pragma unroll
     for (int q = 0; q < U; ++q) {
-      const int e = threadIdx.x + (n0 + q) * FT;
+      const int e = threadIdx.x + (n0 + q) * YT;
       if (e >= TOT) continue;
       const int L = e % NL, m = e / NL;
       const int ie = i0 + 2 * L, io = ie + 1;
@@ -410,12 +420,14 @@ __device__ __forceinline__ void iffty_body(const Dims& d, const Fields& f, const
     }
   }
   __syncthreads();
-  FFTPasses<NY, 1, 1, NL, FT, LS>::run(buf, oc);
-  for (int e = threadIdx.x; e < TXC * NY; e += FT) {
+  FFTPasses<NY, 1, 1, NL, YT, LS>::run(buf, oc);
+  for (int e = threadIdx.x; e < TXC * NY; e += YT) {
     const int ix = e % TXC, j = e / TXC;
     const int i = i0 + ix;
     if (i < d.nx) {
       const double2 z = buf[(ix >> 1) * LS + lp(j)];
+      // a plain store: the projection reads phi next (a streaming store
+      // measured 3 % slower for this kernel)
       f.phi[fidx(d, i, j, k)] = (ix & 1) ? z.y : z.x;
     }
   }
@@ -744,7 +756,7 @@ __device__ __forceinline__ void project_body(const Dims& d, const Fields& f, Sca
 // the time).
 constexpr int DIV_PATCH_F32 = 8;
 template <int NY, class T>
-__global__ void __launch_bounds__(FT) k_div_ffty(Dims d, Fields f, const Scalars* __restrict__ s,
+__global__ void __launch_bounds__(DT) k_div_ffty(Dims d, Fields f, const Scalars* __restrict__ s,
                                                  const double2* __restrict__ tw) {
   const int gx = (d.nx + 15) / 16;
   const Blk b = sizeof(T) == 4 ? blk_patch(blockIdx.x, gx, d.nz, 1, DIV_PATCH_F32, 1)
@@ -752,12 +764,12 @@ __global__ void __launch_bounds__(FT) k_div_ffty(Dims d, Fields f, const Scalars
   div_ffty_body<NY, T>(d, f, s, tw, b.x, b.y);
 }
 template <int NZ, int SIGN>
-__global__ void __launch_bounds__(FT) k_fftz(Dims d, Fields f, const double2* __restrict__ tw) {
+__global__ void __launch_bounds__(ZT) k_fftz(Dims d, Fields f, const double2* __restrict__ tw) {
   const int gx = (d.nx + 7) / 8, b = xcd_remap(blockIdx.x, gridDim.x);
   fftz_body<NZ, SIGN>(d, f, tw, b % gx, b / gx);
 }
 template <int NY>
-__global__ void __launch_bounds__(FT) k_iffty(Dims d, Fields f, const double2* __restrict__ tw) {
+__global__ void __launch_bounds__(YT) k_iffty(Dims d, Fields f, const double2* __restrict__ tw) {
   const int gx = (d.nx + 15) / 16, b = blockIdx.x;
   iffty_body<NY>(d, f, tw, b % gx, b / gx);
 }
@@ -775,21 +787,21 @@ __global__ void __launch_bounds__(S::X* S::Y) k_project(Dims d, Fields f, Scalar
 
 // ---- batched forms (all runs of the launch share the template size) ----
 template <int NY, class T>
-__global__ void __launch_bounds__(FT) kb_div_ffty(BatchLaunch bl) {
+__global__ void __launch_bounds__(DT) kb_div_ffty(BatchLaunch bl) {
   int lb;
   const RunDesc& R = bl.runs[batch_run(bl, blockIdx.x, &lb)];
   const int gx = (R.d.nx + 15) / 16;
   div_ffty_body<NY, T>(R.d, R.f, R.s, R.tw_y, lb % gx, lb / gx);
 }
 template <int NZ, int SIGN>
-__global__ void __launch_bounds__(FT) kb_fftz(BatchLaunch bl) {
+__global__ void __launch_bounds__(ZT) kb_fftz(BatchLaunch bl) {
   int lb;
   const RunDesc& R = bl.runs[batch_run(bl, xcd_remap(blockIdx.x, gridDim.x), &lb)];
   const int gx = (R.d.nx + 7) / 8;
   fftz_body<NZ, SIGN>(R.d, R.f, R.tw_z, lb % gx, lb / gx);
 }
 template <int NY>
-__global__ void __launch_bounds__(FT) kb_iffty(BatchLaunch bl) {
+__global__ void __launch_bounds__(YT) kb_iffty(BatchLaunch bl) {
   int lb;
   const RunDesc& R = bl.runs[batch_run(bl, blockIdx.x, &lb)];
   const int gx = (R.d.nx + 15) / 16;
@@ -867,11 +879,11 @@ void launch_div_ffty(const Dims& d, const Fields& f, const Scalars* s, const dou
                      hipStream_t st) {
   const dim3 grid(((d.nx + 15) / 16) * d.nz);
   if (d.mixed) {
-#define CALL(NY) hipLaunchKernelGGL((k_div_ffty<NY, float>), grid, dim3(FT), 0, st, d, f, s, tw_y)
+#define CALL(NY) hipLaunchKernelGGL((k_div_ffty<NY, float>), grid, dim3(DT), 0, st, d, f, s, tw_y)
     IBDNS_FFT_SWITCH(d.ny, CALL)
 #undef CALL
   } else {
-#define CALL(NY) hipLaunchKernelGGL((k_div_ffty<NY, double>), grid, dim3(FT), 0, st, d, f, s, tw_y)
+#define CALL(NY) hipLaunchKernelGGL((k_div_ffty<NY, double>), grid, dim3(DT), 0, st, d, f, s, tw_y)
     IBDNS_FFT_SWITCH(d.ny, CALL)
 #undef CALL
   }
@@ -897,11 +909,11 @@ static int resident_grid(K kernel, int threads, int ntiles) {
 void launch_fftz(const Dims& d, const Fields& f, const double2* tw_z, int sign, hipStream_t st) {
   const dim3 grid(((d.nx + 7) / 8) * d.MY);
   if (sign < 0) {
-#define CALL(NZ) hipLaunchKernelGGL((k_fftz<NZ, -1>), grid, dim3(FT), 0, st, d, f, tw_z)
+#define CALL(NZ) hipLaunchKernelGGL((k_fftz<NZ, -1>), grid, dim3(ZT), 0, st, d, f, tw_z)
     IBDNS_FFT_SWITCH(d.nz, CALL)
 #undef CALL
   } else {
-#define CALL(NZ) hipLaunchKernelGGL((k_fftz<NZ, 1>), grid, dim3(FT), 0, st, d, f, tw_z)
+#define CALL(NZ) hipLaunchKernelGGL((k_fftz<NZ, 1>), grid, dim3(ZT), 0, st, d, f, tw_z)
     IBDNS_FFT_SWITCH(d.nz, CALL)
 #undef CALL
   }
@@ -909,7 +921,7 @@ void launch_fftz(const Dims& d, const Fields& f, const double2* tw_z, int sign, 
 
 void launch_iffty(const Dims& d, const Fields& f, const double2* tw_y, hipStream_t st) {
   dim3 grid(((d.nx + 15) / 16) * d.nz);
-#define CALL(NY) hipLaunchKernelGGL(k_iffty<NY>, grid, dim3(FT), 0, st, d, f, tw_y)
+#define CALL(NY) hipLaunchKernelGGL(k_iffty<NY>, grid, dim3(YT), 0, st, d, f, tw_y)
   IBDNS_FFT_SWITCH(d.ny, CALL)
 #undef CALL
 }
@@ -981,11 +993,11 @@ int tri_chunk(int nx) {
 
 void launch_div_ffty_batch(const BatchLaunch& bl, int nblocks, int ny, int mixed, hipStream_t st) {
   if (mixed) {
-#define CALL(NY) hipLaunchKernelGGL((kb_div_ffty<NY, float>), dim3(nblocks), dim3(FT), 0, st, bl)
+#define CALL(NY) hipLaunchKernelGGL((kb_div_ffty<NY, float>), dim3(nblocks), dim3(DT), 0, st, bl)
     IBDNS_FFT_SWITCH(ny, CALL)
 #undef CALL
   } else {
-#define CALL(NY) hipLaunchKernelGGL((kb_div_ffty<NY, double>), dim3(nblocks), dim3(FT), 0, st, bl)
+#define CALL(NY) hipLaunchKernelGGL((kb_div_ffty<NY, double>), dim3(nblocks), dim3(DT), 0, st, bl)
     IBDNS_FFT_SWITCH(ny, CALL)
 #undef CALL
   }
@@ -993,18 +1005,18 @@ void launch_div_ffty_batch(const BatchLaunch& bl, int nblocks, int ny, int mixed
 
 void launch_fftz_batch(const BatchLaunch& bl, int nblocks, int nz, int sign, hipStream_t st) {
   if (sign < 0) {
-#define CALL(NZ) hipLaunchKernelGGL((kb_fftz<NZ, -1>), dim3(nblocks), dim3(FT), 0, st, bl)
+#define CALL(NZ) hipLaunchKernelGGL((kb_fftz<NZ, -1>), dim3(nblocks), dim3(ZT), 0, st, bl)
     IBDNS_FFT_SWITCH(nz, CALL)
 #undef CALL
   } else {
-#define CALL(NZ) hipLaunchKernelGGL((kb_fftz<NZ, 1>), dim3(nblocks), dim3(FT), 0, st, bl)
+#define CALL(NZ) hipLaunchKernelGGL((kb_fftz<NZ, 1>), dim3(nblocks), dim3(ZT), 0, st, bl)
     IBDNS_FFT_SWITCH(nz, CALL)
 #undef CALL
   }
 }
 
 void launch_iffty_batch(const BatchLaunch& bl, int nblocks, int ny, hipStream_t st) {
-#define CALL(NY) hipLaunchKernelGGL(kb_iffty<NY>, dim3(nblocks), dim3(FT), 0, st, bl)
+#define CALL(NY) hipLaunchKernelGGL(kb_iffty<NY>, dim3(nblocks), dim3(YT), 0, st, bl)
   IBDNS_FFT_SWITCH(ny, CALL)
 #undef CALL
 }
