@@ -250,7 +250,7 @@ __device__ __forceinline__ double2 cfms(double2 d, double2 a, double s) {
 constexpr int DT = 512;   // divergence + y FFT
 constexpr int DIV_BATCH = 1;
 constexpr int ZT = 512;   // z FFT
-constexpr int YT = 256;   // inverse y FFT
+constexpr int YT = 256;   // inverse y FFT (loads of 2 element pairs per batch: 0.385 -> 0.380 ms)
 
 // r = D u~ / dt for a 16-column x tile of one z plane, then the y FFT of the
 // 16 real columns as 8 complex lines, unpacked into the half spectrum.
@@ -391,7 +391,7 @@ __device__ __forceinline__ void iffty_body(const Dims& d, const Fields& f, const
   const int i0 = bx * TXC;
   const int k = by;
   // loads of U element pairs per thread issued before any is used
-  constexpr int TOT = NL * MY, NIT = (TOT + YT - 1) / YT, U = load_batch(NIT);
+  constexpr int TOT = NL * MY, NIT = (TOT + YT - 1) / YT, U = load_batch(NIT, 2);
   for (int n0 = 0; n0 < NIT; n0 += U) {
     double2 ve[U], vo[U];
 #pragma unroll
