@@ -267,39 +267,40 @@ __device__ __forceinline__ void div_ffty_body(const Dims& d, const Fields& f, co
   const int k = by;
   const int kp = (k + 1 == d.nz) ? 0 : k + 1;
   const double dt = s->dt;
-  // Every thread keeps two neighbouring columns, the real and imaginary parts
-  // of one complex line (2 cx, 2 cx + 1), and walks the rows
-  // j = tid / TP + RP n; per row it loads the column pair of u~ (faces 2 cx
-  // and 2 cx + 1), face 2 cx + 2, and the pairs of v~ at rows j, j + 1 and of
-  // w~ at planes k, k + 1 (pair loads: the pitch and the pair's first column
-  // are even), the loads of U rows issued before any is used.  Pairs past nx
-  // read the last full pair and store 0.  Measured on the 768 x 384 x 384
-  // step with 256 threads: one column per thread 0.80 / 0.64 ms (FP64 / FP32
-  // u~), column pairs 0.77 / 0.65 ms.  The kernel waits on these loads:
-  // running the first radix-12 FFT pass in registers (each thread's rows are
-  // one butterfly of it) measured no faster; more threads per workgroup, each
-  // with one row in flight, did (above).
-  static_assert(DT % (TXC / 2) == 0, "one column pair per thread");
-  typedef T T2 __attribute__((ext_vector_type(2)));
-  constexpr int TP = TXC / 2, RP = DT / TP, NIT = (NY + RP - 1) / RP, U = load_batch(NIT, DIV_BATCH);
-  const int cx = threadIdx.x % TP, ie = bx * TXC + 2 * cx;
-  const bool live0 = ie < d.nx, live1 = ie + 1 < d.nx;
-  const int ic = live0 ? ie : ((d.nx - 1) & ~1);     // an even column inside the box
-  const int f2 = min(ic + 2, d.nx);                   // face ic + 2 (the ghost slot nx at most)
+  // Every thread keeps G = 16 / sizeof(T) neighbouring columns g0 .. g0 + G - 1
+  // (G / 2 complex lines: columns 2L and 2L + 1 are the real and imaginary
+  // parts of line L) and walks the rows j = tid / TP + RP n; per row it loads
+  // the G faces g0 .. g0 + G - 1 of u~ and face g0 + G, the G cells of v~ at
+  // rows j, j + 1 and of w~ at planes k, k + 1, all as 16-byte loads (the
+  // pitch and g0 are multiples of G), the loads of U rows issued before any
+  // is used.  Groups past nx read the last full group and store 0.
+  // Measured on the 768 x 384 x 384 step with 256 threads: one column per
+  // thread 0.80 / 0.64 ms (FP64 / FP32 u~), column pairs 0.77 / 0.65 ms.
+  // The kernel waits on these loads: running the first radix-12 FFT pass in
+  // registers (each thread's rows are one butterfly of it) measured no
+  // faster; more threads per workgroup, each with one row in flight, did
+  // (above), and for FP32 u~ groups of four columns (16-byte loads).
+  constexpr int G = 16 / sizeof(T);
+  static_assert(DT % (TXC / G) == 0 && TXC % G == 0, "one column group per thread");
+  typedef T TG __attribute__((ext_vector_type(G)));
+  constexpr int TP = TXC / G, RP = DT / TP, NIT = (NY + RP - 1) / RP, U = load_batch(NIT, DIV_BATCH);
+  const int cx = threadIdx.x % TP, g0 = bx * TXC + G * cx;
+  const int ic = g0 < d.nx ? g0 : ((d.nx - 1) & ~(G - 1));   // a group inside the box
+  const int fG = min(ic + G, d.nx);                           // face ic + G (the ghost slot nx at most)
   for (int n0 = 0; n0 < NIT; n0 += U) {
-    T2 a[U], b1[U], b0[U], c1[U], c0[U];
+    TG a[U], b1[U], b0[U], c1[U], c0[U];
     T a2[U];
 #pragma unroll
     for (int q = 0; q < U; ++q) {
       const int j = min((n0 + q) * RP + (int)threadIdx.x / TP, NY - 1);
       const int jp = (j + 1 == NY) ? 0 : j + 1;
       const long long c = fidx(d, ic, j, k);
-      a[q] = *reinterpret_cast<const T2*>(ut + c);      // faces ic, ic + 1 (ic + 1 = nx: ghost slot)
-      a2[q] = ut[c - ic + f2];
-      b1[q] = *reinterpret_cast<const T2*>(vt + fidx(d, ic, jp, k));
-      b0[q] = *reinterpret_cast<const T2*>(vt + c);
-      c1[q] = *reinterpret_cast<const T2*>(wt + fidx(d, ic, j, kp));
-      c0[q] = *reinterpret_cast<const T2*>(wt + c);
+      a[q] = *reinterpret_cast<const TG*>(ut + c);      // faces ic .. ic + G - 1 (nx: ghost slot)
+      a2[q] = ut[c - ic + fG];
+      b1[q] = *reinterpret_cast<const TG*>(vt + fidx(d, ic, jp, k));
+      b0[q] = *reinterpret_cast<const TG*>(vt + c);
+      c1[q] = *reinterpret_cast<const TG*>(wt + fidx(d, ic, j, kp));
+      c0[q] = *reinterpret_cast<const TG*>(wt + c);
     }
 #pragma unroll
     for (int q = 0; q < U; ++q) {
@@ -307,17 +308,22 @@ __device__ __forceinline__ void div_ffty_body(const Dims& d, const Fields& f, co
       if (j < NY) {
         // boundary faces: the inlet from u, the outlet from the FP64 plane
         const double onx = f.bnd[j + (long long)NY * k];
-        double ua = (double)a[q].x, ub = (double)a[q].y, uc = (double)a2[q];
-        if (ic == 0) ua = f.u[fidx(d, 0, j, k)];
-        if (ic + 1 == d.nx) ub = onx;
-        if (ic + 2 == d.nx) uc = onx;
-        const double r0 = live0 ? (((ub - ua) + ((double)b1[q].x - (double)b0[q].x)) +
-                                   ((double)c1[q].x - (double)c0[q].x)) / d.h / dt
-                                : 0.0;
-        const double r1 = live1 ? (((uc - ub) + ((double)b1[q].y - (double)b0[q].y)) +
-                                   ((double)c1[q].y - (double)c0[q].y)) / d.h / dt
-                                : 0.0;
-        buf[cx * LS + lp(j)] = make_double2(r0, r1);
+        double uf[G + 1];
+#pragma unroll
+        for (int g = 0; g < G; ++g) uf[g] = (double)a[q][g];
+        uf[G] = (double)a2[q];
+        if (ic == 0) uf[0] = f.u[fidx(d, 0, j, k)];
+#pragma unroll
+        for (int g = 1; g <= G; ++g)
+          if (ic + g == d.nx) uf[g] = onx;
+        double r[G];
+#pragma unroll
+        for (int g = 0; g < G; ++g)
+          r[g] = g0 + g < d.nx ? (((uf[g + 1] - uf[g]) + ((double)b1[q][g] - (double)b0[q][g])) +
+                                  ((double)c1[q][g] - (double)c0[q][g])) / d.h / dt
+                               : 0.0;
+#pragma unroll
+        for (int g = 0; g < G; g += 2) buf[(G / 2 * cx + g / 2) * LS + lp(j)] = make_double2(r[g], r[g + 1]);
       }
     }
   }
