@@ -247,9 +247,11 @@ __device__ __forceinline__ double2 cfms(double2 d, double2 a, double s) {
 // step: the divergence 0.77 ms with 256 threads (batches of 2 rows) and 0.72
 // ms with 512 (1 row; 1024: 0.72), FP32 u~ 0.66 -> 0.58 ms; the z FFT 0.353
 // -> 0.347 ms with 512; the inverse y FFT 0.383 ms with 256, 0.388 with 512.
-constexpr int DT = 512;   // divergence + y FFT
+// Short lines (the batched ensembles' 48 to 96 points) keep 256 threads:
+// with 512 most of them would idle.
+__host__ __device__ constexpr int div_threads(int ny) { return ny >= 192 ? 512 : 256; }
+__host__ __device__ constexpr int fftz_threads(int nz) { return nz >= 192 ? 512 : 256; }
 constexpr int DIV_BATCH = 1;
-constexpr int ZT = 512;   // z FFT
 constexpr int YT = 256;   // inverse y FFT (loads of 2 element pairs per batch: 0.385 -> 0.380 ms)
 
 // r = D u~ / dt for a 16-column x tile of one z plane, then the y FFT of the
@@ -257,6 +259,7 @@ constexpr int YT = 256;   // inverse y FFT (loads of 2 element pairs per batch: 
 template <int NY, class T>
 __device__ __forceinline__ void div_ffty_body(const Dims& d, const Fields& f, const Scalars* __restrict__ s,
                                               const double2* __restrict__ tw, const int bx, const int by) {
+  constexpr int DT = div_threads(NY);
   constexpr int TXC = 16, NL = 8, LS = line_stride(NY), MY = NY / 2 + 1;
   __shared__ double2 buf[NL * LS];
   __shared__ double2 oc[NY / 8 + 1];
@@ -349,6 +352,7 @@ __device__ __forceinline__ void div_ffty_body(const Dims& d, const Fields& f, co
 template <int NZ, int SIGN>
 __device__ __forceinline__ void fftz_body(const Dims& d, const Fields& f, const double2* __restrict__ tw,
                                           const int bx, const int by) {
+  constexpr int ZT = fftz_threads(NZ);
   constexpr int TXC = 8, NL = 8, LS = line_stride(NZ);
   __shared__ double2 buf[NL * LS];
   __shared__ double2 oc[NZ / 8 + 1];
@@ -762,7 +766,7 @@ __device__ __forceinline__ void project_body(const Dims& d, const Fields& f, Sca
 // the time).
 constexpr int DIV_PATCH_F32 = 8;
 template <int NY, class T>
-__global__ void __launch_bounds__(DT) k_div_ffty(Dims d, Fields f, const Scalars* __restrict__ s,
+__global__ void __launch_bounds__(div_threads(NY)) k_div_ffty(Dims d, Fields f, const Scalars* __restrict__ s,
                                                  const double2* __restrict__ tw) {
   const int gx = (d.nx + 15) / 16;
   const Blk b = sizeof(T) == 4 ? blk_patch(blockIdx.x, gx, d.nz, 1, DIV_PATCH_F32, 1)
@@ -770,7 +774,7 @@ __global__ void __launch_bounds__(DT) k_div_ffty(Dims d, Fields f, const Scalars
   div_ffty_body<NY, T>(d, f, s, tw, b.x, b.y);
 }
 template <int NZ, int SIGN>
-__global__ void __launch_bounds__(ZT) k_fftz(Dims d, Fields f, const double2* __restrict__ tw) {
+__global__ void __launch_bounds__(fftz_threads(NZ)) k_fftz(Dims d, Fields f, const double2* __restrict__ tw) {
   const int gx = (d.nx + 7) / 8, b = xcd_remap(blockIdx.x, gridDim.x);
   fftz_body<NZ, SIGN>(d, f, tw, b % gx, b / gx);
 }
@@ -793,14 +797,14 @@ __global__ void __launch_bounds__(S::X* S::Y) k_project(Dims d, Fields f, Scalar
 
 // ---- batched forms (all runs of the launch share the template size) ----
 template <int NY, class T>
-__global__ void __launch_bounds__(DT) kb_div_ffty(BatchLaunch bl) {
+__global__ void __launch_bounds__(div_threads(NY)) kb_div_ffty(BatchLaunch bl) {
   int lb;
   const RunDesc& R = bl.runs[batch_run(bl, blockIdx.x, &lb)];
   const int gx = (R.d.nx + 15) / 16;
   div_ffty_body<NY, T>(R.d, R.f, R.s, R.tw_y, lb % gx, lb / gx);
 }
 template <int NZ, int SIGN>
-__global__ void __launch_bounds__(ZT) kb_fftz(BatchLaunch bl) {
+__global__ void __launch_bounds__(fftz_threads(NZ)) kb_fftz(BatchLaunch bl) {
   int lb;
   const RunDesc& R = bl.runs[batch_run(bl, xcd_remap(blockIdx.x, gridDim.x), &lb)];
   const int gx = (R.d.nx + 7) / 8;
@@ -885,11 +889,11 @@ void launch_div_ffty(const Dims& d, const Fields& f, const Scalars* s, const dou
                      hipStream_t st) {
   const dim3 grid(((d.nx + 15) / 16) * d.nz);
   if (d.mixed) {
-#define CALL(NY) hipLaunchKernelGGL((k_div_ffty<NY, float>), grid, dim3(DT), 0, st, d, f, s, tw_y)
+#define CALL(NY) hipLaunchKernelGGL((k_div_ffty<NY, float>), grid, dim3(div_threads(NY)), 0, st, d, f, s, tw_y)
     IBDNS_FFT_SWITCH(d.ny, CALL)
 #undef CALL
   } else {
-#define CALL(NY) hipLaunchKernelGGL((k_div_ffty<NY, double>), grid, dim3(DT), 0, st, d, f, s, tw_y)
+#define CALL(NY) hipLaunchKernelGGL((k_div_ffty<NY, double>), grid, dim3(div_threads(NY)), 0, st, d, f, s, tw_y)
     IBDNS_FFT_SWITCH(d.ny, CALL)
 #undef CALL
   }
@@ -915,11 +919,11 @@ static int resident_grid(K kernel, int threads, int ntiles) {
 void launch_fftz(const Dims& d, const Fields& f, const double2* tw_z, int sign, hipStream_t st) {
   const dim3 grid(((d.nx + 7) / 8) * d.MY);
   if (sign < 0) {
-#define CALL(NZ) hipLaunchKernelGGL((k_fftz<NZ, -1>), grid, dim3(ZT), 0, st, d, f, tw_z)
+#define CALL(NZ) hipLaunchKernelGGL((k_fftz<NZ, -1>), grid, dim3(fftz_threads(NZ)), 0, st, d, f, tw_z)
     IBDNS_FFT_SWITCH(d.nz, CALL)
 #undef CALL
   } else {
-#define CALL(NZ) hipLaunchKernelGGL((k_fftz<NZ, 1>), grid, dim3(ZT), 0, st, d, f, tw_z)
+#define CALL(NZ) hipLaunchKernelGGL((k_fftz<NZ, 1>), grid, dim3(fftz_threads(NZ)), 0, st, d, f, tw_z)
     IBDNS_FFT_SWITCH(d.nz, CALL)
 #undef CALL
   }
@@ -999,11 +1003,11 @@ int tri_chunk(int nx) {
 
 void launch_div_ffty_batch(const BatchLaunch& bl, int nblocks, int ny, int mixed, hipStream_t st) {
   if (mixed) {
-#define CALL(NY) hipLaunchKernelGGL((kb_div_ffty<NY, float>), dim3(nblocks), dim3(DT), 0, st, bl)
+#define CALL(NY) hipLaunchKernelGGL((kb_div_ffty<NY, float>), dim3(nblocks), dim3(div_threads(NY)), 0, st, bl)
     IBDNS_FFT_SWITCH(ny, CALL)
 #undef CALL
   } else {
-#define CALL(NY) hipLaunchKernelGGL((kb_div_ffty<NY, double>), dim3(nblocks), dim3(DT), 0, st, bl)
+#define CALL(NY) hipLaunchKernelGGL((kb_div_ffty<NY, double>), dim3(nblocks), dim3(div_threads(NY)), 0, st, bl)
     IBDNS_FFT_SWITCH(ny, CALL)
 #undef CALL
   }
@@ -1011,11 +1015,11 @@ void launch_div_ffty_batch(const BatchLaunch& bl, int nblocks, int ny, int mixed
 
 void launch_fftz_batch(const BatchLaunch& bl, int nblocks, int nz, int sign, hipStream_t st) {
   if (sign < 0) {
-#define CALL(NZ) hipLaunchKernelGGL((kb_fftz<NZ, -1>), dim3(nblocks), dim3(ZT), 0, st, bl)
+#define CALL(NZ) hipLaunchKernelGGL((kb_fftz<NZ, -1>), dim3(nblocks), dim3(fftz_threads(NZ)), 0, st, bl)
     IBDNS_FFT_SWITCH(nz, CALL)
 #undef CALL
   } else {
-#define CALL(NZ) hipLaunchKernelGGL((kb_fftz<NZ, 1>), dim3(nblocks), dim3(ZT), 0, st, bl)
+#define CALL(NZ) hipLaunchKernelGGL((kb_fftz<NZ, 1>), dim3(nblocks), dim3(fftz_threads(NZ)), 0, st, bl)
     IBDNS_FFT_SWITCH(nz, CALL)
 #undef CALL
   }
