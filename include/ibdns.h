@@ -67,6 +67,12 @@ enum { IBDNS_LE_HINGED = 0, IBDNS_LE_CLAMPED = 1 };
  * zero-inflow ghost and the convective outflow (keeps x-invariant flows such
  * as a y-z Taylor-Green vortex x-invariant). */
 enum { IBDNS_TEST_VW_NEUMANN_X = 1u << 0 };
+/* Test hook: the flag's bands (a flag of more than 32 x 32 nodes is split
+ * into bands that exchange edge rows every sub-step) wait for a sub-step
+ * count their neighbours never reach, with a spin limit of 64 polls, so that
+ * every band gives up at once and the step reports IBDNS_ETIMEOUT; every
+ * kernel still ends normally.  For the tests of that error path. */
+enum { IBDNS_TEST_FLAG_WAIT_TIMEOUT = 1u << 1 };
 
 /* Domain and physics (Sec. II.A: box lx*ly*lz, Re = U L / nu with L = 1). */
 typedef struct {

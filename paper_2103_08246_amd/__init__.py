@@ -21,6 +21,7 @@ FP64, MIXED = 0, 1
 DIFFUSION_EXPLICIT, DIFFUSION_CN = 0, 1
 LE_HINGED, LE_CLAMPED = 0, 1
 TEST_VW_NEUMANN_X = 1
+TEST_FLAG_WAIT_TIMEOUT = 2
 STAGE_PREDICT, STAGE_FLUX, STAGE_IBM, STAGE_PROJECT, STAGE_FLAG, STAGE_ADVANCE = range(6)
 (ARR_U, ARR_V, ARR_W, ARR_P, ARR_UT, ARR_VT, ARR_WT, ARR_HU, ARR_HV, ARR_HW, ARR_PHI,
  ARR_POINT_F, ARR_V_GHOST, ARR_W_GHOST) = range(14)

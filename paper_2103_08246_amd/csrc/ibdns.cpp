@@ -813,6 +813,9 @@ int set_flag(ibdns_ctx* c, const ibdns_flag* flag, const double* flag_X0) {
     F.beta = flag->bending;
     F.ks = flag->stretch;
     F.clamped = flag->le_bc == IBDNS_LE_CLAMPED ? 1 : 0;
+    const bool wait_test = (c->dom.flags & IBDNS_TEST_FLAG_WAIT_TIMEOUT) != 0;
+    F.spin_limit = wait_test ? 64 : flag_spin_limit();
+    F.wait_skew = wait_test ? (1 << 30) : 0;
     F.X = c->carve<double>(3 * n);
     F.V = c->carve<double>(3 * n);
     F.Fh = c->carve<double>(3 * n);

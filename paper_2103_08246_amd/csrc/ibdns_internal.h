@@ -125,6 +125,8 @@ struct FlagDev {
   const double* rest;      // ns*ns*6 rest lengths to the (+a, -a, +b, -b, +a+b, -a-b) neighbours
   double* xbuf;            // 2 slots x bands x 4 edge rows x ns x 3: band-edge exchange
   int* counter;            // 64 per-band sub-step counters
+  long long spin_limit;    // polls of a neighbour's counter before a band gives up
+  int wait_skew;           // added to the awaited count (0; the timeout test hook sets it)
 };
 
 // Crank-Nicolson sweeps: factor tables rebuilt on the device each step (dt
@@ -312,6 +314,7 @@ int project_part_slots(const Dims& d);    // per-block maxima slots for both
 hipError_t launch_flag_step(const FlagDev& fl, Scalars* s, hipStream_t st);
 void launch_flag_step_plain(const FlagDev& fl, Scalars* s, hipStream_t st);
 int flag_bands(int ns);
+long long flag_spin_limit();   // polls of a neighbour band's counter before giving up
 void launch_advance(Scalars* s, const double* partial, int nparts, double h, hipStream_t st);
 void launch_probes(const Dims& d, const Fields& f, const ProbeDev& pr, hipStream_t st);
 // per-station statistics of the probe records into out (n/9 stations x (2 + 2L) doubles)

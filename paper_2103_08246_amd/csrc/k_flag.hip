@@ -223,8 +223,9 @@ __device__ __forceinline__ void flag_body(const FlagDev& fl, Scalars* s, const i
         bool ok = true;
         for (int nbh = band - 1; nbh <= band + 1; nbh += 2) {
           if (nbh < 0 || nbh >= nband) continue;
-          while (__hip_atomic_load(&fl.counter[nbh], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) < it + 1) {
-            if (++spins > SPIN_LIMIT) {
+          while (__hip_atomic_load(&fl.counter[nbh], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) <
+                 it + 1 + fl.wait_skew) {
+            if (++spins > fl.spin_limit) {
               ok = false;
               break;
             }
@@ -351,6 +352,7 @@ __global__ void __launch_bounds__(RT) k_set_dt0(Scalars* s, const double* partia
 }  // namespace
 
 int flag_bands(int ns) { return (ns + band_rows(ns) - 1) / band_rows(ns); }
+long long flag_spin_limit() { return SPIN_LIMIT; }
 
 hipError_t launch_flag_step(const FlagDev& fl, Scalars* s, hipStream_t st) {
   const int nb = flag_bands(fl.ns);

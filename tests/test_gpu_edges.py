@@ -77,6 +77,35 @@ def test_largest_flag_parity():
         run.close()
 
 
+@pytest.mark.parametrize("path", ["step", "stages"])
+def test_flag_band_wait_timeout_is_reported(path):
+    """A 48 x 48 flag runs in three bands that exchange edge rows every
+    sub-step.  With the test hook the bands wait for a count their neighbours
+    never reach, under a spin limit of 64 polls: every band gives up, every
+    kernel ends, and the step reports ETIMEOUT, which stays set.  Both the
+    time step (flag on the second stream, plain launch) and the stage path
+    (cooperative launch)."""
+    w = synth.Workload(name="wait_flag", nx=64, ny=32, nz=32, lx=4.0, ly=2.0, lz=2.0, re=200.0,
+                       dt=1e-3, flag=synth.Flag(ns=48, length=1.0, x_le=1.0, y_c=1.0, z_c=1.0,
+                                                bending=0.01))
+    run = ib.create(ib.domain_from(w, flags=ib.TEST_FLAG_WAIT_TIMEOUT), synth.ic_noise(w), flag=w.flag)
+    try:
+        if path == "step":
+            run.step(1)
+        else:
+            for st in (ib.STAGE_PREDICT, ib.STAGE_FLUX, ib.STAGE_IBM, ib.STAGE_PROJECT, ib.STAGE_FLAG,
+                       ib.STAGE_ADVANCE):
+                ib.run_stage(run.ctx, st)
+        with pytest.raises(ib.IbdnsError) as e:
+            ib.sync(run.ctx)
+        assert e.value.code == ib.ETIMEOUT
+        with pytest.raises(ib.IbdnsError) as e:
+            run.fields()
+        assert e.value.code == ib.ETIMEOUT
+    finally:
+        run.close()
+
+
 @pytest.mark.parametrize("ns", [32, 33, 48, 121])
 def test_flag_band_shapes_parity(ns):
     """Bands of min(ns, 1024 // ns) rows: 32 is one band of 1024 nodes, 33 two
