@@ -338,7 +338,7 @@ int div_ffty_blocks(const Dims& d);
 int fftz_blocks(const Dims& d);
 int iffty_blocks(const Dims& d);
 int tri_blocks(const Dims& d);
-int tri_chunk(int nx);
+int tri_chunk(int nx);   // group key of the batched x-solve: lanes per line * 256 + chunk
 void launch_predict_batch(const BatchLaunch& bl, int nblocks, int mixed, int variant, hipStream_t st);
 void launch_outlet_batch(const BatchLaunch& bl, int nblocks, int mixed, hipStream_t st);
 void launch_flux_apply_batch(const BatchLaunch& bl, int nblocks, int mixed, hipStream_t st);
@@ -348,7 +348,7 @@ void launch_point_bbox_batch(const BatchLaunch& bl, int nblocks, hipStream_t st)
 void launch_spread_tiles_batch(const BatchLaunch& bl, int nblocks, int mixed, hipStream_t st);
 void launch_div_ffty_batch(const BatchLaunch& bl, int nblocks, int ny, int mixed, hipStream_t st);
 void launch_fftz_batch(const BatchLaunch& bl, int nblocks, int nz, int sign, hipStream_t st);
-void launch_tri_batch(const BatchLaunch& bl, int nblocks, int C, hipStream_t st);
+void launch_tri_batch(const BatchLaunch& bl, int nblocks, int key, hipStream_t st);
 void launch_iffty_batch(const BatchLaunch& bl, int nblocks, int ny, hipStream_t st);
 void launch_project_batch(const BatchLaunch& bl, int nblocks, int mixed, hipStream_t st);
 void launch_flag_batch(const BatchLaunch& prep, int nprep, const BatchLaunch& bands, int nbands, hipStream_t st);

@@ -11,8 +11,9 @@
 //   k_div_ffty  divergence of u~ fused with the real-to-complex y FFT of r
 //               (two real x-columns packed into one complex line);
 //   k_fftz      complex z FFT in place on the half spectrum (both signs);
-//   k_tri       one wavefront per x-line: each lane eliminates a contiguous
-//               chunk down to its two end unknowns, the 128-row reduced system
+//   k_tri       one wavefront per x-line (two per wavefront for lines of up
+//               to 192 rows): each lane eliminates a contiguous chunk down to
+//               its two end unknowns, the reduced system (two rows per lane)
 //               is solved by cyclic reduction in LDS, then back-substitution
 //               (the singular line too, pinned, then its mean removed);
 //   k_iffty     complex-to-real inverse y FFT to phi;
@@ -444,7 +445,7 @@ __device__ __forceinline__ void iffty_body(const Dims& d, const Fields& f, const
 }
 
 // ---------------------------------------------------------------------------
-// x-tridiagonal solves, one wavefront per mode line.
+// x-tridiagonal solves, one wavefront (or half of one) per mode line.
 constexpr int TRI_WAVES = 4;
 
 __device__ __forceinline__ void tri_coef(int g, int nx, double shift, bool singular, double& a,
@@ -464,8 +465,8 @@ __device__ __forceinline__ void tri_coef(int g, int nx, double shift, bool singu
   }
 }
 
-// The lines of a workgroup are independent: one wavefront per line, and the
-// LDS exchanges inside a line only need wavefront-level ordering (the LDS
+// The lines of a workgroup are independent: each belongs to one wavefront, and
+// the LDS exchanges inside a line only need wavefront-level ordering (the LDS
 // executes a wavefront's accesses in issue order).
 __device__ __forceinline__ void wave_sync() {
   __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
@@ -484,55 +485,67 @@ __device__ __forceinline__ double rcp64(double x) {
 
 // Storage slot of reduced row r (rows 2 lane and 2 lane + 1 of a lane land
 // in the two halves, so that every access of the reduction is unit-stride).
-__device__ __forceinline__ int rpos(int r) { return (r & 1) * 64 + (r >> 1); }
+template <int LPL>
+__device__ __forceinline__ int rpos(int r) { return (r & 1) * LPL + (r >> 1); }
 
-template <int C>
+// LPL lanes per line: 64, or 32 for lines of at most 192 rows, two lines per
+// wavefront (first and stride then count pairs of lines); every reduced
+// system has 2 LPL rows.
+template <int C, int LPL = 64>
 __device__ __forceinline__ void tri_body(const Dims& d, const Fields& f, const double* __restrict__ lam_y,
                                          const double* __restrict__ lam_z, double scale, const long long first,
                                          const long long stride) {
+  static_assert(LPL == 64 || LPL == 32, "one or two lines per wavefront");
+  constexpr int W = 64 / LPL;    // lines per wavefront
   constexpr int LSP = C + 1;     // LDS chunk stride (odd: lanes hit distinct banks)
-  constexpr int R = 128;         // reduced rows (2 per lane)
+  constexpr int R = 2 * LPL;     // reduced rows (2 per lane)
   __shared__ double2 lb[TRI_WAVES][64 * LSP];
-  __shared__ double rA[TRI_WAVES][R], rB[TRI_WAVES][R], rC[TRI_WAVES][R];
-  __shared__ double2 rD[TRI_WAVES][R];
+  __shared__ double rA[TRI_WAVES][128], rB[TRI_WAVES][128], rC[TRI_WAVES][128];
+  __shared__ double2 rD[TRI_WAVES][128];
   const int wv = threadIdx.x / 64, lane0 = threadIdx.x % 64;
+  const int sub = lane0 / LPL, lanel = lane0 % LPL;   // this lane's line of the wavefront
   const long long nlines = (long long)d.MY * d.nz;
+  const long long nwl = (nlines + W - 1) / W;         // wavefront work items
   const int nx = d.nx;
-  double2* L = lb[wv];
-  double* A_ = rA[wv];
-  double* B_ = rB[wv];
-  double* C_ = rC[wv];
-  double2* D_ = rD[wv];
+  double2* L = lb[wv] + sub * LPL * LSP;
+  double* A_ = rA[wv] + sub * R;
+  double* B_ = rB[wv] + sub * R;
+  double* C_ = rC[wv] + sub * R;
+  double2* D_ = rD[wv] + sub * R;
   // lines first, first + stride, ...: the next line is loaded into registers
-  // while the current one is solved
+  // while the current one is solved (a line past the last reads zeros)
   double2 pre[C];
   auto fetch = [&](long long ln) {
-    const double2* gl = f.spec + ln * (long long)nx;
+    const bool ok = ln < nlines;
+    const double2* gl = f.spec + (ok ? ln : 0) * (long long)nx;
 #pragma unroll
     for (int t = 0; t < C; ++t) {
-      const int e = lane0 + 64 * t;
-      pre[t] = e < nx ? gl[e] : make_double2(0.0, 0.0);
+      const int e = lanel + LPL * t;
+      pre[t] = (ok && e < nx) ? gl[e] : make_double2(0.0, 0.0);
     }
   };
-  if (first < nlines) fetch(first);
-  for (long long line = first; line < nlines; line += stride) {
+  if (first < nwl) fetch(first * W + sub);
+  for (long long wl = first; wl < nwl; wl += stride) {
+    const long long line = wl * W + sub;
+    const bool valid = line < nlines;
     // an opaque copy of the lane index per line keeps the compiler from
     // hoisting every line-invariant coefficient and LDS offset into registers
-    int lane = lane0;
+    int lane = lanel;
     asm volatile("" : "+v"(lane));
-    const int m = (int)(line % d.MY);
-    const int l = (int)(line / d.MY);
+    // a line past the last (two lines per wavefront) solves a regular mode on zeros
+    const int m = valid ? (int)(line % d.MY) : 1 % d.MY;
+    const int l = valid ? (int)(line / d.MY) : 0;
     // the (0, 0) mode is singular: its row 0 becomes phi_0 = 0 and its x-mean
     // is removed afterwards
-    const bool singular = m == 0 && l == 0;
-    double2* g = f.spec + line * (long long)nx;
+    const bool singular = valid && m == 0 && l == 0;
+    double2* g = f.spec + (valid ? line : 0) * (long long)nx;
 #pragma unroll
     for (int t = 0; t < C; ++t) {
-      const int e = lane + 64 * t;
+      const int e = lane + LPL * t;
       L[(e / C) * LSP + e % C] = (e < nx && !(singular && e == 0)) ? cscale(pre[t], scale) : make_double2(0.0, 0.0);
     }
     wave_sync();
-    if (line + stride < nlines) fetch(line + stride);
+    if (wl + stride < nwl) fetch((wl + stride) * W + sub);
     const double shift = (d.h * d.h) * (lam_z[l] + lam_y[m]);
     double2 x[C];
     {
@@ -591,8 +604,8 @@ __device__ __forceinline__ void tri_body(const Dims& d, const Fields& f, const d
         A1 = a[1]; B1 = b[1]; C1 = c[1]; D1 = dd[1];
       }
       const int r0 = 2 * lane, r1 = 2 * lane + 1;
-      A_[rpos(r0)] = A0; B_[rpos(r0)] = B0; C_[rpos(r0)] = C0; D_[rpos(r0)] = D0;
-      A_[rpos(r1)] = A1; B_[rpos(r1)] = B1; C_[rpos(r1)] = C1; D_[rpos(r1)] = D1;
+      A_[rpos<LPL>(r0)] = A0; B_[rpos<LPL>(r0)] = B0; C_[rpos<LPL>(r0)] = C0; D_[rpos<LPL>(r0)] = D0;
+      A_[rpos<LPL>(r1)] = A1; B_[rpos<LPL>(r1)] = B1; C_[rpos<LPL>(r1)] = C1; D_[rpos<LPL>(r1)] = D1;
       // parallel cyclic reduction of the reduced system
       for (int st = 1; st < R; st <<= 1) {
         wave_sync();
@@ -602,20 +615,20 @@ __device__ __forceinline__ void tri_body(const Dims& d, const Fields& f, const d
         for (int q = 0; q < 2; ++q) {
           const int r = 2 * lane + q;
           const int rm = r - st, rp = r + st;
-          const double Ar = A_[rpos(r)], Cr = C_[rpos(r)];
-          double Aq = 0.0, Cq = 0.0, Bq = B_[rpos(r)];
-          double2 Dq = D_[rpos(r)];
+          const double Ar = A_[rpos<LPL>(r)], Cr = C_[rpos<LPL>(r)];
+          double Aq = 0.0, Cq = 0.0, Bq = B_[rpos<LPL>(r)];
+          double2 Dq = D_[rpos<LPL>(r)];
           if (rm >= 0) {
-            const double k1 = Ar * rcp64(B_[rpos(rm)]);
-            Aq = -A_[rpos(rm)] * k1;
-            Bq -= C_[rpos(rm)] * k1;
-            Dq = cfms(Dq, D_[rpos(rm)], k1);
+            const double k1 = Ar * rcp64(B_[rpos<LPL>(rm)]);
+            Aq = -A_[rpos<LPL>(rm)] * k1;
+            Bq -= C_[rpos<LPL>(rm)] * k1;
+            Dq = cfms(Dq, D_[rpos<LPL>(rm)], k1);
           }
           if (rp < R) {
-            const double k2 = Cr * rcp64(B_[rpos(rp)]);
-            Cq = -C_[rpos(rp)] * k2;
-            Bq -= A_[rpos(rp)] * k2;
-            Dq = cfms(Dq, D_[rpos(rp)], k2);
+            const double k2 = Cr * rcp64(B_[rpos<LPL>(rp)]);
+            Cq = -C_[rpos<LPL>(rp)] * k2;
+            Bq -= A_[rpos<LPL>(rp)] * k2;
+            Dq = cfms(Dq, D_[rpos<LPL>(rp)], k2);
           }
           nA[q] = Aq; nB[q] = Bq; nC[q] = Cq; nD[q] = Dq;
         }
@@ -623,12 +636,12 @@ __device__ __forceinline__ void tri_body(const Dims& d, const Fields& f, const d
 #pragma unroll
         for (int q = 0; q < 2; ++q) {
           const int r = 2 * lane + q;
-          A_[rpos(r)] = nA[q]; B_[rpos(r)] = nB[q]; C_[rpos(r)] = nC[q]; D_[rpos(r)] = nD[q];
+          A_[rpos<LPL>(r)] = nA[q]; B_[rpos<LPL>(r)] = nB[q]; C_[rpos<LPL>(r)] = nC[q]; D_[rpos<LPL>(r)] = nD[q];
         }
       }
       wave_sync();
-      const double2 xs = cscale(D_[rpos(r0)], rcp64(B_[rpos(r0)]));
-      const double2 xe = cscale(D_[rpos(r1)], rcp64(B_[rpos(r1)]));
+      const double2 xs = cscale(D_[rpos<LPL>(r0)], rcp64(B_[rpos<LPL>(r0)]));
+      const double2 xe = cscale(D_[rpos<LPL>(r1)], rcp64(B_[rpos<LPL>(r1)]));
       x[0] = xs;
       x[C - 1] = xe;
 #pragma unroll
@@ -640,7 +653,7 @@ __device__ __forceinline__ void tri_body(const Dims& d, const Fields& f, const d
 #pragma unroll
       for (int t = 0; t < C; ++t)
         if (lane * C + t < nx) sm = cadd(sm, x[t]);
-      for (int o = 1; o < 64; o <<= 1) {
+      for (int o = 1; o < LPL; o <<= 1) {   // within this line's lanes
         sm.x += __shfl_xor(sm.x, o, 64);
         sm.y += __shfl_xor(sm.y, o, 64);
       }
@@ -653,8 +666,8 @@ __device__ __forceinline__ void tri_body(const Dims& d, const Fields& f, const d
     for (int t = 0; t < C; ++t) L[lane * LSP + t] = x[t];
     wave_sync();
     for (int t = 0; t < C; ++t) {
-      const int e = lane + 64 * t;
-      if (e < nx) stream_store(L[(e / C) * LSP + e % C], &g[e]);
+      const int e = lane + LPL * t;
+      if (valid && e < nx) stream_store(L[(e / C) * LSP + e % C], &g[e]);
     }
     wave_sync();  // the line has left LDS
   }
@@ -783,11 +796,11 @@ __global__ void __launch_bounds__(YT) k_iffty(Dims d, Fields f, const double2* _
   const int gx = (d.nx + 15) / 16, b = blockIdx.x;
   iffty_body<NY>(d, f, tw, b % gx, b / gx);
 }
-template <int C>
+template <int C, int LPL>
 __global__ void __launch_bounds__(64 * TRI_WAVES) k_tri(Dims d, Fields f, const double* __restrict__ lam_y,
                                                        const double* __restrict__ lam_z, double scale) {
-  tri_body<C>(d, f, lam_y, lam_z, scale, (long long)blockIdx.x * TRI_WAVES + threadIdx.x / 64,
-              (long long)gridDim.x * TRI_WAVES);
+  tri_body<C, LPL>(d, f, lam_y, lam_z, scale, (long long)blockIdx.x * TRI_WAVES + threadIdx.x / 64,
+                   (long long)gridDim.x * TRI_WAVES);
 }
 template <class T, class S>
 __global__ void __launch_bounds__(S::X* S::Y) k_project(Dims d, Fields f, Scalars* s, int mode) {
@@ -817,13 +830,14 @@ __global__ void __launch_bounds__(YT) kb_iffty(BatchLaunch bl) {
   const int gx = (R.d.nx + 15) / 16;
   iffty_body<NY>(R.d, R.f, R.tw_y, lb % gx, lb / gx);
 }
-template <int C>
+template <int C, int LPL>
 __global__ void __launch_bounds__(64 * TRI_WAVES) kb_tri(BatchLaunch bl) {
   int lb;
   const RunDesc& R = bl.runs[batch_run(bl, blockIdx.x, &lb)];
   const double scale = (R.d.h * R.d.h) / ((double)R.d.ny * (double)R.d.nz);
-  const long long nl = (long long)R.d.MY * R.d.nz;
-  tri_body<C>(R.d, R.f, R.lam_y, R.lam_z, scale, (long long)lb * TRI_WAVES + threadIdx.x / 64, nl);
+  constexpr int W = 64 / LPL;
+  const long long nwl = ((long long)R.d.MY * R.d.nz + W - 1) / W;   // one work item per wavefront
+  tri_body<C, LPL>(R.d, R.f, R.lam_y, R.lam_z, scale, (long long)lb * TRI_WAVES + threadIdx.x / 64, nwl);
 }
 template <class T>
 __global__ void __launch_bounds__(ProjSquare::X* ProjSquare::Y) kb_project(BatchLaunch bl, int mode) {
@@ -936,34 +950,55 @@ void launch_iffty(const Dims& d, const Fields& f, const double2* tw_y, hipStream
 #undef CALL
 }
 
-bool tri_size_supported(int nx) {
-  int C = (nx + 63) / 64;
-  if (C < 2) C = 2;
-  return nx >= 8 && (C == 2 || C == 3 || C == 4 || C == 5 || C == 6 || C == 8 || C == 12);
+// Lines of up to 192 rows go two to a wavefront (32 lanes each): the reduced
+// system then has 64 rows, one cyclic-reduction step fewer, and each step
+// serves two lines.  Longer lines take the whole wavefront.
+struct TriShape {
+  int lpl, C;
+};
+TriShape tri_shape(int nx) {
+  const int lpl = nx <= 192 ? 32 : 64;
+  return {lpl, std::max(2, (nx + lpl - 1) / lpl)};
 }
+long long tri_waves(const Dims& d) {
+  const int W = 64 / tri_shape(d.nx).lpl;
+  return ((long long)d.MY * d.nz + W - 1) / W;
+}
+
+bool tri_size_supported(int nx) {
+  const TriShape t = tri_shape(nx);
+  if (nx < 8) return false;
+  if (t.lpl == 32) return t.C <= 6;
+  return t.C == 4 || t.C == 5 || t.C == 6 || t.C == 8 || t.C == 12;
+}
+
+// Instantiated (lanes per line, chunk) pairs, for the single-run and the
+// batched launch.
+#define IBDNS_TRI_SWITCH(T, CALL)   \
+  switch ((T).lpl * 256 + (T).C) {  \
+    case 32 * 256 + 2: CALL(2, 32); break;  \
+    case 32 * 256 + 3: CALL(3, 32); break;  \
+    case 32 * 256 + 4: CALL(4, 32); break;  \
+    case 32 * 256 + 5: CALL(5, 32); break;  \
+    case 32 * 256 + 6: CALL(6, 32); break;  \
+    case 64 * 256 + 4: CALL(4, 64); break;  \
+    case 64 * 256 + 5: CALL(5, 64); break;  \
+    case 64 * 256 + 6: CALL(6, 64); break;  \
+    case 64 * 256 + 8: CALL(8, 64); break;  \
+    case 64 * 256 + 12: CALL(12, 64); break; \
+    default: break;                 \
+  }
 
 void launch_tri(const Dims& d, const Fields& f, const double* lam_y, const double* lam_z,
                 hipStream_t st) {
-  const long long nlines = (long long)d.MY * d.nz;
-  const int nblk = (int)((nlines + TRI_WAVES - 1) / TRI_WAVES);
+  const int nblk = (int)((tri_waves(d) + TRI_WAVES - 1) / TRI_WAVES);
   const double scale = (d.h * d.h) / ((double)d.ny * (double)d.nz);
-  int C = (d.nx + 63) / 64;
-  if (C < 2) C = 2;
   // persistent: as many workgroups as are resident, each wavefront walking
   // lines with a stride of the whole grid
-#define CALL(CC)                                                                                        \
-  hipLaunchKernelGGL(k_tri<CC>, dim3(resident_grid(k_tri<CC>, 64 * TRI_WAVES, nblk)), dim3(64 * TRI_WAVES), 0, \
-                     st, d, f, lam_y, lam_z, scale)
-  switch (C) {
-    case 2: CALL(2); break;
-    case 3: CALL(3); break;
-    case 4: CALL(4); break;
-    case 5: CALL(5); break;
-    case 6: CALL(6); break;
-    case 8: CALL(8); break;
-    case 12: CALL(12); break;
-    default: break;
-  }
+#define CALL(CC, LL)                                                                                           \
+  hipLaunchKernelGGL((k_tri<CC, LL>), dim3(resident_grid(k_tri<CC, LL>, 64 * TRI_WAVES, nblk)),               \
+                     dim3(64 * TRI_WAVES), 0, st, d, f, lam_y, lam_z, scale)
+  IBDNS_TRI_SWITCH(tri_shape(d.nx), CALL)
 #undef CALL
 }
 
@@ -995,10 +1030,10 @@ namespace ibdns {
 int div_ffty_blocks(const Dims& d) { return ((d.nx + 15) / 16) * d.nz; }
 int fftz_blocks(const Dims& d) { return ((d.nx + 7) / 8) * d.MY; }
 int iffty_blocks(const Dims& d) { return ((d.nx + 15) / 16) * d.nz; }
-int tri_blocks(const Dims& d) { return (int)(((long long)d.MY * d.nz + TRI_WAVES - 1) / TRI_WAVES); }
+int tri_blocks(const Dims& d) { return (int)((tri_waves(d) + TRI_WAVES - 1) / TRI_WAVES); }
 int tri_chunk(int nx) {
-  int C = (nx + 63) / 64;
-  return C < 2 ? 2 : C;
+  const TriShape t = tri_shape(nx);
+  return t.lpl * 256 + t.C;
 }
 
 void launch_div_ffty_batch(const BatchLaunch& bl, int nblocks, int ny, int mixed, hipStream_t st) {
@@ -1031,18 +1066,12 @@ void launch_iffty_batch(const BatchLaunch& bl, int nblocks, int ny, hipStream_t 
 #undef CALL
 }
 
-void launch_tri_batch(const BatchLaunch& bl, int nblocks, int C, hipStream_t st) {
+void launch_tri_batch(const BatchLaunch& bl, int nblocks, int key, hipStream_t st) {
   const dim3 g(nblocks), b(64 * TRI_WAVES);
-  switch (C) {
-    case 2: hipLaunchKernelGGL(kb_tri<2>, g, b, 0, st, bl); break;
-    case 3: hipLaunchKernelGGL(kb_tri<3>, g, b, 0, st, bl); break;
-    case 4: hipLaunchKernelGGL(kb_tri<4>, g, b, 0, st, bl); break;
-    case 5: hipLaunchKernelGGL(kb_tri<5>, g, b, 0, st, bl); break;
-    case 6: hipLaunchKernelGGL(kb_tri<6>, g, b, 0, st, bl); break;
-    case 8: hipLaunchKernelGGL(kb_tri<8>, g, b, 0, st, bl); break;
-    case 12: hipLaunchKernelGGL(kb_tri<12>, g, b, 0, st, bl); break;
-    default: break;
-  }
+  const TriShape t{key / 256, key % 256};
+#define CALL(CC, LL) hipLaunchKernelGGL((kb_tri<CC, LL>), g, b, 0, st, bl)
+  IBDNS_TRI_SWITCH(t, CALL)
+#undef CALL
 }
 
 void launch_project_batch(const BatchLaunch& bl, int nblocks, int mixed, hipStream_t st) {

@@ -65,7 +65,11 @@ def test_predict_stage(make):
         run.close()
 
 
-@pytest.mark.parametrize("dims", [(64, 32, 32), (96, 48, 24), (128, 64, 96), (200, 24, 48)])
+# x lines of every solver shape: two lines per wavefront (32 lanes) with chunks
+# of 2-6 rows per lane for nx <= 192, one line per wavefront (64 lanes) with
+# chunks of 4, 5, 8 beyond (6 and 12 at 384 and 768 in the timed-instance tests)
+@pytest.mark.parametrize("dims", [(33, 16, 16), (64, 32, 32), (96, 48, 24), (128, 64, 96), (150, 16, 16),
+                                  (170, 48, 16), (200, 24, 48), (300, 24, 16), (500, 16, 16)])
 def test_projection_stage_random(dims):
     nx, ny, nz = dims
     h = 0.05
