@@ -728,25 +728,44 @@ __device__ __forceinline__ void project_body(const Dims& d, const Fields& f, Sca
       const int kp = k == d.nz - 1 ? 0 : k + 1;
       const long long c = fidx(d, i, j, k);
       const long long ckp = fidx(d, i, j, kp);
-      const double ph_p = phi[ckp];
-      const double wkp = (double)wt[ckp] - dt * (ph_p - ph_c) * inv_h;
-      // inlet face keeps U (read from u), outlet face keeps u~ (FP64 plane)
-      const double ui = (i >= 1) ? (double)ut[c] - dt * (ph_c - phi[c - 1]) * inv_h : uo[c];
       const long long qb = j + (long long)d.ny * k;
-      const double uip = (i + 1 <= nx - 1) ? (double)ut[c + 1] - dt * (phi[c + 1] - ph_c) * inv_h
-                                           : bnd[qb];
       const long long cjm = fidx(d, i, jm, k), cjp = fidx(d, i, jp, k);
-      const double vj = (double)vt[c] - dt * (ph_c - phi[cjm]) * inv_h;
-      const double vjp = (double)vt[cjp] - dt * (phi[cjp] - ph_c) * inv_h;
+      // Every load of the plane is issued before any value is used: the x
+      // neighbours are clamped at the inlet and outlet (their terms are then
+      // discarded), and the inlet, outlet and pressure values are conditional
+      // loads, which merge without a wait.  With the face terms computed
+      // inside the branches, each branch waited for its own loads.
+      const bool in = i >= 1, out = i + 1 <= nx - 1, last = i == nx - 1;
+      const double ph_p = phi[ckp];
+      const T wt_p = wt[ckp];
+      const T ut_c = ut[c];
+      const double ph_m = phi[in ? c - 1 : c];
+      const T ut_e = ut[out ? c + 1 : c];
+      const double ph_e = phi[out ? c + 1 : c];
+      const T vt_c = vt[c], vt_p = vt[cjp];
+      const double ph_s = phi[cjm], ph_n = phi[cjp];
+      double u_in = 0.0, u_out = 0.0, v_out = 0.0, w_out = 0.0, p_c = 0.0;
+      if (!in) u_in = uo[c];          // inlet face keeps U (read from u)
+      if (!out) u_out = bnd[qb];      // outlet face keeps u~ (FP64 plane)
+      if (last) {                     // outlet ghosts keep their provisional values
+        v_out = bnd[nplane + qb];
+        w_out = bnd[2 * nplane + qb];
+      }
+      if (mode == 0) p_c = po[c];
+      const double wkp = (double)wt_p - dt * (ph_p - ph_c) * inv_h;
+      const double ui = in ? (double)ut_c - dt * (ph_c - ph_m) * inv_h : u_in;
+      const double uip = out ? (double)ut_e - dt * (ph_e - ph_c) * inv_h : u_out;
+      const double vj = (double)vt_c - dt * (ph_c - ph_s) * inv_h;
+      const double vjp = (double)vt_p - dt * (ph_n - ph_c) * inv_h;
       stream_store(ui, &uo[c]);
       stream_store(vj, &vo[c]);
       stream_store(wk, &wo[c]);
-      if (i == nx - 1) {
-        uo[c + 1] = uip;                 // outlet face keeps u~
-        vo[c + 1] = bnd[nplane + qb];    // outlet ghosts keep their provisional values
-        wo[c + 1] = bnd[2 * nplane + qb];
+      if (last) {
+        uo[c + 1] = uip;
+        vo[c + 1] = v_out;
+        wo[c + 1] = w_out;
       }
-      if (mode == 0) stream_store(po[c] + ph_c, &po[c]);
+      if (mode == 0) stream_store(p_c + ph_c, &po[c]);
       double speed = fabs(0.5 * (ui + uip)) + fabs(0.5 * (vj + vjp)) + fabs(0.5 * (wk + wkp));
       if (!(speed <= 1.7976931348623157e308)) {
         atomicOr(&s->status, (int)ST_NONFINITE);

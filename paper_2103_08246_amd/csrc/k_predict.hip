@@ -51,8 +51,10 @@ __device__ __forceinline__ void predict_body(const Dims& d, const Fields& f, con
 
   // Plane loads go through registers: the loads of plane k+2 (and p of
   // plane k+1) are issued before the work on plane k and land in LDS after it.
+  // They stay FP64 until then: converted as they arrive, the FP32 tiles
+  // waited for each load in turn.
   constexpr int NT = TX * TY, NE = (LP + NT - 1) / NT;
-  T ru[NE], rv[NE], rw[NE], rp[NE];
+  double ru[NE], rv[NE], rw[NE], rp[NE];
   auto fetch_plane = [&](int kk_unwrapped) {
     const int kk = wrapi(kk_unwrapped, d.nz);
 #pragma unroll
@@ -60,12 +62,12 @@ __device__ __forceinline__ void predict_body(const Dims& d, const Fields& f, con
       const int e = tid + q * NT;
       const int lx = e % LX, ly = e / LX;
       const int gi = i0 - 1 + lx, gj = wrapi(j0 - 1 + ly, d.ny);
-      T a = 0, b = 0, c = 0;
+      double a = 0, b = 0, c = 0;
       if (e < LP && gi >= 0 && gi <= nx) {
         const long long o = fidx(d, gi, gj, kk);
-        a = (T)u[o];
-        b = (T)v[o];
-        c = (T)w[o];
+        a = u[o];
+        b = v[o];
+        c = w[o];
       }
       ru[q] = a;
       rv[q] = b;
@@ -81,8 +83,7 @@ __device__ __forceinline__ void predict_body(const Dims& d, const Fields& f, con
       const int e = tid + q * NT;
       const int lx = e % LX, ly = e / LX;
       const int gi = i0 - 1 + lx, gj = wrapi(j0 - 1 + ly, d.ny);
-      rp[q] = (e < LP && gi >= 0 && gi < nx && lx < LX - 1 && ly < LY - 1) ? (T)p[fidx(d, gi, gj, kk)]
-                                                                           : (T)0;
+      rp[q] = (e < LP && gi >= 0 && gi < nx && lx < LX - 1 && ly < LY - 1) ? p[fidx(d, gi, gj, kk)] : 0.0;
     }
   };
   auto commit_plane = [&](int slot) {
@@ -90,9 +91,9 @@ __device__ __forceinline__ void predict_body(const Dims& d, const Fields& f, con
     for (int q = 0; q < NE; ++q) {
       const int e = tid + q * NT;
       if (e < LP) {
-        su[slot][e] = ru[q];
-        sv[slot][e] = rv[q];
-        sw[slot][e] = rw[q];
+        su[slot][e] = (T)ru[q];
+        sv[slot][e] = (T)rv[q];
+        sw[slot][e] = (T)rw[q];
       }
     }
   };
@@ -100,7 +101,7 @@ __device__ __forceinline__ void predict_body(const Dims& d, const Fields& f, con
 #pragma unroll
     for (int q = 0; q < NE; ++q) {
       const int e = tid + q * NT;
-      if (e < LP) spp[e] = rp[q];
+      if (e < LP) spp[e] = (T)rp[q];
     }
   };
   auto load_plane = [&](int kk_unwrapped, int slot) {
@@ -125,13 +126,8 @@ __device__ __forceinline__ void predict_body(const Dims& d, const Fields& f, con
   fetch_p(kb);
   commit_p();
   T p_km = active ? (T)p[fidx(d, i, j, wrapi(kb - 1, d.nz))] : (T)0;
-  // H^{n-1} of this thread's nodes (every value is read once, then
-  // overwritten by H^n).  FP64 tiles load it one plane ahead of its use.  The
-  // FP32 tiles, held to 64 registers, request it at the start of the plane,
-  // before the next plane's loads: four registers then spill, and the
-  // predictor still takes 1.77 instead of 1.89 ms on the 768 x 384 x 384 step
-  // (one plane ahead needs 20 more).
-  constexpr bool H_AHEAD = sizeof(T) == 8;
+  // H^{n-1} of this thread's nodes, loaded one plane ahead of its use (every
+  // value is read once, then overwritten by H^n).
   T hn_u = (T)0, hn_v = (T)0, hn_w = (T)0;
   auto fetch_h = [&](int kk) {
     if (active && !first) {
@@ -141,7 +137,7 @@ __device__ __forceinline__ void predict_body(const Dims& d, const Fields& f, con
       hn_w = stream_load(&hw[c]);
     }
   };
-  if (H_AHEAD) fetch_h(kb);
+  fetch_h(kb);
   __syncthreads();
 
   const int o0 = (ty + 1) * LX + (tx + 1);
@@ -152,12 +148,11 @@ __device__ __forceinline__ void predict_body(const Dims& d, const Fields& f, con
     auto W = [&](int dx, int dy, int sl) { return sw[sl][o0 + dy * LX + dx]; };
     const T p_c = spp[o0];
     const bool more = k + 1 < ke;
-    if (!H_AHEAD) fetch_h(k);
     const T ho_u = hn_u, ho_v = hn_v, ho_w = hn_w;
     if (more) {
       fetch_plane(k + 2);
       fetch_p(k + 1);
-      if (H_AHEAD) fetch_h(k + 1);
+      fetch_h(k + 1);
     }
     if (active) {
       const long long c = fidx(d, i, j, k);
@@ -237,22 +232,21 @@ __device__ __forceinline__ void predict_body(const Dims& d, const Fields& f, con
   }
 }
 
-// FP32 tiles fit in 64 VGPRs (eight waves per SIMD): two 1024-thread
-// workgroups then share a CU, which the 65 registers the compiler picks by
-// itself would not allow (measured: 3.0 -> 2.0 ms for the 128 x 8 x 48 tile
-// on the 768 x 384 x 384 step).
-template <class T>
-constexpr int predict_waves_per_simd() { return sizeof(T) == 4 ? 8 : 1; }
-
+// Both precisions take the registers the compiler chooses (124 FP64, 93 FP32:
+// four or five waves per SIMD).  FP32 tiles held to 64 registers (eight waves)
+// spilled the plane addresses, and each reload from scratch waited for the
+// plane loads in flight; with the loads converted to FP32 as they arrived,
+// they waited for every load in turn.  Measured on the 768 x 384 x 384 step:
+// 1.77 ms (64 registers, converted at the load), 1.63 (72, seven waves,
+// H^{n-1} at the start of its plane), 1.53 (93, H^{n-1} one plane ahead).
 template <class T, int TX, int TY, int KZ>
-__global__ void __launch_bounds__(TX* TY, predict_waves_per_simd<T>())
-    k_predict(Dims d, Fields f, const Scalars* __restrict__ s) {
+__global__ void __launch_bounds__(TX* TY) k_predict(Dims d, Fields f, const Scalars* __restrict__ s) {
   const int gx = (d.nx + TX - 1) / TX, gy = (d.ny + TY - 1) / TY, gz = (d.nz + KZ - 1) / KZ;
   predict_body<T, TX, TY, KZ>(d, f, s, blk_linear(blockIdx.x, gx, gy, gz));
 }
 
 template <class T, int TX, int TY, int KZ>
-__global__ void __launch_bounds__(TX* TY, predict_waves_per_simd<T>()) kb_predict(BatchLaunch bl) {
+__global__ void __launch_bounds__(TX* TY) kb_predict(BatchLaunch bl) {
   int lb;
   const RunDesc& R = bl.runs[batch_run(bl, blockIdx.x, &lb)];
   const Dims& d = R.d;
