@@ -390,14 +390,18 @@ __global__ void __launch_bounds__(64 * CNX_WAVES) k_cn_xline(Dims d, Fields f, C
   };
   // the next line's right-hand side, u^n and outlet values are loaded while
   // the current line is solved
-  double pre[C], pst[C], pout = 0.0, pin = 0.0;
+  // the next line's right-hand side stays in its storage type until the line
+  // goes to LDS: converted as it arrived, the FP32 loads were waited for
+  // before the current line's work
+  T pre[C];
+  double pst[C], pout = 0.0, pin = 0.0;
   auto fetch = [&](long long ln) {
     const int j = (int)(ln % d.ny), k = (int)(ln / d.ny);
     const long long base = fidx(d, ilo, j, k);
 #pragma unroll
     for (int q = 0; q < C; ++q) {
       const int e = min(lane0 + 64 * q, n - 1);   // clamped: rows past the line are not used
-      pre[q] = (double)fa[base + e];
+      pre[q] = fa[base + e];
       pst[q] = st[base + e];
     }
     if (!neumann) {
@@ -416,7 +420,7 @@ __global__ void __launch_bounds__(64 * CNX_WAVES) k_cn_xline(Dims d, Fields f, C
 #pragma unroll
     for (int q = 0; q < C; ++q) {
       const int e = lane + 64 * q;
-      L[(e / C) * LSP + e % C] = e < n ? pre[q] + (e == n - 1 ? r * dout : 0.0) : 0.0;
+      L[(e / C) * LSP + e % C] = e < n ? (double)pre[q] + (e == n - 1 ? r * dout : 0.0) : 0.0;
       sn[q] = pst[q];
     }
     cn_wave_sync();
@@ -561,14 +565,18 @@ __global__ void __launch_bounds__(64 * CNX_WAVES) k_cn_xconv(Dims d, Fields f, C
   // zero pads once: rows -PAD..-1 and n..64C+PAD-1 are never written by a line
   for (int e = lane - PAD; e < 64 * C + PAD; e += 64)
     if (e < 0 || e >= n) L[e] = 0.0;
-  double pre[C], pst[C], pout = 0.0, pin = 0.0;
+  // the next line's right-hand side stays in its storage type until the line
+  // goes to LDS: converted as it arrived, the FP32 loads were waited for
+  // before the current line's work
+  T pre[C];
+  double pst[C], pout = 0.0, pin = 0.0;
   auto fetch = [&](long long ln) {
     const int j = (int)(ln % d.ny), k = (int)(ln / d.ny);
     const long long base = fidx(d, ilo, j, k);
 #pragma unroll
     for (int q = 0; q < C; ++q) {
       const int e = min(lane + 64 * q, n - 1);   // clamped: rows past the line are not used
-      pre[q] = (double)fa[base + e];
+      pre[q] = fa[base + e];
       pst[q] = st[base + e];
     }
     if (!neumann) {
@@ -585,7 +593,7 @@ __global__ void __launch_bounds__(64 * CNX_WAVES) k_cn_xconv(Dims d, Fields f, C
 #pragma unroll
     for (int q = 0; q < C; ++q) {
       const int e = lane + 64 * q;
-      if (e < n) L[e] = pre[q] + (e == n - 1 ? r * dout : 0.0);
+      if (e < n) L[e] = (double)pre[q] + (e == n - 1 ? r * dout : 0.0);
       sn[q] = pst[q];
     }
     cn_wave_sync();
