@@ -57,9 +57,11 @@ CnTables cn_tables_at(double* b, int nx, int ny, int nz) {
 namespace {
 
 // rows the periodic convolution loads ahead of the one it needs next
-// (measured: 4 and 8 rows equal in FP32, 8 faster than 4 in FP64 along z)
+// (measured on the 768 x 384 x 384 step, z factor of three components: FP64
+// 8 rows faster than 4; FP32 4 rows 0.73 ms, 2 rows 0.98, 6 rows 0.93,
+// 8 rows 0.90)
 template <class T>
-__host__ __device__ constexpr int cn_pf() { return 8; }
+__host__ __device__ constexpr int cn_pf() { return sizeof(T) == 4 ? 4 : 8; }
 
 // Tridiagonal (-r, diag, -r) of n rows with the first and last diagonal
 // entries b0, bn: c'_i and 1/pivot_i of the elimination.
@@ -304,10 +306,21 @@ __global__ void __launch_bounds__(256) k_cn_pconv(Dims d, Fields f, CnTables t, 
     e += s0;
     return e >= n ? e - n : e;
   };
-  // ring[e mod W] = d_e for e = k - M .. k + M + PF at step k
+  // At step k, ring[e mod W] = d_e for e = k - M .. k + M + PF.  FP32 rows in
+  // flight (e > k + M) stay in raw[e mod W] and are converted when they enter
+  // the window: converted as it arrived, each FP32 load was waited for at once.
+  constexpr bool RAW = sizeof(T) == 4;
   double ring[W], headx[M];
+  T raw[W];
+  if constexpr (RAW) {
 #pragma unroll
-  for (int e = -M; e <= M + PF; ++e) ring[(e + W) % W] = (double)a[(long long)wrapn(e) * stride];
+    for (int e = -M; e <= M + PF; ++e) raw[(e + W) % W] = a[(long long)wrapn(e) * stride];
+#pragma unroll
+    for (int e = -M; e <= M; ++e) ring[(e + W) % W] = (double)raw[(e + W) % W];
+  } else {
+#pragma unroll
+    for (int e = -M; e <= M + PF; ++e) ring[(e + W) % W] = (double)a[(long long)wrapn(e) * stride];
+  }
   for (int k0 = 0; k0 < n; k0 += W) {
 #pragma unroll
     for (int u = 0; u < W; ++u) {
@@ -323,7 +336,12 @@ __global__ void __launch_bounds__(256) k_cn_pconv(Dims d, Fields f, CnTables t, 
           stream_store((T)x, &a[(long long)wrapn(k) * stride]);
         // d_{k-M} leaves the window; d_{k+M+PF+1} (mod n) takes its slot.
         // Rows past n - 1 + M are never used; they load a valid index.
-        ring[(u - M + W) % W] = (double)a[(long long)wrapn(k + M + PF + 1 >= 2 * n ? 0 : k + M + PF + 1) * stride];
+        if constexpr (RAW) {
+          ring[(u + M + 1) % W] = (double)raw[(u + M + 1) % W];   // d_{k+M+1} enters the window
+          raw[(u - M + W) % W] = a[(long long)wrapn(k + M + PF + 1 >= 2 * n ? 0 : k + M + PF + 1) * stride];
+        } else {
+          ring[(u - M + W) % W] = (double)a[(long long)wrapn(k + M + PF + 1 >= 2 * n ? 0 : k + M + PF + 1) * stride];
+        }
       }
     }
   }
@@ -560,6 +578,18 @@ __global__ void __launch_bounds__(64 * CNX_WAVES) k_cn_xconv(Dims d, Fields f, C
 #pragma unroll
   for (int m = 0; m <= M; ++m) G[m] = t.gx[m];
   const double rho = t.gx[M + 2];
+  // rho^m, m = 0 .. M, picked from registers: indexed loads of the table in
+  // the lane-dependent branches below each waited for their value (about 18
+  // round trips per line for the first and last lanes)
+  double rpow[M + 1];
+#pragma unroll
+  for (int m = 0; m <= M; ++m) rpow[m] = t.gx[M + 1 + m];
+  auto rho_pow = [&](int m) {
+    double v = 0.0;
+#pragma unroll
+    for (int q = 0; q <= M; ++q) v = m == q ? rpow[q] : v;
+    return v;
+  };
   const double den0 = 1.0 / (b0 - r * rho), denn = 1.0 / (bn - r * rho);
   double* L = lb[wv] + PAD;   // L[e], e = -PAD .. 64 C + PAD - 1
   // zero pads once: rows -PAD..-1 and n..64C+PAD-1 are never written by a line
@@ -642,8 +672,8 @@ __global__ void __launch_bounds__(64 * CNX_WAVES) k_cn_xconv(Dims d, Fields f, C
     for (int q = 0; q < C; ++q) {
       const int e = e0 + q;
       double x = y[q];
-      if (e <= M) x += alpha * t.gx[M + 1 + e];                            // alpha rho^e
-      if (e < n && n - 1 - e <= M) x += beta * t.gx[M + 1 + (n - 1 - e)];  // beta rho^(n-1-e)
+      if (e <= M) x += alpha * rho_pow(e);                            // alpha rho^e
+      if (e < n && n - 1 - e <= M) x += beta * rho_pow(n - 1 - e);    // beta rho^(n-1-e)
       if (e < n) L[e] = x;
     }
     cn_wave_sync();
