@@ -791,12 +791,12 @@ __device__ __forceinline__ void project_body(const Dims& d, const Fields& f, Sca
 
 // Single-run kernels: 1-D grids; the z FFT takes its tiles in XCD-aware order.
 // FP32 divergence tiles: a 16-column tile reads half of each 128-byte line of
-// u~, so x-neighbours share lines; they go in XCD patches of 8 (consecutive
-// dispatches on one XCD: 0.687 -> 0.658 ms on the 768 x 384 x 384 step, and
-// 0.685 with patches of 2).  FP64 tiles keep the plain order (patches cut the
-// halo fetches of the x+1 line and the plane above by 12 % without changing
-// the time).
-constexpr int DIV_PATCH_F32 = 8;
+// u~, so x-neighbours share lines; they go in XCD patches of 4 (consecutive
+// dispatches on one XCD; on the 768 x 384 x 384 step the kernel takes 0.541 ms
+// with patches of 4, 0.548 with 8 or 16, 0.556 with 2 and 0.610 in the plain
+// order).  FP64 tiles keep the plain order (patches cut the halo fetches of
+// the x+1 line and the plane above by 12 % without changing the time).
+constexpr int DIV_PATCH_F32 = 4;
 template <int NY, class T>
 __global__ void __launch_bounds__(div_threads(NY)) k_div_ffty(Dims d, Fields f, const Scalars* __restrict__ s,
                                                  const double2* __restrict__ tw) {
