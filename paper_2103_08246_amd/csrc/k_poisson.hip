@@ -833,7 +833,10 @@ __global__ void __launch_bounds__(div_threads(NY)) kb_div_ffty(BatchLaunch bl) {
   int lb;
   const RunDesc& R = bl.runs[batch_run(bl, blockIdx.x, &lb)];
   const int gx = (R.d.nx + 15) / 16;
-  div_ffty_body<NY, T>(R.d, R.f, R.s, R.tw_y, lb % gx, lb / gx);
+  // FP32 tiles in XCD patches within each run, as in the single-run kernel
+  // (6-run 384 x 192 x 192 ensemble, mixed: 5.44 -> 5.42 ms per step)
+  const Blk b = sizeof(T) == 4 ? blk_patch(lb, gx, R.d.nz, 1, DIV_PATCH_F32, 1) : blk_linear(lb, gx, R.d.nz, 1);
+  div_ffty_body<NY, T>(R.d, R.f, R.s, R.tw_y, b.x, b.y);
 }
 template <int NZ, int SIGN>
 __global__ void __launch_bounds__(fftz_threads(NZ)) kb_fftz(BatchLaunch bl) {
