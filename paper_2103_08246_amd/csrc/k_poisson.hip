@@ -794,15 +794,16 @@ __device__ __forceinline__ void project_body(const Dims& d, const Fields& f, Sca
 // u~, so x-neighbours share lines; they go in XCD patches of 4 (consecutive
 // dispatches on one XCD; on the 768 x 384 x 384 step the kernel takes 0.541 ms
 // with patches of 4, 0.548 with 8 or 16, 0.556 with 2 and 0.610 in the plain
-// order).  FP64 tiles keep the plain order (patches cut the halo fetches of
-// the x+1 line and the plane above by 12 % without changing the time).
+// order).  FP64 tiles (whole lines) go in patches of 2: 0.718 ms against
+// 0.722 with 4 and 0.725 in the plain order.
 constexpr int DIV_PATCH_F32 = 4;
+constexpr int DIV_PATCH_F64 = 2;
 template <int NY, class T>
 __global__ void __launch_bounds__(div_threads(NY)) k_div_ffty(Dims d, Fields f, const Scalars* __restrict__ s,
                                                  const double2* __restrict__ tw) {
   const int gx = (d.nx + 15) / 16;
   const Blk b = sizeof(T) == 4 ? blk_patch(blockIdx.x, gx, d.nz, 1, DIV_PATCH_F32, 1)
-                               : blk_linear(blockIdx.x, gx, d.nz, 1);
+                               : blk_patch(blockIdx.x, gx, d.nz, 1, DIV_PATCH_F64, 1);
   div_ffty_body<NY, T>(d, f, s, tw, b.x, b.y);
 }
 template <int NZ, int SIGN>
